@@ -1,0 +1,158 @@
+"""Seeded synthetic inputs for the drop-particle workloads.
+
+This module only builds inputs: configuration dictionaries (lattice units), the
+initial order parameter phi0 and the particle records.  It holds none of the
+method's arithmetic; both the GPU library and the CPU oracle receive exactly the
+arrays made here.  Every random draw comes from
+``numpy.random.Generator(PCG64([seed, index]))``.
+
+Defaults follow the paper's parameter table (Table 1: rho_f = 0.05, beta = 0.7,
+k_n = 2.5, k_t = 1.0, k_r = 0.5, particle density 0.125, damping zero in the
+systematic runs, delta R = 1, capillary k = 0.134 on a 2-degree grid).  The
+surface tension 0.01 is the lower end of the table's range; the downward force
+on a particle is 5.23 sigma R_p, which keeps mu g_p / (sigma R_p) <= 5.2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+DEFAULTS = dict(
+    rho0=0.05, tau_a=1.0, tau_b=1.0, sigma=0.01, beta=0.7, theta_wall_deg=90.0,
+    body_force=(0.0, 0.0, 0.0), kn=2.5, kt=1.0, kr=0.5, gn=0.0, gt=0.0, gr=0.0,
+    delta_R=1.0, cap_k=0.134, cap_dang_deg=2.0, has_wall=1, storage="fp32",
+)
+
+
+def rng(seed: int, index: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([int(seed), int(index)]))
+
+
+def config(nx: int, ny: int, nz: int, **kw) -> dict:
+    c = dict(DEFAULTS)
+    c.update(nx=int(nx), ny=int(ny), nz=int(nz))
+    c.update(kw)
+    c["body_force"] = tuple(float(v) for v in c["body_force"])
+    return c
+
+
+def particle(x, R, theta_deg=90.0, mu_s=0.5, mu_r=0.05, rho_p=0.125, g_p=None, sigma=0.01,
+             v=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), kinematic=0) -> dict:
+    return dict(x=tuple(float(a) for a in x), v=tuple(float(a) for a in v),
+                w=tuple(float(a) for a in w), q=(1.0, 0.0, 0.0, 0.0), R=float(R),
+                rho_p=float(rho_p), theta_deg=float(theta_deg), mu_s=float(mu_s),
+                mu_r=float(mu_r), g_p=float(5.23 * sigma * R if g_p is None else g_p),
+                kinematic=int(kinematic))
+
+
+def _grid(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    return x, y, z
+
+
+def _wrap(d, L):
+    return d - L * np.round(d / L)
+
+
+def drop_phi0(nx, ny, nz, centre, radius, width=2.0, periodic=True) -> np.ndarray:
+    """phi0 = tanh((R - r) / width), shape (nz, ny, nx), float32; +1 inside the drop."""
+    x, y, z = _grid(nx, ny, nz)
+    dx, dy, dz = x - centre[0], y - centre[1], z - centre[2]
+    if periodic:
+        dx, dy = _wrap(dx, nx), _wrap(dy, ny)
+    r = np.sqrt(dx * dx + dy * dy + dz * dz)
+    return np.tanh((radius - r) / width).astype(np.float32)
+
+
+def slab_phi0(nx, ny, nz, z_int, width=2.0) -> np.ndarray:
+    """phi0 = tanh((z_int - z) / width): liquid (fluid a) below z_int."""
+    x, y, z = _grid(nx, ny, nz)
+    return np.tanh((z_int - z) / width).astype(np.float32)
+
+
+def _place(g, n, lo, hi, spacing, L, tries=200000):
+    """n points uniform in the box [lo, hi] with min-image spacing >= spacing."""
+    pts = []
+    for _ in range(tries):
+        if len(pts) == n:
+            break
+        p = g.uniform(lo, hi)
+        ok = True
+        for q in pts:
+            d = _wrap(np.asarray(p) - np.asarray(q), np.asarray(L, dtype=float))
+            if np.dot(d, d) < spacing * spacing:
+                ok = False
+                break
+        if ok:
+            pts.append(p)
+    if len(pts) < n:
+        raise RuntimeError("could not place the particles")
+    return pts
+
+
+def sessile_drop_c1(seed: int = 1):
+    """32^3, hemisphere R_d = 10 on a 90-degree wall, one R_p = 4 sphere with a
+    60-degree contact angle at the drop edge with +-0.5 lu jitter; 200 steps."""
+    g = rng(seed, 0)
+    cfg = config(32, 32, 32, theta_wall_deg=90.0)
+    phi0 = drop_phi0(32, 32, 32, (16.0, 16.0, 0.5), 10.0)
+    R = 4.0
+    x = (26.0 + g.uniform(-0.5, 0.5), 16.0 + g.uniform(-0.5, 0.5), 0.5 + R + cfg["delta_R"])
+    parts = [particle(x, R, theta_deg=60.0, mu_s=0.5, mu_r=0.05, sigma=cfg["sigma"])]
+    return dict(name="sessile drop 32^3, 1 sphere R=4", cfg=cfg, phi0=phi0, particles=parts,
+                steps=200)
+
+
+def drop_sweep_c2(seed: int = 2):
+    """256x128x96, 110-degree wall, hemisphere R_d = 30 pushed along x by a body
+    force 5e-6, 20 spheres R_p = 5 resting on the wall; 10,000 steps."""
+    g = rng(seed, 0)
+    nx, ny, nz = 256, 128, 96
+    cfg = config(nx, ny, nz, theta_wall_deg=110.0, body_force=(5e-6, 0.0, 0.0))
+    phi0 = drop_phi0(nx, ny, nz, (64.0, 64.0, 0.5), 30.0)
+    R, Rc = 5.0, 5.0 + cfg["delta_R"]
+    xy = _place(g, 20, [0.0, 0.0], [nx, ny], 2 * Rc + 1, [nx, ny])
+    parts = []
+    for p in xy:
+        parts.append(particle((p[0] % nx, p[1] % ny, 0.5 + Rc), R,
+                              theta_deg=g.uniform(30.0, 120.0), mu_s=g.uniform(0.0, 1.0),
+                              mu_r=g.uniform(0.0, 0.1), sigma=cfg["sigma"]))
+    return dict(name="drop sweeping particles 256x128x96, 20 spheres R=5", cfg=cfg, phi0=phi0,
+                particles=parts, steps=10000)
+
+
+def slab_c3(seed: int = 3, storage: str = "fp32"):
+    """512x256x192, liquid slab filling 40% of the height, 500 spheres R_p = 4
+    at non-overlapping random positions; 500 steps."""
+    g = rng(seed, 0)
+    nx, ny, nz = 512, 256, 192
+    cfg = config(nx, ny, nz, theta_wall_deg=90.0, storage=storage)
+    phi0 = slab_phi0(nx, ny, nz, 0.4 * nz)
+    R, Rc = 4.0, 4.0 + cfg["delta_R"]
+    pts = _place(g, 500, [0.0, 0.0, 0.5 + Rc], [nx, ny, nz - 0.5 - Rc], 2 * Rc + 1,
+                 [nx, ny, 1e9])
+    parts = [particle((p[0] % nx, p[1] % ny, p[2]), R, theta_deg=90.0, mu_s=0.5, mu_r=0.05,
+                      sigma=cfg["sigma"]) for p in pts]
+    return dict(name="liquid slab 512x256x192, 500 spheres R=4", cfg=cfg, phi0=phi0,
+                particles=parts, steps=500)
+
+
+def ensemble_member_c4(seed: int, index: int, storage: str = "fp32"):
+    """One member of the batched ensemble: cubic box of side L in {48,64,80,96},
+    drop radius 12-24, body force 1e-6..1e-5, one sphere of radius 3-6 in front
+    of the drop; 5,000 steps."""
+    g = rng(seed, index)
+    L = int(g.choice([48, 64, 80, 96]))
+    cfg = config(L, L, L, theta_wall_deg=90.0, storage=storage)
+    Rp = g.uniform(3.0, 6.0)
+    Rc = Rp + cfg["delta_R"]
+    Rd = g.uniform(12.0, min(24.0, (L - 2 * Rc - 8) / 2.0))
+    fx = g.uniform(1e-6, 1e-5)
+    cfg["body_force"] = (fx, 0.0, 0.0)
+    mu_s, mu_r, th = g.uniform(0.0, 1.0), g.uniform(0.0, 0.1), g.uniform(30.0, 150.0)
+    xc = L / 4.0
+    phi0 = drop_phi0(L, L, L, (xc, L / 2.0, 0.5), Rd)
+    px = (xc + Rd + Rc + 2.0, L / 2.0 + g.uniform(-0.5, 0.5), 0.5 + Rc)
+    parts = [particle(px, Rp, theta_deg=th, mu_s=mu_s, mu_r=mu_r, sigma=cfg["sigma"])]
+    return dict(name=f"ensemble member {index}: L={L}", cfg=cfg, phi0=phi0, particles=parts,
+                steps=5000, params=dict(mu_s=mu_s, mu_r=mu_r, R_d=Rd, f_x=fx, theta_p=th, R_p=Rp))

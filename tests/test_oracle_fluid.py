@@ -1,0 +1,187 @@
+"""Pins of the oracle's fluid step against conservation laws and closed forms.
+
+T4  mass of each fluid is conserved with static solids;
+T5  per-step momentum balance: fluid momentum changes by the summed node force
+    minus the momentum given to particles (Guo forcing + momentum exchange);
+T6  body-force driven channel flow between the wall plane's two faces is the
+    parabola u = f/(2 rho nu) (z - 1/2)(nz - 1/2 - z) (half-way bounce-back, TRT
+    "magic" Lambda = 3/16 of the printed relaxation vector);
+T7  the flat colour interface at rest obeys the discrete recolouring balance
+    phi(z) - phi(z+1) = beta/2 (2 - phi(z)^2 - phi(z+1)^2), so sum(1 - phi^2) = 2/beta;
+T8  a free drop holds the Laplace jump c_s^2 (rho_in - rho_out) = 2 sigma / R
+    (CSF surface tension eq.);
+T9  a drop on the wall takes the prescribed contact angle (geometric wetting).
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSim
+from paper_2505_10171_amd import workloads as W
+
+
+def _momentum(sim):
+    fa, fb = sim.pops()
+    from oracle import oracle as O
+    c, w, opp = O.lattice()
+    rho, u, phi, mask = sim.fields()
+    fluid = (mask.reshape(-1) == 0)
+    f = (fa + fb)[fluid]
+    return f.sum(axis=0) @ c
+
+
+def test_T4_mass_static_solids():
+    cfg = W.config(16, 16, 16, sigma=0.01, theta_wall_deg=70.0, body_force=(2e-6, 0, 0))
+    phi0 = W.drop_phi0(16, 16, 16, (8.0, 8.0, 0.5), 6.0)
+    parts = [W.particle((12.3, 8.4, 4.6), 3.0, theta_deg=60.0, kinematic=1)]
+    s = OracleSim(cfg, phi0, parts)
+    m0 = s.mass()
+    s.step(300)
+    m1 = s.mass()
+    assert np.all(np.abs(m1 - m0) <= 1e-13 * m0)
+
+
+def test_T5_momentum_balance():
+    """No wall, one static particle, sigma > 0 and a body force: exact per-step
+    balance between fluid momentum, node forces and the momentum exchange."""
+    from oracle import oracle as O
+    cfg = W.config(14, 12, 12, has_wall=0, sigma=0.02, body_force=(3e-6, 1e-6, 0))
+    phi0 = W.drop_phi0(14, 12, 12, (5.0, 6.0, 6.0), 4.0)
+    parts = [W.particle((10.2, 6.3, 5.8), 2.5, theta_deg=120.0, kinematic=1)]
+    s = OracleSim(cfg, phi0, parts)
+    s.step(20)
+    for _ in range(5):
+        p0 = _momentum(s)
+        G, F = s.grad_force()
+        rho, u, phi, mask = s.fields()
+        Fsum = F.reshape(-1, 3)[mask.reshape(-1) == 0].sum(axis=0)
+        s.step(1)
+        p1 = _momentum(s)
+        Fh = s.particles()[0]["F_hyd"]
+        # exact up to the rounding of sums over ~2,000 nodes of O(|p0|) momentum
+        assert np.abs((p1 - p0) - (Fsum - Fh)).max() <= 1e-13 * np.abs(p0).max()
+        assert np.abs(Fh).max() > 1e-8  # the exchange is not trivially zero
+
+
+@pytest.mark.parametrize("tau,steps", [(0.664, 9000), (1.0, 3000), (2.138, 1500)])
+def test_T6_poiseuille(tau, steps):
+    nz, f = 13, 1e-6
+    cfg = W.config(2, 2, nz, tau_a=tau, tau_b=tau, sigma=0.0, body_force=(f, 0, 0))
+    s = OracleSim(cfg, np.ones((nz, 2, 2), np.float32), [])
+    s.step(steps)
+    rho, u, phi, mask = s.fields()
+    z = np.arange(1, nz, dtype=float)
+    nu = (tau - 0.5) / 3.0
+    exact = f / (2 * cfg["rho0"] * nu) * (z - 0.5) * (nz - 0.5 - z)
+    ux = u[0, 1:, 0, 0]
+    assert np.abs(ux - exact).max() <= 1e-8 * exact.max()
+    assert np.abs(u[1:, 1:]).max() < 1e-12 * exact.max()
+
+
+def _flat_interface(sigma, steps):
+    # two interfaces 32 nodes apart, so their tails overlap only below 1e-12
+    nz = 64
+    cfg = W.config(4, 4, nz, has_wall=0, sigma=sigma)
+    z = np.arange(nz, dtype=float)
+    prof = np.tanh((z - 15.5) / 2.0) * np.tanh((47.5 - z) / 2.0)
+    phi0 = np.broadcast_to(prof[:, None, None], (nz, 4, 4)).astype(np.float32)
+    s = OracleSim(cfg, phi0, [])
+    s.step(steps)
+    rho, u, phi, mask = s.fields()
+    return cfg, phi[:, 0, 0]
+
+
+def test_T7_flat_interface_recolouring():
+    """With n = s(z) z^ the steady colour flux balance of recolouring +
+    streaming at rest is
+    phi(z) - phi(z+1) = -beta/2 [(1 - phi(z)^2) s(z) + (1 - phi(z+1)^2) s(z+1)],
+    where G_z = (phi(z+1) - phi(z-1))/2 and s = sign(G_z), or 0 where
+    |G| <= 1e-8 (the normal is not defined there)."""
+    cfg, p = _flat_interface(0.0, 1500)
+    beta = cfg["beta"]
+    nz = p.size
+    Gz = 0.5 * (np.roll(p, -1) - np.roll(p, 1))
+    s = np.where(np.abs(Gz) > 1e-8, np.sign(Gz), 0.0)
+    for z in range(nz):
+        z1 = (z + 1) % nz
+        lhs = p[z] - p[z1]
+        rhs = -0.5 * beta * ((1 - p[z] ** 2) * s[z] + (1 - p[z1] ** 2) * s[z1])
+        assert abs(lhs - rhs) < 1e-12
+    # each interface carries sum(1 - phi^2) = 2 / beta (up to the tails that the
+    # |G| cut-off leaves unsegregated, ~1e-8 of the sum)
+    assert np.isclose(np.sum(1 - p ** 2), 2 * (2 / beta), rtol=3e-8)
+    # the interface centred between nodes 15 and 16 has the straddling pair
+    # +-(sqrt(1 + beta^2) - 1)/beta
+    a = (np.sqrt(1 + beta ** 2) - 1) / beta
+    assert np.isclose(p[16], a, atol=1e-12) and np.isclose(p[15], -a, atol=1e-12)
+    # sign: fluid a (phi > 0) stays where it started
+    assert p[31] > 0.999 and p[0] < -0.999
+
+
+def test_T7_flat_interface_with_tension():
+    cfg, p = _flat_interface(0.01, 1500)
+    beta = cfg["beta"]
+    assert np.isclose(np.sum(1 - p ** 2), 4 / beta, rtol=1e-6)
+
+
+def _laplace_ratio(L, R, sigma=0.01, steps=1200):
+    cfg = W.config(L, L, L, has_wall=0, sigma=sigma)
+    c = L / 2.0 - 0.5
+    s = OracleSim(cfg, W.drop_phi0(L, L, L, (c, c, c), R), [])
+    s.step(steps)
+    rho, u, phi, mask = s.fields()
+    R_eff = (3 * ((1 + phi) / 2).sum() / (4 * np.pi)) ** (1 / 3)
+    i = L // 2
+    dp = (rho[i, i, i] - rho[0, 0, 0]) / 3.0
+    return R_eff, dp * R_eff / (2 * sigma)
+
+
+@pytest.mark.slow
+def test_T8_laplace():
+    """c_s^2 (rho_in - rho_out) R / (2 sigma) -> 1: the discrete curvature error
+    falls like 1/R^2, and the Richardson extrapolation of two radii is 1."""
+    r1, y1 = _laplace_ratio(24, 6.0)
+    r2, y2 = _laplace_ratio(32, 8.0)
+    assert y1 > 1.0 and y2 > 1.0            # correct sign: higher pressure inside
+    assert y2 - 1 < (y1 - 1) * (r1 / r2) ** 2 * 1.25
+    y_inf = (r2 ** 2 * y2 - r1 ** 2 * y1) / (r2 ** 2 - r1 ** 2)
+    assert abs(y_inf - 1.0) < 0.03, y_inf
+
+
+def _cap_angle(phi, zmin=2):
+    """Contact angle of a quasi-2-D (ny = 1) sessile drop from a least-squares
+    circle through the phi = 0 contour (wall surface at z = 0.5)."""
+    nz, nx = phi.shape
+    pts = []
+    for z in range(zmin, nz):
+        row = phi[z]
+        for x in range(nx - 1):
+            a, b = row[x], row[x + 1]
+            if a * b < 0:
+                pts.append((x + a / (a - b), z))
+    for x in range(nx):
+        col = phi[:, x]
+        for z in range(zmin, nz - 1):
+            a, b = col[z], col[z + 1]
+            if a * b < 0:
+                pts.append((x, z + a / (a - b)))
+    P = np.array(pts)
+    A = np.c_[2 * P[:, 0], 2 * P[:, 1], np.ones(len(P))]
+    bvec = (P ** 2).sum(axis=1)
+    (xc, zc, k), *_ = np.linalg.lstsq(A, bvec, rcond=None)
+    r = np.sqrt(k + xc ** 2 + zc ** 2)
+    return np.degrees(np.arccos(np.clip((0.5 - zc) / r, -1, 1)))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
+def test_T9_contact_angle_flat_wall(theta):
+    nx, nz = 80, 36
+    cfg = W.config(nx, 1, nz, sigma=0.01, theta_wall_deg=theta)
+    x, z = np.meshgrid(np.arange(nx, dtype=float), np.arange(nz, dtype=float))
+    r = np.sqrt((x - 40.0) ** 2 + (z - 0.5) ** 2)
+    phi0 = np.tanh((14.0 - r) / 2.0)[:, None, :].astype(np.float32)
+    s = OracleSim(cfg, phi0, [])
+    s.step(6000)
+    rho, u, phi, mask = s.fields()
+    th = _cap_angle(phi[:, 0, :])
+    assert abs(th - theta) < 6.0, th
