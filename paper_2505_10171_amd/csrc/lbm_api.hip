@@ -1,0 +1,650 @@
+// lbm_api.hip -- host implementation of the C ABI declared in include/lbm.h.
+//
+// The context carves the caller's device workspace, uploads the initial state,
+// and issues the per-step kernel sequence on the caller's stream:
+//   k_fused (collide + recolour + stream + bounce-back + momentum exchange)
+//   k_capbox, k_capillary (capillary force)      -- if the sim has particles
+//   k_dem (contacts, friction, Verlet sub-steps)
+//   k_claim, k_release, k_cover (solid mask of the new positions)
+//   k_refill (fresh fluid nodes)
+//   k_moments (order parameter of the new state)
+// No device memory is allocated and nothing is synchronised inside lbm_step.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+
+namespace lbm {
+hipError_t launch_fused(const SimDev& s, const void* src, void* dst, int mode, int LZ, float* orho,
+                        float* ou, float* ophi, float* oF, hipStream_t st);
+hipError_t launch_moments(const SimDev& s, const void* pops, hipStream_t st);
+hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
+hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
+hipError_t launch_mass(const SimDev& s, const void* pops, hipStream_t st);
+hipError_t launch_mask_update(const SimDev& s, int Bmask, bool with_release, hipStream_t st);
+hipError_t launch_refill(const SimDev& s, void* pops, hipStream_t st);
+hipError_t launch_capillary(const SimDev& s, hipStream_t st);
+hipError_t launch_dem(const SimDev& s, hipStream_t st);
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_PARTICLES = 4096;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct SimLayout {
+  long long N;
+  int np, Bmask, Bcap, hist_cap;
+  size_t pop_bytes, fresh_cap;
+  size_t off_pops0, off_pops1, off_phi, off_mask, off_claim, off_fresh, off_fresh_own,
+      off_counters, off_P, off_ct, off_nb, off_hist, off_capbox, off_caporg, off_mass, off_step;
+  size_t total;
+};
+
+double max_radius(const lbm_config& c, const lbm_particle* parts) {
+  double r = 0.0;
+  for (int p = 0; p < c.n_particles; ++p) r = std::max(r, parts ? parts[p].R : 0.0);
+  return r;
+}
+
+bool valid_config(const lbm_config& c, char* msg, size_t len) {
+  auto fail = [&](const char* m) {
+    snprintf(msg, len, "%s", m);
+    return false;
+  };
+  if (c.nx < 1 || c.ny < 1 || c.nz < 3) return fail("lattice must be nx, ny >= 1 and nz >= 3");
+  if ((long long)c.nx * c.ny * c.nz > (1ll << 31) - 1) return fail("lattice too large");
+  if (!(c.rho0 > 0.0)) return fail("rho0 must be positive");
+  if (!(c.tau_a > 0.5) || !(c.tau_b > 0.5)) return fail("relaxation times must exceed 1/2");
+  if (!(c.sigma >= 0.0) || !(c.beta >= 0.0)) return fail("sigma and beta must be >= 0");
+  if (!(c.theta_wall_deg > 0.0 && c.theta_wall_deg < 180.0))
+    return fail("wall contact angle must be in (0, 180) degrees");
+  if (c.storage != LBM_STORE_FP32 && c.storage != LBM_STORE_FP16) return fail("unknown storage");
+  if (c.n_particles < 0 || c.n_particles > MAX_PARTICLES) return fail("n_particles out of range");
+  if (c.n_particles > 0) {
+    if (!(c.kn > 0.0) || c.kt < 0.0 || c.kr < 0.0 || c.gn < 0.0 || c.gt < 0.0 || c.gr < 0.0 ||
+        c.delta_R < 0.0)
+      return fail("invalid contact parameters");
+    if (!(c.cap_dang_deg > 0.0) || c.cap_dang_deg > 90.0) return fail("invalid capillary grid");
+  }
+  return true;
+}
+
+bool valid_particle(const lbm_config& c, const lbm_particle& p, char* msg, size_t len) {
+  if (!(p.R > 0.5) || !(p.rho_p > 0.0)) {
+    snprintf(msg, len, "particle radius must exceed 0.5 and density be positive");
+    return false;
+  }
+  if (!(p.theta_deg > 0.0 && p.theta_deg < 180.0)) {
+    snprintf(msg, len, "particle contact angle must be in (0, 180) degrees");
+    return false;
+  }
+  if (2.0 * p.R + 4.0 > std::min(c.nx, std::min(c.ny, c.nz))) {
+    snprintf(msg, len, "particle too large for the box");
+    return false;
+  }
+  if (p.mu_s < 0.0 || p.mu_r < 0.0) {
+    snprintf(msg, len, "friction coefficients must be >= 0");
+    return false;
+  }
+  return true;
+}
+
+SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
+  SimLayout L{};
+  L.N = (long long)c.nx * c.ny * c.nz;
+  L.np = c.n_particles;
+  L.Bmask = (int)ceil(2.0 * Rmax) + 4;
+  L.Bcap = (int)ceil(2.0 * Rmax) + 3;
+  L.hist_cap = L.np > 0 ? hist_cap : 0;
+  L.pop_bytes = (size_t)38 * L.N * (c.storage == LBM_STORE_FP16 ? 2 : 4);
+  L.fresh_cap = L.np > 0 ? (size_t)L.np * L.Bmask * L.Bmask * L.Bmask : 0;
+  size_t o = align_up(base);
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return r;
+  };
+  L.off_pops0 = take(L.pop_bytes);
+  L.off_pops1 = take(L.pop_bytes);
+  L.off_phi = take(4 * L.N);
+  L.off_mask = take(2 * L.N);
+  L.off_claim = take(4 * L.N);
+  L.off_fresh = take(4 * L.fresh_cap);
+  L.off_fresh_own = take(4 * L.fresh_cap);
+  L.off_counters = take(64);
+  L.off_P = take(sizeof(DevParticle) * L.np);
+  L.off_ct = take(sizeof(Contact) * (size_t)L.np * MAXC);
+  L.off_nb = take(sizeof(int) * (size_t)L.np * MAXNB);
+  L.off_hist = take(sizeof(double) * (size_t)L.hist_cap * L.np * LBM_HIST_DOUBLES);
+  L.off_capbox = take(sizeof(float4) * (size_t)L.np * L.Bcap * L.Bcap * L.Bcap);
+  L.off_caporg = take(sizeof(int) * 3 * (size_t)L.np);
+  L.off_mass = take(2 * sizeof(double));
+  L.off_step = take(sizeof(unsigned long long));
+  L.total = o;
+  return L;
+}
+
+int dem_substeps(const lbm_config& c, const lbm_particle* parts, bool* ok) {
+  *ok = true;
+  if (c.n_particles == 0) return 1;
+  double m1 = INFINITY, m2 = INFINITY;
+  for (int p = 0; p < c.n_particles; ++p) {
+    const double m = parts[p].rho_p * 4.0 / 3.0 * M_PI * parts[p].R * parts[p].R * parts[p].R;
+    if (m < m1) {
+      m2 = m1;
+      m1 = m;
+    } else if (m < m2) {
+      m2 = m;
+    }
+  }
+  const double meff = c.n_particles >= 2 ? m1 * m2 / (m1 + m2) : m1;
+  const double eta = c.gn / (2.0 * meff);
+  const double w2 = c.kn / meff - eta * eta;
+  if (!(w2 > 0.0)) {
+    *ok = false;
+    return 1;
+  }
+  const double tc = M_PI / sqrt(w2);
+  const int ns = (int)ceil(45.0 / tc);
+  return ns < 1 ? 1 : ns;
+}
+
+void fill_dev_particle(DevParticle& d, const lbm_particle& p, double delta_R, bool keep_dynamics) {
+  for (int k = 0; k < 3; ++k) {
+    d.x[k] = p.x[k];
+    d.v[k] = p.v[k];
+    d.w[k] = p.w[k];
+  }
+  for (int k = 0; k < 4; ++k) d.q[k] = p.q[k];
+  d.R = p.R;
+  d.rho_p = p.rho_p;
+  d.theta = p.theta_deg * M_PI / 180.0;
+  d.mu_s = p.mu_s;
+  d.mu_r = p.mu_r;
+  d.g_p = p.g_p;
+  d.mass = p.rho_p * 4.0 / 3.0 * M_PI * p.R * p.R * p.R;
+  d.inertia = 0.4 * d.mass * p.R * p.R;
+  d.Rc = p.R + delta_R;
+  d.neg_cos_t = (float)(-cos(d.theta));
+  d.sin_t = (float)sin(d.theta);
+  d.kin = p.kinematic ? 1 : 0;
+  if (!keep_dynamics) {
+    for (int k = 0; k < 3; ++k) {
+      d.Fh[k] = d.Th[k] = d.Fcap[k] = d.Tcap[k] = d.Fcon[k] = d.Tcon[k] = 0.0;
+      d.Fcp[k] = d.Tcp[k] = d.Fh_last[k] = d.Th_last[k] = 0.0;
+    }
+  }
+}
+
+}  // namespace
+
+struct SimHost {
+  lbm_config cfg;
+  SimLayout L;
+  SimDev d;
+  int cur;  // index of the population buffer holding the current state
+  int LZ;
+  double Rmax;
+};
+
+struct lbm_ctx {
+  std::vector<SimHost> sims;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  int err;
+  char msg[512];
+};
+
+static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
+  if (!c) return code;
+  if (c->err == 0) {
+    c->err = code;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->msg, sizeof(c->msg), fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return set_err((ctx), LBM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+static int choose_LZ(const SimDev& s) {
+  const char* env = getenv("LBM_LZ");
+  if (env && atoi(env) > 0) return atoi(env);
+  const int TX = s.nx >= 64 ? 64 : 32, TY = s.nx >= 64 ? 4 : 8;
+  const long long nxy = (long long)((s.nx + TX - 1) / TX) * ((s.ny + TY - 1) / TY);
+  long long lz = (long long)s.nz * nxy / 2048;
+  lz = std::max<long long>(4, std::min<long long>(32, lz));
+  return (int)lz;
+}
+
+// mask of the new particle positions, fresh nodes, refill, moments
+static int post_dem_pipeline(lbm_ctx* ctx, SimHost& sh, bool with_release) {
+  SimDev& s = sh.d;
+  void* cur = s.pops[sh.cur];
+  if (s.np > 0) {
+    HIPCHK(ctx, launch_mask_update(s, sh.L.Bmask, with_release, ctx->stream));
+    HIPCHK(ctx, launch_refill(s, cur, ctx->stream));
+  }
+  HIPCHK(ctx, launch_moments(s, cur, ctx->stream));
+  return LBM_OK;
+}
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_config* cfg, int32_t n_sims,
+                           const lbm_particle* const* parts, int32_t history_steps) {
+  if (!cfg || n_sims < 1 || history_steps < 0) return 0;
+  char msg[256];
+  size_t o = 0;
+  for (int s = 0; s < n_sims; ++s) {
+    if (!valid_config(cfg[s], msg, sizeof msg)) return 0;
+    if (cfg[s].n_particles > 0 && (!parts || !parts[s])) return 0;
+    const double Rmax = max_radius(cfg[s], cfg[s].n_particles > 0 ? parts[s] : nullptr);
+    o = layout(cfg[s], Rmax, history_steps, o).total;
+  }
+  return o;
+}
+
+int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
+               const lbm_particle* const* parts, int32_t history_steps, void* dev_workspace,
+               size_t ws_bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
+  if (!ctx) return LBM_ENOMEM;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->ws = (char*)dev_workspace;
+  ctx->ws_bytes = ws_bytes;
+  ctx->err = 0;
+  ctx->msg[0] = 0;
+  auto fail = [&](int code, const char* m) {
+    set_err(ctx, code, "%s", m);
+    *out = ctx;  // the caller reads lbm_last_error, then destroys
+    return code;
+  };
+  if (!cfg || n_sims < 1 || !dev_workspace || history_steps < 0)
+    return fail(LBM_EINVAL, "invalid arguments");
+  size_t need = lbm_workspace_bytes(cfg, n_sims, parts, history_steps);
+  if (need == 0) {
+    char msg[256] = "invalid configuration";
+    for (int s = 0; s < n_sims; ++s) valid_config(cfg[s], msg, sizeof msg);
+    return fail(LBM_EINVAL, msg);
+  }
+  if (ws_bytes < need) return fail(LBM_ENOMEM, "workspace too small");
+  ctx->sims.resize(n_sims);
+  size_t off = 0;
+  for (int si = 0; si < n_sims; ++si) {
+    const lbm_config& c = cfg[si];
+    const lbm_particle* pp = (parts && c.n_particles > 0) ? parts[si] : nullptr;
+    if (c.n_particles > 0 && !pp) return fail(LBM_EINVAL, "particles missing");
+    char msg[256];
+    for (int p = 0; p < c.n_particles; ++p)
+      if (!valid_particle(c, pp[p], msg, sizeof msg)) return fail(LBM_EINVAL, msg);
+    bool ok;
+    const int n_sub = dem_substeps(c, pp, &ok);
+    if (!ok) return fail(LBM_EINVAL, "normal damping too large: k_n/m - (g_n/2m)^2 <= 0");
+    SimHost& sh = ctx->sims[si];
+    sh.cfg = c;
+    sh.Rmax = max_radius(c, pp);
+    sh.L = layout(c, sh.Rmax, history_steps, off);
+    off = sh.L.total;
+    SimDev& d = sh.d;
+    memset(&d, 0, sizeof d);
+    d.nx = c.nx;
+    d.ny = c.ny;
+    d.nz = c.nz;
+    d.has_wall = c.has_wall ? 1 : 0;
+    d.N = sh.L.N;
+    d.storage = c.storage;
+    d.np = c.n_particles;
+    d.rho0 = (float)c.rho0;
+    d.sigma = (float)c.sigma;
+    d.beta = (float)c.beta;
+    const double nua = (c.tau_a - 0.5) / 3.0, nub = (c.tau_b - 0.5) / 3.0;
+    d.inv2nua = (float)(1.0 / (2.0 * nua));
+    d.inv2nub = (float)(1.0 / (2.0 * nub));
+    for (int k = 0; k < 3; ++k) d.body[k] = (float)c.body_force[k];
+    d.wall_neg_cos = (float)(-cos(c.theta_wall_deg * M_PI / 180.0));
+    d.wall_sin = (float)sin(c.theta_wall_deg * M_PI / 180.0);
+    char* b = ctx->ws;
+    d.pops[0] = b + sh.L.off_pops0;
+    d.pops[1] = b + sh.L.off_pops1;
+    d.phi = (float*)(b + sh.L.off_phi);
+    d.mask = (uint16_t*)(b + sh.L.off_mask);
+    d.claim = (uint32_t*)(b + sh.L.off_claim);
+    d.fresh = (uint32_t*)(b + sh.L.off_fresh);
+    d.fresh_own = (uint32_t*)(b + sh.L.off_fresh_own);
+    d.counters = (uint32_t*)(b + sh.L.off_counters);
+    d.fresh_cap = (uint32_t)sh.L.fresh_cap;
+    d.P = (DevParticle*)(b + sh.L.off_P);
+    d.ct = (Contact*)(b + sh.L.off_ct);
+    d.nb = (int*)(b + sh.L.off_nb);
+    d.hist = (double*)(b + sh.L.off_hist);
+    d.hist_cap = sh.L.hist_cap;
+    d.n_sub = n_sub;
+    d.kn = c.kn;
+    d.kt = c.kt;
+    d.kr = c.kr;
+    d.gn = c.gn;
+    d.gt = c.gt;
+    d.gr = c.gr;
+    d.delta_R = c.delta_R;
+    d.cap_pref = c.sigma * 4.5 * c.cap_k * c.beta;
+    d.cap_dang = c.cap_dang_deg * M_PI / 180.0;
+    d.cap_na = (int)llround(180.0 / c.cap_dang_deg);
+    d.cap_nphi = (int)llround(360.0 / c.cap_dang_deg);
+    d.cap_B = sh.L.Bcap;
+    d.capbox = (float4*)(b + sh.L.off_capbox);
+    d.capbox_org = (int*)(b + sh.L.off_caporg);
+    d.mass_acc = (double*)(b + sh.L.off_mass);
+    d.step_counter = (unsigned long long*)(b + sh.L.off_step);
+    sh.cur = 0;
+    sh.LZ = choose_LZ(d);
+
+    // upload particles and contact tables
+    hipStream_t st = ctx->stream;
+    if (d.np > 0) {
+      std::vector<DevParticle> hp(d.np);
+      memset(hp.data(), 0, sizeof(DevParticle) * d.np);
+      for (int p = 0; p < d.np; ++p) {
+        fill_dev_particle(hp[p], pp[p], c.delta_R, false);
+        for (int k = 0; k < 3; ++k) hp[p].xo[k] = hp[p].x[k];
+        hp[p].Ro = hp[p].R;
+      }
+      std::vector<Contact> ct((size_t)d.np * MAXC);
+      for (auto& e : ct) {
+        memset(&e, 0, sizeof e);
+        e.partner = -100;
+      }
+      if (hipMemcpyAsync(d.P, hp.data(), sizeof(DevParticle) * d.np, hipMemcpyHostToDevice,
+                         st) != hipSuccess ||
+          hipMemcpyAsync(d.ct, ct.data(), sizeof(Contact) * ct.size(), hipMemcpyHostToDevice,
+                         st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(LBM_EHIP, "particle upload failed");
+    }
+    if (hipMemsetAsync(d.counters, 0, 64, st) != hipSuccess ||
+        hipMemsetAsync(d.step_counter, 0, sizeof(unsigned long long), st) != hipSuccess)
+      return fail(LBM_EHIP, "counter initialisation failed");
+    // phi0 staged in the phi field
+    if (phi0 && phi0[si]) {
+      if (hipMemcpyAsync(d.phi, phi0[si], sizeof(float) * d.N, hipMemcpyHostToDevice, st) !=
+          hipSuccess)
+        return fail(LBM_EHIP, "phi0 upload failed");
+    } else {
+      std::vector<float> ones(d.N, 1.0f);
+      if (hipMemcpyAsync(d.phi, ones.data(), sizeof(float) * d.N, hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(LBM_EHIP, "phi0 upload failed");
+    }
+    if (launch_init_mask(d, st) != hipSuccess) return fail(LBM_EHIP, "mask init failed");
+    if (d.np > 0 && launch_mask_update(d, sh.L.Bmask, false, st) != hipSuccess)
+      return fail(LBM_EHIP, "mask build failed");
+    if (launch_init_pops(d, d.pops[0], st) != hipSuccess)
+      return fail(LBM_EHIP, "population init failed");
+    if (launch_moments(d, d.pops[0], st) != hipSuccess) return fail(LBM_EHIP, "moments failed");
+    if (phi0 && phi0[si]) {
+      // the host buffer must stay valid until the copy has completed
+      if (hipStreamSynchronize(st) != hipSuccess) return fail(LBM_EHIP, "synchronise failed");
+    }
+  }
+  *out = ctx;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  if (n_steps < 0) return set_err(ctx, LBM_EINVAL, "negative step count");
+  for (int t = 0; t < n_steps; ++t) {
+    for (auto& sh : ctx->sims) {
+      SimDev& s = sh.d;
+      void* src = s.pops[sh.cur];
+      void* dst = s.pops[sh.cur ^ 1];
+      HIPCHK(ctx, launch_fused(s, src, dst, 0, sh.LZ, nullptr, nullptr, nullptr, nullptr,
+                               ctx->stream));
+      if (s.np > 0) {
+        HIPCHK(ctx, launch_capillary(s, ctx->stream));
+        HIPCHK(ctx, launch_dem(s, ctx->stream));
+      }
+      sh.cur ^= 1;
+      int rc = post_dem_pipeline(ctx, sh, true);
+      if (rc) return rc;
+    }
+  }
+  return LBM_OK;
+}
+
+static int check_status(lbm_ctx* ctx) {
+  for (auto& sh : ctx->sims) {
+    uint32_t cnt[4];
+    HIPCHK(ctx, hipMemcpyAsync(cnt, sh.d.counters, sizeof cnt, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (cnt[1] & ST_UNSTABLE)
+      return set_err(ctx, LBM_EUNSTABLE, "unstable flow: NaN, rho <= 0 or |u| > 0.3");
+    if (cnt[1] & ST_CONTACT_FULL)
+      return set_err(ctx, LBM_ERANGE, "contact table or pair candidate list overflow");
+    if (cnt[1] & ST_FRESH_FULL) return set_err(ctx, LBM_ERANGE, "fresh-node list overflow");
+  }
+  return LBM_OK;
+}
+
+int lbm_sync(lbm_ctx* ctx) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return check_status(ctx);
+}
+
+static SimHost* get_sim(lbm_ctx* ctx, int sim) {
+  if (sim < 0 || sim >= (int)ctx->sims.size()) return nullptr;
+  return &ctx->sims[sim];
+}
+
+int lbm_particles_sync(lbm_ctx* ctx, int32_t sim, int32_t dir, lbm_particle* parts, int32_t n,
+                       double* history, int32_t max_steps, int32_t* n_hist) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  SimHost* sh = get_sim(ctx, sim);
+  if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
+  SimDev& d = sh->d;
+  if (n != d.np || (n > 0 && !parts)) return set_err(ctx, LBM_EINVAL, "particle count mismatch");
+  int rc = lbm_sync(ctx);
+  if (rc) return rc;
+  if (n_hist) *n_hist = 0;
+  if (d.np == 0) return LBM_OK;
+  std::vector<DevParticle> hp(d.np);
+  HIPCHK(ctx, hipMemcpyAsync(hp.data(), d.P, sizeof(DevParticle) * d.np, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (dir == 0) {
+    for (int p = 0; p < d.np; ++p) {
+      const DevParticle& s = hp[p];
+      lbm_particle& o = parts[p];
+      memset(&o, 0, sizeof o);
+      for (int k = 0; k < 3; ++k) {
+        o.x[k] = s.x[k];
+        o.v[k] = s.v[k];
+        o.w[k] = s.w[k];
+        o.F_hyd[k] = s.Fh_last[k];
+        o.T_hyd[k] = s.Th_last[k];
+        o.F_cap[k] = s.Fcap[k];
+        o.T_cap[k] = s.Tcap[k];
+        o.F_con[k] = s.Fcon[k];
+        o.T_con[k] = s.Tcon[k];
+      }
+      for (int k = 0; k < 4; ++k) o.q[k] = s.q[k];
+      o.R = s.R;
+      o.rho_p = s.rho_p;
+      o.theta_deg = s.theta * 180.0 / M_PI;
+      o.mu_s = s.mu_s;
+      o.mu_r = s.mu_r;
+      o.g_p = s.g_p;
+      o.kinematic = s.kin;
+    }
+    if (history && max_steps > 0 && d.hist_cap > 0) {
+      unsigned long long steps = 0;
+      HIPCHK(ctx, hipMemcpyAsync(&steps, d.step_counter, sizeof steps, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      const long long avail = (long long)std::min<unsigned long long>(steps, (unsigned long long)d.hist_cap);
+      const long long cnt = std::min<long long>(avail, max_steps);
+      std::vector<double> ring((size_t)d.hist_cap * d.np * LBM_HIST_DOUBLES);
+      HIPCHK(ctx, hipMemcpyAsync(ring.data(), d.hist, sizeof(double) * ring.size(),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      const size_t rec = (size_t)d.np * LBM_HIST_DOUBLES;
+      for (long long k = 0; k < cnt; ++k) {
+        const unsigned long long step = steps - cnt + k;
+        memcpy(history + k * rec, ring.data() + (step % d.hist_cap) * rec, sizeof(double) * rec);
+      }
+      if (n_hist) *n_hist = (int32_t)cnt;
+    }
+    return LBM_OK;
+  }
+  if (dir != 1) return set_err(ctx, LBM_EINVAL, "dir must be 0 (pull) or 1 (push)");
+  char msg[256];
+  for (int p = 0; p < d.np; ++p) {
+    if (!valid_particle(sh->cfg, parts[p], msg, sizeof msg)) return set_err(ctx, LBM_EINVAL, "%s", msg);
+    if (parts[p].R > sh->Rmax)
+      return set_err(ctx, LBM_ERANGE, "radius exceeds the largest radius the context was sized for");
+  }
+  for (int p = 0; p < d.np; ++p) {
+    DevParticle& s = hp[p];
+    for (int k = 0; k < 3; ++k) s.xo[k] = s.x[k];
+    s.Ro = s.R;
+    fill_dev_particle(s, parts[p], sh->cfg.delta_R, true);
+  }
+  HIPCHK(ctx, hipMemcpyAsync(d.P, hp.data(), sizeof(DevParticle) * d.np, hipMemcpyHostToDevice,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  rc = post_dem_pipeline(ctx, *sh, true);
+  if (rc) return rc;
+  return lbm_sync(ctx);
+}
+
+int lbm_fields(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, float* phi,
+               uint16_t* mask, void* pops, int32_t dst_is_device) {
+  return lbm_fields2(ctx, sim, what, rho, u, phi, nullptr, mask, pops, dst_is_device);
+}
+
+int lbm_fields2(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, float* phi,
+                float* force, uint16_t* mask, void* pops, int32_t dst_is_device) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  SimHost* sh = get_sim(ctx, sim);
+  if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
+  SimDev& d = sh->d;
+  const long long N = d.N;
+  const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (what & (LBM_F_RHO | LBM_F_U | LBM_F_PHI | LBM_F_FORCE)) {
+    // the spare population buffer holds the outputs: rho | phi | u | F (8N floats)
+    float* scratch = (float*)d.pops[sh->cur ^ 1];
+    float* orho = scratch;
+    float* ophi = scratch + N;
+    float* ou = scratch + 2 * N;
+    float* oF = scratch + 5 * N;
+    HIPCHK(ctx, launch_fused(d, d.pops[sh->cur], nullptr, 1, sh->LZ, orho, ou, ophi, oF,
+                             ctx->stream));
+    if ((what & LBM_F_FORCE) && force)
+      HIPCHK(ctx, hipMemcpyAsync(force, oF, 12 * N, kind, ctx->stream));
+    if ((what & LBM_F_RHO) && rho)
+      HIPCHK(ctx, hipMemcpyAsync(rho, orho, 4 * N, kind, ctx->stream));
+    if ((what & LBM_F_PHI) && phi)
+      HIPCHK(ctx, hipMemcpyAsync(phi, ophi, 4 * N, kind, ctx->stream));
+    if ((what & LBM_F_U) && u) HIPCHK(ctx, hipMemcpyAsync(u, ou, 12 * N, kind, ctx->stream));
+  }
+  if ((what & LBM_F_MASK) && mask)
+    HIPCHK(ctx, hipMemcpyAsync(mask, d.mask, 2 * N, kind, ctx->stream));
+  if ((what & LBM_F_POPS) && pops)
+    HIPCHK(ctx, hipMemcpyAsync(pops, d.pops[sh->cur], sh->L.pop_bytes, kind, ctx->stream));
+  return lbm_sync(ctx);
+}
+
+int lbm_links(lbm_ctx* ctx, int32_t sim, uint32_t* out, int32_t* pid, int64_t max, int64_t* count) {
+  if (!ctx || !count) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  SimHost* sh = get_sim(ctx, sim);
+  if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
+  const SimDev& d = sh->d;
+  std::vector<uint16_t> m(d.N);
+  int rc = lbm_sync(ctx);
+  if (rc) return rc;
+  HIPCHK(ctx, hipMemcpyAsync(m.data(), d.mask, 2 * d.N, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  int64_t cnt = 0;
+  for (int p = 0; p < d.np; ++p)
+    for (long long n = 0; n < d.N; ++n) {
+      if (m[n] != 0) continue;
+      const int x = (int)(n % d.nx), y = (int)((n / d.nx) % d.ny), z = (int)(n / ((long long)d.nx * d.ny));
+      for (int i = 1; i < Q; ++i) {
+        const long long t = (long long)wrapi(x + cx(i), d.nx) +
+                            (long long)d.nx * ((long long)wrapi(y + cy(i), d.ny) +
+                                               (long long)d.ny * wrapi(z + cz(i), d.nz));
+        if (m[t] == 2 + p) {
+          if (cnt < max) {
+            if (out) out[cnt] = (uint32_t)((n << 5) | i);
+            if (pid) pid[cnt] = p;
+          }
+          ++cnt;
+        }
+      }
+    }
+  *count = cnt;
+  return LBM_OK;
+}
+
+int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]) {
+  if (!ctx || !out) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  SimHost* sh = get_sim(ctx, sim);
+  if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
+  SimDev& d = sh->d;
+  HIPCHK(ctx, hipMemsetAsync(d.mass_acc, 0, 2 * sizeof(double), ctx->stream));
+  HIPCHK(ctx, launch_mass(d, d.pops[sh->cur], ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(out, d.mass_acc, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  return lbm_sync(ctx);
+}
+
+int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out) {
+  if (!ctx || !out) return LBM_EINVAL;
+  SimHost* sh = get_sim(ctx, sim);
+  if (!sh) return LBM_ERANGE;
+  *out = sh->d.n_sub;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx) {
+  if (!ctx || ctx->err == 0) return nullptr;
+  return ctx->msg;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// lbm_device.h -- device-side data structures and lattice constants shared by the
+// HIP kernels of liblbm (gfx950).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------- lattice
+// D3Q19: rest, +-x, +-y, +-z, (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1).
+constexpr int Q = 19;
+__host__ __device__ constexpr int cx(int i) {
+  constexpr int t[Q] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
+  return t[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+  constexpr int t[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
+  return t[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+  constexpr int t[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+  return t[i];
+}
+__host__ __device__ constexpr int opp(int i) {
+  constexpr int t[Q] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+  return t[i];
+}
+__host__ __device__ constexpr float wq(int i) {
+  return i == 0 ? (1.0f / 3.0f) : (i <= 6 ? (1.0f / 18.0f) : (1.0f / 36.0f));
+}
+__host__ __device__ constexpr double wqd(int i) {
+  return i == 0 ? (1.0 / 3.0) : (i <= 6 ? (1.0 / 18.0) : (1.0 / 36.0));
+}
+
+constexpr float EPS_G = 1e-8f;  // |grad phi| below which the normal is undefined
+constexpr float EPS_T = 1e-6f;  // tangential part below which wetting leaves G alone
+constexpr int MAXC = 16;        // contact slots per particle
+constexpr int MAXNB = 24;       // DEM pair candidates per particle
+constexpr uint16_t FRESH_BIT = 0x8000;
+
+// -------------------------------------------------------------- particles
+struct alignas(16) DevParticle {
+  double x[3], v[3], w[3], q[4];
+  double R, rho_p, theta, mu_s, mu_r, g_p;
+  double mass, inertia, Rc;
+  float neg_cos_t, sin_t;   // -cos(theta), sin(theta) for the wetting rotation
+  int kin, pad;
+  double Fh[3], Th[3];      // momentum exchange accumulators (FP64 atomics)
+  double Fcap[3], Tcap[3];  // capillary force, last step
+  double Fcon[3], Tcon[3];  // contact force, sub-step mean of the last step
+  double Fcp[3], Tcp[3];    // contact force/torque of the last DEM sub-step
+  double Fh_last[3], Th_last[3];  // momentum exchange of the last step (output copy)
+  // DEM scratch
+  double xo[3], Ro;         // centre and radius before the last update (mask release)
+  double Ff[3], Tf[3];      // fluid force/torque held over the sub-steps (incl. gravity)
+  double Facc[3], Tacc[3];  // contact sums over the sub-steps
+  double ao[3], bo[3];      // accelerations at the start of the sub-step
+  double vp[3], wp[3];      // predicted velocities
+  double Fcn[3], Tcn[3];    // contact force/torque of the current sub-step
+};
+
+constexpr int LBM_HIST_DOUBLES_DEV = 27;
+
+struct Contact {
+  int partner;  // -1 wall surface, -2 wall underside, >= 0 particle, -100 free
+  int pad;
+  double xt[3], xr[3];
+};
+
+// ------------------------------------------------------------- simulation
+struct SimDev {
+  int nx, ny, nz, has_wall;
+  long long N;
+  int storage, np;
+  float rho0, sigma, beta, inv2nua, inv2nub;
+  float body[3];
+  float wall_neg_cos, wall_sin;
+  // fields
+  void* pops[2];       // ping-pong population buffers: 38 planes of N
+  float* phi;          // order parameter of the current state
+  uint16_t* mask;      // 0 fluid, 1 wall, 2+p particle p; FRESH_BIT while refilling
+  uint32_t* claim;     // per node: lowest particle claiming it in the new mask, ~0u none
+  uint32_t* fresh;     // fresh-node list: node index
+  uint32_t* fresh_own; // fresh-node list: particle that uncovered it
+  uint32_t* counters;  // [0] fresh count, [1] status flags, [2] fresh overflow
+  uint32_t fresh_cap;
+  // particles
+  DevParticle* P;
+  Contact* ct;         // np * MAXC
+  int* nb;             // np * MAXNB candidate partners
+  double* hist;        // hist_cap * np * 27
+  int hist_cap;
+  int n_sub;
+  double kn, kt, kr, gn, gt, gr, delta_R;
+  double cap_pref;     // sigma * 9/2 * k * beta (times sin(theta_p) per particle)
+  double cap_dang;     // radians
+  int cap_na, cap_nphi;
+  int cap_B;           // side of the per-particle capillary box
+  float4* capbox;      // np * B^3: (phi, Gx, Gy, Gz); phi = 2 marks a solid corner
+  int* capbox_org;     // np * 3 box origins
+  double* mass_acc;    // 2 doubles
+  unsigned long long* step_counter;
+};
+
+enum StatusBits : uint32_t { ST_UNSTABLE = 1u, ST_CONTACT_FULL = 2u, ST_FRESH_FULL = 4u };
+
+__host__ __device__ inline int wrapi(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+// minimum image: wrap once into (-L/2, L/2]
+__host__ __device__ inline double wrapd(double d, double L) {
+  if (d > 0.5 * L)
+    d -= L;
+  else if (d <= -0.5 * L)
+    d += L;
+  return d;
+}
+
+}  // namespace lbm

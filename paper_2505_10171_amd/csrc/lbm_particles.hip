@@ -1,0 +1,686 @@
+// lbm_particles.hip -- particle kernels of liblbm for gfx950: solid mask update,
+// refilling of fresh fluid nodes, capillary force on the Lagrangian surface grid
+// and the DEM (contacts with sliding and rolling friction, velocity Verlet).
+#include "lbm_device.h"
+
+namespace lbm {
+
+template <int STORE>
+struct PIO;
+template <>
+struct PIO<0> {
+  using T = float;
+  static __device__ __forceinline__ float ld(const T* p, float) { return *p; }
+  static __device__ __forceinline__ void st(T* p, float v, float) { *p = v; }
+};
+template <>
+struct PIO<1> {
+  using T = __half;
+  static __device__ __forceinline__ float ld(const T* p, float scale) {
+    return __half2float(*p) * scale;
+  }
+  static __device__ __forceinline__ void st(T* p, float v, float inv_scale) {
+    *p = __float2half_rn(v * inv_scale);
+  }
+};
+
+// ------------------------------------------------------------------ masks
+// Particle bounding box: every node inside the sphere lies in it.
+struct Box {
+  int lo[3], w[3];
+};
+__device__ __forceinline__ Box particle_box(const SimDev& s, const double* X, double R) {
+  Box b;
+  const int L[3] = {s.nx, s.ny, s.nz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    b.lo[k] = (int)floor(X[k] - R) - 1;
+    b.w[k] = (int)floor(X[k] + R) + 1 - b.lo[k] + 1;
+    if (b.w[k] > L[k]) {
+      b.lo[k] = 0;
+      b.w[k] = L[k];
+    }
+  }
+  return b;
+}
+
+// Inside test: ((dx*dx)+(dy*dy))+(dz*dz) < R*R in FP64, rounded operation by
+// operation (no contraction), d wrapped once into (-L/2, L/2].
+__device__ __attribute__((noinline)) bool inside_sphere(int x, int y, int z, const double* X,
+                                                        double R, int nx, int ny, int nz) {
+#pragma clang fp contract(off)
+  double dx = wrapd((double)x - X[0], (double)nx);
+  double dy = wrapd((double)y - X[1], (double)ny);
+  double dz = wrapd((double)z - X[2], (double)nz);
+  double a = dx * dx;
+  double b = dy * dy;
+  double c = dz * dz;
+  double d2 = (a + b) + c;
+  return d2 < R * R;
+}
+
+// claim: lowest particle index inside which a node lies (new positions)
+__global__ void k_claim(SimDev s) {
+  const int p = blockIdx.y;
+  const DevParticle& P = s.P[p];
+  const Box b = particle_box(s, P.x, P.R);
+  const int vol = b.w[0] * b.w[1] * b.w[2];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < vol; k += gridDim.x * blockDim.x) {
+    const int ix = k % b.w[0], iy = (k / b.w[0]) % b.w[1], iz = k / (b.w[0] * b.w[1]);
+    const int x = wrapi(b.lo[0] + ix, s.nx), y = wrapi(b.lo[1] + iy, s.ny),
+              z = wrapi(b.lo[2] + iz, s.nz);
+    if (s.has_wall && z == 0) continue;
+    if (inside_sphere(x, y, z, P.x, P.R, s.nx, s.ny, s.nz)) {
+      const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
+      atomicMin(&s.claim[n], (uint32_t)p);
+    }
+  }
+}
+
+// release: nodes that belonged to p (old box) become fluid (fresh) or pass to
+// the particle that claims them now.  Each such node is visited once (by p).
+__global__ void k_release(SimDev s) {
+  const int p = blockIdx.y;
+  const DevParticle& P = s.P[p];
+  double Xo[3] = {P.xo[0], P.xo[1], P.xo[2]};
+  const Box b = particle_box(s, Xo, P.Ro);
+  const int vol = b.w[0] * b.w[1] * b.w[2];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < vol; k += gridDim.x * blockDim.x) {
+    const int ix = k % b.w[0], iy = (k / b.w[0]) % b.w[1], iz = k / (b.w[0] * b.w[1]);
+    const int x = wrapi(b.lo[0] + ix, s.nx), y = wrapi(b.lo[1] + iy, s.ny),
+              z = wrapi(b.lo[2] + iz, s.nz);
+    const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
+    if (s.mask[n] != (uint16_t)(2 + p)) continue;
+    const uint32_t c = s.claim[n];
+    if (c == 0xFFFFFFFFu) {
+      s.mask[n] = FRESH_BIT;
+      const uint32_t slot = atomicAdd(&s.counters[0], 1u);
+      if (slot < s.fresh_cap) {
+        s.fresh[slot] = (uint32_t)n;
+        s.fresh_own[slot] = (uint32_t)p;
+      } else {
+        atomicOr(&s.counters[1], (uint32_t)ST_FRESH_FULL);
+      }
+    } else if (c != (uint32_t)p) {
+      s.mask[n] = (uint16_t)(2 + c);
+    }
+  }
+}
+
+// cover: nodes claimed by p become p's solid nodes; claims are cleared
+__global__ void k_cover(SimDev s) {
+  const int p = blockIdx.y;
+  const DevParticle& P = s.P[p];
+  const Box b = particle_box(s, P.x, P.R);
+  const int vol = b.w[0] * b.w[1] * b.w[2];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < vol; k += gridDim.x * blockDim.x) {
+    const int ix = k % b.w[0], iy = (k / b.w[0]) % b.w[1], iz = k / (b.w[0] * b.w[1]);
+    const int x = wrapi(b.lo[0] + ix, s.nx), y = wrapi(b.lo[1] + iy, s.ny),
+              z = wrapi(b.lo[2] + iz, s.nz);
+    const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
+    if (s.claim[n] == (uint32_t)p) {
+      s.mask[n] = (uint16_t)(2 + p);
+      s.claim[n] = 0xFFFFFFFFu;
+    }
+  }
+}
+
+// Refilling (refilling eqs.): f_a, f_b of a fresh node = equilibria of the mean
+// neighbour densities (fluid, not fresh, D3Q19 neighbours; rho0/2 each if none)
+// at the surface velocity of the particle that uncovered it.
+template <int STORE>
+__global__ void k_refill(SimDev s, void* pops) {
+  using IO = PIO<STORE>;
+  using T = typename IO::T;
+  T* b = (T*)pops;
+  const uint32_t cnt = min(s.counters[0], s.fresh_cap);
+  const long long N = s.N;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+    const long long n = s.fresh[k];
+    const int p = (int)s.fresh_own[k];
+    const int x = (int)(n % s.nx), y = (int)((n / s.nx) % s.ny), z = (int)(n / ((long long)s.nx * s.ny));
+    float sa = 0.f, sb = 0.f;
+    int c = 0;
+    for (int i = 1; i < Q; ++i) {
+      const long long m = (long long)wrapi(x + cx(i), s.nx) +
+                          (long long)s.nx * ((long long)wrapi(y + cy(i), s.ny) +
+                                             (long long)s.ny * wrapi(z + cz(i), s.nz));
+      if (s.mask[m] != 0) continue;
+      float drho = 0.f, sg = 0.f;
+      for (int q = 0; q < Q; ++q) {
+        const float sc = wq(q) * s.rho0;
+        drho += IO::ld(b + (long long)q * N + m, sc);
+        sg += IO::ld(b + (long long)(Q + q) * N + m, sc);
+      }
+      const float rho = s.rho0 + drho;
+      sa += 0.5f * (rho + sg);
+      sb += 0.5f * (rho - sg);
+      ++c;
+    }
+    const float ra = c ? sa / c : 0.5f * s.rho0;
+    const float rb = c ? sb / c : 0.5f * s.rho0;
+    const DevParticle& P = s.P[p];
+    const double rx = wrapd((double)x - P.x[0], (double)s.nx);
+    const double ry = wrapd((double)y - P.x[1], (double)s.ny);
+    const double rz = wrapd((double)z - P.x[2], (double)s.nz);
+    const float ux = (float)(P.v[0] + P.w[1] * rz - P.w[2] * ry);
+    const float uy = (float)(P.v[1] + P.w[2] * rx - P.w[0] * rz);
+    const float uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float rho = ra + rb;
+    for (int q = 0; q < Q; ++q) {
+      const float cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
+      const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+      const float sc = wq(q) * s.rho0;
+      const float dq = wq(q) * ((rho - s.rho0) + rho * poly);
+      const float gq = wq(q) * (ra - rb) * (1.0f + poly);
+      IO::st(b + (long long)q * N + n, dq, 1.0f / sc);
+      IO::st(b + (long long)(Q + q) * N + n, gq, 1.0f / sc);
+    }
+  }
+}
+
+// -------------------------------------------------------------- capillary
+// Colour gradient with the wetting rotation at one node, from global phi/mask
+// (the same stencil, closure and rotation as the fused kernel).
+__device__ void node_gradient(const SimDev& s, int x, int y, int z, float& Gx, float& Gy, float& Gz) {
+  const long long n0 = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
+  const float p0 = s.phi[n0];
+  Gx = Gy = Gz = 0.f;
+  int minp = 0x7fffffff;
+  bool solid = false, wall = false;
+  constexpr int pd[9] = {1, 3, 5, 7, 8, 11, 12, 15, 16};
+  for (int q = 0; q < 9; ++q) {
+    const int i = pd[q];
+    const long long mp = (long long)wrapi(x + cx(i), s.nx) +
+                         (long long)s.nx * ((long long)wrapi(y + cy(i), s.ny) +
+                                            (long long)s.ny * wrapi(z + cz(i), s.nz));
+    const long long mm = (long long)wrapi(x - cx(i), s.nx) +
+                         (long long)s.nx * ((long long)wrapi(y - cy(i), s.ny) +
+                                            (long long)s.ny * wrapi(z - cz(i), s.nz));
+    const uint16_t kp = s.mask[mp], km = s.mask[mm];
+    const float vp = kp == 0 ? s.phi[mp] : p0;
+    const float vm = km == 0 ? s.phi[mm] : p0;
+    const float d = 3.0f * wq(i) * (vp - vm);
+    Gx += (float)cx(i) * d;
+    Gy += (float)cy(i) * d;
+    Gz += (float)cz(i) * d;
+    if (kp) {
+      solid = true;
+      if (kp >= 2) minp = min(minp, (int)kp - 2); else wall = true;
+    }
+    if (km) {
+      solid = true;
+      if (km >= 2) minp = min(minp, (int)km - 2); else wall = true;
+    }
+  }
+  if (!solid) return;
+  // wetting rotation (n_pm equation)
+  float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
+  if (!(g > EPS_G)) return;
+  float nsx, nsy, nsz, nc, ns;
+  if (minp != 0x7fffffff) {
+    const DevParticle& P = s.P[minp];
+    double dx = wrapd((double)x - P.x[0], (double)s.nx);
+    double dy = wrapd((double)y - P.x[1], (double)s.ny);
+    double dz = wrapd((double)z - P.x[2], (double)s.nz);
+    double dn = sqrt(dx * dx + dy * dy + dz * dz);
+    nsx = (float)(dx / dn);
+    nsy = (float)(dy / dn);
+    nsz = (float)(dz / dn);
+    nc = P.neg_cos_t;
+    ns = P.sin_t;
+  } else {
+    nsx = 0.f;
+    nsy = 0.f;
+    nsz = (z == 1) ? 1.f : -1.f;
+    nc = s.wall_neg_cos;
+    ns = s.wall_sin;
+  }
+  float inv = 1.0f / g;
+  float ax = Gx * inv, ay = Gy * inv, az = Gz * inv;
+  float a = ax * nsx + ay * nsy + az * nsz;
+  float tx = ax - a * nsx, ty = ay - a * nsy, tz = az - a * nsz;
+  float tn = sqrtf(tx * tx + ty * ty + tz * tz);
+  if (!(tn > EPS_T)) return;
+  float it = 1.0f / tn;
+  Gx = g * (nc * nsx + ns * tx * it);
+  Gy = g * (nc * nsy + ns * ty * it);
+  Gz = g * (nc * nsz + ns * tz * it);
+}
+
+// per-particle box of (phi, G) at the nodes the Lagrangian points interpolate
+__global__ void k_capbox(SimDev s) {
+  const int p = blockIdx.y;
+  const DevParticle& P = s.P[p];
+  const int B = s.cap_B;
+  int org[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) org[k] = (int)floor(P.x[k] - P.R);
+  if (blockIdx.x == 0 && threadIdx.x < 3) s.capbox_org[3 * p + threadIdx.x] = org[threadIdx.x];
+  float4* box = s.capbox + (long long)p * B * B * B;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < B * B * B; k += gridDim.x * blockDim.x) {
+    const int ix = k % B, iy = (k / B) % B, iz = k / (B * B);
+    const int x = wrapi(org[0] + ix, s.nx), y = wrapi(org[1] + iy, s.ny), z = wrapi(org[2] + iz, s.nz);
+    const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
+    float4 v = make_float4(2.f, 0.f, 0.f, 0.f);  // phi = 2 marks a solid node
+    if (s.mask[n] == 0) {
+      float Gx, Gy, Gz;
+      node_gradient(s, x, y, z, Gx, Gy, Gz);
+      v = make_float4(s.phi[n], Gx, Gy, Gz);
+    }
+    box[k] = v;
+  }
+}
+
+// Capillary force (capillary-force eq.): sum over the polar/azimuthal grid of
+// sigma 9/2 k beta max(0, 1 - phi^2) dA sin(theta_p) m^, m^ = normalise(n_s - (n.n_s) n),
+// torque arm R n_s; phi and G trilinear over fluid corners.  One workgroup per
+// particle, FP64 block reduction.
+__global__ __launch_bounds__(256) void k_capillary(SimDev s) {
+  const int p = blockIdx.x;
+  DevParticle& P = s.P[p];
+  const int B = s.cap_B;
+  const float4* box = s.capbox + (long long)p * B * B * B;
+  const int org0 = (int)floor(P.x[0] - P.R), org1 = (int)floor(P.x[1] - P.R),
+            org2 = (int)floor(P.x[2] - P.R);
+  const double R = P.R, da = s.cap_dang;
+  const double pref = s.cap_pref * (double)P.sin_t;
+  const int na = s.cap_na, nph = s.cap_nphi;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int idx = threadIdx.x; idx < na * nph; idx += blockDim.x) {
+    const int j = idx / nph, k = idx % nph;
+    const double al = (j + 0.5) * da, ph = k * da;
+    double sa, ca, sp, cp;
+    sincos(al, &sa, &ca);
+    sincos(ph, &sp, &cp);
+    const double sh[3] = {sa * cp, sa * sp, ca};
+    const double xp[3] = {P.x[0] + R * sh[0], P.x[1] + R * sh[1], P.x[2] + R * sh[2]};
+    const double f0 = floor(xp[0]), f1 = floor(xp[1]), f2 = floor(xp[2]);
+    const float fr0 = (float)(xp[0] - f0), fr1 = (float)(xp[1] - f1), fr2 = (float)(xp[2] - f2);
+    const int i0 = (int)f0 - org0, i1 = (int)f1 - org1, i2 = (int)f2 - org2;
+    float W = 0.f, phi = 0.f, Gx = 0.f, Gy = 0.f, Gz = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+      const float4 v = box[(i0 + ox) + B * ((i1 + oy) + B * (i2 + oz))];
+      if (v.x > 1.5f) continue;
+      const float w = (ox ? fr0 : 1.f - fr0) * (oy ? fr1 : 1.f - fr1) * (oz ? fr2 : 1.f - fr2);
+      W += w;
+      phi += w * v.x;
+      Gx += w * v.y;
+      Gy += w * v.z;
+      Gz += w * v.w;
+    }
+    if (!(W > 0.f)) continue;
+    const float iW = 1.0f / W;
+    phi *= iW;
+    Gx *= iW;
+    Gy *= iW;
+    Gz *= iW;
+    const float wgt = (1.0f - phi) * (1.0f + phi);
+    if (!(wgt > 0.f)) continue;
+    const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
+    if (!(g > EPS_G)) continue;
+    const float ig = 1.0f / g;
+    const float nx_ = Gx * ig, ny_ = Gy * ig, nz_ = Gz * ig;
+    const float s0 = (float)sh[0], s1 = (float)sh[1], s2 = (float)sh[2];
+    const float a = nx_ * s0 + ny_ * s1 + nz_ * s2;
+    const float mx = s0 - a * nx_, my = s1 - a * ny_, mz = s2 - a * nz_;
+    const float mn = sqrtf(mx * mx + my * my + mz * mz);
+    if (!(mn > EPS_T)) continue;
+    const double dA = R * R * sa * da * da;
+    const double coef = pref * (double)wgt * dA / (double)mn;
+    const double dF[3] = {coef * mx, coef * my, coef * mz};
+    const double arm[3] = {R * sh[0], R * sh[1], R * sh[2]};
+    acc[0] += dF[0];
+    acc[1] += dF[1];
+    acc[2] += dF[2];
+    acc[3] += arm[1] * dF[2] - arm[2] * dF[1];
+    acc[4] += arm[2] * dF[0] - arm[0] * dF[2];
+    acc[5] += arm[0] * dF[1] - arm[1] * dF[0];
+  }
+  __shared__ double red[6][256];
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      P.Fcap[k] = red[k][0];
+      P.Tcap[k] = red[3 + k][0];
+    }
+  }
+}
+
+// -------------------------------------------------------------------- DEM
+__device__ inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ Contact* find_slot(Contact* t, int partner, bool create, uint32_t* status) {
+  for (int k = 0; k < MAXC; ++k)
+    if (t[k].partner == partner) return &t[k];
+  if (!create) return nullptr;
+  for (int k = 0; k < MAXC; ++k)
+    if (t[k].partner == -100) {
+      t[k].partner = partner;
+      for (int d = 0; d < 3; ++d) t[k].xt[d] = t[k].xr[d] = 0.0;
+      return &t[k];
+    }
+  atomicOr(status, (uint32_t)ST_CONTACT_FULL);
+  return nullptr;
+}
+
+// spring with a Coulomb cap (sliding friction eqs.; rolling uses the same rule)
+__device__ inline void capped_spring(double k, double gam, double cap, double* xi, const double* v,
+                                     double dt, double* F) {
+  double F0[3];
+  for (int d = 0; d < 3; ++d) F0[d] = -k * xi[d] - gam * v[d];
+  const double f0 = sqrt(dot3(F0, F0));
+  if (f0 <= cap) {
+    for (int d = 0; d < 3; ++d) {
+      F[d] = F0[d];
+      xi[d] += v[d] * dt;
+    }
+  } else {
+    for (int d = 0; d < 3; ++d) F[d] = cap * F0[d] / f0;
+    for (int d = 0; d < 3; ++d) xi[d] = (k > 0.0) ? -(F[d] + gam * v[d]) / k : 0.0;
+  }
+}
+
+// Contact of particle i with one partner (normal spring-dashpot, sliding and
+// rolling friction after Luding's model as the paper describes it).
+__device__ bool contact(const SimDev& s, Contact* tab, int partner, double delta, const double* nh,
+                        const double* vi, const double* wi, const double* vj, const double* wj,
+                        double Rci, double Rcj, const double* armj, double mu, double mur,
+                        double dt, double* Fo, double* To) {
+  if (!(delta > 0.0)) {
+    Contact* sl = find_slot(tab, partner, false, &s.counters[1]);
+    if (sl) sl->partner = -100;
+    return false;
+  }
+  Contact* sl = find_slot(tab, partner, true, &s.counters[1]);
+  if (!sl) return false;
+  double vrel[3];
+  for (int d = 0; d < 3; ++d) vrel[d] = vi[d] - vj[d];
+  const double ddot = -dot3(vrel, nh);
+  const double Fn = s.kn * delta + s.gn * ddot;
+  double ri[3], rj[3], t1[3], t2[3], vc[3];
+  for (int d = 0; d < 3; ++d) ri[d] = -(Rci - 0.5 * delta) * nh[d];
+  for (int d = 0; d < 3; ++d) rj[d] = ri[d] + armj[d];
+  cross3(wi, ri, t1);
+  cross3(wj, rj, t2);
+  for (int d = 0; d < 3; ++d) vc[d] = vrel[d] + t1[d] - t2[d];
+  const double vn = dot3(vc, nh);
+  double vt[3];
+  for (int d = 0; d < 3; ++d) vt[d] = vc[d] - vn * nh[d];
+  double xn = dot3(sl->xt, nh);
+  for (int d = 0; d < 3; ++d) sl->xt[d] -= xn * nh[d];
+  xn = dot3(sl->xr, nh);
+  for (int d = 0; d < 3; ++d) sl->xr[d] -= xn * nh[d];
+  const double Fcap = mu * (Fn > 0.0 ? Fn : 0.0);
+  double Ft[3];
+  capped_spring(s.kt, s.gt, Fcap, sl->xt, vt, dt, Ft);
+  const double ap = (Rcj > 0.0) ? Rci * Rcj / (Rci + Rcj) : Rci;
+  double nwi[3], nwj[3], vr[3], Fr[3];
+  cross3(nh, wi, nwi);
+  cross3(nh, wj, nwj);
+  for (int d = 0; d < 3; ++d) vr[d] = -ap * (nwi[d] - nwj[d]);
+  const double Rcap = mur * (Fn > 0.0 ? Fn : 0.0);
+  capped_spring(s.kr, s.gr, Rcap, sl->xr, vr, dt, Fr);
+  double Tt[3], Tr[3];
+  cross3(ri, Ft, Tt);
+  cross3(nh, Fr, Tr);
+  for (int d = 0; d < 3; ++d) {
+    Fo[d] = Fn * nh[d] + Ft[d];
+    To[d] = Tt[d] + ap * Tr[d];
+  }
+  return true;
+}
+
+__device__ inline void rel_vec(const SimDev& s, const double* a, const double* b, double* d) {
+  d[0] = wrapd(a[0] - b[0], (double)s.nx);
+  d[1] = wrapd(a[1] - b[1], (double)s.ny);
+  d[2] = wrapd(a[2] - b[2], (double)s.nz);
+}
+
+__device__ void quat_rotate(double* q, const double* th) {
+  const double a = sqrt(dot3(th, th));
+  if (!(a > 0.0)) return;
+  const double h = 0.5 * a, sh = sin(h) / a;
+  const double dq[4] = {cos(h), th[0] * sh, th[1] * sh, th[2] * sh};
+  double r[4] = {dq[0] * q[0] - dq[1] * q[1] - dq[2] * q[2] - dq[3] * q[3],
+                 dq[0] * q[1] + dq[1] * q[0] + dq[2] * q[3] - dq[3] * q[2],
+                 dq[0] * q[2] - dq[1] * q[3] + dq[2] * q[0] + dq[3] * q[1],
+                 dq[0] * q[3] + dq[1] * q[2] - dq[2] * q[1] + dq[3] * q[0]};
+  const double nq = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+  for (int k = 0; k < 4; ++k) q[k] = r[k] / nq;
+}
+
+// One workgroup per simulation.  Fluid forces (momentum exchange + capillary)
+// are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
+// new positions with the predicted velocities; gravity is the downward g_p.
+__global__ __launch_bounds__(256) void k_dem(SimDev s) {
+  const int np = s.np;
+  const int nt = blockDim.x;
+  const double dt = 1.0 / s.n_sub;
+  const double skin = 1.5;
+  // per-step set-up
+  for (int i = threadIdx.x; i < np; i += nt) {
+    DevParticle& P = s.P[i];
+    for (int d = 0; d < 3; ++d) {
+      P.Ff[d] = P.Fh[d] + P.Fcap[d];
+      P.Tf[d] = P.Th[d] + P.Tcap[d];
+      P.Fh_last[d] = P.Fh[d];
+      P.Th_last[d] = P.Th[d];
+      P.Fh[d] = 0.0;
+      P.Th[d] = 0.0;
+      P.xo[d] = P.x[d];
+      P.Facc[d] = 0.0;
+      P.Tacc[d] = 0.0;
+    }
+    P.Ff[2] -= P.g_p;
+    P.Ro = P.R;
+  }
+  __syncthreads();
+  // pair candidates within Rc_i + Rc_j + skin (ascending index)
+  for (int i = threadIdx.x; i < np; i += nt) {
+    const DevParticle& P = s.P[i];
+    int* nb = s.nb + (long long)i * MAXNB;
+    int c = 0;
+    for (int j = 0; j < np; ++j) {
+      if (j == i) continue;
+      const DevParticle& Pj = s.P[j];
+      double dx[3];
+      rel_vec(s, P.x, Pj.x, dx);
+      const double lim = P.Rc + Pj.Rc + skin;
+      if (dot3(dx, dx) < lim * lim) {
+        if (c < MAXNB)
+          nb[c++] = j;
+        else
+          atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+      }
+    }
+    if (c < MAXNB) nb[c] = -1;
+    // free pair springs whose partner is out of range
+    Contact* tab = s.ct + (long long)i * MAXC;
+    for (int k = 0; k < MAXC; ++k) {
+      const int pt = tab[k].partner;
+      if (pt < 0) continue;
+      bool found = false;
+      for (int q = 0; q < c && q < MAXNB; ++q) found |= (nb[q] == pt);
+      if (!found) tab[k].partner = -100;
+    }
+  }
+  __syncthreads();
+  for (int sub = 0; sub < s.n_sub; ++sub) {
+    for (int i = threadIdx.x; i < np; i += nt) {
+      DevParticle& P = s.P[i];
+      double th[3];
+      for (int d = 0; d < 3; ++d) {
+        if (P.kin) {
+          P.ao[d] = 0.0;
+          P.bo[d] = 0.0;
+        } else {
+          P.ao[d] = (P.Ff[d] + P.Fcp[d]) / P.mass;
+          P.bo[d] = (P.Tf[d] + P.Tcp[d]) / P.inertia;
+        }
+        P.x[d] += P.v[d] * dt + 0.5 * P.ao[d] * dt * dt;
+        th[d] = P.w[d] * dt + 0.5 * P.bo[d] * dt * dt;
+        P.vp[d] = P.v[d] + P.ao[d] * dt;
+        P.wp[d] = P.w[d] + P.bo[d] * dt;
+      }
+      quat_rotate(P.q, th);
+      const double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
+      for (int d = 0; d < 3; ++d) {
+        if (d == 2 && s.has_wall) continue;
+        if (P.x[d] >= L[d])
+          P.x[d] -= L[d];
+        else if (P.x[d] < 0.0)
+          P.x[d] += L[d];
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += nt) {
+      DevParticle& P = s.P[i];
+      Contact* tab = s.ct + (long long)i * MAXC;
+      const double Rci = P.Rc;
+      const double zero[3] = {0, 0, 0};
+      double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0}, Fo[3], To[3];
+      if (s.has_wall) {
+        const double nb_[3] = {0, 0, 1}, nt_[3] = {0, 0, -1};
+        const double db = Rci - (P.x[2] - 0.5);
+        if (contact(s, tab, -1, db, nb_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r, dt,
+                    Fo, To))
+          for (int d = 0; d < 3; ++d) {
+            Fs[d] += Fo[d];
+            Ts[d] += To[d];
+          }
+        const double dtp = Rci - (((double)s.nz - 0.5) - P.x[2]);
+        if (contact(s, tab, -2, dtp, nt_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r,
+                    dt, Fo, To))
+          for (int d = 0; d < 3; ++d) {
+            Fs[d] += Fo[d];
+            Ts[d] += To[d];
+          }
+      }
+      const int* nb = s.nb + (long long)i * MAXNB;
+      for (int q = 0; q < MAXNB; ++q) {
+        const int j = nb[q];
+        if (j < 0) break;
+        const DevParticle& Pj = s.P[j];
+        const double Rcj = Pj.Rc;
+        double dx[3];
+        rel_vec(s, P.x, Pj.x, dx);
+        const double dist = sqrt(dot3(dx, dx));
+        const double delta = Rci + Rcj - dist;
+        double nh[3] = {0, 0, 0};
+        if (dist > 0.0)
+          for (int d = 0; d < 3; ++d) nh[d] = dx[d] / dist;
+        if (contact(s, tab, j, delta, nh, P.vp, P.wp, Pj.vp, Pj.wp, Rci, Rcj, dx,
+                    0.5 * (P.mu_s + Pj.mu_s), 0.5 * (P.mu_r + Pj.mu_r), dt, Fo, To))
+          for (int d = 0; d < 3; ++d) {
+            Fs[d] += Fo[d];
+            Ts[d] += To[d];
+          }
+      }
+      for (int d = 0; d < 3; ++d) {
+        P.Fcn[d] = Fs[d];
+        P.Tcn[d] = Ts[d];
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += nt) {
+      DevParticle& P = s.P[i];
+      for (int d = 0; d < 3; ++d) {
+        if (!P.kin) {
+          const double an = (P.Ff[d] + P.Fcn[d]) / P.mass;
+          const double bn = (P.Tf[d] + P.Tcn[d]) / P.inertia;
+          P.v[d] += 0.5 * (P.ao[d] + an) * dt;
+          P.w[d] += 0.5 * (P.bo[d] + bn) * dt;
+        }
+        P.Fcp[d] = P.Fcn[d];
+        P.Tcp[d] = P.Tcn[d];
+        P.Facc[d] += P.Fcn[d];
+        P.Tacc[d] += P.Tcn[d];
+      }
+    }
+    __syncthreads();
+  }
+  const unsigned long long step = *s.step_counter;
+  for (int i = threadIdx.x; i < np; i += nt) {
+    DevParticle& P = s.P[i];
+    for (int d = 0; d < 3; ++d) {
+      P.Fcon[d] = P.Facc[d] / s.n_sub;
+      P.Tcon[d] = P.Tacc[d] / s.n_sub;
+    }
+    if (s.hist_cap > 0) {
+      double* h = s.hist + ((long long)(step % (unsigned long long)s.hist_cap) * np + i) *
+                               LBM_HIST_DOUBLES_DEV;
+      for (int d = 0; d < 3; ++d) {
+        h[d] = P.Fh_last[d];
+        h[3 + d] = P.Th_last[d];
+        h[6 + d] = P.Fcap[d];
+        h[9 + d] = P.Tcap[d];
+        h[12 + d] = P.Fcon[d];
+        h[15 + d] = P.Tcon[d];
+        h[18 + d] = P.x[d];
+        h[21 + d] = P.v[d];
+        h[24 + d] = P.w[d];
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *s.step_counter = step + 1;
+}
+
+// ------------------------------------------------------------ host launchers
+static inline unsigned box_blocks(int B) {
+  const int v = B * B * B;
+  return (unsigned)((v + 255) / 256);
+}
+
+hipError_t launch_mask_update(const SimDev& s, int Bmask, bool with_release, hipStream_t st) {
+  if (s.np == 0) return hipSuccess;
+  dim3 grid(box_blocks(Bmask), s.np);
+  hipLaunchKernelGGL(k_claim, grid, dim3(256), 0, st, s);
+  if (with_release) hipLaunchKernelGGL(k_release, grid, dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_cover, grid, dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_refill(const SimDev& s, void* pops, hipStream_t st) {
+  if (s.np == 0) return hipSuccess;
+  unsigned nb = (s.fresh_cap + 255) / 256;
+  if (nb > 256) nb = 256;
+  if (nb == 0) nb = 1;
+  if (s.storage == 0)
+    hipLaunchKernelGGL(k_refill<0>, dim3(nb), dim3(256), 0, st, s, pops);
+  else
+    hipLaunchKernelGGL(k_refill<1>, dim3(nb), dim3(256), 0, st, s, pops);
+  return hipGetLastError();
+}
+
+hipError_t launch_capillary(const SimDev& s, hipStream_t st) {
+  if (s.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_capbox, dim3(box_blocks(s.cap_B), s.np), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_capillary, dim3(s.np), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_dem(const SimDev& s, hipStream_t st) {
+  if (s.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

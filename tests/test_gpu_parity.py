@@ -1,0 +1,206 @@
+"""GPU (HIP library through the C ABI) against the FP64 CPU oracle.
+
+Bars: masks and link lists bit-exact; FP32-storage fields rho, u, phi within
+1e-5 relative L2 over the fluid nodes; FP64 particle force/torque histories
+within 1e-5 of their maximum magnitude.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSim
+from paper_2505_10171_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(cfg, phi0, parts, hist=0):
+    from paper_2505_10171_amd.lbm import Simulation
+    return Simulation(cfg, phi0, parts, history_steps=hist)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _compare_fields(g, o, tol=1e-5, label=""):
+    rg, ug, pg, mg = g.fields()
+    ro, uo, po, mo = o.fields()
+    assert np.array_equal(mg, mo), f"{label}: masks differ at {np.argwhere(mg != mo)[:5]}"
+    fl = mo == 0
+    e = dict(rho=rel_l2(rg[fl], ro[fl]), u=rel_l2(ug[:, fl], uo[:, fl]), phi=rel_l2(pg[fl], po[fl]))
+    print(label, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k, v in e.items():
+        assert v <= tol, (label, k, v)
+    return e
+
+
+def test_c1_sessile_drop_with_sphere():
+    w = W.sessile_drop_c1()
+    steps = w["steps"]
+    g = _gpu(w["cfg"], w["phi0"], w["particles"], hist=steps)
+    o = OracleSim(w["cfg"], w["phi0"], w["particles"])
+    assert g.dem_substeps() == o.n_sub
+    hist_o = []
+    for t in range(steps):
+        o.step(1)
+        p = o.particles()[0]
+        hist_o.append(np.concatenate([p[k] for k in ("F_hyd", "T_hyd", "F_cap", "T_cap", "F_con",
+                                                      "T_con", "x", "v", "w")]))
+    g.step(steps)
+    _compare_fields(g, o, label="C1 200 steps")
+    parts, hist_g = g.particles(history=True)
+    hist_o = np.array(hist_o)
+    assert hist_g.shape == (steps, 1, 27)
+    hg = hist_g[:, 0, :]
+    for k, name in enumerate(("F_hyd", "T_hyd", "F_cap", "T_cap", "F_con", "T_con", "x", "v", "w")):
+        a, b = hg[:, 3 * k:3 * k + 3], hist_o[:, 3 * k:3 * k + 3]
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max() / scale if scale > 0 else np.abs(a).max()
+        print(name, f"{err:.2e}")
+        assert err <= 1e-5, (name, err)
+    lg, pg = g.links()
+    lo, po = o.links()
+    assert np.array_equal(lg, lo) and np.array_equal(pg, po)
+
+
+def test_drop_ragged_lattice_no_particles():
+    cfg = W.config(37, 29, 23, theta_wall_deg=70.0, sigma=0.02, body_force=(4e-6, -1e-6, 0.0))
+    phi0 = W.drop_phi0(37, 29, 23, (15.3, 14.1, 0.5), 9.0)
+    g = _gpu(cfg, phi0, [])
+    o = OracleSim(cfg, phi0, [])
+    g.step(80)
+    o.step(80)
+    _compare_fields(g, o, label="ragged 37x29x23")
+
+
+def test_drop_free_periodic():
+    cfg = W.config(24, 20, 28, has_wall=0, sigma=0.01, tau_a=0.8, tau_b=1.4)
+    phi0 = W.drop_phi0(24, 20, 28, (11.5, 9.5, 13.5), 7.0)
+    g = _gpu(cfg, phi0, [])
+    o = OracleSim(cfg, phi0, [])
+    g.step(100)
+    o.step(100)
+    _compare_fields(g, o, label="free drop, viscosity ratio")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_mask_and_links_bitexact(seed):
+    g_ = np.random.default_rng(500 + seed)
+    L = (26, 22, 24)
+    cfg = W.config(*L, has_wall=seed % 2)
+    parts = []
+    for k in range(5):
+        R = float(g_.choice([1.5, 2.0, 2.5, 3.0, 4.0]))
+        if k % 3 == 0:
+            x = (L[0] - 0.5, 0.5, float(g_.integers(6, L[2] - 6)) + 0.5)
+        elif k % 3 == 1:
+            x = (float(g_.integers(0, L[0])), float(g_.integers(0, L[1])), 10.0)
+            R = 3.0
+        else:
+            x = (g_.uniform(0, L[0]), g_.uniform(0, L[1]), g_.uniform(6, L[2] - 6))
+        parts.append(W.particle(x, R, kinematic=1))
+    g = _gpu(cfg, None, parts)
+    o = OracleSim(cfg, None, parts)
+    _, _, _, mg = g.fields()
+    _, _, _, mo = o.fields()
+    assert np.array_equal(mg, mo)
+    lg, pg = g.links()
+    lo, po = o.links()
+    assert np.array_equal(lg, lo) and np.array_equal(pg, po)
+    # moved state pushed to both sides: still bit-exact, fresh nodes refilled
+    moved = [dict(p, x=tuple(np.array(p["x"]) + g_.uniform(-1.5, 1.5, 3))) for p in parts]
+    for p in moved:
+        p["x"] = (p["x"][0] % L[0], p["x"][1] % L[1], p["x"][2])
+    g.push_particles(moved)
+    o.set_particles(moved)
+    _, _, _, mg = g.fields()
+    _, _, _, mo = o.fields()
+    assert np.array_equal(mg, mo)
+
+
+def test_moving_particle_refill_and_bounce():
+    """A particle with prescribed velocity and spin through a two-fluid box:
+    moving bounce-back, momentum exchange and refilling against the oracle."""
+    L = 24
+    cfg = W.config(L, L, L, has_wall=0, sigma=0.01)
+    phi0 = W.slab_phi0(L, L, L, 12.3)
+    parts = [W.particle((6.2, 11.7, 12.1), 3.5, theta_deg=70.0, v=(0.03, 0.01, -0.005),
+                        w=(0.0, 0.002, 0.001), kinematic=1)]
+    g = _gpu(cfg, phi0, parts, hist=60)
+    o = OracleSim(cfg, phi0, parts)
+    Fo = []
+    for _ in range(60):
+        o.step(1)
+        Fo.append(o.particles()[0]["F_hyd"])
+    g.step(60)
+    _compare_fields(g, o, label="moving particle")
+    _, h = g.particles(history=True)
+    Fo = np.array(Fo)
+    err = np.abs(h[:, 0, 0:3] - Fo).max() / np.abs(Fo).max()
+    assert err <= 1e-5, err
+
+
+def test_mass_conservation_static_solids_gpu():
+    cfg = W.config(32, 32, 24, sigma=0.01, theta_wall_deg=75.0)
+    phi0 = W.drop_phi0(32, 32, 24, (16.0, 16.0, 0.5), 9.0)
+    g = _gpu(cfg, phi0, [W.particle((24.0, 16.0, 5.5), 3.0, kinematic=1)])
+    m0 = g.mass()
+    g.step(500)
+    m1 = g.mass()
+    assert np.all(np.abs(m1 - m0) <= 2e-6 * m0.sum()), (m0, m1)
+
+
+def test_poiseuille_gpu():
+    nz, f, tau = 17, 1e-6, 0.8
+    cfg = W.config(4, 4, nz, tau_a=tau, tau_b=tau, sigma=0.0, body_force=(f, 0, 0))
+    g = _gpu(cfg, np.ones((nz, 4, 4), np.float32), [])
+    g.step(6000)
+    rho, u, phi, mask = g.fields()
+    z = np.arange(1, nz, dtype=float)
+    nu = (tau - 0.5) / 3.0
+    exact = f / (2 * cfg["rho0"] * nu) * (z - 0.5) * (nz - 0.5 - z)
+    assert np.abs(u[0, 1:, 0, 0] - exact).max() <= 1e-4 * exact.max()
+
+
+def test_unstable_flow_is_reported():
+    from paper_2505_10171_amd.lbm import LbmError, LBM_EUNSTABLE
+    cfg = W.config(8, 8, 8, has_wall=0, body_force=(2e-2, 0, 0), sigma=0.0)
+    g = _gpu(cfg, None, [])
+    g.step(50)
+    with pytest.raises(LbmError) as e:
+        g.sync()
+    assert e.value.code == LBM_EUNSTABLE
+    with pytest.raises(LbmError):
+        g.step(1)  # sticky error state
+
+
+def test_full_size_drop_sweep_c2_parity():
+    """The 256x128x96 drop-sweeping workload with its 20 spheres, in the launch
+    configuration the benchmark times, for a few steps against the oracle."""
+    w = W.drop_sweep_c2()
+    g = _gpu(w["cfg"], w["phi0"], w["particles"])
+    o = OracleSim(w["cfg"], w["phi0"], w["particles"])
+    g.step(3)
+    o.step(3)
+    _compare_fields(g, o, label="C2 full size, 3 steps")
+    pg, po = g.particles(), o.particles()
+    # per quantity, errors relative to the largest magnitude over all particles
+    for k in ("F_hyd", "T_hyd", "F_cap", "T_cap", "F_con", "x", "v"):
+        a = np.array([p[k] for p in pg])
+        b = np.array([p[k] for p in po])
+        scale = np.abs(b).max()
+        assert np.abs(a - b).max() <= 1e-5 * scale, (k, np.abs(a - b).max(), scale)
+
+
+def test_device_fields_match_host_fields():
+    w = W.sessile_drop_c1()
+    g = _gpu(w["cfg"], w["phi0"], w["particles"])
+    g.step(10)
+    rho, u, phi, mask = g.fields()
+    rd, ud, pd = g.fields_device()
+    assert np.array_equal(rd.cpu().numpy().reshape(rho.shape), rho)
+    assert np.array_equal(pd.cpu().numpy().reshape(phi.shape), phi)
+    assert np.array_equal(ud.cpu().numpy().reshape(u.shape), u)
