@@ -327,12 +327,19 @@ static void moments_node(const orc_sim *s, int64_t n) {
   s->phi[n] = (ra - rb) / (ra + rb);
 }
 
-#define EPS_G 1e-8
-#define EPS_T 1e-6
+/* reading: the interface normal is n = G / max(|G|, EPS_G).  Inside the
+ * diffuse interface (|G| > EPS_G, within about five nodes of its centre) this
+ * is the unit normal; outside it fades continuously to zero with G, so that
+ * rounding noise in a nearly uniform phi cannot turn into an O(1) normal. */
+#define EPS_G 1e-4
+/* reading: the wetting rotation needs the tangential part t of n*; where n*
+ * is within 1e-3 of the wall normal (about 0.06 degrees) the rotation axis is
+ * not defined to single precision, and G is left unrotated */
+#define EPS_T 1e-3
 
 /* S3, geometric wetting (wetting-condition eq. for n_pm).
  * reading: it is applied at every fluid node that has at least one solid
- * D3Q19 neighbour and |G| > EPS_G.  The solid is the lowest-index particle
+ * D3Q19 neighbour and lies in the diffuse interface, |G| > EPS_G.  The solid is the lowest-index particle
  * among the neighbours, else the wall.  theta is measured through fluid a
  * (phi = +1), so with n_s the outward solid normal the target is
  * n.n_s = -cos(theta): the paper's n_+ with theta -> pi - theta.  Writing
@@ -406,8 +413,8 @@ static void prepare(orc_sim *s) {
     }
     wetting_node(s, n, x, y, z, G);
     double g = norm3(G);
-    if (g > EPS_G)
-      for (int k = 0; k < 3; ++k) nr[k] = G[k] / g;
+    double den = g > EPS_G ? g : EPS_G;
+    for (int k = 0; k < 3; ++k) nr[k] = G[k] / den;
   }
   /* S5 - S7
    * reading: kappa = div n with the same stencil and closure, so that the CSF

@@ -33,8 +33,10 @@ __host__ __device__ constexpr double wqd(int i) {
   return i == 0 ? (1.0 / 3.0) : (i <= 6 ? (1.0 / 18.0) : (1.0 / 36.0));
 }
 
-constexpr float EPS_G = 1e-8f;  // |grad phi| below which the normal is undefined
-constexpr float EPS_T = 1e-6f;  // tangential part below which wetting leaves G alone
+// interface normal n = G / max(|G|, EPS_G): the unit normal inside the diffuse
+// interface, fading continuously to zero where phi is nearly uniform
+constexpr float EPS_G = 1e-4f;
+constexpr float EPS_T = 1e-3f;  // tangential part below which wetting leaves G alone
 constexpr int MAXC = 16;        // contact slots per particle
 constexpr int MAXNB = 24;       // DEM pair candidates per particle
 constexpr uint16_t FRESH_BIT = 0x8000;

@@ -53,7 +53,8 @@ __device__ __forceinline__ long long node_index(const SimDev& s, int x, int y, i
 // colour gradient is rotated to make the angle theta (through fluid a) with the
 // solid's outward normal n_s, keeping |G|: G <- |G| (-cos(theta) n_s + sin(theta) t^),
 // t = n* - (n*.n_s) n_s.  The solid is the lowest-index neighbouring particle,
-// else the wall.  Left unchanged if |G| <= EPS_G or |t| <= EPS_T.
+// else the wall.  Applied inside the diffuse interface (|G| > EPS_G); left
+// unchanged if |t| <= EPS_T (rotation axis undefined).
 __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, int gz, int minp,
                                                bool wall_nb, float& Gx, float& Gy, float& Gz) {
   float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
@@ -304,10 +305,8 @@ __global__ __launch_bounds__(TX* TY) void k_fused(SimDev s, const void* __restri
           wetting_rotate(s, hgx, hgy, gz, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
         }
         const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
-        if (g > EPS_G) {
-          const float ig = 1.0f / g;
-          out = make_float4(Gx * ig, Gy * ig, Gz * ig, g);
-        }
+        const float ig = 1.0f / fmaxf(g, EPS_G);
+        out = make_float4(Gx * ig, Gy * ig, Gz * ig, g);
       }
       s_n[so][hy][hx] = out;
     }
@@ -398,8 +397,9 @@ __global__ __launch_bounds__(TX* TY) void k_fused(SimDev s, const void* __restri
                  ((float)cx(i) * (np_.x - nm_.x) + (float)cy(i) * (np_.y - nm_.y) +
                   (float)cz(i) * (np_.z - nm_.z));
       }
-      // force: CSF surface tension + body force on fluid a (weight (1+phi)/2)
-      const float cst = -0.5f * s.sigma * kappa * nc.w;
+      // force: CSF surface tension -sigma kappa G / 2 + body force on fluid a
+      // (weight (1+phi)/2); G = n max(|G|, EPS_G)
+      const float cst = -0.5f * s.sigma * kappa * fmaxf(nc.w, EPS_G);
       const float fa = 0.5f * (1.0f + phi);
       const float Fx = cst * nc.x + s.body[0] * fa;
       const float Fy = cst * nc.y + s.body[1] * fa;
