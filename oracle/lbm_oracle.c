@@ -332,9 +332,12 @@ static void moments_node(const orc_sim *s, int64_t n) {
  * is the unit normal; outside it fades continuously to zero with G, so that
  * rounding noise in a nearly uniform phi cannot turn into an O(1) normal. */
 #define EPS_G 1e-4
-/* reading: the wetting rotation needs the tangential part t of n*; where n*
- * is within 1e-3 of the wall normal (about 0.06 degrees) the rotation axis is
- * not defined to single precision, and G is left unrotated */
+/* reading: the wetting rotation turns G about the direction of its tangential
+ * part G_t = G - (G.n_s) n_s; where |G_t| <= EPS_GT (the interface parallel to
+ * the solid, or G_t below what single precision resolves) the axis is not
+ * defined and G is left unrotated */
+#define EPS_GT 1e-4
+/* capillary direction m = n_s - (n.n_s) n is skipped below this length */
 #define EPS_T 1e-3
 
 /* S3, geometric wetting (wetting-condition eq. for n_pm).
@@ -344,7 +347,7 @@ static void moments_node(const orc_sim *s, int64_t n) {
  * (phi = +1), so with n_s the outward solid normal the target is
  * n.n_s = -cos(theta): the paper's n_+ with theta -> pi - theta.  Writing
  * n* = cos(a*) n_s + sin(a*) t^, n_+ = cos(theta) n_s + sin(theta) t^ is always
- * at least as close to n* as n_-, so n_+ is taken; if |t| < EPS_T the
+ * at least as close to n* as n_-, so n_+ is taken; if |G_t| <= EPS_GT the
  * direction is left unchanged.  |G| is kept. */
 static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, double G[3]) {
   int solid_p = -1, has_wall = 0;
@@ -374,11 +377,10 @@ static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, doubl
     ns[2] = (z == 1) ? 1.0 : -1.0;
     theta = s->c.theta_wall_deg * M_PI / 180.0;
   }
-  double nstar[3] = {G[0] / g, G[1] / g, G[2] / g};
-  double a = dot3(nstar, ns);
-  double t[3] = {nstar[0] - a * ns[0], nstar[1] - a * ns[1], nstar[2] - a * ns[2]};
+  double a = dot3(G, ns);
+  double t[3] = {G[0] - a * ns[0], G[1] - a * ns[1], G[2] - a * ns[2]};
   double tn = norm3(t);
-  if (!(tn > EPS_T)) return;
+  if (!(tn > EPS_GT)) return;
   double ct = -cos(theta), st = sin(theta);
   for (int k = 0; k < 3; ++k) G[k] = g * (ct * ns[k] + st * t[k] / tn);
 }

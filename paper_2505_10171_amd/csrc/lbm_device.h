@@ -36,7 +36,8 @@ __host__ __device__ constexpr double wqd(int i) {
 // interface normal n = G / max(|G|, EPS_G): the unit normal inside the diffuse
 // interface, fading continuously to zero where phi is nearly uniform
 constexpr float EPS_G = 1e-4f;
-constexpr float EPS_T = 1e-3f;  // tangential part below which wetting leaves G alone
+constexpr float EPS_GT = 1e-4f;  // tangential |G| below which wetting leaves G alone
+constexpr float EPS_T = 1e-3f;   // capillary direction length below which a point is skipped
 constexpr int MAXC = 16;        // contact slots per particle
 constexpr int MAXNB = 24;       // DEM pair candidates per particle
 constexpr uint16_t FRESH_BIT = 0x8000;

@@ -54,7 +54,7 @@ __device__ __forceinline__ long long node_index(const SimDev& s, int x, int y, i
 // solid's outward normal n_s, keeping |G|: G <- |G| (-cos(theta) n_s + sin(theta) t^),
 // t = n* - (n*.n_s) n_s.  The solid is the lowest-index neighbouring particle,
 // else the wall.  Applied inside the diffuse interface (|G| > EPS_G); left
-// unchanged if |t| <= EPS_T (rotation axis undefined).
+// unchanged if the tangential part |G - (G.n_s) n_s| <= EPS_GT (axis undefined).
 __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, int gz, int minp,
                                                bool wall_nb, float& Gx, float& Gy, float& Gz) {
   float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
@@ -80,12 +80,10 @@ __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, 
   } else {
     return;
   }
-  float inv = 1.0f / g;
-  float ax = Gx * inv, ay = Gy * inv, az = Gz * inv;
-  float a = ax * nsx + ay * nsy + az * nsz;
-  float tx = ax - a * nsx, ty = ay - a * nsy, tz = az - a * nsz;
+  float a = Gx * nsx + Gy * nsy + Gz * nsz;
+  float tx = Gx - a * nsx, ty = Gy - a * nsy, tz = Gz - a * nsz;
   float tn = sqrtf(tx * tx + ty * ty + tz * tz);
-  if (!(tn > EPS_T)) return;
+  if (!(tn > EPS_GT)) return;
   float it = 1.0f / tn;
   Gx = g * (nc * nsx + ns * tx * it);
   Gy = g * (nc * nsy + ns * ty * it);

@@ -237,12 +237,10 @@ __device__ void node_gradient(const SimDev& s, int x, int y, int z, float& Gx, f
     nc = s.wall_neg_cos;
     ns = s.wall_sin;
   }
-  float inv = 1.0f / g;
-  float ax = Gx * inv, ay = Gy * inv, az = Gz * inv;
-  float a = ax * nsx + ay * nsy + az * nsz;
-  float tx = ax - a * nsx, ty = ay - a * nsy, tz = az - a * nsz;
+  float a = Gx * nsx + Gy * nsy + Gz * nsz;
+  float tx = Gx - a * nsx, ty = Gy - a * nsy, tz = Gz - a * nsz;
   float tn = sqrtf(tx * tx + ty * ty + tz * tz);
-  if (!(tn > EPS_T)) return;
+  if (!(tn > EPS_GT)) return;
   float it = 1.0f / tn;
   Gx = g * (nc * nsx + ns * tx * it);
   Gy = g * (nc * nsy + ns * ty * it);
@@ -297,40 +295,39 @@ __global__ __launch_bounds__(256) void k_capillary(SimDev s) {
     const double sh[3] = {sa * cp, sa * sp, ca};
     const double xp[3] = {P.x[0] + R * sh[0], P.x[1] + R * sh[1], P.x[2] + R * sh[2]};
     const double f0 = floor(xp[0]), f1 = floor(xp[1]), f2 = floor(xp[2]);
-    const float fr0 = (float)(xp[0] - f0), fr1 = (float)(xp[1] - f1), fr2 = (float)(xp[2] - f2);
+    const double fr0 = xp[0] - f0, fr1 = xp[1] - f1, fr2 = xp[2] - f2;
     const int i0 = (int)f0 - org0, i1 = (int)f1 - org1, i2 = (int)f2 - org2;
-    float W = 0.f, phi = 0.f, Gx = 0.f, Gy = 0.f, Gz = 0.f;
+    // per-point arithmetic in FP64: the torque is a small residual of large,
+    // cancelling per-point moments
+    double W = 0.0, phi = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
       const float4 v = box[(i0 + ox) + B * ((i1 + oy) + B * (i2 + oz))];
       if (v.x > 1.5f) continue;
-      const float w = (ox ? fr0 : 1.f - fr0) * (oy ? fr1 : 1.f - fr1) * (oz ? fr2 : 1.f - fr2);
+      const double w = (ox ? fr0 : 1.0 - fr0) * (oy ? fr1 : 1.0 - fr1) * (oz ? fr2 : 1.0 - fr2);
       W += w;
-      phi += w * v.x;
-      Gx += w * v.y;
-      Gy += w * v.z;
-      Gz += w * v.w;
+      phi += w * (double)v.x;
+      Gx += w * (double)v.y;
+      Gy += w * (double)v.z;
+      Gz += w * (double)v.w;
     }
-    if (!(W > 0.f)) continue;
-    const float iW = 1.0f / W;
-    phi *= iW;
-    Gx *= iW;
-    Gy *= iW;
-    Gz *= iW;
-    const float wgt = (1.0f - phi) * (1.0f + phi);
-    if (!(wgt > 0.f)) continue;
-    const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
-    if (!(g > EPS_G)) continue;
-    const float ig = 1.0f / g;
-    const float nx_ = Gx * ig, ny_ = Gy * ig, nz_ = Gz * ig;
-    const float s0 = (float)sh[0], s1 = (float)sh[1], s2 = (float)sh[2];
-    const float a = nx_ * s0 + ny_ * s1 + nz_ * s2;
-    const float mx = s0 - a * nx_, my = s1 - a * ny_, mz = s2 - a * nz_;
-    const float mn = sqrtf(mx * mx + my * my + mz * mz);
-    if (!(mn > EPS_T)) continue;
+    if (!(W > 0.0)) continue;
+    phi /= W;
+    Gx /= W;
+    Gy /= W;
+    Gz /= W;
+    const double wgt = 1.0 - phi * phi;
+    if (!(wgt > 0.0)) continue;
+    const double g = sqrt(Gx * Gx + Gy * Gy + Gz * Gz);
+    if (!(g > (double)EPS_G)) continue;
+    const double nx_ = Gx / g, ny_ = Gy / g, nz_ = Gz / g;
+    const double a = nx_ * sh[0] + ny_ * sh[1] + nz_ * sh[2];
+    const double mx = sh[0] - a * nx_, my = sh[1] - a * ny_, mz = sh[2] - a * nz_;
+    const double mn = sqrt(mx * mx + my * my + mz * mz);
+    if (!(mn > (double)EPS_T)) continue;
     const double dA = R * R * sa * da * da;
-    const double coef = pref * (double)wgt * dA / (double)mn;
+    const double coef = pref * wgt * dA / mn;
     const double dF[3] = {coef * mx, coef * my, coef * mz};
     const double arm[3] = {R * sh[0], R * sh[1], R * sh[2]};
     acc[0] += dF[0];
