@@ -173,6 +173,16 @@ int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]);
  * collision-duration rule dt_DEM ~ t_c / 45). */
 int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out);
 
+/* Per-phase timing for benchmarks.  lbm_profile(ctx, 1) starts (or restarts)
+ * recording HIP events on the context's stream around each step's phases:
+ * kind 0 the fused collide-stream kernel, kind 1 the particle kernels
+ * (capillary, DEM, mask update, refill), kind 2 the order-parameter kernel;
+ * lbm_profile(ctx, 0) stops.  lbm_profile_read waits for the recorded steps and
+ * writes, for the first n_kinds kinds, the summed GPU time in milliseconds and
+ * the number of timed launches (per simulation and step). */
+int lbm_profile(lbm_ctx* ctx, int32_t enable);
+int lbm_profile_read(lbm_ctx* ctx, double* total_ms, int64_t* launches, int32_t n_kinds);
+
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Sticky error message of the context, or NULL if there is none. */

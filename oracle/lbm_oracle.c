@@ -98,6 +98,8 @@ typedef struct {
   orc_particle *P;
   orc_contact *ct;             /* n_particles * MAXC */
   double *Fc_prev, *Tc_prev;   /* contact force/torque of the last DEM sub-step */
+  double *Ff_prev, *Tf_prev;   /* fluid force/torque of the previous lattice step */
+  int have_prev;
   int n_sub;
   int64_t n_fresh;
   int status;
@@ -823,14 +825,24 @@ static void dem(orc_sim *s, const double *Fext) {
   double *Ff = malloc(sizeof(double) * 3 * np), *Tf = malloc(sizeof(double) * 3 * np);
   double *ao = malloc(sizeof(double) * 3 * np), *bo = malloc(sizeof(double) * 3 * np);
   double *Facc = calloc(3 * np, sizeof(double)), *Tacc = calloc(3 * np, sizeof(double));
+  /* reading of the Verlet passage ("an average of the forces/torques in the
+   * previous and current time step"): the fluid force and torque (momentum
+   * exchange + capillary) applied over this lattice step are the means of the
+   * values computed at this and at the previous lattice step. */
   for (int i = 0; i < np; ++i) {
     orc_particle *P = &s->P[i];
     for (int d = 0; d < 3; ++d) {
-      Ff[3 * i + d] = P->F_hyd[d] + P->F_cap[d] + (Fext ? Fext[3 * i + d] : 0.0);
-      Tf[3 * i + d] = P->T_hyd[d] + P->T_cap[d];
+      double fc = P->F_hyd[d] + P->F_cap[d], tc = P->T_hyd[d] + P->T_cap[d];
+      double fp = s->have_prev ? s->Ff_prev[3 * i + d] : fc;
+      double tp = s->have_prev ? s->Tf_prev[3 * i + d] : tc;
+      Ff[3 * i + d] = 0.5 * (fc + fp) + (Fext ? Fext[3 * i + d] : 0.0);
+      Tf[3 * i + d] = 0.5 * (tc + tp);
+      s->Ff_prev[3 * i + d] = fc;
+      s->Tf_prev[3 * i + d] = tc;
     }
     Ff[3 * i + 2] -= P->g_p;
   }
+  s->have_prev = 1;
   for (int sub = 0; sub < s->n_sub; ++sub) {
     for (int i = 0; i < np; ++i) {
       orc_particle *P = &s->P[i];
@@ -979,6 +991,8 @@ orc_sim *orc_create(const orc_config *cfg, const float *phi0, const orc_particle
   s->ct = calloc((np ? np : 1) * MAXC, sizeof(orc_contact));
   s->Fc_prev = calloc(3 * (np ? np : 1), sizeof(double));
   s->Tc_prev = calloc(3 * (np ? np : 1), sizeof(double));
+  s->Ff_prev = calloc(3 * (np ? np : 1), sizeof(double));
+  s->Tf_prev = calloc(3 * (np ? np : 1), sizeof(double));
   if (!s->fa || !s->fb || !s->fa_new || !s->fb_new || !s->G || !s->u) {
     orc_destroy(s);
     return NULL;
@@ -1011,7 +1025,7 @@ void orc_destroy(orc_sim *s) {
   free(s->mask); free(s->mask_new);
   free(s->rho_a); free(s->rho_b); free(s->phi);
   free(s->G); free(s->nrm); free(s->F); free(s->u);
-  free(s->P); free(s->ct); free(s->Fc_prev); free(s->Tc_prev);
+  free(s->P); free(s->ct); free(s->Fc_prev); free(s->Tc_prev); free(s->Ff_prev); free(s->Tf_prev);
   free(s);
 }
 

@@ -200,6 +200,21 @@ struct SimHost {
   double Rmax;
 };
 
+// Per-phase timing with HIP events on the context's stream: per step four
+// events bracket k_fused, the particle kernels and k_moments.  A small ring of
+// event sets is reused; a set is harvested (its elapsed times accumulated)
+// before it is recorded again.
+constexpr int PROF_RING = 32;
+constexpr int PROF_KINDS = 3;  // 0 k_fused, 1 particle kernels, 2 k_moments
+struct Profiler {
+  bool on = false;
+  hipEvent_t ev[PROF_RING][4];
+  bool pending[PROF_RING];
+  int next = 0;
+  double total_ms[PROF_KINDS];
+  long long count[PROF_KINDS];
+};
+
 struct lbm_ctx {
   std::vector<SimHost> sims;
   hipStream_t stream;
@@ -207,6 +222,7 @@ struct lbm_ctx {
   size_t ws_bytes;
   int err;
   char msg[512];
+  Profiler prof;
 };
 
 static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
@@ -414,25 +430,98 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
   return LBM_OK;
 }
 
+static int prof_harvest(lbm_ctx* ctx, int slot) {
+  Profiler& P = ctx->prof;
+  if (!P.pending[slot]) return LBM_OK;
+  HIPCHK(ctx, hipEventSynchronize(P.ev[slot][3]));
+  for (int k = 0; k < PROF_KINDS; ++k) {
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, P.ev[slot][k], P.ev[slot][k + 1]));
+    P.total_ms[k] += ms;
+    P.count[k] += 1;
+  }
+  P.pending[slot] = false;
+  return LBM_OK;
+}
+
 int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
   if (!ctx) return LBM_EINVAL;
   if (ctx->err) return LBM_ESTATE;
   if (n_steps < 0) return set_err(ctx, LBM_EINVAL, "negative step count");
+  Profiler& P = ctx->prof;
   for (int t = 0; t < n_steps; ++t) {
     for (auto& sh : ctx->sims) {
       SimDev& s = sh.d;
       void* src = s.pops[sh.cur];
       void* dst = s.pops[sh.cur ^ 1];
+      int slot = -1;
+      if (P.on) {
+        slot = P.next;
+        P.next = (P.next + 1) % PROF_RING;
+        int rc = prof_harvest(ctx, slot);
+        if (rc) return rc;
+        HIPCHK(ctx, hipEventRecord(P.ev[slot][0], ctx->stream));
+      }
       HIPCHK(ctx, launch_fused(s, src, dst, 0, sh.LZ, nullptr, nullptr, nullptr, nullptr,
                                ctx->stream));
+      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][1], ctx->stream));
+      sh.cur ^= 1;
+      void* cur = s.pops[sh.cur];
       if (s.np > 0) {
         HIPCHK(ctx, launch_capillary(s, ctx->stream));
         HIPCHK(ctx, launch_dem(s, ctx->stream));
+        HIPCHK(ctx, launch_mask_update(s, sh.L.Bmask, true, ctx->stream));
+        HIPCHK(ctx, launch_refill(s, cur, ctx->stream));
       }
-      sh.cur ^= 1;
-      int rc = post_dem_pipeline(ctx, sh, true);
-      if (rc) return rc;
+      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], ctx->stream));
+      HIPCHK(ctx, launch_moments(s, cur, ctx->stream));
+      if (slot >= 0) {
+        HIPCHK(ctx, hipEventRecord(P.ev[slot][3], ctx->stream));
+        P.pending[slot] = true;
+      }
     }
+  }
+  return LBM_OK;
+}
+
+int lbm_profile(lbm_ctx* ctx, int32_t enable) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  Profiler& P = ctx->prof;
+  if (enable && !P.on) {
+    for (int r = 0; r < PROF_RING; ++r) {
+      for (int k = 0; k < 4; ++k) HIPCHK(ctx, hipEventCreate(&P.ev[r][k]));
+      P.pending[r] = false;
+    }
+    P.next = 0;
+    P.on = true;
+  }
+  if (P.on)
+    for (int k = 0; k < PROF_KINDS; ++k) {
+      P.total_ms[k] = 0.0;
+      P.count[k] = 0;
+    }
+  if (!enable && P.on) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int r = 0; r < PROF_RING; ++r)
+      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(P.ev[r][k]);
+    P.on = false;
+  }
+  return LBM_OK;
+}
+
+int lbm_profile_read(lbm_ctx* ctx, double* total_ms, int64_t* launches, int32_t n_kinds) {
+  if (!ctx || !total_ms || !launches || n_kinds < 1) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  Profiler& P = ctx->prof;
+  if (!P.on) return set_err(ctx, LBM_EINVAL, "profiling is not enabled");
+  for (int r = 0; r < PROF_RING; ++r) {
+    int rc = prof_harvest(ctx, r);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < n_kinds && k < PROF_KINDS; ++k) {
+    total_ms[k] = P.total_ms[k];
+    launches[k] = P.count[k];
   }
   return LBM_OK;
 }
@@ -639,6 +728,9 @@ int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out) {
 void lbm_destroy(lbm_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->prof.on)
+    for (int r = 0; r < PROF_RING; ++r)
+      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ctx->prof.ev[r][k]);
   delete ctx;
 }
 

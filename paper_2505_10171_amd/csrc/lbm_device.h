@@ -61,6 +61,8 @@ struct alignas(16) DevParticle {
   double ao[3], bo[3];      // accelerations at the start of the sub-step
   double vp[3], wp[3];      // predicted velocities
   double Fcn[3], Tcn[3];    // contact force/torque of the current sub-step
+  double Ffp[3], Tfp[3];    // fluid force/torque of the previous lattice step
+  int havep, pad2;          // 1 once Ffp/Tfp hold a previous step
 };
 
 constexpr int LBM_HIST_DOUBLES_DEV = 27;

@@ -472,11 +472,17 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
   const double dt = 1.0 / s.n_sub;
   const double skin = 1.5;
   // per-step set-up
+  // fluid force and torque: mean of this and the previous lattice step (the
+  // averaging of the Verlet update over the previous and current step)
   for (int i = threadIdx.x; i < np; i += nt) {
     DevParticle& P = s.P[i];
     for (int d = 0; d < 3; ++d) {
-      P.Ff[d] = P.Fh[d] + P.Fcap[d];
-      P.Tf[d] = P.Th[d] + P.Tcap[d];
+      const double fc = P.Fh[d] + P.Fcap[d], tc = P.Th[d] + P.Tcap[d];
+      const double fp = P.havep ? P.Ffp[d] : fc, tp = P.havep ? P.Tfp[d] : tc;
+      P.Ff[d] = 0.5 * (fc + fp);
+      P.Tf[d] = 0.5 * (tc + tp);
+      P.Ffp[d] = fc;
+      P.Tfp[d] = tc;
       P.Fh_last[d] = P.Fh[d];
       P.Th_last[d] = P.Th[d];
       P.Fh[d] = 0.0;
@@ -487,6 +493,7 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
     }
     P.Ff[2] -= P.g_p;
     P.Ro = P.R;
+    P.havep = 1;
   }
   __syncthreads();
   // pair candidates within Rc_i + Rc_j + skin (ascending index)

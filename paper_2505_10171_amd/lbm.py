@@ -22,7 +22,8 @@ HIST_DOUBLES = 27
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_sync", "lbm_particles_sync",
            "lbm_fields", "lbm_fields2", "lbm_links", "lbm_mass", "lbm_dem_substeps", "lbm_destroy",
-           "lbm_last_error"]
+           "lbm_last_error", "lbm_profile", "lbm_profile_read"]
+PROFILE_KINDS = ("fused", "particles", "moments")
 
 
 class LbmConfig(C.Structure):
@@ -73,6 +74,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.lbm_links.argtypes = [vp, i32, C.POINTER(C.c_uint32), C.POINTER(i32), i64, C.POINTER(i64)]
     L.lbm_mass.argtypes = [vp, i32, C.POINTER(C.c_double)]
     L.lbm_dem_substeps.argtypes = [vp, i32, C.POINTER(i32)]
+    L.lbm_profile.argtypes = [vp, i32]
+    L.lbm_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = [vp]
@@ -286,6 +289,17 @@ class Context:
         out = np.zeros(2)
         self._check(load_library().lbm_mass(self.h, sim, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+    def profile(self, enable: bool = True):
+        self._check(load_library().lbm_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kind: (total_ms, launches)} for the fused, particle and moments phases."""
+        n = len(PROFILE_KINDS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        self._check(load_library().lbm_profile_read(self.h, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_KINDS)}
 
     def dem_substeps(self, sim: int = 0):
         v = C.c_int32(0)

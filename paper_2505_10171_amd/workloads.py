@@ -105,18 +105,30 @@ def sessile_drop_c1(seed: int = 1):
 
 def drop_sweep_c2(seed: int = 2):
     """256x128x96, 110-degree wall, hemisphere R_d = 30 pushed along x by a body
-    force 5e-6, 20 spheres R_p = 5 resting on the wall; 10,000 steps."""
+    force 5e-6, 20 spheres R_p = 5 resting on the dry wall at seeded uniform
+    positions outside the drop footprint (as the paper starts its particles in
+    front of the drop), downward force 10 sigma R_p; 10,000 steps."""
     g = rng(seed, 0)
     nx, ny, nz = 256, 128, 96
+    Rd, xc = 30.0, (64.0, 64.0)
     cfg = config(nx, ny, nz, theta_wall_deg=110.0, body_force=(5e-6, 0.0, 0.0))
-    phi0 = drop_phi0(nx, ny, nz, (64.0, 64.0, 0.5), 30.0)
+    phi0 = drop_phi0(nx, ny, nz, (xc[0], xc[1], 0.5), Rd)
     R, Rc = 5.0, 5.0 + cfg["delta_R"]
-    xy = _place(g, 20, [0.0, 0.0], [nx, ny], 2 * Rc + 1, [nx, ny])
-    parts = []
-    for p in xy:
+    parts, pts = [], []
+    while len(pts) < 20:
+        q = _place(g, 1, [0.0, 0.0], [nx, ny], 0.0, [nx, ny])[0]
+        d = _wrap(np.asarray(q) - np.asarray(xc), np.asarray([nx, ny], float))
+        if np.hypot(*d) < Rd + Rc + 4.0:
+            continue
+        if any(np.hypot(*_wrap(np.asarray(q) - np.asarray(o), np.asarray([nx, ny], float)))
+               < 2 * Rc + 1 for o in pts):
+            continue
+        pts.append(q)
+    for p in pts:
         parts.append(particle((p[0] % nx, p[1] % ny, 0.5 + Rc), R,
                               theta_deg=g.uniform(30.0, 120.0), mu_s=g.uniform(0.0, 1.0),
-                              mu_r=g.uniform(0.0, 0.1), sigma=cfg["sigma"]))
+                              mu_r=g.uniform(0.0, 0.1), g_p=10.0 * cfg["sigma"] * R,
+                              sigma=cfg["sigma"]))
     return dict(name="drop sweeping particles 256x128x96, 20 spheres R=5", cfg=cfg, phi0=phi0,
                 particles=parts, steps=10000)
 

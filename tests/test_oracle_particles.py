@@ -220,3 +220,20 @@ def test_T17_thread_count_independence():
     O.set_num_threads(8)
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+def test_resting_light_particle_is_stable():
+    """A light sphere (particle/fluid density 2.5) pressed onto the wall by its
+    contact spring in quiescent fluid: with the fluid force averaged over the
+    previous and current lattice step (Verlet passage) the coupled oscillation
+    decays instead of growing; the particle settles at the static overlap
+    g_p/k_n."""
+    cfg = W.config(24, 24, 20, theta_wall_deg=110.0)
+    p = W.particle((12.03, 12.70, 6.5), 5.0, theta_deg=35.0, mu_s=0.98, mu_r=0.045, g_p=0.5)
+    s = OracleSim(cfg, -np.ones((20, 24, 24), np.float32), [p])
+    s.step(1500)
+    q = s.particles()[0]
+    assert abs(q["v"][2]) < 1e-8
+    assert abs(q["x"][2] - (0.5 + 6.0 - 0.5 / cfg["kn"])) < 1e-3
+    rho, u, phi, mask = s.fields()
+    assert np.abs(u[:, mask == 0]).max() < 5e-3
