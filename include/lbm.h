@@ -176,7 +176,8 @@ int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out);
 /* Per-phase timing for benchmarks.  lbm_profile(ctx, 1) starts (or restarts)
  * recording HIP events on the context's stream around each step's phases:
  * kind 0 the fused collide-stream kernel, kind 1 the particle kernels
- * (capillary, DEM, mask update, refill), kind 2 the order-parameter kernel;
+ * (capillary, DEM, mask update, refill), kind 2 the order-parameter kernel,
+ * kind 3 the interface kernel (normal and curvature);
  * lbm_profile(ctx, 0) stops.  lbm_profile_read waits for the recorded steps and
  * writes, for the first n_kinds kinds, the summed GPU time in milliseconds and
  * the number of timed launches (per simulation and step). */

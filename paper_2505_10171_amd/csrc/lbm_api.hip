@@ -23,8 +23,11 @@
 #include "lbm_device.h"
 
 namespace lbm {
-hipError_t launch_fused(const SimDev& s, const void* src, void* dst, int mode, int LZ, float* orho,
-                        float* ou, float* ophi, float* oF, hipStream_t st);
+hipError_t launch_interface(const SimDev& s, float4* nrm, float2* cur, hipStream_t st);
+hipError_t launch_fused(const SimDev& s, const void* src, void* dst, const float4* nrm,
+                        const float2* cur, int mode, float* orho, float* ou, float* ophi,
+                        float* oF, hipStream_t st);
+hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, hipStream_t st);
 hipError_t launch_moments(const SimDev& s, const void* pops, hipStream_t st);
 hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
 hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
@@ -48,7 +51,7 @@ struct SimLayout {
   long long N;
   int np, Bmask, Bcap, hist_cap;
   size_t pop_bytes, fresh_cap;
-  size_t off_pops0, off_pops1, off_phi, off_mask, off_claim, off_fresh, off_fresh_own,
+  size_t off_pops0, off_pops1, off_phi, off_nrm, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
       off_counters, off_P, off_ct, off_nb, off_hist, off_capbox, off_caporg, off_mass, off_step;
   size_t total;
 };
@@ -120,6 +123,8 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   L.off_pops0 = take(L.pop_bytes);
   L.off_pops1 = take(L.pop_bytes);
   L.off_phi = take(4 * L.N);
+  L.off_nrm = take(16 * L.N);
+  L.off_cur = take(8 * L.N);
   L.off_mask = take(2 * L.N);
   L.off_claim = take(4 * L.N);
   L.off_fresh = take(4 * L.fresh_cap);
@@ -195,6 +200,8 @@ struct SimHost {
   lbm_config cfg;
   SimLayout L;
   SimDev d;
+  float4* nrm;  // per node (n, |G|): interface normal and gradient magnitude
+  float2* curv;  // per node (c, solid-direction bits): CSF coefficient
   int cur;  // index of the population buffer holding the current state
   int LZ;
   double Rmax;
@@ -205,10 +212,11 @@ struct SimHost {
 // event sets is reused; a set is harvested (its elapsed times accumulated)
 // before it is recorded again.
 constexpr int PROF_RING = 32;
-constexpr int PROF_KINDS = 3;  // 0 k_fused, 1 particle kernels, 2 k_moments
+constexpr int PROF_KINDS = 4;  // 0 k_fused, 1 particle kernels, 2 k_moments, 3 k_interface
+constexpr int PROF_EVENTS = PROF_KINDS + 1;
 struct Profiler {
   bool on = false;
-  hipEvent_t ev[PROF_RING][4];
+  hipEvent_t ev[PROF_RING][PROF_EVENTS];
   bool pending[PROF_RING];
   int next = 0;
   double total_ms[PROF_KINDS];
@@ -347,6 +355,9 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.pops[0] = b + sh.L.off_pops0;
     d.pops[1] = b + sh.L.off_pops1;
     d.phi = (float*)(b + sh.L.off_phi);
+    sh.nrm = (float4*)(b + sh.L.off_nrm);
+    d.nrm = sh.nrm;
+    sh.curv = (float2*)(b + sh.L.off_cur);
     d.mask = (uint16_t*)(b + sh.L.off_mask);
     d.claim = (uint32_t*)(b + sh.L.off_claim);
     d.fresh = (uint32_t*)(b + sh.L.off_fresh);
@@ -433,12 +444,14 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
 static int prof_harvest(lbm_ctx* ctx, int slot) {
   Profiler& P = ctx->prof;
   if (!P.pending[slot]) return LBM_OK;
-  HIPCHK(ctx, hipEventSynchronize(P.ev[slot][3]));
+  HIPCHK(ctx, hipEventSynchronize(P.ev[slot][PROF_EVENTS - 1]));
+  // events: 0 | interface | 1 | fused | 2 | particles | 3 | moments | 4
+  const int kind_of_gap[PROF_KINDS] = {3, 0, 1, 2};
   for (int k = 0; k < PROF_KINDS; ++k) {
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, P.ev[slot][k], P.ev[slot][k + 1]));
-    P.total_ms[k] += ms;
-    P.count[k] += 1;
+    P.total_ms[kind_of_gap[k]] += ms;
+    P.count[kind_of_gap[k]] += 1;
   }
   P.pending[slot] = false;
   return LBM_OK;
@@ -462,9 +475,12 @@ int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
         if (rc) return rc;
         HIPCHK(ctx, hipEventRecord(P.ev[slot][0], ctx->stream));
       }
-      HIPCHK(ctx, launch_fused(s, src, dst, 0, sh.LZ, nullptr, nullptr, nullptr, nullptr,
-                               ctx->stream));
+      HIPCHK(ctx, launch_interface(s, sh.nrm, sh.curv, ctx->stream));
       if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][1], ctx->stream));
+      HIPCHK(ctx, launch_fused(s, src, dst, sh.nrm, sh.curv, 0, nullptr, nullptr, nullptr, nullptr,
+                               ctx->stream));
+      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], ctx->stream));
+      HIPCHK(ctx, launch_links(s, src, dst, sh.L.Bmask, ctx->stream));
       sh.cur ^= 1;
       void* cur = s.pops[sh.cur];
       if (s.np > 0) {
@@ -473,10 +489,10 @@ int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
         HIPCHK(ctx, launch_mask_update(s, sh.L.Bmask, true, ctx->stream));
         HIPCHK(ctx, launch_refill(s, cur, ctx->stream));
       }
-      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], ctx->stream));
+      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], ctx->stream));
       HIPCHK(ctx, launch_moments(s, cur, ctx->stream));
       if (slot >= 0) {
-        HIPCHK(ctx, hipEventRecord(P.ev[slot][3], ctx->stream));
+        HIPCHK(ctx, hipEventRecord(P.ev[slot][4], ctx->stream));
         P.pending[slot] = true;
       }
     }
@@ -490,7 +506,7 @@ int lbm_profile(lbm_ctx* ctx, int32_t enable) {
   Profiler& P = ctx->prof;
   if (enable && !P.on) {
     for (int r = 0; r < PROF_RING; ++r) {
-      for (int k = 0; k < 4; ++k) HIPCHK(ctx, hipEventCreate(&P.ev[r][k]));
+      for (int k = 0; k < PROF_EVENTS; ++k) HIPCHK(ctx, hipEventCreate(&P.ev[r][k]));
       P.pending[r] = false;
     }
     P.next = 0;
@@ -504,7 +520,7 @@ int lbm_profile(lbm_ctx* ctx, int32_t enable) {
   if (!enable && P.on) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     for (int r = 0; r < PROF_RING; ++r)
-      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(P.ev[r][k]);
+      for (int k = 0; k < PROF_EVENTS; ++k) (void)hipEventDestroy(P.ev[r][k]);
     P.on = false;
   }
   return LBM_OK;
@@ -655,8 +671,9 @@ int lbm_fields2(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, 
     float* ophi = scratch + N;
     float* ou = scratch + 2 * N;
     float* oF = scratch + 5 * N;
-    HIPCHK(ctx, launch_fused(d, d.pops[sh->cur], nullptr, 1, sh->LZ, orho, ou, ophi, oF,
-                             ctx->stream));
+    HIPCHK(ctx, launch_interface(d, sh->nrm, sh->curv, ctx->stream));
+    HIPCHK(ctx, launch_fused(d, d.pops[sh->cur], nullptr, sh->nrm, sh->curv, 1, orho, ou, ophi,
+                             oF, ctx->stream));
     if ((what & LBM_F_FORCE) && force)
       HIPCHK(ctx, hipMemcpyAsync(force, oF, 12 * N, kind, ctx->stream));
     if ((what & LBM_F_RHO) && rho)
@@ -730,7 +747,7 @@ void lbm_destroy(lbm_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->prof.on)
     for (int r = 0; r < PROF_RING; ++r)
-      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ctx->prof.ev[r][k]);
+      for (int k = 0; k < PROF_EVENTS; ++k) (void)hipEventDestroy(ctx->prof.ev[r][k]);
   delete ctx;
 }
 

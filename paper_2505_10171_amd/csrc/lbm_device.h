@@ -41,6 +41,8 @@ constexpr float EPS_T = 1e-3f;   // capillary direction length below which a poi
 constexpr int MAXC = 16;        // contact slots per particle
 constexpr int MAXNB = 24;       // DEM pair candidates per particle
 constexpr uint16_t FRESH_BIT = 0x8000;
+constexpr float PHI_SOLID = 4.0f;       // phi stored at solid nodes (never a fluid value)
+constexpr float PHI_SOLID_TEST = 2.0f;  // phi above this marks a solid node
 
 // -------------------------------------------------------------- particles
 struct alignas(16) DevParticle {
@@ -62,6 +64,7 @@ struct alignas(16) DevParticle {
   double vp[3], wp[3];      // predicted velocities
   double Fcn[3], Tcn[3];    // contact force/torque of the current sub-step
   double Ffp[3], Tfp[3];    // fluid force/torque of the previous lattice step
+  double Fca[3], Tca[3];    // capillary accumulators (FP64 atomics)
   int havep, pad2;          // 1 once Ffp/Tfp hold a previous step
 };
 
@@ -83,7 +86,8 @@ struct SimDev {
   float wall_neg_cos, wall_sin;
   // fields
   void* pops[2];       // ping-pong population buffers: 38 planes of N
-  float* phi;          // order parameter of the current state
+  float* phi;          // order parameter of the current state (PHI_SOLID at solids)
+  float4* nrm;         // per node (n, |G|) of the current state; w = -1 at solids
   uint16_t* mask;      // 0 fluid, 1 wall, 2+p particle p; FRESH_BIT while refilling
   uint32_t* claim;     // per node: lowest particle claiming it in the new mask, ~0u none
   uint32_t* fresh;     // fresh-node list: node index

@@ -7,17 +7,11 @@
 // h_i = f_i / (w_i rho0) - 1 and k_i = g_i / (w_i rho0).  All arithmetic is FP32;
 // momentum exchange sums are FP64.
 //
-// k_fused performs, per fluid node, the paper's collision step on the total f
-// (MRT with Guo forcing; the printed relaxation vector gives omega to every even
-// and omega' = 8(2-omega)/(8-omega) to every odd non-conserved moment, which is
-// the two-relaxation-time operator computed here), the CSF surface-tension force
-// -sigma kappa grad(phi)/2 with the geometric wetting rotation of grad(phi) next
-// to solids, the recolouring of f* into the two colours, push streaming, the
-// half-way bounce-back with moving walls and the momentum exchange on particle
-// links.  A workgroup owns a TX x TY column tile and marches along z through LZ
-// planes, keeping five planes of phi and mask (halo 2) and three planes of the
-// interface normal (halo 1) in LDS, so phi and the normals are computed once per
-// node and the populations are read and written exactly once.
+// A step of the fluid runs three kernels: k_moments (order parameter of the
+// post-stream state), k_interface (interface normal and CSF coefficient, an LDS
+// z-march over phi and the mask) and k_fused (collision, force, recolouring,
+// streaming, bounce-back and momentum exchange, one thread per node, reading and
+// writing every population exactly once).
 #include "lbm_device.h"
 
 namespace lbm {
@@ -43,10 +37,6 @@ struct PopIO<1> {
     *p = __float2half_rn(v * inv_scale);
   }
 };
-
-__device__ __forceinline__ long long node_index(const SimDev& s, int x, int y, int z) {
-  return (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
-}
 
 // ------------------------------------------------------------ wetting rotation
 // Geometric wetting (n_pm equation): at a fluid node with a solid neighbour the
@@ -99,7 +89,8 @@ __host__ __device__ constexpr int pair_dir(int k) {
 
 // ------------------------------------------------------------- moments kernel
 // Order parameter phi = sum g / rho of every fluid node (order-parameter eq.),
-// after the refill of fresh nodes; clears their FRESH mark.
+// after the refill of fresh nodes; clears their FRESH mark.  Solid nodes get
+// the sentinel PHI_SOLID, so stencils can tell solids from phi alone.
 template <int STORE>
 __global__ __launch_bounds__(256) void k_moments(SimDev s, const void* __restrict__ pops) {
   using IO = PopIO<STORE>;
@@ -127,6 +118,8 @@ __global__ __launch_bounds__(256) void k_moments(SimDev s, const void* __restric
       sg += IO::ld(b + (long long)(Q + i) * N + n, sc, 0.f);
     }
     out = sg / rabs;
+  } else {
+    out = PHI_SOLID;
   }
   s.phi[n] = out;
 }
@@ -195,395 +188,417 @@ __global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__
   }
 }
 
-// ------------------------------------------------------------- fused kernel
 enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 
-// wave64 sum of a double
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-template <int STORE, int TX, int TY, int MODE>
-__global__ __launch_bounds__(TX* TY) void k_fused(SimDev s, const void* __restrict__ src,
-                                                 void* __restrict__ dst, int LZ, int ntx, int nty,
-                                                 int ntz, float* __restrict__ out_rho,
-                                                 float* __restrict__ out_u,
-                                                 float* __restrict__ out_phi,
-                                                 float* __restrict__ out_F) {
-  using IO = PopIO<STORE>;
-  using T = typename IO::T;
-  constexpr int NT = TX * TY;
-  constexpr int HX = TX + 4, HY = TY + 4;
-  constexpr int NX1 = TX + 2, NY1 = TY + 2;
-  __shared__ float s_phi[5][HY][HX];
-  __shared__ uint16_t s_mask[5][HY][HX];
-  __shared__ float4 s_n[3][NY1][NX1];
-
-  const int nx = s.nx, ny = s.ny, nz = s.nz;
-  const long long N = s.N;
-
-  // XCD-aware tile order: consecutive dispatches go round-robin over the 8
-  // XCDs; give each XCD a contiguous range of tiles so that halo planes shared
-  // by neighbouring tiles meet in the same L2.
-  const int nblk = ntx * nty * ntz;
-  int lin = blockIdx.x;
-  int tile = lin;
+// XCD-aware block order: consecutive dispatches go round-robin over the 8 XCDs;
+// give each XCD a contiguous range of blocks so that data shared by neighbouring
+// blocks (halo reads, pushed populations) meets in the same L2.
+__device__ __forceinline__ int xcd_tile(int lin, int nblk) {
   if ((nblk & 7) == 0) {
     const int per = nblk >> 3;
-    tile = (lin & 7) * per + (lin >> 3);
+    return (lin & 7) * per + (lin >> 3);
   }
-  const int bx = tile % ntx;
-  const int rr = tile / ntx;
-  const int by = rr % nty;
-  const int bz = rr / nty;
-  const int x0 = bx * TX, y0 = by * TY, z0 = bz * LZ;
-  const int z1 = min(z0 + LZ, nz);
-  const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
-  const int gx = x0 + tx, gy = y0 + ty;
-  const bool active = (gx < nx) && (gy < ny);
+  return lin;
+}
 
-  auto slot5 = [](int zrel) { return (zrel + 10) % 5; };
-  auto slot3 = [](int zrel) { return (zrel + 9) % 3; };
+// ------------------------------------------------------ interface kernels
+// wrapped neighbour offsets of node (x, y, z): index of x + c is
+// X[1+cx] + Y[1+cy] + Z[1+cz]
+struct Nbr {
+  int X[3], Y[3], Z[3];
+  __device__ __forceinline__ Nbr(int gx, int gy, int gz, int nx, int ny, int nz) {
+    const int nxny = nx * ny;
+    X[0] = gx == 0 ? nx - 1 : gx - 1;
+    X[1] = gx;
+    X[2] = gx == nx - 1 ? 0 : gx + 1;
+    Y[0] = (gy == 0 ? ny - 1 : gy - 1) * nx;
+    Y[1] = gy * nx;
+    Y[2] = (gy == ny - 1 ? 0 : gy + 1) * nx;
+    Z[0] = (gz == 0 ? nz - 1 : gz - 1) * nxny;
+    Z[1] = gz * nxny;
+    Z[2] = (gz == nz - 1 ? 0 : gz + 1) * nxny;
+  }
+  __device__ __forceinline__ int operator()(int i) const {
+    return X[1 + cx(i)] + Y[1 + cy(i)] + Z[1 + cz(i)];
+  }
+};
 
-  auto load_plane = [&](int zrel) {
-    const int gz = wrapi(z0 + zrel, nz);
-    const int sl = slot5(zrel);
-    for (int k = tid; k < HX * HY; k += NT) {
-      const int lx = k % HX, ly = k / HX;
-      const int xg = wrapi(x0 - 2 + lx, nx), yg = wrapi(y0 - 2 + ly, ny);
-      const long long n = node_index(s, xg, yg, gz);
-      const uint16_t m = s.mask[n];
-      s_mask[sl][ly][lx] = m;
-      s_phi[sl][ly][lx] = (m == 0) ? s.phi[n] : 0.f;
-    }
-  };
-
-  // colour gradient (isotropic stencil with the zero-gradient closure at solid
-  // neighbours), wetting rotation, unit normal; for the halo-1 region of a plane
-  auto normals_plane = [&](int zrel) {
-    const int gz = wrapi(z0 + zrel, nz);
-    const int sc = slot5(zrel), sm = slot5(zrel - 1), sp = slot5(zrel + 1);
-    const int so = slot3(zrel);
-    for (int k = tid; k < NX1 * NY1; k += NT) {
-      const int hx = k % NX1, hy = k / NX1;
-      const int lx = hx + 1, ly = hy + 1;
-      float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (s_mask[sc][ly][lx] == 0) {
-        const float p0 = s_phi[sc][ly][lx];
-        float Gx = 0.f, Gy = 0.f, Gz = 0.f;
-        int minp = 0x7fffffff;
-        bool solid = false, wall = false;
+// Colour gradient G = 3 sum_i w_i c_i phi(x + c_i) (isotropic stencil, the value
+// at x for solid neighbours), the geometric wetting rotation next to solids, and
+// the normal n = G / max(|G|, EPS_G); written as (n, |G|).
+__global__ __launch_bounds__(256) void k_normal(SimDev s, float4* __restrict__ nrm) {
+  const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
+  const int n = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (n >= (int)s.N) return;
+  float4 out = make_float4(0.f, 0.f, 0.f, -1.0f);  // w < 0 marks a solid node
+  const float p0 = s.phi[n];
+  if (p0 < PHI_SOLID_TEST) {
+    const int gz = n / nxny, rem = n - gz * nxny, gy = rem / nx, gx = rem - gy * nx;
+    const Nbr nb(gx, gy, gz, nx, ny, nz);
+    float Gx = 0.f, Gy = 0.f, Gz = 0.f;
+    bool solid = false;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const int i = pair_dir(q);
-          const int slp = cz(i) > 0 ? sp : (cz(i) < 0 ? sm : sc);
-          const int slm = cz(i) > 0 ? sm : (cz(i) < 0 ? sp : sc);
-          const uint16_t mp = s_mask[slp][ly + cy(i)][lx + cx(i)];
-          const uint16_t mm = s_mask[slm][ly - cy(i)][lx - cx(i)];
-          const float vp = (mp == 0) ? s_phi[slp][ly + cy(i)][lx + cx(i)] : p0;
-          const float vm = (mm == 0) ? s_phi[slm][ly - cy(i)][lx - cx(i)] : p0;
-          const float d = 3.0f * wq(i) * (vp - vm);
-          Gx += (float)cx(i) * d;
-          Gy += (float)cy(i) * d;
-          Gz += (float)cz(i) * d;
-          if (mp) {
-            solid = true;
-            if (mp >= 2) minp = min(minp, (int)mp - 2); else wall = true;
-          }
-          if (mm) {
-            solid = true;
-            if (mm >= 2) minp = min(minp, (int)mm - 2); else wall = true;
-          }
-        }
-        if (solid) {
-          const int hgx = wrapi(x0 - 1 + hx, nx), hgy = wrapi(y0 - 1 + hy, ny);
-          wetting_rotate(s, hgx, hgy, gz, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
-        }
-        const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
-        const float ig = 1.0f / fmaxf(g, EPS_G);
-        out = make_float4(Gx * ig, Gy * ig, Gz * ig, g);
-      }
-      s_n[so][hy][hx] = out;
+    for (int q = 0; q < 9; ++q) {
+      const int i = pair_dir(q);
+      float vp = s.phi[nb(i)];
+      float vm = s.phi[nb(opp(i))];
+      const bool sp = vp > PHI_SOLID_TEST, sm = vm > PHI_SOLID_TEST;
+      solid |= sp | sm;
+      vp = sp ? p0 : vp;
+      vm = sm ? p0 : vm;
+      const float d = 3.0f * wq(i) * (vp - vm);
+      Gx += (float)cx(i) * d;
+      Gy += (float)cy(i) * d;
+      Gz += (float)cz(i) * d;
     }
-  };
+    if (solid) {
+      // identify the solid: the lowest-index neighbouring particle, else the wall
+      int minp = 0x7fffffff;
+      bool wall = false;
+      for (int i = 1; i < Q; ++i) {
+        const uint16_t m = s.mask[nb(i)];
+        if (m >= 2) minp = min(minp, (int)m - 2);
+        else if (m == 1) wall = true;
+      }
+      wetting_rotate(s, gx, gy, gz, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
+    }
+    const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
+    const float ig = 1.0f / fmaxf(g, EPS_G);
+    out = make_float4(Gx * ig, Gy * ig, Gz * ig, g);
+  }
+  nrm[n] = out;
+}
 
-  // prologue
-  for (int zr = -2; zr <= 1; ++zr) load_plane(zr);
-  __syncthreads();
-  normals_plane(-1);
-  normals_plane(0);
+// Curvature kappa = div n (same stencil and closure) and the CSF coefficient
+// c = -sigma kappa max(|G|, EPS_G) / 2 (the surface-tension force is c n); plus
+// the set of directions whose neighbour is solid (bit i), bit 31 = node solid.
+__global__ __launch_bounds__(256) void k_curv(SimDev s, const float4* __restrict__ nrm,
+                                              float2* __restrict__ cur) {
+  const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
+  const int n = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (n >= (int)s.N) return;
+  float c = 0.f;
+  uint32_t bits = 0x80000000u;
+  const float4 nc = nrm[n];
+  if (nc.w >= 0.f) {
+    const int gz = n / nxny, rem = n - gz * nxny, gy = rem / nx, gx = rem - gy * nx;
+    const Nbr nb(gx, gy, gz, nx, ny, nz);
+    float kappa = 0.f;
+    bits = 0u;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int i = pair_dir(q), o = opp(i);
+      float4 np_ = nrm[nb(i)];
+      float4 nm_ = nrm[nb(o)];
+      const bool sp = np_.w < 0.f, sm = nm_.w < 0.f;
+      if (sp) np_ = nc;
+      if (sm) nm_ = nc;
+      kappa += 3.0f * wq(i) *
+               ((float)cx(i) * (np_.x - nm_.x) + (float)cy(i) * (np_.y - nm_.y) +
+                (float)cz(i) * (np_.z - nm_.z));
+      bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
+    }
+    c = -0.5f * s.sigma * kappa * fmaxf(nc.w, EPS_G);
+  }
+  cur[n] = make_float2(c, __uint_as_float(bits));
+}
 
+// ------------------------------------------------------------- fused kernel
+// Per fluid node (one thread, x-fastest): populations in, the paper's collision
+// on the total f (MRT + Guo forcing; the printed relaxation vector gives omega
+// to every even and omega' = 8(2-omega)/(8-omega) to every odd non-conserved
+// moment -- the two-relaxation-time operator computed here), the force c n +
+// body force on fluid a, the recolouring of f* into the two colours, push
+// streaming, and half-way bounce-back at every solid link.  At particle links
+// the moving-wall term and the momentum exchange are added by k_links.
+template <int STORE, int MODE>
+__global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict__ src,
+                                              void* __restrict__ dst,
+                                              const float4* __restrict__ nrm,
+                                              const float2* __restrict__ cur,
+                                              float* __restrict__ out_rho,
+                                              float* __restrict__ out_u,
+                                              float* __restrict__ out_phi,
+                                              float* __restrict__ out_F) {
+  using IO = PopIO<STORE>;
+  using T = typename IO::T;
+  const int nx = s.nx, ny = s.ny, nz = s.nz;
+  const int N = (int)s.N;
+  const int nxny = nx * ny;
+  const int n = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (n >= N) return;
+  const float rho0 = s.rho0;
   const T* __restrict__ sp_ = (const T*)src;
   T* __restrict__ dp_ = (T*)dst;
-  const float rho0 = s.rho0;
+  const float2 cb = cur[n];
+  const uint32_t bits = __float_as_uint(cb.y);
+  const int gz = n / nxny;
+  const int rem = n - gz * nxny;
+  const int gy = rem / nx;
+  const int gx = rem - gy * nx;
 
-  for (int z = z0; z < z1; ++z) {
-    const int zrel = z - z0;
-    load_plane(zrel + 2);
-    __syncthreads();
-    normals_plane(zrel + 1);
-    __syncthreads();
-
-    // ------------------------------------------------------- node update
-    double accF0 = 0.0, accF1 = 0.0, accF2 = 0.0, accT0 = 0.0, accT1 = 0.0, accT2 = 0.0;
-    int key = -1;
-    const int lx = tx + 2, ly = ty + 2;
-    const int sc = slot5(zrel), sm = slot5(zrel - 1), spl = slot5(zrel + 1);
-    const uint16_t m0 = active ? s_mask[sc][ly][lx] : (uint16_t)1;
-    const long long n = active ? node_index(s, gx, gy, z) : 0;
-
-    if (active && m0 != 0) {
-      if (MODE == MODE_FIELDS) {
-        float ux = 0.f, uy = 0.f, uz = 0.f;
-        if (m0 >= 2) {
-          const DevParticle& P = s.P[m0 - 2];
-          double rx = wrapd((double)gx - P.x[0], (double)nx);
-          double ry = wrapd((double)gy - P.x[1], (double)ny);
-          double rz = wrapd((double)z - P.x[2], (double)nz);
-          ux = (float)(P.v[0] + P.w[1] * rz - P.w[2] * ry);
-          uy = (float)(P.v[1] + P.w[2] * rx - P.w[0] * rz);
-          uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
-        }
-        out_rho[n] = 0.f;
-        out_phi[n] = 0.f;
-        out_u[n] = ux;
-        out_u[N + n] = uy;
-        out_u[2 * N + n] = uz;
-        out_F[n] = 0.f;
-        out_F[N + n] = 0.f;
-        out_F[2 * N + n] = 0.f;
+  if (bits & 0x80000000u) {
+    if (MODE == MODE_FIELDS) {
+      const uint16_t m0 = s.mask[n];
+      float ux = 0.f, uy = 0.f, uz = 0.f;
+      if (m0 >= 2) {
+        const DevParticle& P = s.P[m0 - 2];
+        double rx = wrapd((double)gx - P.x[0], (double)nx);
+        double ry = wrapd((double)gy - P.x[1], (double)ny);
+        double rz = wrapd((double)gz - P.x[2], (double)nz);
+        ux = (float)(P.v[0] + P.w[1] * rz - P.w[2] * ry);
+        uy = (float)(P.v[1] + P.w[2] * rx - P.w[0] * rz);
+        uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
       }
-    } else if (active) {
-      // own populations
-      float d[Q], g[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const float sc_ = wq(i) * rho0;
-        d[i] = IO::ld(sp_ + (long long)i * N + n, sc_, 0.f);
-        g[i] = IO::ld(sp_ + (long long)(Q + i) * N + n, sc_, 0.f);
-      }
-      float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        drho += d[i];
-        jx += (float)cx(i) * d[i];
-        jy += (float)cy(i) * d[i];
-        jz += (float)cz(i) * d[i];
-      }
-      const float rho = rho0 + drho;
-      const float phi = s_phi[sc][ly][lx];
-
-      // curvature kappa = div n (same stencil and closure as the gradient)
-      const int nsl = slot3(zrel), nsm = slot3(zrel - 1), nsp = slot3(zrel + 1);
-      const float4 nc = s_n[nsl][ty + 1][tx + 1];
-      float kappa = 0.f;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const int i = pair_dir(q);
-        const int slp = cz(i) > 0 ? spl : (cz(i) < 0 ? sm : sc);
-        const int slm = cz(i) > 0 ? sm : (cz(i) < 0 ? spl : sc);
-        const int nlp = cz(i) > 0 ? nsp : (cz(i) < 0 ? nsm : nsl);
-        const int nlm = cz(i) > 0 ? nsm : (cz(i) < 0 ? nsp : nsl);
-        const float4 np_ = (s_mask[slp][ly + cy(i)][lx + cx(i)] == 0)
-                               ? s_n[nlp][ty + 1 + cy(i)][tx + 1 + cx(i)] : nc;
-        const float4 nm_ = (s_mask[slm][ly - cy(i)][lx - cx(i)] == 0)
-                               ? s_n[nlm][ty + 1 - cy(i)][tx + 1 - cx(i)] : nc;
-        kappa += 3.0f * wq(i) *
-                 ((float)cx(i) * (np_.x - nm_.x) + (float)cy(i) * (np_.y - nm_.y) +
-                  (float)cz(i) * (np_.z - nm_.z));
-      }
-      // force: CSF surface tension -sigma kappa G / 2 + body force on fluid a
-      // (weight (1+phi)/2); G = n max(|G|, EPS_G)
-      const float cst = -0.5f * s.sigma * kappa * fmaxf(nc.w, EPS_G);
-      const float fa = 0.5f * (1.0f + phi);
-      const float Fx = cst * nc.x + s.body[0] * fa;
-      const float Fy = cst * nc.y + s.body[1] * fa;
-      const float Fz = cst * nc.z + s.body[2] * fa;
-      const float irho = 1.0f / rho;
-      const float ux = (jx + 0.5f * Fx) * irho;
-      const float uy = (jy + 0.5f * Fy) * irho;
-      const float uz = (jz + 0.5f * Fz) * irho;
-      const float uu = ux * ux + uy * uy + uz * uz;
-
-      if (MODE == MODE_FIELDS) {
-        out_rho[n] = rho;
-        out_phi[n] = phi;
-        out_u[n] = ux;
-        out_u[N + n] = uy;
-        out_u[2 * N + n] = uz;
-        out_F[n] = Fx;
-        out_F[N + n] = Fy;
-        out_F[2 * N + n] = Fz;
-      } else {
-        if (!(rho > 0.f) || !(uu <= 0.09f)) atomicOr(&s.counters[1], (uint32_t)ST_UNSTABLE);
-        // local relaxation: harmonic mean of the kinematic viscosities
-        const float inv_nu = (1.0f + phi) * s.inv2nua + (1.0f - phi) * s.inv2nub;
-        const float om = 1.0f / (0.5f + 3.0f / inv_nu);
-        const float om2 = 8.0f * (2.0f - om) / (8.0f - om);
-        const float cfs = 1.0f - 0.5f * om, cfa = 1.0f - 0.5f * om2;
-        const float uF = ux * Fx + uy * Fy + uz * Fz;
-        const float rec = 0.5f * s.beta * rho * (1.0f - phi) * (1.0f + phi);
-
-        // rest population
-        {
-          const float w0 = wq(0);
-          const float deq = w0 * (drho - 1.5f * rho * uu);
-          const float fb = w0 * (-3.0f * uF);
-          const float ds = d[0] - om * (d[0] - deq) + cfs * fb;
-          const float gs = phi * (ds + w0 * rho0);
-          const float sc_ = w0 * rho0;
-          IO::st(dp_ + n, ds, 1.0f / sc_);
-          IO::st(dp_ + (long long)Q * N + n, gs, 1.0f / sc_);
-        }
-
-        auto emit = [&](int i, float ds, float gs, float rci) {
-          const int xx = wrapi(gx + cx(i), nx), yy = wrapi(gy + cy(i), ny),
-                    zz = wrapi(z + cz(i), nz);
-          const int sl = cz(i) > 0 ? spl : (cz(i) < 0 ? sm : sc);
-          const uint16_t mt = s_mask[sl][ly + cy(i)][lx + cx(i)];
-          const float sc_ = wq(i) * rho0;
-          if (mt == 0) {
-            const long long m = node_index(s, xx, yy, zz);
-            IO::st(dp_ + (long long)i * N + m, ds, 1.0f / sc_);
-            IO::st(dp_ + (long long)(Q + i) * N + m, gs, 1.0f / sc_);
-          } else {
-            const int o = opp(i);
-            if (mt == 1) {
-              IO::st(dp_ + (long long)o * N + n, ds, 1.0f / sc_);
-              IO::st(dp_ + (long long)(Q + o) * N + n, gs, 1.0f / sc_);
-            } else {
-              const int p = mt - 2;
-              const DevParticle& P = s.P[p];
-              // wall velocity at the link midpoint
-              const double rx = wrapd((double)gx + 0.5 * cx(i) - P.x[0], (double)nx);
-              const double ry = wrapd((double)gy + 0.5 * cy(i) - P.x[1], (double)ny);
-              const double rz = wrapd((double)z + 0.5 * cz(i) - P.x[2], (double)nz);
-              const double uwx = P.v[0] + (P.w[1] * rz - P.w[2] * ry);
-              const double uwy = P.v[1] + (P.w[2] * rx - P.w[0] * rz);
-              const double uwz = P.v[2] + (P.w[0] * ry - P.w[1] * rx);
-              // c_opp . u_w
-              const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));
-              // f_opp = f*_i + 6 w rho (c_opp.u_w); g_opp = phi f_opp + recolour
-              // term (the same as g*_i + 6 w rho phi (c_opp.u_w))
-              const float dso = ds + 6.0f * wq(i) * rho * cu;
-              const float gso = phi * (dso + wq(i) * rho0) + rci;
-              IO::st(dp_ + (long long)o * N + n, dso, 1.0f / sc_);
-              IO::st(dp_ + (long long)(Q + o) * N + n, gso, 1.0f / sc_);
-              // momentum exchange (Galilean invariant): momentum given to p
-              const double wr = wqd(i) * (double)rho0;
-              const double fin = (double)ds + wr;
-              const double fout = (double)dso + wr;
-              const double dPx = (cx(i) - uwx) * fin - (-cx(i) - uwx) * fout;
-              const double dPy = (cy(i) - uwy) * fin - (-cy(i) - uwy) * fout;
-              const double dPz = (cz(i) - uwz) * fin - (-cz(i) - uwz) * fout;
-              const double tX = ry * dPz - rz * dPy;
-              const double tY = rz * dPx - rx * dPz;
-              const double tZ = rx * dPy - ry * dPx;
-              if (key < 0) key = p;
-              if (p == key) {
-                accF0 += dPx; accF1 += dPy; accF2 += dPz;
-                accT0 += tX; accT1 += tY; accT2 += tZ;
-              } else {
-                DevParticle* Pw = s.P + p;
-                atomicAdd(&Pw->Fh[0], dPx); atomicAdd(&Pw->Fh[1], dPy);
-                atomicAdd(&Pw->Fh[2], dPz); atomicAdd(&Pw->Th[0], tX);
-                atomicAdd(&Pw->Th[1], tY); atomicAdd(&Pw->Th[2], tZ);
-              }
-            }
-          }
-        };
-
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const int i = pair_dir(q);
-          const int o = opp(i);
-          const float w = wq(i);
-          const float cu = (float)cx(i) * ux + (float)cy(i) * uy + (float)cz(i) * uz;
-          const float cF = (float)cx(i) * Fx + (float)cy(i) * Fy + (float)cz(i) * Fz;
-          const float eqs = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
-          const float eqa = w * rho * 3.0f * cu;
-          const float fs = w * (9.0f * cu * cF - 3.0f * uF);
-          const float fa2 = w * 3.0f * cF;
-          const float sy = 0.5f * (d[i] + d[o]) - eqs;
-          const float an = 0.5f * (d[i] - d[o]) - eqa;
-          const float common = -om * sy + cfs * fs;
-          const float anti = -om2 * an + cfa * fa2;
-          const float ds_i = d[i] + common + anti;
-          const float ds_o = d[o] + common - anti;
-          const float cn = (float)cx(i) * nc.x + (float)cy(i) * nc.y + (float)cz(i) * nc.z;
-          const float rc = rec * w * cn;
-          const float wr0 = w * rho0;
-          const float gs_i = phi * (ds_i + wr0) + rc;
-          const float gs_o = phi * (ds_o + wr0) - rc;
-          emit(i, ds_i, gs_i, rc);
-          emit(o, ds_o, gs_o, -rc);
-        }
-        (void)g;
-      }
+      out_rho[n] = 0.f;
+      out_phi[n] = 0.f;
+      out_u[n] = ux;
+      out_u[N + n] = uy;
+      out_u[2 * N + n] = uz;
+      out_F[n] = 0.f;
+      out_F[N + n] = 0.f;
+      out_F[2 * N + n] = 0.f;
     }
+    return;
+  }
+  const Nbr nb(gx, gy, gz, nx, ny, nz);
+  float d[Q], g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float sc_ = wq(i) * rho0;
+    d[i] = IO::ld(sp_ + (unsigned)(i * N + n), sc_, 0.f);
+    g[i] = IO::ld(sp_ + (unsigned)((Q + i) * N + n), sc_, 0.f);
+  }
+  const float4 nc = nrm[n];
+  const float phi = s.phi[n];
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += d[i];
+    jx += (float)cx(i) * d[i];
+    jy += (float)cy(i) * d[i];
+    jz += (float)cz(i) * d[i];
+  }
+  const float rho = rho0 + drho;
+  // force: CSF surface tension c n + body force on fluid a (weight (1+phi)/2)
+  const float fa = 0.5f * (1.0f + phi);
+  const float Fx = cb.x * nc.x + s.body[0] * fa;
+  const float Fy = cb.x * nc.y + s.body[1] * fa;
+  const float Fz = cb.x * nc.z + s.body[2] * fa;
+  const float irho = 1.0f / rho;
+  const float ux = (jx + 0.5f * Fx) * irho;
+  const float uy = (jy + 0.5f * Fy) * irho;
+  const float uz = (jz + 0.5f * Fz) * irho;
+  const float uu = ux * ux + uy * uy + uz * uz;
 
-    if (MODE == MODE_STEP && s.np > 0) {
-      // segmented wave64 reduction of the per-particle momentum exchange
-      while (true) {
-        const unsigned long long act = __ballot(key >= 0);
-        if (act == 0ull) break;
-        const int leader = __ffsll((long long)act) - 1;
-        const int lk = __shfl(key, leader, 64);
-        const bool mine = (key == lk);
-        const double v0 = wave_sum(mine ? accF0 : 0.0);
-        const double v1 = wave_sum(mine ? accF1 : 0.0);
-        const double v2 = wave_sum(mine ? accF2 : 0.0);
-        const double v3 = wave_sum(mine ? accT0 : 0.0);
-        const double v4 = wave_sum(mine ? accT1 : 0.0);
-        const double v5 = wave_sum(mine ? accT2 : 0.0);
-        if ((int)(threadIdx.x & 63) == leader) {
-          DevParticle* Pw = s.P + lk;
-          atomicAdd(&Pw->Fh[0], v0); atomicAdd(&Pw->Fh[1], v1); atomicAdd(&Pw->Fh[2], v2);
-          atomicAdd(&Pw->Th[0], v3); atomicAdd(&Pw->Th[1], v4); atomicAdd(&Pw->Th[2], v5);
-        }
-        if (mine) key = -1;
-      }
+  if (MODE == MODE_FIELDS) {
+    out_rho[n] = rho;
+    out_phi[n] = phi;
+    out_u[n] = ux;
+    out_u[N + n] = uy;
+    out_u[2 * N + n] = uz;
+    out_F[n] = Fx;
+    out_F[N + n] = Fy;
+    out_F[2 * N + n] = Fz;
+    (void)g;
+    return;
+  }
+  if (!(rho > 0.f) || !(uu <= 0.09f)) atomicOr(&s.counters[1], (uint32_t)ST_UNSTABLE);
+  // local relaxation: harmonic mean of the kinematic viscosities
+  const float inv_nu = (1.0f + phi) * s.inv2nua + (1.0f - phi) * s.inv2nub;
+  const float om = 1.0f / (0.5f + 3.0f / inv_nu);
+  const float om2 = 8.0f * (2.0f - om) / (8.0f - om);
+  const float cfs = 1.0f - 0.5f * om, cfa = 1.0f - 0.5f * om2;
+  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  const float recl = 0.5f * s.beta * rho * (1.0f - phi) * (1.0f + phi);
+
+  auto st_pop = [&](int i, int node, float dv, float gv) {
+    const float isc = 1.0f / (wq(i) * rho0);
+    IO::st(dp_ + (unsigned)(i * N + node), dv, isc);
+    IO::st(dp_ + (unsigned)((Q + i) * N + node), gv, isc);
+  };
+  // push to the neighbour in direction i, or bounce back into direction opp(i)
+  auto emit = [&](int i, float dv, float gv) {
+    if (bits & (1u << i))
+      st_pop(opp(i), n, dv, gv);
+    else
+      st_pop(i, nb(i), dv, gv);
+  };
+
+  {
+    const float w0 = wq(0);
+    const float deq = w0 * (drho - 1.5f * rho * uu);
+    const float fb = w0 * (-3.0f * uF);
+    const float ds = d[0] - om * (d[0] - deq) + cfs * fb;
+    st_pop(0, n, ds, phi * (ds + w0 * rho0));
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int i = pair_dir(q);
+    const int o = opp(i);
+    const float w = wq(i);
+    const float cu = (float)cx(i) * ux + (float)cy(i) * uy + (float)cz(i) * uz;
+    const float cF = (float)cx(i) * Fx + (float)cy(i) * Fy + (float)cz(i) * Fz;
+    const float eqs = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
+    const float eqa = w * rho * 3.0f * cu;
+    const float fs = w * (9.0f * cu * cF - 3.0f * uF);
+    const float fa2 = w * 3.0f * cF;
+    const float sy = 0.5f * (d[i] + d[o]) - eqs;
+    const float an = 0.5f * (d[i] - d[o]) - eqa;
+    const float common = -om * sy + cfs * fs;
+    const float anti = -om2 * an + cfa * fa2;
+    const float ds_i = d[i] + common + anti;
+    const float ds_o = d[o] + common - anti;
+    const float cn = (float)cx(i) * nc.x + (float)cy(i) * nc.y + (float)cz(i) * nc.z;
+    const float rc = recl * w * cn;
+    const float wr0 = w * rho0;
+    emit(i, ds_i, phi * (ds_i + wr0) + rc);
+    emit(o, ds_o, phi * (ds_o + wr0) - rc);
+  }
+  (void)g;
+}
+
+// Moving-wall correction and momentum exchange on particle links, after
+// k_fused has bounced f*_i back into direction opp(i) at the fluid node x:
+// f_opp(x) += 6 w_i rho(x) (c_opp . u_w), g_opp(x) += phi(x) * the same, with
+// u_w = V + Omega x (x + c_i/2 - X) (half-way bounce-back eqs.), and the
+// momentum given to the particle dP = (c_i - u_w) f*_i - (c_opp - u_w) f_opp
+// (hydrodynamic force eqs.), summed in FP64 per particle.  One grid row per
+// particle over the nodes of its bounding box grown by one.
+template <int STORE>
+__global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict__ src,
+                                              void* __restrict__ dst, int B) {
+  using IO = PopIO<STORE>;
+  using T = typename IO::T;
+  const int p = blockIdx.y;
+  const DevParticle& P = s.P[p];
+  const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny, N = (int)s.N;
+  const float rho0 = s.rho0;
+  int lo[3], w[3];
+  const int L[3] = {nx, ny, nz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = (int)floor(P.x[k] - P.R) - 2;
+    w[k] = (int)floor(P.x[k] + P.R) + 2 - lo[k] + 1;
+    if (w[k] > L[k]) {
+      lo[k] = 0;
+      w[k] = L[k];
     }
   }
+  const int vol = w[0] * w[1] * w[2];
+  const T* __restrict__ sp_ = (const T*)src;
+  T* __restrict__ dp_ = (T*)dst;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const uint16_t me = (uint16_t)(2 + p);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < vol; k += gridDim.x * blockDim.x) {
+    const int gx = wrapi(lo[0] + k % w[0], nx);
+    const int gy = wrapi(lo[1] + (k / w[0]) % w[1], ny);
+    const int gz = wrapi(lo[2] + k / (w[0] * w[1]), nz);
+    const int n = gx + nx * gy + nxny * gz;
+    if (s.mask[n] != 0) continue;
+    const Nbr nb(gx, gy, gz, nx, ny, nz);
+    bool any = false;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) any |= (s.mask[nb(i)] == me);
+    if (!any) continue;
+    float drho = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) drho += IO::ld(sp_ + (unsigned)(i * N + n), wq(i) * rho0, 0.f);
+    const float rho = rho0 + drho;
+    const float phi = s.phi[n];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (s.mask[nb(i)] != me) continue;
+      const int o = opp(i);
+      const float sc_ = wq(i) * rho0;
+      T* fo = dp_ + (unsigned)(o * N + n);
+      T* go = dp_ + (unsigned)((Q + o) * N + n);
+      const float ds = IO::ld(fo, sc_, 0.f);  // f*_i bounced by k_fused
+      const double rx = wrapd((double)gx + 0.5 * cx(i) - P.x[0], (double)nx);
+      const double ry = wrapd((double)gy + 0.5 * cy(i) - P.x[1], (double)ny);
+      const double rz = wrapd((double)gz + 0.5 * cz(i) - P.x[2], (double)nz);
+      const double uwx = P.v[0] + (P.w[1] * rz - P.w[2] * ry);
+      const double uwy = P.v[1] + (P.w[2] * rx - P.w[0] * rz);
+      const double uwz = P.v[2] + (P.w[0] * ry - P.w[1] * rx);
+      const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));  // c_opp . u_w
+      const float corr = 6.0f * wq(i) * rho * cu;
+      const float dso = ds + corr;
+      IO::st(fo, dso, 1.0f / sc_);
+      IO::st(go, IO::ld(go, sc_, 0.f) + phi * corr, 1.0f / sc_);
+      const double wr = wqd(i) * (double)rho0;
+      const double fin = (double)ds + wr;
+      const double fout = (double)dso + wr;
+      const double dPx = (cx(i) - uwx) * fin - (-cx(i) - uwx) * fout;
+      const double dPy = (cy(i) - uwy) * fin - (-cy(i) - uwy) * fout;
+      const double dPz = (cz(i) - uwz) * fin - (-cz(i) - uwz) * fout;
+      acc[0] += dPx;
+      acc[1] += dPy;
+      acc[2] += dPz;
+      acc[3] += ry * dPz - rz * dPy;
+      acc[4] += rz * dPx - rx * dPz;
+      acc[5] += rx * dPy - ry * dPx;
+    }
+  }
+  __shared__ double red[6][256];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    DevParticle* Pw = s.P + p;
+    for (int k = 0; k < 3; ++k) {
+      atomicAdd(&Pw->Fh[k], red[k][0]);
+      atomicAdd(&Pw->Th[k], red[3 + k][0]);
+    }
+  }
+  (void)B;
 }
 
 // ------------------------------------------------------------ host launchers
 static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <int STORE>
-static hipError_t launch_fused_t(const SimDev& s, const void* src, void* dst, int mode, int LZ,
-                                 float* orho, float* ou, float* ophi, float* oF, hipStream_t st) {
-  if (s.nx >= 64) {
-    constexpr int TX = 64, TY = 4;
-    int ntx = (s.nx + TX - 1) / TX, nty = (s.ny + TY - 1) / TY, ntz = (s.nz + LZ - 1) / LZ;
-    dim3 grid(ntx * nty * ntz);
+hipError_t launch_interface(const SimDev& s, float4* nrm, float2* cur, hipStream_t st) {
+  const dim3 grid(nblocks(s.N, 256));
+  hipLaunchKernelGGL(k_normal, grid, dim3(256), 0, st, s, nrm);
+  hipLaunchKernelGGL(k_curv, grid, dim3(256), 0, st, s, (const float4*)nrm, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const SimDev& s, const void* src, void* dst, const float4* nrm,
+                        const float2* cur, int mode, float* orho, float* ou, float* ophi,
+                        float* oF, hipStream_t st) {
+  const dim3 grid(nblocks(s.N, 256));
+  if (s.storage == 0) {
     if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_fused<STORE, TX, TY, MODE_STEP>), grid, dim3(TX * TY), 0, st, s, src,
-                         dst, LZ, ntx, nty, ntz, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<0, MODE_STEP>), grid, dim3(256), 0, st, s, src, dst, nrm, cur,
+                         orho, ou, ophi, oF);
     else
-      hipLaunchKernelGGL((k_fused<STORE, TX, TY, MODE_FIELDS>), grid, dim3(TX * TY), 0, st, s,
-                         src, dst, LZ, ntx, nty, ntz, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<0, MODE_FIELDS>), grid, dim3(256), 0, st, s, src, dst, nrm,
+                         cur, orho, ou, ophi, oF);
   } else {
-    constexpr int TX = 32, TY = 8;
-    int ntx = (s.nx + TX - 1) / TX, nty = (s.ny + TY - 1) / TY, ntz = (s.nz + LZ - 1) / LZ;
-    dim3 grid(ntx * nty * ntz);
     if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_fused<STORE, TX, TY, MODE_STEP>), grid, dim3(TX * TY), 0, st, s, src,
-                         dst, LZ, ntx, nty, ntz, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<1, MODE_STEP>), grid, dim3(256), 0, st, s, src, dst, nrm, cur,
+                         orho, ou, ophi, oF);
     else
-      hipLaunchKernelGGL((k_fused<STORE, TX, TY, MODE_FIELDS>), grid, dim3(TX * TY), 0, st, s,
-                         src, dst, LZ, ntx, nty, ntz, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<1, MODE_FIELDS>), grid, dim3(256), 0, st, s, src, dst, nrm,
+                         cur, orho, ou, ophi, oF);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_fused(const SimDev& s, const void* src, void* dst, int mode, int LZ, float* orho,
-                        float* ou, float* ophi, float* oF, hipStream_t st) {
-  return s.storage == 0 ? launch_fused_t<0>(s, src, dst, mode, LZ, orho, ou, ophi, oF, st)
-                        : launch_fused_t<1>(s, src, dst, mode, LZ, orho, ou, ophi, oF, st);
+hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, hipStream_t st) {
+  if (s.np == 0) return hipSuccess;
+  const int B = Bmask + 2;
+  const dim3 grid((unsigned)((B * B * B + 255) / 256), s.np);
+  if (s.storage == 0)
+    hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, s, src, dst, B);
+  else
+    hipLaunchKernelGGL(k_links<1>, grid, dim3(256), 0, st, s, src, dst, B);
+  return hipGetLastError();
 }
 
 hipError_t launch_moments(const SimDev& s, const void* pops, hipStream_t st) {

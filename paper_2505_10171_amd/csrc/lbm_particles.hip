@@ -1,6 +1,8 @@
 // lbm_particles.hip -- particle kernels of liblbm for gfx950: solid mask update,
 // refilling of fresh fluid nodes, capillary force on the Lagrangian surface grid
 // and the DEM (contacts with sliding and rolling friction, velocity Verlet).
+#include <algorithm>
+
 #include "lbm_device.h"
 
 namespace lbm {
@@ -129,125 +131,89 @@ __global__ void k_cover(SimDev s) {
 // neighbour densities (fluid, not fresh, D3Q19 neighbours; rho0/2 each if none)
 // at the surface velocity of the particle that uncovered it.
 template <int STORE>
-__global__ void k_refill(SimDev s, void* pops) {
+__global__ __launch_bounds__(256) void k_refill(SimDev s, void* pops) {
+  // one thread per (fresh node, neighbour direction): 14 fresh nodes per block
   using IO = PIO<STORE>;
   using T = typename IO::T;
+  constexpr int PER = 14;
+  __shared__ float sh_a[PER][18], sh_b[PER][18];
+  __shared__ int sh_c[PER][18];
   T* b = (T*)pops;
   const uint32_t cnt = min(s.counters[0], s.fresh_cap);
   const long long N = s.N;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
-    const long long n = s.fresh[k];
-    const int p = (int)s.fresh_own[k];
-    const int x = (int)(n % s.nx), y = (int)((n / s.nx) % s.ny), z = (int)(n / ((long long)s.nx * s.ny));
-    float sa = 0.f, sb = 0.f;
-    int c = 0;
-    for (int i = 1; i < Q; ++i) {
-      const long long m = (long long)wrapi(x + cx(i), s.nx) +
-                          (long long)s.nx * ((long long)wrapi(y + cy(i), s.ny) +
-                                             (long long)s.ny * wrapi(z + cz(i), s.nz));
-      if (s.mask[m] != 0) continue;
-      float drho = 0.f, sg = 0.f;
-      for (int q = 0; q < Q; ++q) {
-        const float sc = wq(q) * s.rho0;
-        drho += IO::ld(b + (long long)q * N + m, sc);
-        sg += IO::ld(b + (long long)(Q + q) * N + m, sc);
+  const int slot = threadIdx.x / 18, dir = threadIdx.x % 18 + 1;
+  for (uint32_t base = blockIdx.x * PER; base < cnt; base += gridDim.x * PER) {
+    const uint32_t k = base + slot;
+    if (slot < PER) {
+      float ra = 0.f, rb = 0.f;
+      int c = 0;
+      if (k < cnt) {
+        const long long n = s.fresh[k];
+        const int x = (int)(n % s.nx), y = (int)((n / s.nx) % s.ny),
+                  z = (int)(n / ((long long)s.nx * s.ny));
+        const long long m = (long long)wrapi(x + cx(dir), s.nx) +
+                            (long long)s.nx * ((long long)wrapi(y + cy(dir), s.ny) +
+                                               (long long)s.ny * wrapi(z + cz(dir), s.nz));
+        if (s.mask[m] == 0) {
+          float drho = 0.f, sg = 0.f;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const float sc = wq(q) * s.rho0;
+            drho += IO::ld(b + (long long)q * N + m, sc);
+            sg += IO::ld(b + (long long)(Q + q) * N + m, sc);
+          }
+          const float rho = s.rho0 + drho;
+          ra = 0.5f * (rho + sg);
+          rb = 0.5f * (rho - sg);
+          c = 1;
+        }
       }
-      const float rho = s.rho0 + drho;
-      sa += 0.5f * (rho + sg);
-      sb += 0.5f * (rho - sg);
-      ++c;
+      sh_a[slot][dir - 1] = ra;
+      sh_b[slot][dir - 1] = rb;
+      sh_c[slot][dir - 1] = c;
     }
-    const float ra = c ? sa / c : 0.5f * s.rho0;
-    const float rb = c ? sb / c : 0.5f * s.rho0;
-    const DevParticle& P = s.P[p];
-    const double rx = wrapd((double)x - P.x[0], (double)s.nx);
-    const double ry = wrapd((double)y - P.x[1], (double)s.ny);
-    const double rz = wrapd((double)z - P.x[2], (double)s.nz);
-    const float ux = (float)(P.v[0] + P.w[1] * rz - P.w[2] * ry);
-    const float uy = (float)(P.v[1] + P.w[2] * rx - P.w[0] * rz);
-    const float uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
-    const float uu = ux * ux + uy * uy + uz * uz;
-    const float rho = ra + rb;
-    for (int q = 0; q < Q; ++q) {
-      const float cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
-      const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
-      const float sc = wq(q) * s.rho0;
-      const float dq = wq(q) * ((rho - s.rho0) + rho * poly);
-      const float gq = wq(q) * (ra - rb) * (1.0f + poly);
-      IO::st(b + (long long)q * N + n, dq, 1.0f / sc);
-      IO::st(b + (long long)(Q + q) * N + n, gq, 1.0f / sc);
+    __syncthreads();
+    if ((int)threadIdx.x < PER && base + threadIdx.x < cnt) {
+      const uint32_t kk = base + threadIdx.x;
+      float sa = 0.f, sb = 0.f;
+      int c = 0;
+      for (int i = 0; i < 18; ++i) {
+        sa += sh_a[threadIdx.x][i];
+        sb += sh_b[threadIdx.x][i];
+        c += sh_c[threadIdx.x][i];
+      }
+      const long long n = s.fresh[kk];
+      const int p = (int)s.fresh_own[kk];
+      const int x = (int)(n % s.nx), y = (int)((n / s.nx) % s.ny),
+                z = (int)(n / ((long long)s.nx * s.ny));
+      const float ra = c ? sa / c : 0.5f * s.rho0;
+      const float rb = c ? sb / c : 0.5f * s.rho0;
+      const DevParticle& P = s.P[p];
+      const double rx = wrapd((double)x - P.x[0], (double)s.nx);
+      const double ry = wrapd((double)y - P.x[1], (double)s.ny);
+      const double rz = wrapd((double)z - P.x[2], (double)s.nz);
+      const float ux = (float)(P.v[0] + P.w[1] * rz - P.w[2] * ry);
+      const float uy = (float)(P.v[1] + P.w[2] * rx - P.w[0] * rz);
+      const float uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
+      const float uu = ux * ux + uy * uy + uz * uz;
+      const float rho = ra + rb;
+      for (int q = 0; q < Q; ++q) {
+        const float cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
+        const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+        const float sc = wq(q) * s.rho0;
+        const float dq = wq(q) * ((rho - s.rho0) + rho * poly);
+        const float gq = wq(q) * (ra - rb) * (1.0f + poly);
+        IO::st(b + (long long)q * N + n, dq, 1.0f / sc);
+        IO::st(b + (long long)(Q + q) * N + n, gq, 1.0f / sc);
+      }
     }
+    __syncthreads();
   }
 }
 
 // -------------------------------------------------------------- capillary
-// Colour gradient with the wetting rotation at one node, from global phi/mask
-// (the same stencil, closure and rotation as the fused kernel).
-__device__ void node_gradient(const SimDev& s, int x, int y, int z, float& Gx, float& Gy, float& Gz) {
-  const long long n0 = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
-  const float p0 = s.phi[n0];
-  Gx = Gy = Gz = 0.f;
-  int minp = 0x7fffffff;
-  bool solid = false, wall = false;
-  constexpr int pd[9] = {1, 3, 5, 7, 8, 11, 12, 15, 16};
-  for (int q = 0; q < 9; ++q) {
-    const int i = pd[q];
-    const long long mp = (long long)wrapi(x + cx(i), s.nx) +
-                         (long long)s.nx * ((long long)wrapi(y + cy(i), s.ny) +
-                                            (long long)s.ny * wrapi(z + cz(i), s.nz));
-    const long long mm = (long long)wrapi(x - cx(i), s.nx) +
-                         (long long)s.nx * ((long long)wrapi(y - cy(i), s.ny) +
-                                            (long long)s.ny * wrapi(z - cz(i), s.nz));
-    const uint16_t kp = s.mask[mp], km = s.mask[mm];
-    const float vp = kp == 0 ? s.phi[mp] : p0;
-    const float vm = km == 0 ? s.phi[mm] : p0;
-    const float d = 3.0f * wq(i) * (vp - vm);
-    Gx += (float)cx(i) * d;
-    Gy += (float)cy(i) * d;
-    Gz += (float)cz(i) * d;
-    if (kp) {
-      solid = true;
-      if (kp >= 2) minp = min(minp, (int)kp - 2); else wall = true;
-    }
-    if (km) {
-      solid = true;
-      if (km >= 2) minp = min(minp, (int)km - 2); else wall = true;
-    }
-  }
-  if (!solid) return;
-  // wetting rotation (n_pm equation)
-  float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
-  if (!(g > EPS_G)) return;
-  float nsx, nsy, nsz, nc, ns;
-  if (minp != 0x7fffffff) {
-    const DevParticle& P = s.P[minp];
-    double dx = wrapd((double)x - P.x[0], (double)s.nx);
-    double dy = wrapd((double)y - P.x[1], (double)s.ny);
-    double dz = wrapd((double)z - P.x[2], (double)s.nz);
-    double dn = sqrt(dx * dx + dy * dy + dz * dz);
-    nsx = (float)(dx / dn);
-    nsy = (float)(dy / dn);
-    nsz = (float)(dz / dn);
-    nc = P.neg_cos_t;
-    ns = P.sin_t;
-  } else {
-    nsx = 0.f;
-    nsy = 0.f;
-    nsz = (z == 1) ? 1.f : -1.f;
-    nc = s.wall_neg_cos;
-    ns = s.wall_sin;
-  }
-  float a = Gx * nsx + Gy * nsy + Gz * nsz;
-  float tx = Gx - a * nsx, ty = Gy - a * nsy, tz = Gz - a * nsz;
-  float tn = sqrtf(tx * tx + ty * ty + tz * tz);
-  if (!(tn > EPS_GT)) return;
-  float it = 1.0f / tn;
-  Gx = g * (nc * nsx + ns * tx * it);
-  Gy = g * (nc * nsy + ns * ty * it);
-  Gz = g * (nc * nsz + ns * tz * it);
-}
-
 // per-particle box of (phi, G) at the nodes the Lagrangian points interpolate
+// (G after the wetting rotation, from the step's normal field)
 __global__ void k_capbox(SimDev s) {
   const int p = blockIdx.y;
   const DevParticle& P = s.P[p];
@@ -262,10 +228,11 @@ __global__ void k_capbox(SimDev s) {
     const int x = wrapi(org[0] + ix, s.nx), y = wrapi(org[1] + iy, s.ny), z = wrapi(org[2] + iz, s.nz);
     const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
     float4 v = make_float4(2.f, 0.f, 0.f, 0.f);  // phi = 2 marks a solid node
-    if (s.mask[n] == 0) {
-      float Gx, Gy, Gz;
-      node_gradient(s, x, y, z, Gx, Gy, Gz);
-      v = make_float4(s.phi[n], Gx, Gy, Gz);
+    const float4 nr = s.nrm[n];
+    if (nr.w >= 0.f) {
+      // G = n max(|G|, EPS_G): the colour gradient after the wetting rotation
+      const float gm = fmaxf(nr.w, EPS_G);
+      v = make_float4(s.phi[n], nr.x * gm, nr.y * gm, nr.z * gm);
     }
     box[k] = v;
   }
@@ -273,10 +240,11 @@ __global__ void k_capbox(SimDev s) {
 
 // Capillary force (capillary-force eq.): sum over the polar/azimuthal grid of
 // sigma 9/2 k beta max(0, 1 - phi^2) dA sin(theta_p) m^, m^ = normalise(n_s - (n.n_s) n),
-// torque arm R n_s; phi and G trilinear over fluid corners.  One workgroup per
-// particle, FP64 block reduction.
+// torque arm R n_s; phi and G trilinear over fluid corners.  A grid row of
+// workgroups per particle, FP64 block reductions combined with FP64 atomics
+// (the accumulators are consumed and cleared by the DEM).
 __global__ __launch_bounds__(256) void k_capillary(SimDev s) {
-  const int p = blockIdx.x;
+  const int p = blockIdx.y;
   DevParticle& P = s.P[p];
   const int B = s.cap_B;
   const float4* box = s.capbox + (long long)p * B * B * B;
@@ -286,7 +254,8 @@ __global__ __launch_bounds__(256) void k_capillary(SimDev s) {
   const double pref = s.cap_pref * (double)P.sin_t;
   const int na = s.cap_na, nph = s.cap_nphi;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int idx = threadIdx.x; idx < na * nph; idx += blockDim.x) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < na * nph;
+       idx += gridDim.x * blockDim.x) {
     const int j = idx / nph, k = idx % nph;
     const double al = (j + 0.5) * da, ph = k * da;
     double sa, ca, sp, cp;
@@ -347,8 +316,8 @@ __global__ __launch_bounds__(256) void k_capillary(SimDev s) {
   }
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
-      P.Fcap[k] = red[k][0];
-      P.Tcap[k] = red[3 + k][0];
+      atomicAdd(&P.Fca[k], red[k][0]);
+      atomicAdd(&P.Tca[k], red[3 + k][0]);
     }
   }
 }
@@ -477,6 +446,10 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
   for (int i = threadIdx.x; i < np; i += nt) {
     DevParticle& P = s.P[i];
     for (int d = 0; d < 3; ++d) {
+      P.Fcap[d] = P.Fca[d];
+      P.Tcap[d] = P.Tca[d];
+      P.Fca[d] = 0.0;
+      P.Tca[d] = 0.0;
       const double fc = P.Fh[d] + P.Fcap[d], tc = P.Th[d] + P.Tcap[d];
       const double fp = P.havep ? P.Ffp[d] : fc, tp = P.havep ? P.Tfp[d] : tc;
       P.Ff[d] = 0.5 * (fc + fp);
@@ -664,8 +637,8 @@ hipError_t launch_mask_update(const SimDev& s, int Bmask, bool with_release, hip
 
 hipError_t launch_refill(const SimDev& s, void* pops, hipStream_t st) {
   if (s.np == 0) return hipSuccess;
-  unsigned nb = (s.fresh_cap + 255) / 256;
-  if (nb > 256) nb = 256;
+  unsigned nb = (s.fresh_cap + 13) / 14;
+  if (nb > 128) nb = 128;
   if (nb == 0) nb = 1;
   if (s.storage == 0)
     hipLaunchKernelGGL(k_refill<0>, dim3(nb), dim3(256), 0, st, s, pops);
@@ -677,7 +650,9 @@ hipError_t launch_refill(const SimDev& s, void* pops, hipStream_t st) {
 hipError_t launch_capillary(const SimDev& s, hipStream_t st) {
   if (s.np == 0) return hipSuccess;
   hipLaunchKernelGGL(k_capbox, dim3(box_blocks(s.cap_B), s.np), dim3(256), 0, st, s);
-  hipLaunchKernelGGL(k_capillary, dim3(s.np), dim3(256), 0, st, s);
+  const int npts = s.cap_na * s.cap_nphi;
+  const unsigned split = (unsigned)std::max(1, std::min(64, npts / (256 * 4)));
+  hipLaunchKernelGGL(k_capillary, dim3(split, s.np), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ HIST_DOUBLES = 27
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_sync", "lbm_particles_sync",
            "lbm_fields", "lbm_fields2", "lbm_links", "lbm_mass", "lbm_dem_substeps", "lbm_destroy",
            "lbm_last_error", "lbm_profile", "lbm_profile_read"]
-PROFILE_KINDS = ("fused", "particles", "moments")
+PROFILE_KINDS = ("fused", "particles", "moments", "interface")
 
 
 class LbmConfig(C.Structure):
@@ -294,7 +294,8 @@ class Context:
         self._check(load_library().lbm_profile(self.h, 1 if enable else 0))
 
     def profile_read(self):
-        """{kind: (total_ms, launches)} for the fused, particle and moments phases."""
+        """{kind: (total_ms, launches)} for the fused, particle, moments and
+        interface phases."""
         n = len(PROFILE_KINDS)
         ms = (C.c_double * n)()
         cnt = (C.c_int64 * n)()
