@@ -124,8 +124,10 @@ size_t lbm_workspace_bytes(const lbm_config* cfg, int32_t n_sims,
  * values, or NULL for phi = +1 everywhere) and the particles (per simulation
  * cfg[s].n_particles host records, state at rest is allowed), sets the fluid at
  * rest with f_a = w rho0 (1+phi0)/2, f_b = w rho0 (1-phi0)/2, builds the solid
- * mask and computes the first moments.  hip_stream is a hipStream_t (NULL: the
- * null stream).  On success *out owns the context. */
+ * mask and computes the first moments.  The workspace must be 256-byte aligned
+ * and at least lbm_workspace_bytes long (LBM_EINVAL / LBM_ENOMEM otherwise).
+ * hip_stream is a hipStream_t (NULL: the null stream).  On success *out owns the
+ * context. */
 int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
                const lbm_particle* const* parts, int32_t history_steps,
                void* dev_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);

@@ -316,6 +316,8 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     return fail(LBM_EINVAL, msg);
   }
   if (ws_bytes < need) return fail(LBM_ENOMEM, "workspace too small");
+  if (((uintptr_t)dev_workspace) % ALIGN != 0)
+    return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
   ctx->sims.resize(n_sims);
   size_t off = 0;
   for (int si = 0; si < n_sims; ++si) {

@@ -467,12 +467,13 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
 // particle over the nodes of its bounding box grown by one.
 template <int STORE>
 __global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict__ src,
-                                              void* __restrict__ dst, int B) {
+                                              void* __restrict__ dst) {
+  // one thread per (node of the particle's box, direction 1..18)
   using IO = PopIO<STORE>;
   using T = typename IO::T;
   const int p = blockIdx.y;
   const DevParticle& P = s.P[p];
-  const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny, N = (int)s.N;
+  const int nx = s.nx, ny = s.ny, nz = s.nz, N = (int)s.N;
   const float rho0 = s.rho0;
   int lo[3], w[3];
   const int L[3] = {nx, ny, nz};
@@ -486,34 +487,30 @@ __global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict_
     }
   }
   const int vol = w[0] * w[1] * w[2];
-  const T* __restrict__ sp_ = (const T*)src;
-  T* __restrict__ dp_ = (T*)dst;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = t / 18, i = 1 + t - 18 * (t / 18);
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  const uint16_t me = (uint16_t)(2 + p);
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < vol; k += gridDim.x * blockDim.x) {
+  if (k < vol) {
     const int gx = wrapi(lo[0] + k % w[0], nx);
     const int gy = wrapi(lo[1] + (k / w[0]) % w[1], ny);
     const int gz = wrapi(lo[2] + k / (w[0] * w[1]), nz);
-    const int n = gx + nx * gy + nxny * gz;
-    if (s.mask[n] != 0) continue;
-    const Nbr nb(gx, gy, gz, nx, ny, nz);
-    bool any = false;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) any |= (s.mask[nb(i)] == me);
-    if (!any) continue;
-    float drho = 0.f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) drho += IO::ld(sp_ + (unsigned)(i * N + n), wq(i) * rho0, 0.f);
-    const float rho = rho0 + drho;
-    const float phi = s.phi[n];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if (s.mask[nb(i)] != me) continue;
+    const int n = gx + nx * (gy + ny * gz);
+    const int m = wrapi(gx + cx(i), nx) + nx * (wrapi(gy + cy(i), ny) + ny * wrapi(gz + cz(i), nz));
+    const uint16_t mn = s.mask[n], mm = s.mask[m];
+    if (mn == 0 && mm == (uint16_t)(2 + p)) {
+      const T* __restrict__ sp_ = (const T*)src;
+      T* __restrict__ dp_ = (T*)dst;
       const int o = opp(i);
       const float sc_ = wq(i) * rho0;
       T* fo = dp_ + (unsigned)(o * N + n);
       T* go = dp_ + (unsigned)((Q + o) * N + n);
       const float ds = IO::ld(fo, sc_, 0.f);  // f*_i bounced by k_fused
+      const float gs = IO::ld(go, sc_, 0.f);
+      const float phi = s.phi[n];
+      float drho = 0.f;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) drho += IO::ld(sp_ + (unsigned)(q * N + n), wq(q) * rho0, 0.f);
+      const float rho = rho0 + drho;
       const double rx = wrapd((double)gx + 0.5 * cx(i) - P.x[0], (double)nx);
       const double ry = wrapd((double)gy + 0.5 * cy(i) - P.x[1], (double)ny);
       const double rz = wrapd((double)gz + 0.5 * cz(i) - P.x[2], (double)nz);
@@ -524,38 +521,41 @@ __global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict_
       const float corr = 6.0f * wq(i) * rho * cu;
       const float dso = ds + corr;
       IO::st(fo, dso, 1.0f / sc_);
-      IO::st(go, IO::ld(go, sc_, 0.f) + phi * corr, 1.0f / sc_);
+      IO::st(go, gs + phi * corr, 1.0f / sc_);
       const double wr = wqd(i) * (double)rho0;
       const double fin = (double)ds + wr;
       const double fout = (double)dso + wr;
       const double dPx = (cx(i) - uwx) * fin - (-cx(i) - uwx) * fout;
       const double dPy = (cy(i) - uwy) * fin - (-cy(i) - uwy) * fout;
       const double dPz = (cz(i) - uwz) * fin - (-cz(i) - uwz) * fout;
-      acc[0] += dPx;
-      acc[1] += dPy;
-      acc[2] += dPz;
-      acc[3] += ry * dPz - rz * dPy;
-      acc[4] += rz * dPx - rx * dPz;
-      acc[5] += rx * dPy - ry * dPx;
+      acc[0] = dPx;
+      acc[1] = dPy;
+      acc[2] = dPz;
+      acc[3] = ry * dPz - rz * dPy;
+      acc[4] = rz * dPx - rx * dPz;
+      acc[5] = rx * dPy - ry * dPx;
     }
   }
-  __shared__ double red[6][256];
+  // wave reduction, then across the block's waves
 #pragma unroll
-  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  for (int c = 0; c < 6; ++c)
+    for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+  __shared__ double red[4][6];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 6; ++c) red[wave][c] = acc[c];
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o)
-      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    DevParticle* Pw = s.P + p;
-    for (int k = 0; k < 3; ++k) {
-      atomicAdd(&Pw->Fh[k], red[k][0]);
-      atomicAdd(&Pw->Th[k], red[3 + k][0]);
+  if (threadIdx.x < 6) {
+    const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                     red[3][threadIdx.x];
+    if (v != 0.0) {
+      DevParticle* Pw = s.P + p;
+      if (threadIdx.x < 3)
+        atomicAdd(&Pw->Fh[threadIdx.x], v);
+      else
+        atomicAdd(&Pw->Th[threadIdx.x - 3], v);
     }
   }
-  (void)B;
 }
 
 // ------------------------------------------------------------ host launchers
@@ -592,12 +592,13 @@ hipError_t launch_fused(const SimDev& s, const void* src, void* dst, const float
 
 hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, hipStream_t st) {
   if (s.np == 0) return hipSuccess;
-  const int B = Bmask + 2;
-  const dim3 grid((unsigned)((B * B * B + 255) / 256), s.np);
+  // the box of k_links spans at most 2 R + 6 nodes per axis, R <= (Bmask - 5) / 2
+  const long long B = Bmask + 1;
+  const dim3 grid((unsigned)((B * B * B * 18 + 255) / 256), s.np);
   if (s.storage == 0)
-    hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, s, src, dst, B);
+    hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, s, src, dst);
   else
-    hipLaunchKernelGGL(k_links<1>, grid, dim3(256), 0, st, s, src, dst, B);
+    hipLaunchKernelGGL(k_links<1>, grid, dim3(256), 0, st, s, src, dst);
   return hipGetLastError();
 }
 

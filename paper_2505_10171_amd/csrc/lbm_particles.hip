@@ -435,7 +435,27 @@ __device__ void quat_rotate(double* q, const double* th) {
 // One workgroup per simulation.  Fluid forces (momentum exchange + capillary)
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
+template <bool SH>
 __global__ __launch_bounds__(256) void k_dem(SimDev s) {
+  // SH: particle records, contact tables and candidate lists staged in LDS
+  // for the whole lattice step (dependent FP64 chains then wait on LDS, not
+  // on L2/HBM), written back at the end
+  extern __shared__ double dem_lds[];
+  DevParticle* PP = s.P;
+  Contact* CT = s.ct;
+  int* NB = s.nb;
+  const size_t wP = (size_t)s.np * sizeof(DevParticle) / 8;
+  const size_t wC = (size_t)s.np * MAXC * sizeof(Contact) / 8;
+  if (SH) {
+    double* lp = dem_lds;
+    double* lc = lp + wP;
+    PP = (DevParticle*)lp;
+    CT = (Contact*)lc;
+    NB = (int*)(lc + wC);
+    for (size_t k = threadIdx.x; k < wP; k += blockDim.x) lp[k] = ((const double*)s.P)[k];
+    for (size_t k = threadIdx.x; k < wC; k += blockDim.x) lc[k] = ((const double*)s.ct)[k];
+    __syncthreads();
+  }
   const int np = s.np;
   const int nt = blockDim.x;
   const double dt = 1.0 / s.n_sub;
@@ -444,7 +464,7 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
   // fluid force and torque: mean of this and the previous lattice step (the
   // averaging of the Verlet update over the previous and current step)
   for (int i = threadIdx.x; i < np; i += nt) {
-    DevParticle& P = s.P[i];
+    DevParticle& P = PP[i];
     for (int d = 0; d < 3; ++d) {
       P.Fcap[d] = P.Fca[d];
       P.Tcap[d] = P.Tca[d];
@@ -471,12 +491,12 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
   __syncthreads();
   // pair candidates within Rc_i + Rc_j + skin (ascending index)
   for (int i = threadIdx.x; i < np; i += nt) {
-    const DevParticle& P = s.P[i];
-    int* nb = s.nb + (long long)i * MAXNB;
+    const DevParticle& P = PP[i];
+    int* nb = NB + (long long)i * MAXNB;
     int c = 0;
     for (int j = 0; j < np; ++j) {
       if (j == i) continue;
-      const DevParticle& Pj = s.P[j];
+      const DevParticle& Pj = PP[j];
       double dx[3];
       rel_vec(s, P.x, Pj.x, dx);
       const double lim = P.Rc + Pj.Rc + skin;
@@ -489,7 +509,7 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
     }
     if (c < MAXNB) nb[c] = -1;
     // free pair springs whose partner is out of range
-    Contact* tab = s.ct + (long long)i * MAXC;
+    Contact* tab = CT + (long long)i * MAXC;
     for (int k = 0; k < MAXC; ++k) {
       const int pt = tab[k].partner;
       if (pt < 0) continue;
@@ -501,7 +521,7 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
   __syncthreads();
   for (int sub = 0; sub < s.n_sub; ++sub) {
     for (int i = threadIdx.x; i < np; i += nt) {
-      DevParticle& P = s.P[i];
+      DevParticle& P = PP[i];
       double th[3];
       for (int d = 0; d < 3; ++d) {
         if (P.kin) {
@@ -528,8 +548,8 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < np; i += nt) {
-      DevParticle& P = s.P[i];
-      Contact* tab = s.ct + (long long)i * MAXC;
+      DevParticle& P = PP[i];
+      Contact* tab = CT + (long long)i * MAXC;
       const double Rci = P.Rc;
       const double zero[3] = {0, 0, 0};
       double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0}, Fo[3], To[3];
@@ -550,11 +570,11 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
             Ts[d] += To[d];
           }
       }
-      const int* nb = s.nb + (long long)i * MAXNB;
+      const int* nb = NB + (long long)i * MAXNB;
       for (int q = 0; q < MAXNB; ++q) {
         const int j = nb[q];
         if (j < 0) break;
-        const DevParticle& Pj = s.P[j];
+        const DevParticle& Pj = PP[j];
         const double Rcj = Pj.Rc;
         double dx[3];
         rel_vec(s, P.x, Pj.x, dx);
@@ -577,7 +597,7 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < np; i += nt) {
-      DevParticle& P = s.P[i];
+      DevParticle& P = PP[i];
       for (int d = 0; d < 3; ++d) {
         if (!P.kin) {
           const double an = (P.Ff[d] + P.Fcn[d]) / P.mass;
@@ -595,7 +615,7 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
   }
   const unsigned long long step = *s.step_counter;
   for (int i = threadIdx.x; i < np; i += nt) {
-    DevParticle& P = s.P[i];
+    DevParticle& P = PP[i];
     for (int d = 0; d < 3; ++d) {
       P.Fcon[d] = P.Facc[d] / s.n_sub;
       P.Tcon[d] = P.Tacc[d] / s.n_sub;
@@ -617,6 +637,10 @@ __global__ __launch_bounds__(256) void k_dem(SimDev s) {
     }
   }
   __syncthreads();
+  if (SH) {
+    for (size_t k = threadIdx.x; k < wP; k += blockDim.x) ((double*)s.P)[k] = dem_lds[k];
+    for (size_t k = threadIdx.x; k < wC; k += blockDim.x) ((double*)s.ct)[k] = dem_lds[wP + k];
+  }
   if (threadIdx.x == 0) *s.step_counter = step + 1;
 }
 
@@ -658,7 +682,20 @@ hipError_t launch_capillary(const SimDev& s, hipStream_t st) {
 
 hipError_t launch_dem(const SimDev& s, hipStream_t st) {
   if (s.np == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, st, s);
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 0;
+    max_lds = v;
+  }
+  const size_t need = (size_t)s.np * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
+                      (size_t)s.np * MAXNB * sizeof(int);
+  if (need <= (size_t)max_lds && need <= 64 * 1024)
+    hipLaunchKernelGGL(k_dem<true>, dim3(1), dim3(256), need, st, s);
+  else
+    hipLaunchKernelGGL(k_dem<false>, dim3(1), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 
