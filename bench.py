@@ -12,7 +12,6 @@ inside the timed steps, and the FP64 CPU oracle timed on a bounded sample of the
 same workload on this host.
 """
 import argparse
-import hashlib
 import json
 import os
 import re
@@ -24,24 +23,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (f+g+particles) & % HBM peak; ensemble runs/hour at ≤1e-3 error"
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "k_fused_drop_sweep_256x128x96_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2505_10171_amd", "csrc", "lbm_fluid.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "k_fused_drop_sweep_256x128x96_fp32_counters.txt")
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
-def traffic_from_profile(n_launch_nodes):
+def traffic_from_profile():
     """HBM bytes per k_fused launch from the committed rocprofv3 counter
-    summary, or None if it is missing or was taken on a different kernel."""
+    summary, or None if it is missing or was taken on different kernel sources."""
+    from paper_2505_10171_amd.prof_summary import kernel_sources_hash
     if not os.path.exists(COUNTERS):
         return None
     txt = open(COUNTERS).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_hash():
+    if not m or not b or m.group(1) != kernel_sources_hash():
         return None
     return float(b.group(1))
 
@@ -68,7 +62,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter scaling)")
@@ -114,15 +108,20 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     mlups = N * args.steps / (t1 - t0) / 1e6
 
-    # algorithmic bytes of one k_fused launch: 38 populations read and written
-    # per fluid node (4 B, or 2 B in FP16 storage), phi (4 B) and mask (2 B)
-    # read per node
+    # algorithmic bytes of one k_fused launch.  Per fluid node: the 19 total
+    # populations read (the collision needs f only; the colour enters through
+    # phi), all 38 populations written (4 B each, 2 B in FP16 storage), the
+    # interface normal (12 B), the curvature term + solid-link word (8 B) and
+    # phi (4 B) read; FP16 adds the references: the node's own density for
+    # decoding (4 B) and the (rho, phi) references of the nodes written to
+    # (8 B per node).  Per solid node the link word.
     pop_b = 2 if args.storage == "fp16" else 4
-    alg_bytes = n_fluid * 38 * pop_b * 2 + N * (4 + 2)
+    ref_b = 12 if args.storage == "fp16" else 0
+    alg_bytes = n_fluid * (19 * pop_b + 38 * pop_b + 12 + 8 + 4 + ref_b) + (N - n_fluid) * 8
     fused_ms, fused_n = prof["fused"]
     t_fused = fused_ms / max(fused_n, 1) * 1e-3
     achieved = alg_bytes / t_fused / 1e9
-    traffic = traffic_from_profile(N) if args.storage == "fp32" else None
+    traffic = traffic_from_profile() if args.storage == "fp32" else None
     # whole-step effective fraction: B_alg per node-step (populations r+w, phi
     # w+r, mask r) at the measured MLUPS
     b_alg_node = 38 * pop_b * 2 + 8 + 2

@@ -57,7 +57,9 @@ enum lbm_status {
 
 enum lbm_storage {
   LBM_STORE_FP32 = 0, /* populations stored as FP32 deviations f - w rho0, g  */
-  LBM_STORE_FP16 = 1  /* FP16 scaled offsets f/(w rho0) - 1, g/(w rho0)       */
+  LBM_STORE_FP16 = 1  /* FP16: h = (f - w R)/(w rho0), k = (g - P f)/(w rho0)
+                         with (R, P) the node's density and order parameter
+                         of the previous step; FP32 arithmetic               */
 };
 
 enum lbm_field_bits {
@@ -66,7 +68,10 @@ enum lbm_field_bits {
   LBM_F_PHI = 4u,  /* order parameter (order-parameter eq.)         (float) */
   LBM_F_MASK = 8u, /* solid mask                                 (uint16_t) */
   LBM_F_POPS = 16u, /* raw stored populations: 38 planes of N values in the
-                       storage type (19 of f, then 19 of g)                 */
+                       storage type.  FP32: 19 planes of f - w rho0, then 19
+                       of g = f^a - f^b.  FP16: the encoded pairs (h, g/f)
+                       of LBM_STORE_FP16 (the reference densities are
+                       internal)                                           */
   LBM_F_FORCE = 32u  /* force per volume: CSF surface tension (CSF eq.) plus
                        the body force on fluid a                    (float) */
 };

@@ -25,15 +25,16 @@
 namespace lbm {
 hipError_t launch_interface(const SimDev& s, float4* nrm, float2* cur, hipStream_t st);
 hipError_t launch_fused(const SimDev& s, const void* src, void* dst, const float4* nrm,
-                        const float2* cur, int mode, float* orho, float* ou, float* ophi,
+                        const float2* cur, int mode, int rd, float* orho, float* ou, float* ophi,
                         float* oF, hipStream_t st);
-hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, hipStream_t st);
-hipError_t launch_moments(const SimDev& s, const void* pops, hipStream_t st);
+hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, int rd,
+                        hipStream_t st);
+hipError_t launch_moments(const SimDev& s, const void* pops, int rd, hipStream_t st);
 hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
 hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
-hipError_t launch_mass(const SimDev& s, const void* pops, hipStream_t st);
+hipError_t launch_mass(const SimDev& s, const void* pops, int rd, hipStream_t st);
 hipError_t launch_mask_update(const SimDev& s, int Bmask, bool with_release, hipStream_t st);
-hipError_t launch_refill(const SimDev& s, void* pops, hipStream_t st);
+hipError_t launch_refill(const SimDev& s, void* pops, int rd, hipStream_t st);
 hipError_t launch_capillary(const SimDev& s, hipStream_t st);
 hipError_t launch_dem(const SimDev& s, hipStream_t st);
 }  // namespace lbm
@@ -51,7 +52,7 @@ struct SimLayout {
   long long N;
   int np, Bmask, Bcap, hist_cap;
   size_t pop_bytes, fresh_cap;
-  size_t off_pops0, off_pops1, off_phi, off_nrm, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
+  size_t off_pops0, off_pops1, off_ref0, off_ref1, off_phi, off_nrm, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
       off_counters, off_P, off_ct, off_nb, off_hist, off_capbox, off_caporg, off_mass, off_step;
   size_t total;
 };
@@ -122,6 +123,10 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   };
   L.off_pops0 = take(L.pop_bytes);
   L.off_pops1 = take(L.pop_bytes);
+  // FP16 storage: two per-node references (rho, phi) (ping-pong)
+  const size_t ref_bytes = c.storage == LBM_STORE_FP16 ? 8 * (size_t)L.N : 0;
+  L.off_ref0 = take(ref_bytes);
+  L.off_ref1 = take(ref_bytes);
   L.off_phi = take(4 * L.N);
   L.off_nrm = take(16 * L.N);
   L.off_cur = take(8 * L.N);
@@ -203,6 +208,7 @@ struct SimHost {
   float4* nrm;  // per node (n, |G|): interface normal and gradient magnitude
   float2* curv;  // per node (c, solid-direction bits): CSF coefficient
   int cur;  // index of the population buffer holding the current state
+  int rd;   // FP16: index of the references the current state is encoded with
   int LZ;
   double Rmax;
 };
@@ -268,9 +274,9 @@ static int post_dem_pipeline(lbm_ctx* ctx, SimHost& sh, bool with_release) {
   void* cur = s.pops[sh.cur];
   if (s.np > 0) {
     HIPCHK(ctx, launch_mask_update(s, sh.L.Bmask, with_release, ctx->stream));
-    HIPCHK(ctx, launch_refill(s, cur, ctx->stream));
+    HIPCHK(ctx, launch_refill(s, cur, sh.rd, ctx->stream));
   }
-  HIPCHK(ctx, launch_moments(s, cur, ctx->stream));
+  HIPCHK(ctx, launch_moments(s, cur, sh.rd, ctx->stream));
   return LBM_OK;
 }
 
@@ -356,6 +362,12 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     char* b = ctx->ws;
     d.pops[0] = b + sh.L.off_pops0;
     d.pops[1] = b + sh.L.off_pops1;
+    if (c.storage == LBM_STORE_FP16) {
+      d.ref[0] = (float2*)(b + sh.L.off_ref0);
+      d.ref[1] = (float2*)(b + sh.L.off_ref1);
+    } else {
+      d.ref[0] = d.ref[1] = nullptr;
+    }
     d.phi = (float*)(b + sh.L.off_phi);
     sh.nrm = (float4*)(b + sh.L.off_nrm);
     d.nrm = sh.nrm;
@@ -389,6 +401,7 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.mass_acc = (double*)(b + sh.L.off_mass);
     d.step_counter = (unsigned long long*)(b + sh.L.off_step);
     sh.cur = 0;
+    sh.rd = 0;
     sh.LZ = choose_LZ(d);
 
     // upload particles and contact tables
@@ -433,7 +446,7 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
       return fail(LBM_EHIP, "mask build failed");
     if (launch_init_pops(d, d.pops[0], st) != hipSuccess)
       return fail(LBM_EHIP, "population init failed");
-    if (launch_moments(d, d.pops[0], st) != hipSuccess) return fail(LBM_EHIP, "moments failed");
+    if (launch_moments(d, d.pops[0], 0, st) != hipSuccess) return fail(LBM_EHIP, "moments failed");
     if (phi0 && phi0[si]) {
       // the host buffer must stay valid until the copy has completed
       if (hipStreamSynchronize(st) != hipSuccess) return fail(LBM_EHIP, "synchronise failed");
@@ -479,20 +492,21 @@ int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
       }
       HIPCHK(ctx, launch_interface(s, sh.nrm, sh.curv, ctx->stream));
       if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][1], ctx->stream));
-      HIPCHK(ctx, launch_fused(s, src, dst, sh.nrm, sh.curv, 0, nullptr, nullptr, nullptr, nullptr,
+      HIPCHK(ctx, launch_fused(s, src, dst, sh.nrm, sh.curv, 0, sh.rd, nullptr, nullptr, nullptr, nullptr,
                                ctx->stream));
       if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], ctx->stream));
-      HIPCHK(ctx, launch_links(s, src, dst, sh.L.Bmask, ctx->stream));
+      HIPCHK(ctx, launch_links(s, src, dst, sh.L.Bmask, sh.rd, ctx->stream));
       sh.cur ^= 1;
+      sh.rd ^= 1;
       void* cur = s.pops[sh.cur];
       if (s.np > 0) {
         HIPCHK(ctx, launch_capillary(s, ctx->stream));
         HIPCHK(ctx, launch_dem(s, ctx->stream));
         HIPCHK(ctx, launch_mask_update(s, sh.L.Bmask, true, ctx->stream));
-        HIPCHK(ctx, launch_refill(s, cur, ctx->stream));
+        HIPCHK(ctx, launch_refill(s, cur, sh.rd, ctx->stream));
       }
       if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], ctx->stream));
-      HIPCHK(ctx, launch_moments(s, cur, ctx->stream));
+      HIPCHK(ctx, launch_moments(s, cur, sh.rd, ctx->stream));
       if (slot >= 0) {
         HIPCHK(ctx, hipEventRecord(P.ev[slot][4], ctx->stream));
         P.pending[slot] = true;
@@ -674,7 +688,7 @@ int lbm_fields2(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, 
     float* ou = scratch + 2 * N;
     float* oF = scratch + 5 * N;
     HIPCHK(ctx, launch_interface(d, sh->nrm, sh->curv, ctx->stream));
-    HIPCHK(ctx, launch_fused(d, d.pops[sh->cur], nullptr, sh->nrm, sh->curv, 1, orho, ou, ophi,
+    HIPCHK(ctx, launch_fused(d, d.pops[sh->cur], nullptr, sh->nrm, sh->curv, 1, sh->rd, orho, ou, ophi,
                              oF, ctx->stream));
     if ((what & LBM_F_FORCE) && force)
       HIPCHK(ctx, hipMemcpyAsync(force, oF, 12 * N, kind, ctx->stream));
@@ -731,7 +745,7 @@ int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]) {
   if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
   SimDev& d = sh->d;
   HIPCHK(ctx, hipMemsetAsync(d.mass_acc, 0, 2 * sizeof(double), ctx->stream));
-  HIPCHK(ctx, launch_mass(d, d.pops[sh->cur], ctx->stream));
+  HIPCHK(ctx, launch_mass(d, d.pops[sh->cur], sh->rd, ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(out, d.mass_acc, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   return lbm_sync(ctx);
 }

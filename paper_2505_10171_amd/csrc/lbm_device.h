@@ -77,6 +77,61 @@ struct Contact {
 };
 
 // ------------------------------------------------------------- simulation
+// ------------------------------------------------------ population codecs
+// Every population i of a node is held as a pair (d, g): d = f_i - w_i rho0 the
+// deviation of the total population from rest, g = f^a_i - f^b_i the colour
+// population.  Arguments: wr0 = w_i rho0; for FP16 the node's reference
+// (R, P) enters as wR = w_i R and P.
+//
+// FP32: d and g stored as they are.
+// FP16: h = (f - w_i R) / wr0 and k = (g - P f) / wr0, with (R, P) the node's
+// density and order parameter of the previous step.  h and k then hold only
+// the parts of f and g that the previous state does not predict (velocity,
+// non-equilibrium, interface motion), not the Laplace pressure offset or the
+// bulk colour, and keep FP16's relative precision for them.  In the bulk of
+// either fluid (P = +-1, g = +-f) k is exactly 0, so g = +-f and phi = +-1 hold
+// exactly after decoding.
+template <int STORE>
+struct Codec;
+
+template <>
+struct Codec<0> {
+  using T = float;
+  static __device__ __forceinline__ void ld(const T* pd, const T* pg, float, float, float,
+                                            float& d, float& g) {
+    d = *pd;
+    g = *pg;
+  }
+  static __device__ __forceinline__ float ld_d(const T* pd, float, float) { return *pd; }
+  static __device__ __forceinline__ void st(T* pd, T* pg, float, float, float, float d, float g) {
+    *pd = d;
+    *pg = g;
+  }
+};
+
+template <>
+struct Codec<1> {
+  using T = __half;
+  static __device__ __forceinline__ float f_of(const T* pd, float wr0, float wR) {
+    return __fadd_rn(wR, __fmul_rn(wr0, __half2float(*pd)));
+  }
+  static __device__ __forceinline__ void ld(const T* pd, const T* pg, float wr0, float wR, float P,
+                                            float& d, float& g) {
+    const float f = f_of(pd, wr0, wR);
+    d = __fsub_rn(f, wr0);
+    g = __fadd_rn(__fmul_rn(P, f), __fmul_rn(wr0, __half2float(*pg)));
+  }
+  static __device__ __forceinline__ float ld_d(const T* pd, float wr0, float wR) {
+    return __fsub_rn(f_of(pd, wr0, wR), wr0);
+  }
+  static __device__ __forceinline__ void st(T* pd, T* pg, float wr0, float wR, float P, float d,
+                                            float g) {
+    const float f = __fadd_rn(d, wr0);
+    *pd = __float2half_rn(__fdividef(f - wR, wr0));
+    *pg = __float2half_rn(__fdividef(__fsub_rn(g, __fmul_rn(P, f)), wr0));
+  }
+};
+
 struct SimDev {
   int nx, ny, nz, has_wall;
   long long N;
@@ -86,6 +141,7 @@ struct SimDev {
   float wall_neg_cos, wall_sin;
   // fields
   void* pops[2];       // ping-pong population buffers: 38 planes of N
+  float2* ref[2];      // FP16 storage: per-node reference (rho, phi), ping-pong
   float* phi;          // order parameter of the current state (PHI_SOLID at solids)
   float4* nrm;         // per node (n, |G|) of the current state; w = -1 at solids
   uint16_t* mask;      // 0 fluid, 1 wall, 2+p particle p; FRESH_BIT while refilling

@@ -16,28 +16,6 @@
 
 namespace lbm {
 
-// ------------------------------------------------------- population storage
-template <int STORE>
-struct PopIO;
-
-template <>
-struct PopIO<0> {
-  using T = float;
-  static __device__ __forceinline__ float ld(const T* p, float, float) { return *p; }
-  static __device__ __forceinline__ void st(T* p, float v, float) { *p = v; }
-};
-template <>
-struct PopIO<1> {
-  using T = __half;
-  // value = stored * scale ; stored = value * inv_scale
-  static __device__ __forceinline__ float ld(const T* p, float scale, float) {
-    return __half2float(*p) * scale;
-  }
-  static __device__ __forceinline__ void st(T* p, float v, float inv_scale) {
-    *p = __float2half_rn(v * inv_scale);
-  }
-};
-
 // ------------------------------------------------------------ wetting rotation
 // Geometric wetting (n_pm equation): at a fluid node with a solid neighbour the
 // colour gradient is rotated to make the angle theta (through fluid a) with the
@@ -92,8 +70,10 @@ __host__ __device__ constexpr int pair_dir(int k) {
 // after the refill of fresh nodes; clears their FRESH mark.  Solid nodes get
 // the sentinel PHI_SOLID, so stencils can tell solids from phi alone.
 template <int STORE>
-__global__ __launch_bounds__(256) void k_moments(SimDev s, const void* __restrict__ pops) {
-  using IO = PopIO<STORE>;
+__global__ __launch_bounds__(256) void k_moments(SimDev s, const void* __restrict__ pops,
+                                                const float2* __restrict__ rdec,
+                                                float2* __restrict__ rnext) {
+  using IO = Codec<STORE>;
   using T = typename IO::T;
   const long long N = s.N;
   long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,24 +84,29 @@ __global__ __launch_bounds__(256) void k_moments(SimDev s, const void* __restric
     m = (uint16_t)(m & ~FRESH_BIT);
     s.mask[n] = m;
   }
-  float out = 0.f;
+  float out = PHI_SOLID, rho = s.rho0;
   if (m == 0) {
     const T* b = (const T*)pops;
+    const float2 R = STORE ? rdec[n] : make_float2(0.f, 0.f);
     // phi = sum g / sum f with f_i = d_i + w_i rho0 rounded exactly as the
     // recolouring forms it, so that a pure fluid (g_i = +-f_i) has phi = +-1
-    // exactly and its colour stays segregated without FP32 leakage
+    // exactly and its colour stays segregated without rounding leakage
     float rabs = 0.f, sg = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      float sc = wq(i) * s.rho0;
-      rabs += IO::ld(b + (long long)i * N + n, sc, 0.f) + sc;
-      sg += IO::ld(b + (long long)(Q + i) * N + n, sc, 0.f);
+      const float wr0 = wq(i) * s.rho0;
+      float d, g;
+      IO::ld(b + (long long)i * N + n, b + (long long)(Q + i) * N + n, wr0, wq(i) * R.x, R.y, d,
+             g);
+      rabs += d + wr0;
+      sg += g;
     }
     out = sg / rabs;
-  } else {
-    out = PHI_SOLID;
+    rho = rabs;
   }
   s.phi[n] = out;
+  // reference of the next encoding: this state's density and order parameter
+  if (STORE) rnext[n] = make_float2(rho, m == 0 ? out : 0.f);
 }
 
 // ------------------------------------------------------------ init kernels
@@ -133,10 +118,11 @@ __global__ void k_init_mask(SimDev s) {
   s.claim[n] = 0xFFFFFFFFu;
 }
 
-// fluid at rest: f = w rho0, g = w rho0 phi0 (phi0 staged in s.phi)
+// fluid at rest: f = w rho0, g = w rho0 phi0 (phi0 staged in s.phi); FP16
+// references (rho0, phi0)
 template <int STORE>
 __global__ void k_init_pops(SimDev s, void* pops) {
-  using IO = PopIO<STORE>;
+  using IO = Codec<STORE>;
   using T = typename IO::T;
   long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= s.N) return;
@@ -144,16 +130,21 @@ __global__ void k_init_pops(SimDev s, void* pops) {
   float p0 = (s.mask[n] == 0) ? s.phi[n] : 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    float sc = wq(i) * s.rho0;
-    IO::st(b + (long long)i * s.N + n, 0.f, 1.0f / sc);
-    IO::st(b + (long long)(Q + i) * s.N + n, sc * p0, 1.0f / sc);
+    const float wr0 = wq(i) * s.rho0;
+    IO::st(b + (long long)i * s.N + n, b + (long long)(Q + i) * s.N + n, wr0, wr0, p0, 0.f,
+           wr0 * p0);
+  }
+  if (STORE) {
+    s.ref[0][n] = make_float2(s.rho0, p0);
+    s.ref[1][n] = make_float2(s.rho0, p0);
   }
 }
 
 // --------------------------------------------------------- global mass (FP64)
 template <int STORE>
-__global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__ pops) {
-  using IO = PopIO<STORE>;
+__global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__ pops,
+                                             const float2* __restrict__ rdec) {
+  using IO = Codec<STORE>;
   using T = typename IO::T;
   __shared__ double sh[2][256];
   double a = 0.0, b = 0.0;
@@ -162,11 +153,14 @@ __global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__
        n += (long long)gridDim.x * blockDim.x) {
     if (s.mask[n] != 0) continue;
     double drho = 0.0, sg = 0.0;
+    const float2 R = STORE ? rdec[n] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      float sc = wq(i) * s.rho0;
-      drho += (double)IO::ld(p + (long long)i * s.N + n, sc, 0.f);
-      sg += (double)IO::ld(p + (long long)(Q + i) * s.N + n, sc, 0.f);
+      float d, g;
+      IO::ld(p + (long long)i * s.N + n, p + (long long)(Q + i) * s.N + n, wq(i) * s.rho0,
+             wq(i) * R.x, R.y, d, g);
+      drho += (double)d;
+      sg += (double)g;
     }
     double rho = (double)s.rho0 + drho;
     a += 0.5 * (rho + sg);
@@ -316,11 +310,13 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
                                               void* __restrict__ dst,
                                               const float4* __restrict__ nrm,
                                               const float2* __restrict__ cur,
+                                              const float2* __restrict__ rdec,
+                                              const float2* __restrict__ renc,
                                               float* __restrict__ out_rho,
                                               float* __restrict__ out_u,
                                               float* __restrict__ out_phi,
                                               float* __restrict__ out_F) {
-  using IO = PopIO<STORE>;
+  using IO = Codec<STORE>;
   using T = typename IO::T;
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   const int N = (int)s.N;
@@ -362,13 +358,12 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
     return;
   }
   const Nbr nb(gx, gy, gz, nx, ny, nz);
-  float d[Q], g[Q];
+  // the collision needs the total populations only: the colour enters through
+  // phi (moments pass) in the recolouring
+  float d[Q];
+  const float Rn = STORE ? rdec[n].x : 0.f;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float sc_ = wq(i) * rho0;
-    d[i] = IO::ld(sp_ + (unsigned)(i * N + n), sc_, 0.f);
-    g[i] = IO::ld(sp_ + (unsigned)((Q + i) * N + n), sc_, 0.f);
-  }
+  for (int i = 0; i < Q; ++i) d[i] = IO::ld_d(sp_ + (unsigned)(i * N + n), wq(i) * rho0, wq(i) * Rn);
   const float4 nc = nrm[n];
   const float phi = s.phi[n];
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -400,7 +395,6 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
     out_F[n] = Fx;
     out_F[N + n] = Fy;
     out_F[2 * N + n] = Fz;
-    (void)g;
     return;
   }
   if (!(rho > 0.f) || !(uu <= 0.09f)) atomicOr(&s.counters[1], (uint32_t)ST_UNSTABLE);
@@ -412,10 +406,12 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
   const float uF = ux * Fx + uy * Fy + uz * Fz;
   const float recl = 0.5f * s.beta * rho * (1.0f - phi) * (1.0f + phi);
 
+  // FP16: each population is encoded with the reference of the node that
+  // stores it
   auto st_pop = [&](int i, int node, float dv, float gv) {
-    const float isc = 1.0f / (wq(i) * rho0);
-    IO::st(dp_ + (unsigned)(i * N + node), dv, isc);
-    IO::st(dp_ + (unsigned)((Q + i) * N + node), gv, isc);
+    const float2 R = STORE ? renc[node] : make_float2(0.f, 0.f);
+    IO::st(dp_ + (unsigned)(i * N + node), dp_ + (unsigned)((Q + i) * N + node), wq(i) * rho0,
+           wq(i) * R.x, R.y, dv, gv);
   };
   // push to the neighbour in direction i, or bounce back into direction opp(i)
   auto emit = [&](int i, float dv, float gv) {
@@ -455,7 +451,6 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
     emit(i, ds_i, phi * (ds_i + wr0) + rc);
     emit(o, ds_o, phi * (ds_o + wr0) - rc);
   }
-  (void)g;
 }
 
 // Moving-wall correction and momentum exchange on particle links, after
@@ -467,9 +462,11 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
 // particle over the nodes of its bounding box grown by one.
 template <int STORE>
 __global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict__ src,
-                                              void* __restrict__ dst) {
+                                              void* __restrict__ dst,
+                                              const float2* __restrict__ rdec,
+                                              const float2* __restrict__ renc) {
   // one thread per (node of the particle's box, direction 1..18)
-  using IO = PopIO<STORE>;
+  using IO = Codec<STORE>;
   using T = typename IO::T;
   const int p = blockIdx.y;
   const DevParticle& P = s.P[p];
@@ -501,15 +498,19 @@ __global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict_
       const T* __restrict__ sp_ = (const T*)src;
       T* __restrict__ dp_ = (T*)dst;
       const int o = opp(i);
-      const float sc_ = wq(i) * rho0;
+      // f*_i bounced by k_fused into direction opp(i) at x (same weight w_i)
+      const float wr0 = wq(o) * rho0;
+      const float2 Re = STORE ? renc[n] : make_float2(0.f, 0.f);
+      const float wRe = wq(o) * Re.x;
       T* fo = dp_ + (unsigned)(o * N + n);
       T* go = dp_ + (unsigned)((Q + o) * N + n);
-      const float ds = IO::ld(fo, sc_, 0.f);  // f*_i bounced by k_fused
-      const float gs = IO::ld(go, sc_, 0.f);
+      float ds, gs;
+      IO::ld(fo, go, wr0, wRe, Re.y, ds, gs);
       const float phi = s.phi[n];
+      const float Rd = STORE ? rdec[n].x : 0.f;
       float drho = 0.f;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) drho += IO::ld(sp_ + (unsigned)(q * N + n), wq(q) * rho0, 0.f);
+      for (int q = 0; q < Q; ++q) drho += IO::ld_d(sp_ + (unsigned)(q * N + n), wq(q) * rho0, wq(q) * Rd);
       const float rho = rho0 + drho;
       const double rx = wrapd((double)gx + 0.5 * cx(i) - P.x[0], (double)nx);
       const double ry = wrapd((double)gy + 0.5 * cy(i) - P.x[1], (double)ny);
@@ -520,8 +521,7 @@ __global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict_
       const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));  // c_opp . u_w
       const float corr = 6.0f * wq(i) * rho * cu;
       const float dso = ds + corr;
-      IO::st(fo, dso, 1.0f / sc_);
-      IO::st(go, gs + phi * corr, 1.0f / sc_);
+      IO::st(fo, go, wr0, wRe, Re.y, dso, gs + phi * corr);
       const double wr = wqd(i) * (double)rho0;
       const double fin = (double)ds + wr;
       const double fout = (double)dso + wr;
@@ -568,45 +568,51 @@ hipError_t launch_interface(const SimDev& s, float4* nrm, float2* cur, hipStream
   return hipGetLastError();
 }
 
+// rd: index of the reference-density buffer the current populations are
+// encoded with (FP16 storage); new populations use the other one
 hipError_t launch_fused(const SimDev& s, const void* src, void* dst, const float4* nrm,
-                        const float2* cur, int mode, float* orho, float* ou, float* ophi,
+                        const float2* cur, int mode, int rd, float* orho, float* ou, float* ophi,
                         float* oF, hipStream_t st) {
   const dim3 grid(nblocks(s.N, 256));
+  const float2* rdec = s.ref[rd];
+  const float2* renc = s.ref[rd ^ 1];
   if (s.storage == 0) {
     if (mode == MODE_STEP)
       hipLaunchKernelGGL((k_fused<0, MODE_STEP>), grid, dim3(256), 0, st, s, src, dst, nrm, cur,
-                         orho, ou, ophi, oF);
+                         rdec, renc, orho, ou, ophi, oF);
     else
       hipLaunchKernelGGL((k_fused<0, MODE_FIELDS>), grid, dim3(256), 0, st, s, src, dst, nrm,
-                         cur, orho, ou, ophi, oF);
+                         cur, rdec, renc, orho, ou, ophi, oF);
   } else {
     if (mode == MODE_STEP)
       hipLaunchKernelGGL((k_fused<1, MODE_STEP>), grid, dim3(256), 0, st, s, src, dst, nrm, cur,
-                         orho, ou, ophi, oF);
+                         rdec, renc, orho, ou, ophi, oF);
     else
       hipLaunchKernelGGL((k_fused<1, MODE_FIELDS>), grid, dim3(256), 0, st, s, src, dst, nrm,
-                         cur, orho, ou, ophi, oF);
+                         cur, rdec, renc, orho, ou, ophi, oF);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, hipStream_t st) {
+hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, int rd,
+                        hipStream_t st) {
   if (s.np == 0) return hipSuccess;
   // the box of k_links spans at most 2 R + 6 nodes per axis, R <= (Bmask - 5) / 2
   const long long B = Bmask + 1;
   const dim3 grid((unsigned)((B * B * B * 18 + 255) / 256), s.np);
   if (s.storage == 0)
-    hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, s, src, dst);
+    hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, s, src, dst, s.ref[rd], s.ref[rd ^ 1]);
   else
-    hipLaunchKernelGGL(k_links<1>, grid, dim3(256), 0, st, s, src, dst);
+    hipLaunchKernelGGL(k_links<1>, grid, dim3(256), 0, st, s, src, dst, s.ref[rd], s.ref[rd ^ 1]);
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const SimDev& s, const void* pops, hipStream_t st) {
+hipError_t launch_moments(const SimDev& s, const void* pops, int rd, hipStream_t st) {
+  const dim3 grid(nblocks(s.N, 256));
   if (s.storage == 0)
-    hipLaunchKernelGGL(k_moments<0>, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, pops);
+    hipLaunchKernelGGL(k_moments<0>, grid, dim3(256), 0, st, s, pops, s.ref[rd], s.ref[rd ^ 1]);
   else
-    hipLaunchKernelGGL(k_moments<1>, dim3(nblocks(s.N, 256)), dim3(256), 0, st, s, pops);
+    hipLaunchKernelGGL(k_moments<1>, grid, dim3(256), 0, st, s, pops, s.ref[rd], s.ref[rd ^ 1]);
   return hipGetLastError();
 }
 
@@ -623,13 +629,13 @@ hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_mass(const SimDev& s, const void* pops, hipStream_t st) {
+hipError_t launch_mass(const SimDev& s, const void* pops, int rd, hipStream_t st) {
   unsigned nb = nblocks(s.N, 256);
   if (nb > 4096) nb = 4096;
   if (s.storage == 0)
-    hipLaunchKernelGGL(k_mass<0>, dim3(nb), dim3(256), 0, st, s, pops);
+    hipLaunchKernelGGL(k_mass<0>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
   else
-    hipLaunchKernelGGL(k_mass<1>, dim3(nb), dim3(256), 0, st, s, pops);
+    hipLaunchKernelGGL(k_mass<1>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
   return hipGetLastError();
 }
 

@@ -7,25 +7,6 @@
 
 namespace lbm {
 
-template <int STORE>
-struct PIO;
-template <>
-struct PIO<0> {
-  using T = float;
-  static __device__ __forceinline__ float ld(const T* p, float) { return *p; }
-  static __device__ __forceinline__ void st(T* p, float v, float) { *p = v; }
-};
-template <>
-struct PIO<1> {
-  using T = __half;
-  static __device__ __forceinline__ float ld(const T* p, float scale) {
-    return __half2float(*p) * scale;
-  }
-  static __device__ __forceinline__ void st(T* p, float v, float inv_scale) {
-    *p = __float2half_rn(v * inv_scale);
-  }
-};
-
 // ------------------------------------------------------------------ masks
 // Particle bounding box: every node inside the sphere lies in it.
 struct Box {
@@ -131,9 +112,10 @@ __global__ void k_cover(SimDev s) {
 // neighbour densities (fluid, not fresh, D3Q19 neighbours; rho0/2 each if none)
 // at the surface velocity of the particle that uncovered it.
 template <int STORE>
-__global__ __launch_bounds__(256) void k_refill(SimDev s, void* pops) {
+__global__ __launch_bounds__(256) void k_refill(SimDev s, void* pops,
+                                               const float2* __restrict__ rdec) {
   // one thread per (fresh node, neighbour direction): 14 fresh nodes per block
-  using IO = PIO<STORE>;
+  using IO = Codec<STORE>;
   using T = typename IO::T;
   constexpr int PER = 14;
   __shared__ float sh_a[PER][18], sh_b[PER][18];
@@ -156,11 +138,14 @@ __global__ __launch_bounds__(256) void k_refill(SimDev s, void* pops) {
                                                (long long)s.ny * wrapi(z + cz(dir), s.nz));
         if (s.mask[m] == 0) {
           float drho = 0.f, sg = 0.f;
+          const float2 R = STORE ? rdec[m] : make_float2(0.f, 0.f);
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
-            const float sc = wq(q) * s.rho0;
-            drho += IO::ld(b + (long long)q * N + m, sc);
-            sg += IO::ld(b + (long long)(Q + q) * N + m, sc);
+            float d, g;
+            IO::ld(b + (long long)q * N + m, b + (long long)(Q + q) * N + m, wq(q) * s.rho0,
+                   wq(q) * R.x, R.y, d, g);
+            drho += d;
+            sg += g;
           }
           const float rho = s.rho0 + drho;
           ra = 0.5f * (rho + sg);
@@ -197,14 +182,14 @@ __global__ __launch_bounds__(256) void k_refill(SimDev s, void* pops) {
       const float uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
       const float uu = ux * ux + uy * uy + uz * uz;
       const float rho = ra + rb;
+      const float2 Rn = STORE ? rdec[n] : make_float2(0.f, 0.f);
       for (int q = 0; q < Q; ++q) {
         const float cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
         const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
-        const float sc = wq(q) * s.rho0;
         const float dq = wq(q) * ((rho - s.rho0) + rho * poly);
         const float gq = wq(q) * (ra - rb) * (1.0f + poly);
-        IO::st(b + (long long)q * N + n, dq, 1.0f / sc);
-        IO::st(b + (long long)(Q + q) * N + n, gq, 1.0f / sc);
+        IO::st(b + (long long)q * N + n, b + (long long)(Q + q) * N + n, wq(q) * s.rho0,
+               wq(q) * Rn.x, Rn.y, dq, gq);
       }
     }
     __syncthreads();
@@ -659,15 +644,15 @@ hipError_t launch_mask_update(const SimDev& s, int Bmask, bool with_release, hip
   return hipGetLastError();
 }
 
-hipError_t launch_refill(const SimDev& s, void* pops, hipStream_t st) {
+hipError_t launch_refill(const SimDev& s, void* pops, int rd, hipStream_t st) {
   if (s.np == 0) return hipSuccess;
   unsigned nb = (s.fresh_cap + 13) / 14;
   if (nb > 128) nb = 128;
   if (nb == 0) nb = 1;
   if (s.storage == 0)
-    hipLaunchKernelGGL(k_refill<0>, dim3(nb), dim3(256), 0, st, s, pops);
+    hipLaunchKernelGGL(k_refill<0>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
   else
-    hipLaunchKernelGGL(k_refill<1>, dim3(nb), dim3(256), 0, st, s, pops);
+    hipLaunchKernelGGL(k_refill<1>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
   return hipGetLastError();
 }
 

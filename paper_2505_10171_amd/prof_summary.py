@@ -1,0 +1,124 @@
+"""Summaries of rocprofv3 CSV output for the lbm kernels.
+
+    python -m paper_2505_10171_amd.prof_summary stats KERNEL_STATS_CSV OUT --command "..."
+    python -m paper_2505_10171_amd.prof_summary counters --fetch CSV --write CSV \
+        --kernel k_fused --probe-bytes BYTES OUT --command "..." --command "..."
+
+``stats`` condenses a ``--kernel-trace --stats`` kernel_stats CSV into a short
+table (calls, average and total duration, share of GPU time per kernel).
+
+``counters`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs into HBM
+bytes per launch of one kernel.  Both runs must contain one plain device copy of
+known size (the largest ``__amd_rocclr_copyBuffer`` dispatch): each counter is
+scaled by (copy bytes / what the same counter reads for that copy), which
+calibrates the counter's unit and coverage on this chip.  The summary records a
+hash of the kernel sources so that consumers can tell when it is stale.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", "lbm_fluid.hip"),
+                  os.path.join(HERE, "csrc", "lbm_device.h")]
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    m = re.match(r"(?:void )?([\w:]+(?:<[^()]*>)?)\(", name)
+    return m.group(1) if m else name[:60]
+
+
+def stats(path, out, commands):
+    rows = list(csv.DictReader(open(path)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# kernel time summary (rocprofv3 --kernel-trace --stats)", ""]
+    for c in commands:
+        lines.append(f"command: {c}")
+    lines += ["", f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'share':>7s}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{short_name(r['Name']):60s} {int(r['Calls']):7d} "
+                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                     f"{100 * float(r['TotalDurationNs']) / total:6.2f}%")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _per_kernel(path, counter):
+    vals, probe = {}, []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        name = r["Kernel_Name"]
+        if "copyBuffer" in name:
+            probe.append(v)
+        else:
+            vals.setdefault(short_name(name), []).append(v)
+    return vals, probe
+
+
+def counters(fetch, write, kernel, probe_bytes, out, commands):
+    lines = ["# HBM traffic per launch from rocprofv3 counters", ""]
+    for c in commands:
+        lines.append(f"command: {c}")
+    lines.append("")
+    result = {}
+    for label, path, ctr in (("fetch", fetch, "FETCH_SIZE"), ("write", write, "WRITE_SIZE")):
+        vals, probe = _per_kernel(path, ctr)
+        if not probe:
+            raise SystemExit(f"{path}: no copy probe dispatch")
+        pk = max(probe)  # KiB reported for the probe copy
+        scale = probe_bytes / (pk * 1024.0)
+        ks = [k for k in vals if re.search(kernel, k)]
+        if not ks:
+            raise SystemExit(f"{path}: no dispatch of {kernel}")
+        k = ks[0]
+        kib = statistics.mean(vals[k])
+        result[label] = kib * 1024.0 * scale
+        lines.append(f"{ctr}: kernel {k}: {len(vals[k])} dispatches, mean {kib:.1f} KiB; "
+                     f"copy probe {probe_bytes} B reads as {pk:.1f} KiB -> scale {scale:.4f}; "
+                     f"scaled bytes per launch {result[label]:.4e}")
+    lines += ["", f"fetch_bytes_per_launch: {result['fetch']:.6e}",
+              f"write_bytes_per_launch: {result['write']:.6e}",
+              f"hbm_bytes_per_launch: {result['fetch'] + result['write']:.6e}",
+              f"kernel_source_sha256_16: {kernel_sources_hash()}"]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("out")
+    a.add_argument("--command", action="append", default=[])
+    b = sub.add_parser("counters")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", default="k_fused")
+    b.add_argument("--probe-bytes", type=float, required=True)
+    b.add_argument("out")
+    b.add_argument("--command", action="append", default=[])
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        stats(args.csv, args.out, args.command)
+    else:
+        counters(args.fetch, args.write, args.kernel, args.probe_bytes, args.out, args.command)
+
+
+if __name__ == "__main__":
+    main()

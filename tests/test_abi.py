@@ -77,7 +77,8 @@ def test_workspace_sizing_and_validation():
     assert L.lbm_workspace_bytes(c, 1, None, 0) == 0
     # FP16 storage halves the population bytes
     c16 = (lbm.LbmConfig * 1)(lbm.make_config(dict(cfg, storage="fp16"), 0))
-    assert L.lbm_workspace_bytes(c16, 1, None, 0) < 0.5 * (nb - 34 * N) + 36 * N + 4096
+    # FP16 adds two per-node references (rho, phi): 16 B
+    assert L.lbm_workspace_bytes(c16, 1, None, 0) < 0.5 * (nb - 34 * N) + 52 * N + 4096
 
 
 def test_error_paths_without_gpu():

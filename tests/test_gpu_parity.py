@@ -219,3 +219,40 @@ def test_device_fields_match_host_fields():
     assert np.array_equal(rd.cpu().numpy().reshape(rho.shape), rho)
     assert np.array_equal(pd.cpu().numpy().reshape(phi.shape), phi)
     assert np.array_equal(ud.cpu().numpy().reshape(u.shape), u)
+
+
+def test_fp16_storage_c1_against_oracle():
+    """FP16 population storage (scaled offsets, FP32 arithmetic) on the C1
+    workload: masks bit-exact, velocity within 1e-3 relative L2 of the FP64
+    oracle after 200 steps; rho and phi errors reported."""
+    w = W.sessile_drop_c1()
+    cfg = dict(w["cfg"], storage="fp16")
+    g = _gpu(cfg, w["phi0"], w["particles"])
+    o = OracleSim(w["cfg"], w["phi0"], w["particles"])
+    g.step(w["steps"])
+    o.step(w["steps"])
+    rg, ug, pg, mg = g.fields()
+    ro, uo, po, mo = o.fields()
+    assert np.array_equal(mg, mo)
+    fl = mo == 0
+    e = dict(rho=rel_l2(rg[fl], ro[fl]), u=rel_l2(ug[:, fl], uo[:, fl]), phi=rel_l2(pg[fl], po[fl]))
+    print("FP16 C1 200 steps", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    pgp, pop_ = g.particles()[0], o.particles()[0]
+    for k in ("F_hyd", "F_cap", "x"):
+        print(k, np.abs(np.array(pgp[k]) - np.array(pop_[k])).max(), np.abs(pop_[k]).max())
+    assert e["u"] <= 1e-3, e
+    assert e["rho"] <= 1e-3 and e["phi"] <= 1e-3, e
+
+
+def test_fp16_storage_free_drop():
+    cfg = W.config(24, 20, 28, has_wall=0, sigma=0.01, tau_a=0.8, tau_b=1.4, storage="fp16")
+    phi0 = W.drop_phi0(24, 20, 28, (11.5, 9.5, 13.5), 7.0)
+    g = _gpu(cfg, phi0, [])
+    o = OracleSim(dict(cfg, storage="fp32"), phi0, [])
+    g.step(100)
+    o.step(100)
+    rg, ug, pg, mg = g.fields()
+    ro, uo, po, mo = o.fields()
+    e = dict(rho=rel_l2(rg, ro), u=rel_l2(ug, uo), phi=rel_l2(pg, po))
+    print("FP16 free drop", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    assert e["u"] <= 1e-3, e
