@@ -23,20 +23,19 @@
 #include "lbm_device.h"
 
 namespace lbm {
-hipError_t launch_interface(const SimDev& s, float4* nrm, float2* cur, hipStream_t st);
-hipError_t launch_fused(const SimDev& s, const void* src, void* dst, const float4* nrm,
-                        const float2* cur, int mode, int rd, float* orho, float* ou, float* ophi,
-                        float* oF, hipStream_t st);
-hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, int rd,
-                        hipStream_t st);
-hipError_t launch_moments(const SimDev& s, const void* pops, int rd, hipStream_t st);
+hipError_t launch_interface(const Batch& b, unsigned nblk, hipStream_t st);
+hipError_t launch_fused(const Batch& b, int storage, unsigned nblk, int mode, float* orho,
+                        float* ou, float* ophi, float* oF, hipStream_t st);
+hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipStream_t st);
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, hipStream_t st);
 hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
 hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
 hipError_t launch_mass(const SimDev& s, const void* pops, int rd, hipStream_t st);
-hipError_t launch_mask_update(const SimDev& s, int Bmask, bool with_release, hipStream_t st);
-hipError_t launch_refill(const SimDev& s, void* pops, int rd, hipStream_t st);
-hipError_t launch_capillary(const SimDev& s, hipStream_t st);
-hipError_t launch_dem(const SimDev& s, hipStream_t st);
+hipError_t launch_mask_update(const Batch& b, int np_rows, int Bmax, bool with_release,
+                              hipStream_t st);
+hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, hipStream_t st);
+hipError_t launch_capillary(const Batch& b, int np_rows, int cap_B, int npts, hipStream_t st);
+hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st);
 }  // namespace lbm
 
 using namespace lbm;
@@ -205,11 +204,6 @@ struct SimHost {
   lbm_config cfg;
   SimLayout L;
   SimDev d;
-  float4* nrm;  // per node (n, |G|): interface normal and gradient magnitude
-  float2* curv;  // per node (c, solid-direction bits): CSF coefficient
-  int cur;  // index of the population buffer holding the current state
-  int rd;   // FP16: index of the references the current state is encoded with
-  int LZ;
   double Rmax;
 };
 
@@ -237,7 +231,33 @@ struct lbm_ctx {
   int err;
   char msg[512];
   Profiler prof;
+  // every simulation steps together: one population buffer index and one
+  // FP16 reference index for all of them
+  int cur = 0, rd = 0;
+  int storage = 0;
+  // batch tables (in the workspace) and their host-side extents
+  SimDev* d_tab = nullptr;
+  uint32_t* d_blk = nullptr;
+  int2* d_pmap = nullptr;
+  unsigned nblk = 0;
+  int np_rows = 0, np_max = 0, Bmax = 0, cap_B = 0, npts = 0;
+  size_t fresh_cap_max = 0;
 };
+
+static unsigned sim_blocks(const SimDev& d) { return (unsigned)((d.N + 255) / 256); }
+
+static Batch batch_all(const lbm_ctx* c) {
+  return Batch{c->d_tab, c->d_blk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd};
+}
+static Batch batch_one(const lbm_ctx* c, int si) {
+  return Batch{c->d_tab + si, nullptr, nullptr, 1, c->cur, c->rd};
+}
+
+// workspace tail holding the batch tables
+static size_t batch_tables_bytes(int n_sims, long long np_total) {
+  return align_up(sizeof(SimDev) * (size_t)n_sims) + align_up(4 * (size_t)(n_sims + 1)) +
+         align_up(8 * (size_t)std::max<long long>(np_total, 1));
+}
 
 static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
   if (!c) return code;
@@ -258,25 +278,17 @@ static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
       return set_err((ctx), LBM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
 
-static int choose_LZ(const SimDev& s) {
-  const char* env = getenv("LBM_LZ");
-  if (env && atoi(env) > 0) return atoi(env);
-  const int TX = s.nx >= 64 ? 64 : 32, TY = s.nx >= 64 ? 4 : 8;
-  const long long nxy = (long long)((s.nx + TX - 1) / TX) * ((s.ny + TY - 1) / TY);
-  long long lz = (long long)s.nz * nxy / 2048;
-  lz = std::max<long long>(4, std::min<long long>(32, lz));
-  return (int)lz;
-}
-
-// mask of the new particle positions, fresh nodes, refill, moments
-static int post_dem_pipeline(lbm_ctx* ctx, SimHost& sh, bool with_release) {
-  SimDev& s = sh.d;
-  void* cur = s.pops[sh.cur];
+// mask of the new particle positions, fresh nodes, refill, moments (one
+// simulation, between steps)
+static int post_dem_pipeline(lbm_ctx* ctx, int si, bool with_release) {
+  const SimHost& sh = ctx->sims[si];
+  const SimDev& s = sh.d;
+  const Batch b = batch_one(ctx, si);
   if (s.np > 0) {
-    HIPCHK(ctx, launch_mask_update(s, sh.L.Bmask, with_release, ctx->stream));
-    HIPCHK(ctx, launch_refill(s, cur, sh.rd, ctx->stream));
+    HIPCHK(ctx, launch_mask_update(b, s.np, sh.L.Bmask, with_release, ctx->stream));
+    HIPCHK(ctx, launch_refill(b, ctx->storage, s.fresh_cap, ctx->stream));
   }
-  HIPCHK(ctx, launch_moments(s, cur, sh.rd, ctx->stream));
+  HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), ctx->stream));
   return LBM_OK;
 }
 
@@ -287,13 +299,16 @@ size_t lbm_workspace_bytes(const lbm_config* cfg, int32_t n_sims,
   if (!cfg || n_sims < 1 || history_steps < 0) return 0;
   char msg[256];
   size_t o = 0;
+  long long np_total = 0;
   for (int s = 0; s < n_sims; ++s) {
     if (!valid_config(cfg[s], msg, sizeof msg)) return 0;
+    if (cfg[s].storage != cfg[0].storage) return 0;
     if (cfg[s].n_particles > 0 && (!parts || !parts[s])) return 0;
     const double Rmax = max_radius(cfg[s], cfg[s].n_particles > 0 ? parts[s] : nullptr);
     o = layout(cfg[s], Rmax, history_steps, o).total;
+    np_total += cfg[s].n_particles;
   }
-  return o;
+  return align_up(o) + batch_tables_bytes(n_sims, np_total);
 }
 
 int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
@@ -319,6 +334,9 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
   if (need == 0) {
     char msg[256] = "invalid configuration";
     for (int s = 0; s < n_sims; ++s) valid_config(cfg[s], msg, sizeof msg);
+    for (int s = 0; s < n_sims; ++s)
+      if (cfg[s].storage != cfg[0].storage)
+        snprintf(msg, sizeof msg, "all simulations of a context share one storage type");
     return fail(LBM_EINVAL, msg);
   }
   if (ws_bytes < need) return fail(LBM_ENOMEM, "workspace too small");
@@ -369,9 +387,8 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
       d.ref[0] = d.ref[1] = nullptr;
     }
     d.phi = (float*)(b + sh.L.off_phi);
-    sh.nrm = (float4*)(b + sh.L.off_nrm);
-    d.nrm = sh.nrm;
-    sh.curv = (float2*)(b + sh.L.off_cur);
+    d.nrm = (float4*)(b + sh.L.off_nrm);
+    d.curv = (float2*)(b + sh.L.off_cur);
     d.mask = (uint16_t*)(b + sh.L.off_mask);
     d.claim = (uint32_t*)(b + sh.L.off_claim);
     d.fresh = (uint32_t*)(b + sh.L.off_fresh);
@@ -400,9 +417,6 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.capbox_org = (int*)(b + sh.L.off_caporg);
     d.mass_acc = (double*)(b + sh.L.off_mass);
     d.step_counter = (unsigned long long*)(b + sh.L.off_step);
-    sh.cur = 0;
-    sh.rd = 0;
-    sh.LZ = choose_LZ(d);
 
     // upload particles and contact tables
     hipStream_t st = ctx->stream;
@@ -441,17 +455,66 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
           hipStreamSynchronize(st) != hipSuccess)
         return fail(LBM_EHIP, "phi0 upload failed");
     }
-    if (launch_init_mask(d, st) != hipSuccess) return fail(LBM_EHIP, "mask init failed");
-    if (d.np > 0 && launch_mask_update(d, sh.L.Bmask, false, st) != hipSuccess)
-      return fail(LBM_EHIP, "mask build failed");
-    if (launch_init_pops(d, d.pops[0], st) != hipSuccess)
-      return fail(LBM_EHIP, "population init failed");
-    if (launch_moments(d, d.pops[0], 0, st) != hipSuccess) return fail(LBM_EHIP, "moments failed");
     if (phi0 && phi0[si]) {
       // the host buffer must stay valid until the copy has completed
       if (hipStreamSynchronize(st) != hipSuccess) return fail(LBM_EHIP, "synchronise failed");
     }
   }
+  // batch tables: simulation records, block prefix, particle rows
+  {
+    char* b = ctx->ws + align_up(off);
+    ctx->d_tab = (SimDev*)b;
+    b += align_up(sizeof(SimDev) * (size_t)n_sims);
+    ctx->d_blk = (uint32_t*)b;
+    b += align_up(4 * (size_t)(n_sims + 1));
+    ctx->d_pmap = (int2*)b;
+    std::vector<SimDev> tab(n_sims);
+    std::vector<uint32_t> blk(n_sims + 1, 0);
+    std::vector<int2> pmap;
+    ctx->storage = cfg[0].storage;
+    for (int si = 0; si < n_sims; ++si) {
+      const SimHost& sh = ctx->sims[si];
+      tab[si] = sh.d;
+      blk[si + 1] = blk[si] + sim_blocks(sh.d);
+      for (int p = 0; p < sh.d.np; ++p) pmap.push_back(make_int2(si, p));
+      ctx->np_max = std::max(ctx->np_max, sh.d.np);
+      if (sh.d.np > 0) {
+        ctx->Bmax = std::max(ctx->Bmax, sh.L.Bmask);
+        ctx->cap_B = std::max(ctx->cap_B, sh.d.cap_B);
+        ctx->npts = std::max(ctx->npts, sh.d.cap_na * sh.d.cap_nphi);
+        ctx->fresh_cap_max = std::max(ctx->fresh_cap_max, (size_t)sh.d.fresh_cap);
+      }
+    }
+    if (blk[n_sims] > 0x7fffffffu) return fail(LBM_EINVAL, "too many lattice nodes in one context");
+    ctx->nblk = blk[n_sims];
+    ctx->np_rows = (int)pmap.size();
+    hipStream_t st = ctx->stream;
+    if (hipMemcpyAsync(ctx->d_tab, tab.data(), sizeof(SimDev) * n_sims, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(ctx->d_blk, blk.data(), 4 * (size_t)(n_sims + 1), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        (!pmap.empty() && hipMemcpyAsync(ctx->d_pmap, pmap.data(), 8 * pmap.size(),
+                                         hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(LBM_EHIP, "batch table upload failed");
+  }
+  // initial state of every simulation
+  ctx->cur = 0;
+  ctx->rd = 0;
+  for (int si = 0; si < n_sims; ++si) {
+    const SimHost& sh = ctx->sims[si];
+    const SimDev& d = sh.d;
+    const Batch b1 = batch_one(ctx, si);
+    hipStream_t st = ctx->stream;
+    if (launch_init_mask(d, st) != hipSuccess) return fail(LBM_EHIP, "mask init failed");
+    if (d.np > 0 && launch_mask_update(b1, d.np, sh.L.Bmask, false, st) != hipSuccess)
+      return fail(LBM_EHIP, "mask build failed");
+    if (launch_init_pops(d, d.pops[0], st) != hipSuccess)
+      return fail(LBM_EHIP, "population init failed");
+    if (launch_moments(b1, ctx->storage, sim_blocks(d), st) != hipSuccess)
+      return fail(LBM_EHIP, "moments failed");
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(LBM_EHIP, "synchronise failed");
   *out = ctx;
   return LBM_OK;
 }
@@ -472,46 +535,50 @@ static int prof_harvest(lbm_ctx* ctx, int slot) {
   return LBM_OK;
 }
 
+// One step of every simulation: each phase is one launch over the batch.
+static int step_once(lbm_ctx* ctx, int slot) {
+  Profiler& P = ctx->prof;
+  hipStream_t st = ctx->stream;
+  const Batch b = batch_all(ctx);
+  if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][0], st));
+  HIPCHK(ctx, launch_interface(b, ctx->nblk, st));
+  if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][1], st));
+  HIPCHK(ctx, launch_fused(b, ctx->storage, ctx->nblk, 0, nullptr, nullptr, nullptr, nullptr, st));
+  if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], st));
+  HIPCHK(ctx, launch_links(b, ctx->storage, ctx->np_rows, ctx->Bmax, st));
+  ctx->cur ^= 1;
+  ctx->rd ^= 1;
+  const Batch a = batch_all(ctx);
+  if (ctx->np_rows > 0) {
+    HIPCHK(ctx, launch_capillary(a, ctx->np_rows, ctx->cap_B, ctx->npts, st));
+    HIPCHK(ctx, launch_dem(a, ctx->np_max, st));
+    HIPCHK(ctx, launch_mask_update(a, ctx->np_rows, ctx->Bmax, true, st));
+    HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, st));
+  }
+  if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], st));
+  HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, st));
+  if (slot >= 0) {
+    HIPCHK(ctx, hipEventRecord(P.ev[slot][4], st));
+    P.pending[slot] = true;
+  }
+  return LBM_OK;
+}
+
 int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
   if (!ctx) return LBM_EINVAL;
   if (ctx->err) return LBM_ESTATE;
   if (n_steps < 0) return set_err(ctx, LBM_EINVAL, "negative step count");
   Profiler& P = ctx->prof;
   for (int t = 0; t < n_steps; ++t) {
-    for (auto& sh : ctx->sims) {
-      SimDev& s = sh.d;
-      void* src = s.pops[sh.cur];
-      void* dst = s.pops[sh.cur ^ 1];
-      int slot = -1;
-      if (P.on) {
-        slot = P.next;
-        P.next = (P.next + 1) % PROF_RING;
-        int rc = prof_harvest(ctx, slot);
-        if (rc) return rc;
-        HIPCHK(ctx, hipEventRecord(P.ev[slot][0], ctx->stream));
-      }
-      HIPCHK(ctx, launch_interface(s, sh.nrm, sh.curv, ctx->stream));
-      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][1], ctx->stream));
-      HIPCHK(ctx, launch_fused(s, src, dst, sh.nrm, sh.curv, 0, sh.rd, nullptr, nullptr, nullptr, nullptr,
-                               ctx->stream));
-      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], ctx->stream));
-      HIPCHK(ctx, launch_links(s, src, dst, sh.L.Bmask, sh.rd, ctx->stream));
-      sh.cur ^= 1;
-      sh.rd ^= 1;
-      void* cur = s.pops[sh.cur];
-      if (s.np > 0) {
-        HIPCHK(ctx, launch_capillary(s, ctx->stream));
-        HIPCHK(ctx, launch_dem(s, ctx->stream));
-        HIPCHK(ctx, launch_mask_update(s, sh.L.Bmask, true, ctx->stream));
-        HIPCHK(ctx, launch_refill(s, cur, sh.rd, ctx->stream));
-      }
-      if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], ctx->stream));
-      HIPCHK(ctx, launch_moments(s, cur, sh.rd, ctx->stream));
-      if (slot >= 0) {
-        HIPCHK(ctx, hipEventRecord(P.ev[slot][4], ctx->stream));
-        P.pending[slot] = true;
-      }
+    int slot = -1;
+    if (P.on) {
+      slot = P.next;
+      P.next = (P.next + 1) % PROF_RING;
+      int rc = prof_harvest(ctx, slot);
+      if (rc) return rc;
     }
+    int rc = step_once(ctx, slot);
+    if (rc) return rc;
   }
   return LBM_OK;
 }
@@ -661,7 +728,7 @@ int lbm_particles_sync(lbm_ctx* ctx, int32_t sim, int32_t dir, lbm_particle* par
   HIPCHK(ctx, hipMemcpyAsync(d.P, hp.data(), sizeof(DevParticle) * d.np, hipMemcpyHostToDevice,
                              ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  rc = post_dem_pipeline(ctx, *sh, true);
+  rc = post_dem_pipeline(ctx, sim, true);
   if (rc) return rc;
   return lbm_sync(ctx);
 }
@@ -682,14 +749,14 @@ int lbm_fields2(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, 
   const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (what & (LBM_F_RHO | LBM_F_U | LBM_F_PHI | LBM_F_FORCE)) {
     // the spare population buffer holds the outputs: rho | phi | u | F (8N floats)
-    float* scratch = (float*)d.pops[sh->cur ^ 1];
+    float* scratch = (float*)d.pops[ctx->cur ^ 1];
     float* orho = scratch;
     float* ophi = scratch + N;
     float* ou = scratch + 2 * N;
     float* oF = scratch + 5 * N;
-    HIPCHK(ctx, launch_interface(d, sh->nrm, sh->curv, ctx->stream));
-    HIPCHK(ctx, launch_fused(d, d.pops[sh->cur], nullptr, sh->nrm, sh->curv, 1, sh->rd, orho, ou, ophi,
-                             oF, ctx->stream));
+    const Batch b1 = batch_one(ctx, sim);
+    HIPCHK(ctx, launch_interface(b1, sim_blocks(d), ctx->stream));
+    HIPCHK(ctx, launch_fused(b1, ctx->storage, sim_blocks(d), 1, orho, ou, ophi, oF, ctx->stream));
     if ((what & LBM_F_FORCE) && force)
       HIPCHK(ctx, hipMemcpyAsync(force, oF, 12 * N, kind, ctx->stream));
     if ((what & LBM_F_RHO) && rho)
@@ -701,7 +768,7 @@ int lbm_fields2(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, 
   if ((what & LBM_F_MASK) && mask)
     HIPCHK(ctx, hipMemcpyAsync(mask, d.mask, 2 * N, kind, ctx->stream));
   if ((what & LBM_F_POPS) && pops)
-    HIPCHK(ctx, hipMemcpyAsync(pops, d.pops[sh->cur], sh->L.pop_bytes, kind, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(pops, d.pops[ctx->cur], sh->L.pop_bytes, kind, ctx->stream));
   return lbm_sync(ctx);
 }
 
@@ -745,7 +812,7 @@ int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]) {
   if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
   SimDev& d = sh->d;
   HIPCHK(ctx, hipMemsetAsync(d.mass_acc, 0, 2 * sizeof(double), ctx->stream));
-  HIPCHK(ctx, launch_mass(d, d.pops[sh->cur], sh->rd, ctx->stream));
+  HIPCHK(ctx, launch_mass(d, d.pops[ctx->cur], ctx->rd, ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(out, d.mass_acc, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   return lbm_sync(ctx);
 }

@@ -144,6 +144,7 @@ struct SimDev {
   float2* ref[2];      // FP16 storage: per-node reference (rho, phi), ping-pong
   float* phi;          // order parameter of the current state (PHI_SOLID at solids)
   float4* nrm;         // per node (n, |G|) of the current state; w = -1 at solids
+  float2* curv;        // per node (CSF coefficient, solid-neighbour bits as float)
   uint16_t* mask;      // 0 fluid, 1 wall, 2+p particle p; FRESH_BIT while refilling
   uint32_t* claim;     // per node: lowest particle claiming it in the new mask, ~0u none
   uint32_t* fresh;     // fresh-node list: node index
@@ -169,6 +170,40 @@ struct SimDev {
 };
 
 enum StatusBits : uint32_t { ST_UNSTABLE = 1u, ST_CONTACT_FULL = 2u, ST_FRESH_FULL = 4u };
+
+// One launch covers a batch of simulations (an ensemble, or a single one).
+// Per-node kernels run 256-node blocks; blk[s] is the first global block of
+// simulation s (blk[nsim] the total).  Particle kernels run one grid row per
+// particle; pmap[row] = (simulation, particle).  With nsim == 1 the tables are
+// not read: the block index is the simulation's own and row = particle.
+// cur: population buffer holding the current state; rd: FP16 reference buffer
+// it is encoded with (both uniform over the batch).
+struct Batch {
+  const SimDev* tab;
+  const uint32_t* blk;
+  const int2* pmap;
+  int nsim;
+  int cur, rd;
+};
+
+// (simulation, block within it) of global block g
+__device__ __forceinline__ int2 batch_block(const Batch& b, int g) {
+  if (b.nsim == 1) return make_int2(0, g);
+  int lo = 0, hi = b.nsim;  // blk[lo] <= g < blk[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int)b.blk[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return make_int2(lo, g - (int)b.blk[lo]);
+}
+
+// (simulation, particle) of grid row r
+__device__ __forceinline__ int2 batch_particle(const Batch& b, int r) {
+  return b.nsim == 1 ? make_int2(0, r) : b.pmap[r];
+}
 
 __host__ __device__ inline int wrapi(int a, int n) {
   a %= n;

@@ -70,13 +70,16 @@ __host__ __device__ constexpr int pair_dir(int k) {
 // after the refill of fresh nodes; clears their FRESH mark.  Solid nodes get
 // the sentinel PHI_SOLID, so stencils can tell solids from phi alone.
 template <int STORE>
-__global__ __launch_bounds__(256) void k_moments(SimDev s, const void* __restrict__ pops,
-                                                const float2* __restrict__ rdec,
-                                                float2* __restrict__ rnext) {
+__global__ __launch_bounds__(256) void k_moments(Batch bt) {
   using IO = Codec<STORE>;
   using T = typename IO::T;
+  const int2 sb = batch_block(bt, blockIdx.x);
+  const SimDev& s = bt.tab[sb.x];
+  const void* __restrict__ pops = s.pops[bt.cur];
+  const float2* __restrict__ rdec = s.ref[bt.rd];
+  float2* __restrict__ rnext = s.ref[bt.rd ^ 1];
   const long long N = s.N;
-  long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long n = (long long)sb.y * blockDim.x + threadIdx.x;
   if (n == 0) s.counters[0] = 0u;  // fresh list consumed
   if (n >= N) return;
   uint16_t m = s.mask[n];
@@ -220,9 +223,12 @@ struct Nbr {
 // Colour gradient G = 3 sum_i w_i c_i phi(x + c_i) (isotropic stencil, the value
 // at x for solid neighbours), the geometric wetting rotation next to solids, and
 // the normal n = G / max(|G|, EPS_G); written as (n, |G|).
-__global__ __launch_bounds__(256) void k_normal(SimDev s, float4* __restrict__ nrm) {
+__global__ __launch_bounds__(256) void k_normal(Batch bt) {
+  const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
+  const SimDev& s = bt.tab[sb.x];
+  float4* __restrict__ nrm = s.nrm;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
-  const int n = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int n = sb.y * 256 + threadIdx.x;
   if (n >= (int)s.N) return;
   float4 out = make_float4(0.f, 0.f, 0.f, -1.0f);  // w < 0 marks a solid node
   const float p0 = s.phi[n];
@@ -266,10 +272,13 @@ __global__ __launch_bounds__(256) void k_normal(SimDev s, float4* __restrict__ n
 // Curvature kappa = div n (same stencil and closure) and the CSF coefficient
 // c = -sigma kappa max(|G|, EPS_G) / 2 (the surface-tension force is c n); plus
 // the set of directions whose neighbour is solid (bit i), bit 31 = node solid.
-__global__ __launch_bounds__(256) void k_curv(SimDev s, const float4* __restrict__ nrm,
-                                              float2* __restrict__ cur) {
+__global__ __launch_bounds__(256) void k_curv(Batch bt) {
+  const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
+  const SimDev& s = bt.tab[sb.x];
+  const float4* __restrict__ nrm = s.nrm;
+  float2* __restrict__ cur = s.curv;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
-  const int n = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int n = sb.y * 256 + threadIdx.x;
   if (n >= (int)s.N) return;
   float c = 0.f;
   uint32_t bits = 0x80000000u;
@@ -306,22 +315,24 @@ __global__ __launch_bounds__(256) void k_curv(SimDev s, const float4* __restrict
 // streaming, and half-way bounce-back at every solid link.  At particle links
 // the moving-wall term and the momentum exchange are added by k_links.
 template <int STORE, int MODE>
-__global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict__ src,
-                                              void* __restrict__ dst,
-                                              const float4* __restrict__ nrm,
-                                              const float2* __restrict__ cur,
-                                              const float2* __restrict__ rdec,
-                                              const float2* __restrict__ renc,
-                                              float* __restrict__ out_rho,
+__global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out_rho,
                                               float* __restrict__ out_u,
                                               float* __restrict__ out_phi,
                                               float* __restrict__ out_F) {
   using IO = Codec<STORE>;
   using T = typename IO::T;
+  const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
+  const SimDev& s = bt.tab[sb.x];
+  const void* __restrict__ src = s.pops[bt.cur];
+  void* __restrict__ dst = s.pops[bt.cur ^ 1];
+  const float4* __restrict__ nrm = s.nrm;
+  const float2* __restrict__ cur = s.curv;
+  const float2* __restrict__ rdec = s.ref[bt.rd];
+  const float2* __restrict__ renc = s.ref[bt.rd ^ 1];
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   const int N = (int)s.N;
   const int nxny = nx * ny;
-  const int n = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int n = sb.y * 256 + threadIdx.x;
   if (n >= N) return;
   const float rho0 = s.rho0;
   const T* __restrict__ sp_ = (const T*)src;
@@ -461,14 +472,19 @@ __global__ __launch_bounds__(256) void k_fused(SimDev s, const void* __restrict_
 // (hydrodynamic force eqs.), summed in FP64 per particle.  One grid row per
 // particle over the nodes of its bounding box grown by one.
 template <int STORE>
-__global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict__ src,
-                                              void* __restrict__ dst,
-                                              const float2* __restrict__ rdec,
-                                              const float2* __restrict__ renc) {
-  // one thread per (node of the particle's box, direction 1..18)
+__global__ __launch_bounds__(256) void k_links(Batch bt) {
+  // one thread per (node of the particle's box, direction 1..18); runs after
+  // k_fused, before the buffers swap: src holds the state it read, dst the
+  // state it wrote
   using IO = Codec<STORE>;
   using T = typename IO::T;
-  const int p = blockIdx.y;
+  const int2 sp = batch_particle(bt, blockIdx.y);
+  const SimDev& s = bt.tab[sp.x];
+  const int p = sp.y;
+  const void* __restrict__ src = s.pops[bt.cur];
+  void* __restrict__ dst = s.pops[bt.cur ^ 1];
+  const float2* __restrict__ rdec = s.ref[bt.rd];
+  const float2* __restrict__ renc = s.ref[bt.rd ^ 1];
   const DevParticle& P = s.P[p];
   const int nx = s.nx, ny = s.ny, nz = s.nz, N = (int)s.N;
   const float rho0 = s.rho0;
@@ -561,58 +577,51 @@ __global__ __launch_bounds__(256) void k_links(SimDev s, const void* __restrict_
 // ------------------------------------------------------------ host launchers
 static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_interface(const SimDev& s, float4* nrm, float2* cur, hipStream_t st) {
-  const dim3 grid(nblocks(s.N, 256));
-  hipLaunchKernelGGL(k_normal, grid, dim3(256), 0, st, s, nrm);
-  hipLaunchKernelGGL(k_curv, grid, dim3(256), 0, st, s, (const float4*)nrm, cur);
+// Batched launchers: one launch over every simulation of the batch.
+// nblk: total 256-node blocks; np_rows: total particle rows; Bmax: the largest
+// mask-box side of the batch.
+hipError_t launch_interface(const Batch& b, unsigned nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_normal, dim3(nblk), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_curv, dim3(nblk), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
-// rd: index of the reference-density buffer the current populations are
-// encoded with (FP16 storage); new populations use the other one
-hipError_t launch_fused(const SimDev& s, const void* src, void* dst, const float4* nrm,
-                        const float2* cur, int mode, int rd, float* orho, float* ou, float* ophi,
-                        float* oF, hipStream_t st) {
-  const dim3 grid(nblocks(s.N, 256));
-  const float2* rdec = s.ref[rd];
-  const float2* renc = s.ref[rd ^ 1];
-  if (s.storage == 0) {
+hipError_t launch_fused(const Batch& b, int storage, unsigned nblk, int mode, float* orho,
+                        float* ou, float* ophi, float* oF, hipStream_t st) {
+  const dim3 grid(nblk);
+  if (storage == 0) {
     if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_fused<0, MODE_STEP>), grid, dim3(256), 0, st, s, src, dst, nrm, cur,
-                         rdec, renc, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<0, MODE_STEP>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
     else
-      hipLaunchKernelGGL((k_fused<0, MODE_FIELDS>), grid, dim3(256), 0, st, s, src, dst, nrm,
-                         cur, rdec, renc, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<0, MODE_FIELDS>), grid, dim3(256), 0, st, b, orho, ou, ophi,
+                         oF);
   } else {
     if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_fused<1, MODE_STEP>), grid, dim3(256), 0, st, s, src, dst, nrm, cur,
-                         rdec, renc, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<1, MODE_STEP>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
     else
-      hipLaunchKernelGGL((k_fused<1, MODE_FIELDS>), grid, dim3(256), 0, st, s, src, dst, nrm,
-                         cur, rdec, renc, orho, ou, ophi, oF);
+      hipLaunchKernelGGL((k_fused<1, MODE_FIELDS>), grid, dim3(256), 0, st, b, orho, ou, ophi,
+                         oF);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_links(const SimDev& s, const void* src, void* dst, int Bmask, int rd,
-                        hipStream_t st) {
-  if (s.np == 0) return hipSuccess;
+hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipStream_t st) {
+  if (np_rows == 0) return hipSuccess;
   // the box of k_links spans at most 2 R + 6 nodes per axis, R <= (Bmask - 5) / 2
-  const long long B = Bmask + 1;
-  const dim3 grid((unsigned)((B * B * B * 18 + 255) / 256), s.np);
-  if (s.storage == 0)
-    hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, s, src, dst, s.ref[rd], s.ref[rd ^ 1]);
+  const long long B = Bmax + 1;
+  const dim3 grid((unsigned)((B * B * B * 18 + 255) / 256), np_rows);
+  if (storage == 0)
+    hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL(k_links<1>, grid, dim3(256), 0, st, s, src, dst, s.ref[rd], s.ref[rd ^ 1]);
+    hipLaunchKernelGGL(k_links<1>, grid, dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const SimDev& s, const void* pops, int rd, hipStream_t st) {
-  const dim3 grid(nblocks(s.N, 256));
-  if (s.storage == 0)
-    hipLaunchKernelGGL(k_moments<0>, grid, dim3(256), 0, st, s, pops, s.ref[rd], s.ref[rd ^ 1]);
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(k_moments<0>, dim3(nblk), dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL(k_moments<1>, grid, dim3(256), 0, st, s, pops, s.ref[rd], s.ref[rd ^ 1]);
+    hipLaunchKernelGGL(k_moments<1>, dim3(nblk), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

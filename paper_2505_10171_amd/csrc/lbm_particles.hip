@@ -43,8 +43,10 @@ __device__ __attribute__((noinline)) bool inside_sphere(int x, int y, int z, con
 }
 
 // claim: lowest particle index inside which a node lies (new positions)
-__global__ void k_claim(SimDev s) {
-  const int p = blockIdx.y;
+__global__ void k_claim(Batch bt) {
+  const int2 sp = batch_particle(bt, blockIdx.y);
+  const SimDev& s = bt.tab[sp.x];
+  const int p = sp.y;
   const DevParticle& P = s.P[p];
   const Box b = particle_box(s, P.x, P.R);
   const int vol = b.w[0] * b.w[1] * b.w[2];
@@ -62,8 +64,10 @@ __global__ void k_claim(SimDev s) {
 
 // release: nodes that belonged to p (old box) become fluid (fresh) or pass to
 // the particle that claims them now.  Each such node is visited once (by p).
-__global__ void k_release(SimDev s) {
-  const int p = blockIdx.y;
+__global__ void k_release(Batch bt) {
+  const int2 sp = batch_particle(bt, blockIdx.y);
+  const SimDev& s = bt.tab[sp.x];
+  const int p = sp.y;
   const DevParticle& P = s.P[p];
   double Xo[3] = {P.xo[0], P.xo[1], P.xo[2]};
   const Box b = particle_box(s, Xo, P.Ro);
@@ -91,8 +95,10 @@ __global__ void k_release(SimDev s) {
 }
 
 // cover: nodes claimed by p become p's solid nodes; claims are cleared
-__global__ void k_cover(SimDev s) {
-  const int p = blockIdx.y;
+__global__ void k_cover(Batch bt) {
+  const int2 sp = batch_particle(bt, blockIdx.y);
+  const SimDev& s = bt.tab[sp.x];
+  const int p = sp.y;
   const DevParticle& P = s.P[p];
   const Box b = particle_box(s, P.x, P.R);
   const int vol = b.w[0] * b.w[1] * b.w[2];
@@ -112,11 +118,15 @@ __global__ void k_cover(SimDev s) {
 // neighbour densities (fluid, not fresh, D3Q19 neighbours; rho0/2 each if none)
 // at the surface velocity of the particle that uncovered it.
 template <int STORE>
-__global__ __launch_bounds__(256) void k_refill(SimDev s, void* pops,
-                                               const float2* __restrict__ rdec) {
-  // one thread per (fresh node, neighbour direction): 14 fresh nodes per block
+__global__ __launch_bounds__(256) void k_refill(Batch bt) {
+  // one thread per (fresh node, neighbour direction): 14 fresh nodes per
+  // block; grid row = simulation
   using IO = Codec<STORE>;
   using T = typename IO::T;
+  const SimDev& s = bt.tab[blockIdx.y];
+  if (s.np == 0) return;
+  void* pops = s.pops[bt.cur];
+  const float2* __restrict__ rdec = s.ref[bt.rd];
   constexpr int PER = 14;
   __shared__ float sh_a[PER][18], sh_b[PER][18];
   __shared__ int sh_c[PER][18];
@@ -199,8 +209,10 @@ __global__ __launch_bounds__(256) void k_refill(SimDev s, void* pops,
 // -------------------------------------------------------------- capillary
 // per-particle box of (phi, G) at the nodes the Lagrangian points interpolate
 // (G after the wetting rotation, from the step's normal field)
-__global__ void k_capbox(SimDev s) {
-  const int p = blockIdx.y;
+__global__ void k_capbox(Batch bt) {
+  const int2 sp = batch_particle(bt, blockIdx.y);
+  const SimDev& s = bt.tab[sp.x];
+  const int p = sp.y;
   const DevParticle& P = s.P[p];
   const int B = s.cap_B;
   int org[3];
@@ -228,8 +240,10 @@ __global__ void k_capbox(SimDev s) {
 // torque arm R n_s; phi and G trilinear over fluid corners.  A grid row of
 // workgroups per particle, FP64 block reductions combined with FP64 atomics
 // (the accumulators are consumed and cleared by the DEM).
-__global__ __launch_bounds__(256) void k_capillary(SimDev s) {
-  const int p = blockIdx.y;
+__global__ __launch_bounds__(256) void k_capillary(Batch bt) {
+  const int2 sp = batch_particle(bt, blockIdx.y);
+  const SimDev& s = bt.tab[sp.x];
+  const int p = sp.y;
   DevParticle& P = s.P[p];
   const int B = s.cap_B;
   const float4* box = s.capbox + (long long)p * B * B * B;
@@ -421,7 +435,10 @@ __device__ void quat_rotate(double* q, const double* th) {
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
 template <bool SH>
-__global__ __launch_bounds__(256) void k_dem(SimDev s) {
+__global__ __launch_bounds__(256) void k_dem(Batch bt) {
+  // one workgroup per simulation
+  const SimDev& s = bt.tab[blockIdx.x];
+  if (s.np == 0) return;
   // SH: particle records, contact tables and candidate lists staged in LDS
   // for the whole lattice step (dependent FP64 chains then wait on LDS, not
   // on L2/HBM), written back at the end
@@ -635,38 +652,42 @@ static inline unsigned box_blocks(int B) {
   return (unsigned)((v + 255) / 256);
 }
 
-hipError_t launch_mask_update(const SimDev& s, int Bmask, bool with_release, hipStream_t st) {
-  if (s.np == 0) return hipSuccess;
-  dim3 grid(box_blocks(Bmask), s.np);
-  hipLaunchKernelGGL(k_claim, grid, dim3(256), 0, st, s);
-  if (with_release) hipLaunchKernelGGL(k_release, grid, dim3(256), 0, st, s);
-  hipLaunchKernelGGL(k_cover, grid, dim3(256), 0, st, s);
+hipError_t launch_mask_update(const Batch& b, int np_rows, int Bmax, bool with_release,
+                              hipStream_t st) {
+  if (np_rows == 0) return hipSuccess;
+  dim3 grid(box_blocks(Bmax), np_rows);
+  hipLaunchKernelGGL(k_claim, grid, dim3(256), 0, st, b);
+  if (with_release) hipLaunchKernelGGL(k_release, grid, dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_cover, grid, dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
-hipError_t launch_refill(const SimDev& s, void* pops, int rd, hipStream_t st) {
-  if (s.np == 0) return hipSuccess;
-  unsigned nb = (s.fresh_cap + 13) / 14;
+// fresh_cap_max: the largest fresh-list capacity of the batch
+hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, hipStream_t st) {
+  if (fresh_cap_max == 0) return hipSuccess;
+  unsigned nb = (unsigned)((fresh_cap_max + 13) / 14);
   if (nb > 128) nb = 128;
   if (nb == 0) nb = 1;
-  if (s.storage == 0)
-    hipLaunchKernelGGL(k_refill<0>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
+  const dim3 grid(nb, b.nsim);
+  if (storage == 0)
+    hipLaunchKernelGGL(k_refill<0>, grid, dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL(k_refill<1>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
+    hipLaunchKernelGGL(k_refill<1>, grid, dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
-hipError_t launch_capillary(const SimDev& s, hipStream_t st) {
-  if (s.np == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_capbox, dim3(box_blocks(s.cap_B), s.np), dim3(256), 0, st, s);
-  const int npts = s.cap_na * s.cap_nphi;
+// cap_B: the largest capillary-box side; npts: Lagrangian points per particle
+hipError_t launch_capillary(const Batch& b, int np_rows, int cap_B, int npts, hipStream_t st) {
+  if (np_rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_capbox, dim3(box_blocks(cap_B), np_rows), dim3(256), 0, st, b);
   const unsigned split = (unsigned)std::max(1, std::min(64, npts / (256 * 4)));
-  hipLaunchKernelGGL(k_capillary, dim3(split, s.np), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_capillary, dim3(split, np_rows), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
-hipError_t launch_dem(const SimDev& s, hipStream_t st) {
-  if (s.np == 0) return hipSuccess;
+// np_max: the most particles of one simulation in the batch
+hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
+  if (np_max == 0) return hipSuccess;
   static int max_lds = -1;
   if (max_lds < 0) {
     int dev = 0, v = 0;
@@ -675,12 +696,12 @@ hipError_t launch_dem(const SimDev& s, hipStream_t st) {
       v = 0;
     max_lds = v;
   }
-  const size_t need = (size_t)s.np * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
-                      (size_t)s.np * MAXNB * sizeof(int);
+  const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
+                      (size_t)np_max * MAXNB * sizeof(int);
   if (need <= (size_t)max_lds && need <= 64 * 1024)
-    hipLaunchKernelGGL(k_dem<true>, dim3(1), dim3(256), need, st, s);
+    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(256), need, st, b);
   else
-    hipLaunchKernelGGL(k_dem<false>, dim3(1), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -1,0 +1,85 @@
+"""Batched ensembles: several simulations of uneven boxes advanced together,
+one launch per phase over all of them, against the same simulations run one
+per context and against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSim
+from paper_2505_10171_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(24, 24, 24), (32, 20, 22), (20, 20, 20), (28, 24, 26)]
+
+
+def members(storage="fp32"):
+    out = []
+    for i, (nx, ny, nz) in enumerate(SIZES):
+        cfg = W.config(nx, ny, nz, theta_wall_deg=80.0 + 10 * i, storage=storage,
+                       body_force=(2e-6 * (i + 1), 0.0, 0.0))
+        Rd = min(nx, ny) / 4.0
+        phi0 = W.drop_phi0(nx, ny, nz, (nx / 4.0, ny / 2.0, 0.5), Rd)
+        parts = [] if i == 2 else [
+            W.particle((nx / 2.0 + 4.0, ny / 2.0 + 0.3, 0.5 + 4.0), 3.0, theta_deg=60.0 + 10 * i,
+                       mu_s=0.3, mu_r=0.02, sigma=cfg["sigma"])]
+        out.append(dict(cfg=cfg, phi0=phi0, particles=parts))
+    return out
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def field_errors(g, o, sim_g=0, sim_o=0):
+    rg, ug, pg, mg = g.fields(sim_g)
+    ro, uo, po, mo = o.fields(sim_o) if hasattr(o, "n") else o.fields()
+    assert np.array_equal(mg, mo)
+    fl = mo == 0
+    return dict(rho=rel_l2(rg[fl], ro[fl]), u=rel_l2(ug[:, fl], uo[:, fl]),
+                phi=rel_l2(pg[fl], po[fl]))
+
+
+def test_batched_matches_separate_contexts():
+    from paper_2505_10171_amd.lbm import Context, Simulation
+    ms = members()
+    ens = Context(ms)
+    ens.step(60)
+    for i, m in enumerate(ms):
+        one = Simulation(m["cfg"], m["phi0"], m["particles"])
+        one.step(60)
+        e = field_errors(ens, one, sim_g=i)
+        print("member", i, {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        for v in e.values():
+            assert v <= 1e-6, (i, e)
+        if m["particles"]:
+            pe, po = ens.particles(i)[0], one.particles()[0]
+            assert np.abs(np.array(pe["x"]) - np.array(po["x"])).max() <= 1e-9
+        one.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 1e-5), ("fp16", 1e-3)])
+def test_batched_members_against_oracle(storage, tol):
+    from paper_2505_10171_amd.lbm import Context
+    ms = members(storage)
+    ens = Context(ms)
+    ens.step(60)
+    for i in (0, 3):
+        m = ms[i]
+        o = OracleSim(dict(m["cfg"], storage="fp32"), m["phi0"], m["particles"])
+        o.step(60)
+        e = field_errors(ens, o, sim_g=i)
+        print(storage, "member", i, {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        for v in e.values():
+            assert v <= tol, (i, e)
+        o.close()
+
+
+def test_mixed_storage_is_rejected():
+    from paper_2505_10171_amd.lbm import Context, LbmError
+    ms = members()
+    ms[1]["cfg"] = dict(ms[1]["cfg"], storage="fp16")
+    with pytest.raises(LbmError):
+        Context(ms)
