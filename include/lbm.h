@@ -191,6 +191,15 @@ int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out);
 int lbm_profile(lbm_ctx* ctx, int32_t enable);
 int lbm_profile_read(lbm_ctx* ctx, double* total_ms, int64_t* launches, int32_t n_kinds);
 
+/* Graph replay of steps.  With enable = 1, lbm_step captures two consecutive
+ * steps of every simulation into a HIP graph on the context's stream the first
+ * time it runs at least two steps, and from then on replays that graph for each
+ * pair of steps (an odd remaining step runs as ordinary launches).  The result
+ * is the same as without the graph.  Needs a stream other than the null stream
+ * (LBM_EINVAL otherwise); steps taken while lbm_profile is on are never
+ * replayed from the graph.  enable = 0 releases the graph. */
+int lbm_use_graph(lbm_ctx* ctx, int32_t enable);
+
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Sticky error message of the context, or NULL if there is none. */

@@ -22,7 +22,7 @@ HIST_DOUBLES = 27
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_sync", "lbm_particles_sync",
            "lbm_fields", "lbm_fields2", "lbm_links", "lbm_mass", "lbm_dem_substeps", "lbm_destroy",
-           "lbm_last_error", "lbm_profile", "lbm_profile_read"]
+           "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_use_graph"]
 PROFILE_KINDS = ("fused", "particles", "moments", "interface")
 
 
@@ -76,6 +76,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.lbm_dem_substeps.argtypes = [vp, i32, C.POINTER(i32)]
     L.lbm_profile.argtypes = [vp, i32]
     L.lbm_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
+    L.lbm_use_graph.argtypes = [vp, i32]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = [vp]
@@ -301,6 +302,10 @@ class Context:
         cnt = (C.c_int64 * n)()
         self._check(load_library().lbm_profile_read(self.h, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_KINDS)}
+
+    def use_graph(self, enable: bool = True):
+        """Replay pairs of steps from a captured HIP graph (needs a non-null stream)."""
+        self._check(load_library().lbm_use_graph(self.h, int(bool(enable))))
 
     def dem_substeps(self, sim: int = 0):
         v = C.c_int32(0)
