@@ -5,14 +5,14 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(CSRC, "liblbm.so")
-SOURCES = ["lbm_fluid.hip", "lbm_particles.hip", "lbm_api.hip"]
+SOURCES = ["lbm_fluid.hip", "lbm_particles.hip", "lbm_api.hip", "srg.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off: plain scalar/float2 code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     objs = []
     procs = []
     for src in SOURCES:

@@ -1,0 +1,623 @@
+// srg.hip -- BF16 matrix-core training and inference of the run-outcome
+// surrogate (see include/srg.h) for gfx950.
+//
+// Every layer product is one GEMM kernel: a 64x64 output tile per 256-thread
+// workgroup, K in steps of 32 staged through LDS (both operands stored with K
+// contiguous, so each lane reads its eight-element fragment with one 16-byte
+// LDS load), and each of the four waves accumulating a 32x32 sub-tile with
+// four v_mfma_f32_16x16x32_bf16 per K step.  Transposed operands (W^T in dX,
+// X^T in dW) are transposed while staging.  Epilogues fuse the bias, the ReLU
+// and the ReLU derivative.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "../../include/srg.h"
+
+namespace srg {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NL = 5;                                  // layers
+constexpr int KIN[NL] = {32, 256, 256, 256, 256};      // padded fan-in
+constexpr int NOUT[NL] = {256, 256, 256, 256, 64};     // padded fan-out
+constexpr int KREAL[NL] = {SRG_IN, 256, 256, 256, 256};
+constexpr int NREAL[NL] = {256, 256, 256, 256, SRG_OUT};
+constexpr int NCLS = 3, NTRAJ = 48;
+constexpr int ALIGN = 256;
+
+enum { EPI_RELU_BF16 = 0, EPI_LINEAR_F32 = 1, EPI_DRELU_BF16 = 2, EPI_F32 = 3 };
+
+// C[M x N] = A[M x K] * B[K x N].  TA: A stored as [K x M] (lda = its row
+// length); TB: B stored as [N x K].  M, N multiples of 8 (rows/columns outside
+// are skipped), K a multiple of 32.
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A,
+                                              int lda, const bf16* __restrict__ B, int ldb,
+                                              const float* __restrict__ bias,
+                                              const bf16* __restrict__ act, int ldact,
+                                              bf16* __restrict__ Cb, float* __restrict__ Cf,
+                                              int ldc) {
+  constexpr int LD = 40;  // LDS row: 32 K values + 8 padding (80 bytes)
+  __shared__ __attribute__((aligned(16))) bf16 As[64 * LD];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero8 = {};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    __syncthreads();
+    // stage A tile (64 rows of M, 32 of K)
+    if (!TA) {
+      const int r = t >> 2, kc = (t & 3) * 8;
+      bf16x8 v = zero8;
+      if (m0 + r < M) v = *(const bf16x8*)(A + (long long)(m0 + r) * lda + k0 + kc);
+      *(bf16x8*)(As + r * LD + kc) = v;
+    } else {
+      const int k = t >> 3, mc = (t & 7) * 8;
+      bf16x8 v = zero8;
+      if (m0 + mc < M) v = *(const bf16x8*)(A + (long long)(k0 + k) * lda + m0 + mc);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[(mc + j) * LD + k] = v[j];
+    }
+    // stage B tile (64 columns of N, 32 of K), stored column-major in LDS
+    if (TB) {
+      const int r = t >> 2, kc = (t & 3) * 8;
+      bf16x8 v = zero8;
+      if (n0 + r < N) v = *(const bf16x8*)(B + (long long)(n0 + r) * ldb + k0 + kc);
+      *(bf16x8*)(Bs + r * LD + kc) = v;
+    } else {
+      const int k = t >> 3, nc = (t & 7) * 8;
+      bf16x8 v = zero8;
+      if (n0 + nc < N) v = *(const bf16x8*)(B + (long long)(k0 + k) * ldb + n0 + nc);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bs[(nc + j) * LD + k] = v[j];
+    }
+    __syncthreads();
+    // lane l: row (l % 16) of each 16-row block, K elements (l / 16) * 8 .. + 7
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)(As + (wm + i * 16 + fr) * LD + fk);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)(Bs + (wn + j * 16 + fr) * LD + fk);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+  // lane l holds C rows (l / 16) * 4 + r (r = 0..3) of column l % 16 per block
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + j * 16 + (lane & 15);
+      if (n >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        if (m >= M) continue;
+        const float c = acc[i][j][r];
+        const long long o = (long long)m * ldc + n;
+        if (EPI == EPI_RELU_BF16) {
+          Cb[o] = (bf16)fmaxf(c + bias[n], 0.f);
+        } else if (EPI == EPI_LINEAR_F32) {
+          Cf[o] = c + bias[n];
+        } else if (EPI == EPI_DRELU_BF16) {
+          Cb[o] = (bf16)((float)act[(long long)m * ldact + n] > 0.f ? c : 0.f);
+        } else {
+          Cf[o] = c;
+        }
+      }
+    }
+}
+
+// rows of the training set picked by the permutation, as padded BF16 inputs
+__global__ void k_gather(const bf16* __restrict__ Xall, const int* __restrict__ perm, int off,
+                         int B, bf16* __restrict__ Xb) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * 4) return;
+  const int r = t >> 2, c = (t & 3) * 8;
+  *(bf16x8*)(Xb + (long long)r * 32 + c) = *(const bf16x8*)(Xall + (long long)perm[off + r] * 32 + c);
+}
+
+// FP32 inputs (n x 6) -> padded BF16 rows (n x 32)
+__global__ void k_pack_inputs(const float* __restrict__ X, int n, bf16* __restrict__ Xb) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * 32) return;
+  const int r = t >> 5, c = t & 31;
+  Xb[t] = (bf16)(c < SRG_IN ? X[(long long)r * SRG_IN + c] : 0.f);
+}
+
+// loss and its gradient dL/dy (B x 64, BF16, zero in the padding); loss sum in
+// acc[0] (atomic).  Sample r of the batch is training row perm[off + r] (perm
+// null: row r of lab/traj).
+__global__ void k_loss(const float* __restrict__ Y, const int* __restrict__ perm, int off, int B,
+                       const int* __restrict__ lab, const float* __restrict__ traj, float w_traj,
+                       bf16* __restrict__ dY, float* __restrict__ acc) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (r < B) {
+    const int row = perm ? perm[off + r] : r;
+    const float* y = Y + (long long)r * 64;
+    const float mx = fmaxf(y[0], fmaxf(y[1], y[2]));
+    float e[NCLS], se = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+      e[c] = __expf(y[c] - mx);
+      se += e[c];
+    }
+    const int lb = lab[row];
+    bf16* d = dY + (long long)r * 64;
+    const float invB = 1.0f / (float)B;
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+      const float p = e[c] / se;
+      d[c] = (bf16)((p - (c == lb ? 1.f : 0.f)) * invB);
+    }
+    l = -(y[lb] - mx - __logf(se));
+    const float* tr = traj + (long long)row * NTRAJ;
+    const float s = 2.f * w_traj * invB / (float)NTRAJ;
+    float se2 = 0.f;
+    for (int j = 0; j < NTRAJ; ++j) {
+      const float df = y[NCLS + j] - tr[j];
+      se2 += df * df;
+      d[NCLS + j] = (bf16)(s * df);
+    }
+    for (int j = NCLS + NTRAJ; j < 64; ++j) d[j] = (bf16)0.f;
+    l = (l + w_traj * se2 / (float)NTRAJ) * invB;
+  }
+  // wave sum, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(acc, l);
+}
+
+// column sums of a BF16 matrix (bias gradient): one thread per column
+__global__ void k_colsum(const bf16* __restrict__ D, int M, int N, int ld, float* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int m = 0; m < M; ++m) s += (float)D[(long long)m * ld + n];
+  out[n] = s;
+}
+
+// Adam on the whole parameter vector; refreshes the BF16 copy
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, bf16* __restrict__ pb, long long n, float lr,
+                       float bc1, float bc2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+  p[i] = pi;
+  pb[i] = (bf16)pi;
+}
+
+__global__ void k_to_bf16(const float* __restrict__ p, bf16* __restrict__ pb, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pb[i] = (bf16)p[i];
+}
+
+// y (n x 51) from the padded FP32 output rows (n x 64)
+__global__ void k_unpack_outputs(const float* __restrict__ Y, int n, float* __restrict__ y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * SRG_OUT) return;
+  const int r = t / SRG_OUT, c = t - r * SRG_OUT;
+  y[t] = Y[(long long)r * 64 + c];
+}
+
+}  // namespace srg
+
+using namespace srg;
+
+namespace {
+size_t aup(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t w_off[NL], b_off[NL], n_par;  // offsets (elements) in the padded vector
+  size_t off_p, off_g, off_m, off_v, off_pb, off_xall, off_lab, off_traj, off_perm, off_xb,
+      off_act[NL], off_y, off_dy, off_dz[2], off_acc, off_xin, off_yout, total;
+};
+
+Layout make_layout(int max_batch, int max_train) {
+  Layout L{};
+  size_t e = 0;
+  for (int l = 0; l < NL; ++l) {
+    L.w_off[l] = e;
+    e += (size_t)KIN[l] * NOUT[l];
+    L.b_off[l] = e;
+    e += NOUT[l];
+  }
+  L.n_par = e;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = aup(o + std::max<size_t>(bytes, 1));
+    return r;
+  };
+  L.off_p = take(4 * e);
+  L.off_g = take(4 * e);
+  L.off_m = take(4 * e);
+  L.off_v = take(4 * e);
+  L.off_pb = take(2 * e);
+  L.off_xall = take(2 * 32 * (size_t)max_train);
+  L.off_lab = take(4 * (size_t)max_train);
+  L.off_traj = take(4 * NTRAJ * (size_t)max_train);
+  L.off_perm = take(4 * (size_t)max_train);
+  L.off_xb = take(2 * 32 * (size_t)max_batch);
+  for (int l = 0; l < NL; ++l) L.off_act[l] = take(2 * 256 * (size_t)max_batch);  // act[0] unused
+  L.off_y = take(4 * 64 * (size_t)max_batch);
+  L.off_dy = take(2 * 64 * (size_t)max_batch);
+  L.off_dz[0] = take(2 * 256 * (size_t)max_batch);
+  L.off_dz[1] = take(2 * 256 * (size_t)max_batch);
+  L.off_acc = take(64);
+  L.off_xin = take(4 * SRG_IN * (size_t)max_batch);
+  L.off_yout = take(4 * SRG_OUT * (size_t)max_batch);
+  L.total = o;
+  return L;
+}
+
+uint16_t host_bf16(float f) {  // round to nearest even
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+}  // namespace
+
+struct srg_ctx {
+  hipStream_t stream;
+  char* ws;
+  Layout L;
+  int max_batch, max_train, n_train = 0;
+  int step = 0;  // Adam step count
+  int err = 0;
+  char msg[256];
+  float* p() { return (float*)(ws + L.off_p); }
+  float* g() { return (float*)(ws + L.off_g); }
+  bf16* pb() { return (bf16*)(ws + L.off_pb); }
+  bf16* act(int l) { return (bf16*)(ws + L.off_act[l]); }
+};
+
+static int srg_err(srg_ctx* c, int code, const char* fmt, ...) {
+  if (c && c->err == 0) {
+    c->err = code;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->msg, sizeof c->msg, fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+#define SCHK(ctx, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return srg_err((ctx), LBM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+template <bool TA, bool TB, int EPI>
+static hipError_t gemm(hipStream_t st, int M, int N, int K, const bf16* A, int lda, const bf16* B,
+                       int ldb, const float* bias, const bf16* act, int ldact, bf16* Cb, float* Cf,
+                       int ldc) {
+  const dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, bias,
+                     act, ldact, Cb, Cf, ldc);
+  return hipGetLastError();
+}
+
+// forward over B rows of packed inputs Xb: activations act[1..4], output Y
+static int forward(srg_ctx* c, const bf16* Xb, int B) {
+  hipStream_t st = c->stream;
+  const float* p = c->p();
+  const bf16* pb = c->pb();
+  const bf16* in = Xb;
+  int ld_in = 32;
+  for (int l = 0; l < NL - 1; ++l) {
+    SCHK(c, (gemm<false, false, EPI_RELU_BF16>(st, B, NOUT[l], KIN[l], in, ld_in, pb + c->L.w_off[l],
+                                               NOUT[l], p + c->L.b_off[l], nullptr, 0,
+                                               c->act(l + 1), nullptr, 256)));
+    in = c->act(l + 1);
+    ld_in = 256;
+  }
+  SCHK(c, (gemm<false, false, EPI_LINEAR_F32>(st, B, 64, 256, in, 256, pb + c->L.w_off[4], 64,
+                                              p + c->L.b_off[4], nullptr, 0, nullptr,
+                                              (float*)(c->ws + c->L.off_y), 64)));
+  return LBM_OK;
+}
+
+// loss gradient dY is in place; backward through all layers into the gradient vector
+static int backward(srg_ctx* c, const bf16* Xb, int B) {
+  hipStream_t st = c->stream;
+  const bf16* pb = c->pb();
+  float* g = c->g();
+  const bf16* dz = (const bf16*)(c->ws + c->L.off_dy);
+  int ld_dz = 64;
+  int which = 0;
+  for (int l = NL - 1; l >= 0; --l) {
+    const bf16* a_in = l == 0 ? Xb : c->act(l);
+    const int ld_in = l == 0 ? 32 : 256;
+    // dW_l = a_in^T dz  (KIN x NOUT)
+    SCHK(c, (gemm<true, false, EPI_F32>(st, KIN[l], NOUT[l], B, a_in, ld_in, dz, ld_dz, nullptr,
+                                        nullptr, 0, nullptr, g + c->L.w_off[l], NOUT[l])));
+    hipLaunchKernelGGL(k_colsum, dim3((NOUT[l] + 255) / 256), dim3(256), 0, st, dz, B, NOUT[l],
+                       ld_dz, g + c->L.b_off[l]);
+    SCHK(c, hipGetLastError());
+    if (l > 0) {
+      // dz_{l-1} = (dz W_l^T) * relu'(a_in)
+      bf16* nd = (bf16*)(c->ws + c->L.off_dz[which]);
+      SCHK(c, (gemm<false, true, EPI_DRELU_BF16>(st, B, 256, NOUT[l], dz, ld_dz, pb + c->L.w_off[l],
+                                                 NOUT[l], nullptr, a_in, 256, nd, nullptr, 256)));
+      dz = nd;
+      ld_dz = 256;
+      which ^= 1;
+    }
+  }
+  return LBM_OK;
+}
+
+extern "C" {
+
+size_t srg_workspace_bytes(int32_t max_batch, int32_t max_train) {
+  if (max_batch < 64 || max_batch % 64 != 0 || max_train < 0) return 0;
+  return make_layout(max_batch, max_train).total;
+}
+
+int srg_create(void* dev_workspace, size_t ws_bytes, int32_t max_batch, int32_t max_train,
+               void* hip_stream, srg_ctx** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  const size_t need = srg_workspace_bytes(max_batch, max_train);
+  if (need == 0 || !dev_workspace) return LBM_EINVAL;
+  if (ws_bytes < need) return LBM_ENOMEM;
+  if (((uintptr_t)dev_workspace) % ALIGN != 0) return LBM_EINVAL;
+  srg_ctx* c = new (std::nothrow) srg_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)dev_workspace;
+  c->L = make_layout(max_batch, max_train);
+  c->max_batch = max_batch;
+  c->max_train = max_train;
+  c->msg[0] = 0;
+  *out = c;
+  // zero parameters, gradients, moments (padding stays zero forever)
+  SCHK(c, hipMemsetAsync(c->ws, 0, c->L.off_xall, c->stream));
+  SCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int srg_set_params(srg_ctx* c, const float* params) {
+  if (!c || !params) return LBM_EINVAL;
+  if (c->err) return LBM_ESTATE;
+  std::vector<float> pad(c->L.n_par, 0.f);
+  size_t k = 0;
+  for (int l = 0; l < NL; ++l) {
+    for (int i = 0; i < KREAL[l]; ++i)
+      for (int j = 0; j < NREAL[l]; ++j) pad[c->L.w_off[l] + (size_t)i * NOUT[l] + j] = params[k++];
+    for (int j = 0; j < NREAL[l]; ++j) pad[c->L.b_off[l] + j] = params[k++];
+  }
+  const size_t nb = 4 * c->L.n_par;
+  SCHK(c, hipMemcpyAsync(c->p(), pad.data(), nb, hipMemcpyHostToDevice, c->stream));
+  SCHK(c, hipMemsetAsync(c->ws + c->L.off_m, 0, nb, c->stream));
+  SCHK(c, hipMemsetAsync(c->ws + c->L.off_v, 0, nb, c->stream));
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((c->L.n_par + 255) / 256)), dim3(256), 0, c->stream,
+                     c->p(), c->pb(), (long long)c->L.n_par);
+  SCHK(c, hipGetLastError());
+  c->step = 0;
+  SCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+static void unpad(const srg_ctx* c, const std::vector<float>& pad, float* out) {
+  size_t k = 0;
+  for (int l = 0; l < NL; ++l) {
+    for (int i = 0; i < KREAL[l]; ++i)
+      for (int j = 0; j < NREAL[l]; ++j) out[k++] = pad[c->L.w_off[l] + (size_t)i * NOUT[l] + j];
+    for (int j = 0; j < NREAL[l]; ++j) out[k++] = pad[c->L.b_off[l] + j];
+  }
+}
+
+int srg_get_params(srg_ctx* c, float* params) {
+  if (!c || !params) return LBM_EINVAL;
+  if (c->err) return LBM_ESTATE;
+  std::vector<float> pad(c->L.n_par);
+  SCHK(c, hipMemcpyAsync(pad.data(), c->p(), 4 * c->L.n_par, hipMemcpyDeviceToHost, c->stream));
+  SCHK(c, hipStreamSynchronize(c->stream));
+  unpad(c, pad, params);
+  return LBM_OK;
+}
+
+static int upload_set(srg_ctx* c, const float* X, const int32_t* label, const float* traj, int n,
+                      size_t off_x, size_t off_lab, size_t off_traj) {
+  std::vector<uint16_t> xb((size_t)n * 32, 0);
+  for (int r = 0; r < n; ++r)
+    for (int j = 0; j < SRG_IN; ++j) xb[(size_t)r * 32 + j] = host_bf16(X[(size_t)r * SRG_IN + j]);
+  SCHK(c, hipMemcpyAsync(c->ws + off_x, xb.data(), 2 * xb.size(), hipMemcpyHostToDevice, c->stream));
+  if (label)
+    SCHK(c, hipMemcpyAsync(c->ws + off_lab, label, 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  if (traj)
+    SCHK(c, hipMemcpyAsync(c->ws + off_traj, traj, 4 * (size_t)NTRAJ * n, hipMemcpyHostToDevice,
+                           c->stream));
+  SCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int srg_set_train(srg_ctx* c, const float* X, const int32_t* label, const float* traj, int32_t n) {
+  if (!c || !X || !label || !traj || n < 1) return LBM_EINVAL;
+  if (c->err) return LBM_ESTATE;
+  if (n > c->max_train) return srg_err(c, LBM_ERANGE, "training set larger than max_train");
+  for (int i = 0; i < n; ++i)
+    if (label[i] < 0 || label[i] >= NCLS) return srg_err(c, LBM_EINVAL, "label out of range");
+  int rc = upload_set(c, X, label, traj, n, c->L.off_xall, c->L.off_lab, c->L.off_traj);
+  if (rc) return rc;
+  c->n_train = n;
+  return LBM_OK;
+}
+
+static int adam(srg_ctx* c, float lr) {
+  ++c->step;
+  const float bc1 = 1.f - powf(0.9f, (float)c->step), bc2 = 1.f - powf(0.999f, (float)c->step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((c->L.n_par + 255) / 256)), dim3(256), 0, c->stream,
+                     c->p(), c->g(), (float*)(c->ws + c->L.off_m), (float*)(c->ws + c->L.off_v),
+                     c->pb(), (long long)c->L.n_par, lr, bc1, bc2);
+  SCHK(c, hipGetLastError());
+  return LBM_OK;
+}
+
+int srg_train(srg_ctx* c, int32_t epochs, int32_t batch, float lr, float w_traj, uint64_t seed,
+              float* epoch_loss) {
+  if (!c) return LBM_EINVAL;
+  if (c->err) return LBM_ESTATE;
+  if (epochs < 0 || batch < 64 || batch % 64 != 0 || batch > c->max_batch || batch > c->n_train)
+    return srg_err(c, LBM_EINVAL, "batch must be a multiple of 64, <= max_batch and the set size");
+  const int n = c->n_train, nb = n / batch;
+  std::mt19937_64 rng(seed);
+  std::vector<int> perm(n);
+  float* acc = (float*)(c->ws + c->L.off_acc);
+  bf16* Xb = (bf16*)(c->ws + c->L.off_xb);
+  int* dperm = (int*)(c->ws + c->L.off_perm);
+  for (int e = 0; e < epochs; ++e) {
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    std::shuffle(perm.begin(), perm.end(), rng);
+    SCHK(c, hipMemcpyAsync(dperm, perm.data(), 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    SCHK(c, hipMemsetAsync(acc, 0, 4, c->stream));
+    for (int b = 0; b < nb; ++b) {
+      hipLaunchKernelGGL(k_gather, dim3((batch * 4 + 255) / 256), dim3(256), 0, c->stream,
+                         (const bf16*)(c->ws + c->L.off_xall), dperm, b * batch, batch, Xb);
+      SCHK(c, hipGetLastError());
+      int rc = forward(c, Xb, batch);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_loss, dim3((batch + 255) / 256), dim3(256), 0, c->stream,
+                         (const float*)(c->ws + c->L.off_y), dperm, b * batch, batch,
+                         (const int*)(c->ws + c->L.off_lab), (const float*)(c->ws + c->L.off_traj),
+                         w_traj, (bf16*)(c->ws + c->L.off_dy), acc);
+      SCHK(c, hipGetLastError());
+      rc = backward(c, Xb, batch);
+      if (rc) return rc;
+      rc = adam(c, lr);
+      if (rc) return rc;
+    }
+    float s = 0.f;
+    SCHK(c, hipMemcpyAsync(&s, acc, 4, hipMemcpyDeviceToHost, c->stream));
+    SCHK(c, hipStreamSynchronize(c->stream));
+    if (epoch_loss) epoch_loss[e] = nb > 0 ? s / nb : 0.f;
+  }
+  return LBM_OK;
+}
+
+int srg_gradients(srg_ctx* c, const float* X, const int32_t* label, const float* traj, int32_t n,
+                  float w_traj, float* grads, float* loss) {
+  if (!c || !X || !label || !traj || !grads) return LBM_EINVAL;
+  if (c->err) return LBM_ESTATE;
+  if (n < 64 || n % 64 != 0 || n > c->max_batch)
+    return srg_err(c, LBM_EINVAL, "n must be a multiple of 64 and <= max_batch");
+  for (int i = 0; i < n; ++i)
+    if (label[i] < 0 || label[i] >= NCLS) return srg_err(c, LBM_EINVAL, "label out of range");
+  // the batch goes through the training-set buffers' batch slots: inputs in
+  // Xb, labels and trajectories in the (batch-sized) prefix of dedicated rows
+  std::vector<uint16_t> xb((size_t)n * 32, 0);
+  for (int r = 0; r < n; ++r)
+    for (int j = 0; j < SRG_IN; ++j) xb[(size_t)r * 32 + j] = host_bf16(X[(size_t)r * SRG_IN + j]);
+  bf16* Xb = (bf16*)(c->ws + c->L.off_xb);
+  SCHK(c, hipMemcpyAsync(Xb, xb.data(), 2 * xb.size(), hipMemcpyHostToDevice, c->stream));
+  // labels and trajectories staged in the FP32 output buffer region of the
+  // inference path (sized max_batch x 51 floats >= n x 49)
+  int* dlab = (int*)(c->ws + c->L.off_yout);
+  float* dtr = (float*)(c->ws + c->L.off_yout) + n;
+  SCHK(c, hipMemcpyAsync(dlab, label, 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  SCHK(c, hipMemcpyAsync(dtr, traj, 4 * (size_t)NTRAJ * n, hipMemcpyHostToDevice, c->stream));
+  float* acc = (float*)(c->ws + c->L.off_acc);
+  SCHK(c, hipMemsetAsync(acc, 0, 4, c->stream));
+  int rc = forward(c, Xb, n);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_loss, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                     (const float*)(c->ws + c->L.off_y), (const int*)nullptr, 0, n, dlab, dtr, w_traj,
+                     (bf16*)(c->ws + c->L.off_dy), acc);
+  SCHK(c, hipGetLastError());
+  rc = backward(c, Xb, n);
+  if (rc) return rc;
+  std::vector<float> pad(c->L.n_par);
+  SCHK(c, hipMemcpyAsync(pad.data(), c->g(), 4 * c->L.n_par, hipMemcpyDeviceToHost, c->stream));
+  float s = 0.f;
+  SCHK(c, hipMemcpyAsync(&s, acc, 4, hipMemcpyDeviceToHost, c->stream));
+  SCHK(c, hipStreamSynchronize(c->stream));
+  unpad(c, pad, grads);
+  if (loss) *loss = s;
+  return LBM_OK;
+}
+
+int srg_predict(srg_ctx* c, const float* X, int32_t n, float* y, int32_t src_is_device,
+                int32_t dst_is_device) {
+  if (!c || !X || !y || n < 1) return LBM_EINVAL;
+  if (c->err) return LBM_ESTATE;
+  bf16* Xb = (bf16*)(c->ws + c->L.off_xb);
+  float* xin = (float*)(c->ws + c->L.off_xin);
+  float* yout = (float*)(c->ws + c->L.off_yout);
+  for (int r0 = 0; r0 < n; r0 += c->max_batch) {
+    const int m = std::min(c->max_batch, n - r0);
+    const int mp = (m + 63) / 64 * 64;  // rows beyond m are computed and discarded
+    const float* src = X + (size_t)r0 * SRG_IN;
+    if (!src_is_device) {
+      SCHK(c, hipMemcpyAsync(xin, src, 4 * (size_t)SRG_IN * m, hipMemcpyHostToDevice, c->stream));
+      src = xin;
+    }
+    hipLaunchKernelGGL(k_pack_inputs, dim3((mp * 32 + 255) / 256), dim3(256), 0, c->stream, src, m,
+                       Xb);
+    SCHK(c, hipGetLastError());
+    if (mp > m)  // zero the padding rows of the input block
+      SCHK(c, hipMemsetAsync(Xb + (size_t)m * 32, 0, 2 * 32 * (size_t)(mp - m), c->stream));
+    int rc = forward(c, Xb, mp);
+    if (rc) return rc;
+    float* dst = dst_is_device ? y + (size_t)r0 * SRG_OUT : yout;
+    hipLaunchKernelGGL(k_unpack_outputs, dim3((m * SRG_OUT + 255) / 256), dim3(256), 0, c->stream,
+                       (const float*)(c->ws + c->L.off_y), m, dst);
+    SCHK(c, hipGetLastError());
+    if (!dst_is_device) {
+      SCHK(c, hipMemcpyAsync(y + (size_t)r0 * SRG_OUT, yout, 4 * (size_t)SRG_OUT * m,
+                             hipMemcpyDeviceToHost, c->stream));
+      SCHK(c, hipStreamSynchronize(c->stream));
+    }
+  }
+  if (!src_is_device) SCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int srg_sync(srg_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  if (c->err) return LBM_ESTATE;
+  SCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+void srg_destroy(srg_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+const char* srg_last_error(const srg_ctx* c) {
+  if (!c || c->err == 0) return nullptr;
+  return c->msg;
+}
+
+}  // extern "C"

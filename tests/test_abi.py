@@ -10,10 +10,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    txt = open(os.path.join(ROOT, "include", "lbm.h")).read()
+def _declared(header="lbm.h", prefix="lbm_"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
@@ -29,6 +29,28 @@ def test_library_exports_every_declared_symbol():
     for n in _declared():
         assert hasattr(L, n), n
     assert sorted(lbm.EXPORTS) == _declared()
+
+
+def test_library_exports_every_surrogate_symbol():
+    from paper_2505_10171_amd import surrogate
+    L = surrogate.library()
+    names = _declared("srg.h", "srg_")
+    assert "srg_train" in names and "srg_predict" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(surrogate.SRG_EXPORTS) == names
+
+
+def test_surrogate_parameter_count_and_workspace():
+    from oracle.surrogate_oracle import SIZES
+    from paper_2505_10171_amd import surrogate
+    n = sum(a * b + b for a, b in zip(SIZES[:-1], SIZES[1:]))
+    assert n == surrogate.SRG_PARAMS == 212275
+    hdr = open(os.path.join(ROOT, "include", "srg.h")).read()
+    assert "#define SRG_PARAMS 212275" in hdr
+    L = surrogate.library()
+    assert L.srg_workspace_bytes(100, 10) == 0  # batch not a multiple of 64
+    assert L.srg_workspace_bytes(1024, 4096) > 4 * 4 * n
 
 
 def _c_layout(struct, fields, tmp_path):

@@ -1,0 +1,115 @@
+"""The BF16-MFMA surrogate kernels against the FP64 reference: forward outputs,
+gradients of every parameter tensor, one Adam step, and a training run that
+must learn a known function.
+
+The GPU computes layer products from BF16 weights and activations with FP32
+accumulation; the reference gets the same BF16-rounded weights and inputs and
+computes in FP64, so the remaining difference is the BF16 rounding of the
+intermediate activations and of the output gradient (2^-9 relative each):
+outputs within 2e-2 and gradients within 5e-2 relative L2 per tensor."""
+import numpy as np
+import pytest
+
+from oracle import surrogate_oracle as S
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16(a):
+    """Round to BF16 (nearest even), returned as float64."""
+    a = np.ascontiguousarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _setup(seed=7, n=256):
+    from paper_2505_10171_amd.surrogate import Surrogate, flatten
+    ps = S.init_params(seed)
+    g = np.random.default_rng(seed)
+    ps = [p + (0.05 * g.standard_normal(p.shape) if k % 2 else 0.0) for k, p in enumerate(ps)]
+    X = g.standard_normal((n, 6))
+    lab = g.integers(0, 3, n)
+    tr = g.standard_normal((n, 48))
+    s = Surrogate(max_batch=1024, max_train=4096)
+    s.set_params(flatten(ps))
+    # the reference sees exactly what the GPU sees: FP32 biases, BF16 weights and inputs
+    ref = [bf16(p) if k % 2 == 0 else np.asarray(p, np.float32).astype(np.float64)
+           for k, p in enumerate(ps)]
+    return s, ps, ref, bf16(X), X, lab, tr
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a, float) - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_forward_matches_reference():
+    s, ps, ref, Xr, X, lab, tr = _setup()
+    y = s.predict(X)
+    yo, _ = S.forward(ref, Xr)
+    e = rel(y, yo)
+    print("forward rel-L2", e)
+    assert e <= 2e-2
+    # a batch that is not a multiple of 64 and spans two chunks of the batch limit
+    X2 = np.random.default_rng(2).standard_normal((1500, 6))
+    y2 = s.predict(X2)
+    assert rel(y2, S.forward(ref, bf16(X2))[0]) <= 2e-2
+
+
+def test_gradients_match_reference():
+    from paper_2505_10171_amd.surrogate import unflatten
+    s, ps, ref, Xr, X, lab, tr = _setup()
+    g, L = s.gradients(X, lab, tr, w_traj=0.5)
+    go, Lo = S.gradients(ref, Xr, lab, tr, w_traj=0.5)
+    assert abs(L - Lo) <= 2e-2 * abs(Lo), (L, Lo)
+    for k, (a, b) in enumerate(zip(unflatten(g), go)):
+        e = rel(a, b)
+        print("grad tensor", k, f"{e:.2e}")
+        assert e <= 5e-2, (k, e)
+
+
+def test_one_adam_step_matches_reference():
+    from paper_2505_10171_amd.surrogate import flatten
+    s, ps, ref, Xr, X, lab, tr = _setup(n=256)
+    g, _ = s.gradients(X, lab, tr)
+    p0 = s.get_params().astype(np.float64)
+    s.set_train(X, lab, tr)
+    s.train(1, batch=256, lr=1e-3)
+    p1 = s.get_params().astype(np.float64)
+    # Adam from zero moments with the GPU gradient, in FP64
+    po, _, _ = S.adam_step([p0], [g.astype(np.float64)], [np.zeros_like(p0)],
+                           [np.zeros_like(p0)], 1, lr=1e-3)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()  # the first step is lr*sign(g) where g is resolved
+    assert np.abs(p1[big] - po[0][big]).max() <= 2e-5, np.abs(p1[big] - po[0][big]).max()
+
+
+def test_training_learns_a_known_function():
+    """Labels = argmax of a fixed linear map, trajectories = smooth functions
+    of the inputs: after training, held-out accuracy and trajectory error must
+    beat the best constant predictor by a wide margin."""
+    from paper_2505_10171_amd.surrogate import Surrogate, flatten
+    g = np.random.default_rng(11)
+    A = g.standard_normal((6, 3))
+    Bm = g.standard_normal((6, 48)) / np.sqrt(6)
+
+    def make(n):
+        X = g.standard_normal((n, 6))
+        lab = np.argmax(X @ A, axis=1)
+        tr = np.tanh(X @ Bm)
+        return X, lab, tr
+    Xt, lt, tt = make(4096)
+    Xh, lh, th = make(512)
+    s = Surrogate(max_batch=1024, max_train=4096)
+    s.set_params(flatten(S.init_params(1)))
+    s.set_train(Xt, lt, tt)
+    losses = s.train(40, batch=256, lr=2e-3, seed=5)
+    print("loss first/last", losses[0], losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
+    y = s.predict(Xh)
+    acc = np.mean(np.argmax(y[:, :3], axis=1) == lh)
+    base_acc = np.max(np.bincount(lh)) / len(lh)
+    rmse = np.sqrt(np.mean((y[:, 3:] - th) ** 2))
+    base_rmse = np.sqrt(np.mean((th - tt.mean(axis=0)) ** 2))
+    print("accuracy", acc, "vs", base_acc, "rmse", rmse, "vs", base_rmse)
+    assert acc >= 0.9 and acc > base_acc + 0.3
+    assert rmse <= 0.3 * base_rmse
