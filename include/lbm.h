@@ -191,6 +191,19 @@ int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out);
 int lbm_profile(lbm_ctx* ctx, int32_t enable);
 int lbm_profile_read(lbm_ctx* ctx, double* total_ms, int64_t* launches, int32_t n_kinds);
 
+/* Block-shape autotuner for the per-node kernels (256 threads per block: 256
+ * consecutive nodes, or x-y tiles of 256 x 1 .. 16 x 16 nodes).  For each box
+ * class of the context it times `reps` passes of the per-node kernels with
+ * every shape on the current state (which it leaves unchanged) and keeps the
+ * fastest; results are identical with any shape.  chosen (nullable, one per
+ * simulation) receives the tile width (0 = consecutive nodes).  Choices are
+ * cached in the process per (GPU architecture, box size, storage). */
+int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen);
+
+/* Set the block shape of one simulation by hand (tile width 0, 16, 32, 64,
+ * 128 or 256; LBM_EINVAL otherwise). */
+int lbm_set_tile(lbm_ctx* ctx, int32_t sim, int32_t tile_x);
+
 /* Graph replay of steps.  With enable = 1, lbm_step captures two consecutive
  * steps of every simulation into a HIP graph on the context's stream the first
  * time it runs at least two steps, and from then on replays that graph for each

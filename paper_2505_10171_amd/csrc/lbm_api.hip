@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -248,7 +249,22 @@ struct lbm_ctx {
   int graph_cur = 0;
 };
 
-static unsigned sim_blocks(const SimDev& d) { return (unsigned)((d.N + 255) / 256); }
+static unsigned sim_blocks(const SimDev& d) {
+  if (d.tile_x == 0) return (unsigned)((d.N + 255) / 256);
+  return (unsigned)((long long)d.tiles_x * d.tiles_y * d.nz);
+}
+
+// node-block shape of a simulation: tx = 0 (256 consecutive nodes) or an x-y
+// tile tx by 256 / tx (tx a power of two, 16..256)
+static void set_tile(SimDev& d, int tx) {
+  d.tile_x = tx;
+  d.tile_lx = 0;
+  d.tiles_x = d.tiles_y = 0;
+  if (tx == 0) return;
+  while ((1 << d.tile_lx) < tx) ++d.tile_lx;
+  d.tiles_x = (d.nx + tx - 1) / tx;
+  d.tiles_y = (d.ny + (256 / tx) - 1) / (256 / tx);
+}
 
 static Batch batch_all(const lbm_ctx* c) {
   return Batch{c->d_tab, c->d_blk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd};
@@ -281,6 +297,50 @@ static int set_err(lbm_ctx* c, int code, const char* fmt, ...) {
     if (e_ != hipSuccess)                                                                  \
       return set_err((ctx), LBM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
+
+// Device batch tables (simulation records, block prefix of the per-node
+// kernels, particle rows) and their extents; at creation `off` is the end of the
+// last simulation's carve (the tables follow it), afterwards pass 0.
+static int upload_tables(lbm_ctx* ctx, size_t off) {
+  const int n_sims = (int)ctx->sims.size();
+  if (off) {
+    char* b = ctx->ws + align_up(off);
+    ctx->d_tab = (SimDev*)b;
+    b += align_up(sizeof(SimDev) * (size_t)n_sims);
+    ctx->d_blk = (uint32_t*)b;
+    b += align_up(4 * (size_t)(n_sims + 1));
+    ctx->d_pmap = (int2*)b;
+  }
+  std::vector<SimDev> tab(n_sims);
+  std::vector<uint32_t> blk(n_sims + 1, 0);
+  std::vector<int2> pmap;
+  ctx->np_max = ctx->Bmax = ctx->cap_B = ctx->npts = 0;
+  ctx->fresh_cap_max = 0;
+  for (int si = 0; si < n_sims; ++si) {
+    const SimHost& sh = ctx->sims[si];
+    tab[si] = sh.d;
+    const unsigned long long nb = (unsigned long long)blk[si] + sim_blocks(sh.d);
+    if (nb > 0x7fffffffull) return set_err(ctx, LBM_EINVAL, "too many lattice nodes in one context");
+    blk[si + 1] = (uint32_t)nb;
+    for (int p = 0; p < sh.d.np; ++p) pmap.push_back(make_int2(si, p));
+    ctx->np_max = std::max(ctx->np_max, sh.d.np);
+    if (sh.d.np > 0) {
+      ctx->Bmax = std::max(ctx->Bmax, sh.L.Bmask);
+      ctx->cap_B = std::max(ctx->cap_B, sh.d.cap_B);
+      ctx->npts = std::max(ctx->npts, sh.d.cap_na * sh.d.cap_nphi);
+      ctx->fresh_cap_max = std::max(ctx->fresh_cap_max, (size_t)sh.d.fresh_cap);
+    }
+  }
+  ctx->nblk = blk[n_sims];
+  ctx->np_rows = (int)pmap.size();
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_tab, tab.data(), sizeof(SimDev) * n_sims, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_blk, blk.data(), 4 * (size_t)(n_sims + 1), hipMemcpyHostToDevice, st));
+  if (!pmap.empty())
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_pmap, pmap.data(), 8 * pmap.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return LBM_OK;
+}
 
 // mask of the new particle positions, fresh nodes, refill, moments (one
 // simulation, between steps)
@@ -465,43 +525,8 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     }
   }
   // batch tables: simulation records, block prefix, particle rows
-  {
-    char* b = ctx->ws + align_up(off);
-    ctx->d_tab = (SimDev*)b;
-    b += align_up(sizeof(SimDev) * (size_t)n_sims);
-    ctx->d_blk = (uint32_t*)b;
-    b += align_up(4 * (size_t)(n_sims + 1));
-    ctx->d_pmap = (int2*)b;
-    std::vector<SimDev> tab(n_sims);
-    std::vector<uint32_t> blk(n_sims + 1, 0);
-    std::vector<int2> pmap;
-    ctx->storage = cfg[0].storage;
-    for (int si = 0; si < n_sims; ++si) {
-      const SimHost& sh = ctx->sims[si];
-      tab[si] = sh.d;
-      blk[si + 1] = blk[si] + sim_blocks(sh.d);
-      for (int p = 0; p < sh.d.np; ++p) pmap.push_back(make_int2(si, p));
-      ctx->np_max = std::max(ctx->np_max, sh.d.np);
-      if (sh.d.np > 0) {
-        ctx->Bmax = std::max(ctx->Bmax, sh.L.Bmask);
-        ctx->cap_B = std::max(ctx->cap_B, sh.d.cap_B);
-        ctx->npts = std::max(ctx->npts, sh.d.cap_na * sh.d.cap_nphi);
-        ctx->fresh_cap_max = std::max(ctx->fresh_cap_max, (size_t)sh.d.fresh_cap);
-      }
-    }
-    if (blk[n_sims] > 0x7fffffffu) return fail(LBM_EINVAL, "too many lattice nodes in one context");
-    ctx->nblk = blk[n_sims];
-    ctx->np_rows = (int)pmap.size();
-    hipStream_t st = ctx->stream;
-    if (hipMemcpyAsync(ctx->d_tab, tab.data(), sizeof(SimDev) * n_sims, hipMemcpyHostToDevice,
-                       st) != hipSuccess ||
-        hipMemcpyAsync(ctx->d_blk, blk.data(), 4 * (size_t)(n_sims + 1), hipMemcpyHostToDevice,
-                       st) != hipSuccess ||
-        (!pmap.empty() && hipMemcpyAsync(ctx->d_pmap, pmap.data(), 8 * pmap.size(),
-                                         hipMemcpyHostToDevice, st) != hipSuccess) ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return fail(LBM_EHIP, "batch table upload failed");
-  }
+  ctx->storage = cfg[0].storage;
+  if (int rc = upload_tables(ctx, off)) return fail(rc, ctx->msg);
   // initial state of every simulation
   ctx->cur = 0;
   ctx->rd = 0;
@@ -639,6 +664,91 @@ int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
   return LBM_OK;
 }
 
+// Block-shape autotuner.  For every box class (nx, ny, nz) of the context it
+// times the per-node kernels of one representative simulation -- normal,
+// curvature, the fused step into the spare buffer, and the moments pass,
+// which leave the current state unchanged -- with each candidate shape, and
+// gives the whole class the fastest.  Choices are cached per process by
+// (architecture, box, storage).
+int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  if (reps < 1) return set_err(ctx, LBM_EINVAL, "reps must be >= 1");
+  if (ctx->graph_exec) {  // its launches carry the old grid sizes
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+  }
+  static std::vector<std::pair<std::string, int>> cache;
+  int dev = 0;
+  HIPCHK(ctx, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(ctx, hipGetDeviceProperties(&prop, dev));
+  const int cand[] = {0, 256, 128, 64, 32, 16};
+  hipStream_t st = ctx->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  const int n_sims = (int)ctx->sims.size();
+  int rc = LBM_OK;
+  for (int si = 0; si < n_sims && rc == LBM_OK; ++si) {
+    SimDev& d = ctx->sims[si].d;
+    char key[128];
+    snprintf(key, sizeof key, "%s|%d|%d|%d|%d", prop.gcnArchName, d.nx, d.ny, d.nz, d.storage);
+    int best = -1;
+    for (auto& kv : cache)
+      if (kv.first == key) best = kv.second;
+    if (best < 0) {
+      float best_ms = 1e30f;
+      for (int c : cand) {
+        if (c > 0 && c > 2 * d.nx) continue;  // over half the tile idle
+        set_tile(d, c);
+        HIPCHK(ctx, hipMemcpyAsync(ctx->d_tab + si, &d, sizeof(SimDev), hipMemcpyHostToDevice, st));
+        const Batch b1 = batch_one(ctx, si);
+        const unsigned nb = sim_blocks(d);
+        float ms = 0.f;
+        for (int r = 0; r <= reps; ++r) {  // the first pass warms up
+          if (r == 1) HIPCHK(ctx, hipEventRecord(e0, st));
+          HIPCHK(ctx, launch_interface(b1, nb, st));
+          HIPCHK(ctx, launch_fused(b1, ctx->storage, nb, 0, nullptr, nullptr, nullptr, nullptr, st));
+          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, st));
+        }
+        HIPCHK(ctx, hipEventRecord(e1, st));
+        HIPCHK(ctx, hipEventSynchronize(e1));
+        HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      cache.emplace_back(key, best);
+    }
+    set_tile(d, best);
+    if (chosen) chosen[si] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  return upload_tables(ctx, 0);
+}
+
+int lbm_set_tile(lbm_ctx* ctx, int32_t sim, int32_t tile_x) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  if (sim < 0 || sim >= (int)ctx->sims.size())
+    return set_err(ctx, LBM_ERANGE, "simulation index out of range");
+  if (!(tile_x == 0 || tile_x == 16 || tile_x == 32 || tile_x == 64 || tile_x == 128 ||
+        tile_x == 256))
+    return set_err(ctx, LBM_EINVAL, "tile width must be 0, 16, 32, 64, 128 or 256");
+  if (ctx->graph_exec) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+  }
+  set_tile(ctx->sims[sim].d, tile_x);
+  return upload_tables(ctx, 0);
+}
+
 int lbm_profile(lbm_ctx* ctx, int32_t enable) {
   if (!ctx) return LBM_EINVAL;
   if (ctx->err) return LBM_ESTATE;
@@ -681,8 +791,11 @@ int lbm_profile_read(lbm_ctx* ctx, double* total_ms, int64_t* launches, int32_t 
   return LBM_OK;
 }
 
-static int check_status(lbm_ctx* ctx) {
-  for (auto& sh : ctx->sims) {
+// device status words of every simulation (only = one simulation's)
+static int check_status(lbm_ctx* ctx, int only = -1) {
+  for (int si = 0; si < (int)ctx->sims.size(); ++si) {
+    if (only >= 0 && si != only) continue;
+    const SimHost& sh = ctx->sims[si];
     uint32_t cnt[4];
     HIPCHK(ctx, hipMemcpyAsync(cnt, sh.d.counters, sizeof cnt, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -715,7 +828,8 @@ int lbm_particles_sync(lbm_ctx* ctx, int32_t sim, int32_t dir, lbm_particle* par
   if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
   SimDev& d = sh->d;
   if (n != d.np || (n > 0 && !parts)) return set_err(ctx, LBM_EINVAL, "particle count mismatch");
-  int rc = lbm_sync(ctx);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  int rc = check_status(ctx, sim);
   if (rc) return rc;
   if (n_hist) *n_hist = 0;
   if (d.np == 0) return LBM_OK;

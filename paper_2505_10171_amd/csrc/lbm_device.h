@@ -167,7 +167,37 @@ struct SimDev {
   int* capbox_org;     // np * 3 box origins
   double* mass_acc;    // 2 doubles
   unsigned long long* step_counter;
+  // node blocks of the per-node kernels (256 threads): tile_x = 0 runs 256
+  // consecutive nodes per block; otherwise an x-y tile of tile_x by
+  // 256 / tile_x nodes (tile_x = 1 << tile_lx), tiles_x by tiles_y per plane
+  int tile_x, tile_lx, tiles_x, tiles_y;
 };
+
+// lattice node of thread threadIdx.x in block lb of simulation s; false if the
+// thread lies outside the lattice
+__device__ __forceinline__ bool tile_node(const SimDev& s, int lb, int& n, int& gx, int& gy,
+                                          int& gz) {
+  const int nx = s.nx, ny = s.ny;
+  if (s.tile_x == 0) {
+    n = lb * 256 + (int)threadIdx.x;
+    if (n >= (int)s.N) return false;
+    const int nxny = nx * ny;
+    gz = n / nxny;
+    const int rem = n - gz * nxny;
+    gy = rem / nx;
+    gx = rem - gy * nx;
+    return true;
+  }
+  const int tx = (int)threadIdx.x & (s.tile_x - 1), ty = (int)threadIdx.x >> s.tile_lx;
+  const int bx = lb % s.tiles_x, r = lb / s.tiles_x;
+  const int by = r % s.tiles_y;
+  gz = r / s.tiles_y;
+  gx = bx * s.tile_x + tx;
+  gy = by * (256 >> s.tile_lx) + ty;
+  if (gx >= nx || gy >= ny) return false;
+  n = gx + nx * (gy + ny * gz);
+  return true;
+}
 
 enum StatusBits : uint32_t { ST_UNSTABLE = 1u, ST_CONTACT_FULL = 2u, ST_FRESH_FULL = 4u };
 

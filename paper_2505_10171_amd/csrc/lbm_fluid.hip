@@ -79,9 +79,9 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   const float2* __restrict__ rdec = s.ref[bt.rd];
   float2* __restrict__ rnext = s.ref[bt.rd ^ 1];
   const long long N = s.N;
-  long long n = (long long)sb.y * blockDim.x + threadIdx.x;
-  if (n == 0) s.counters[0] = 0u;  // fresh list consumed
-  if (n >= N) return;
+  int n, gx, gy, gz;
+  if (sb.y == 0 && threadIdx.x == 0) s.counters[0] = 0u;  // fresh list consumed
+  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   uint16_t m = s.mask[n];
   if (m & FRESH_BIT) {
     m = (uint16_t)(m & ~FRESH_BIT);
@@ -228,12 +228,11 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   const SimDev& s = bt.tab[sb.x];
   float4* __restrict__ nrm = s.nrm;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
-  const int n = sb.y * 256 + threadIdx.x;
-  if (n >= (int)s.N) return;
+  int n, gx, gy, gz;
+  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   float4 out = make_float4(0.f, 0.f, 0.f, -1.0f);  // w < 0 marks a solid node
   const float p0 = s.phi[n];
   if (p0 < PHI_SOLID_TEST) {
-    const int gz = n / nxny, rem = n - gz * nxny, gy = rem / nx, gx = rem - gy * nx;
     const Nbr nb(gx, gy, gz, nx, ny, nz);
     float Gx = 0.f, Gy = 0.f, Gz = 0.f;
     bool solid = false;
@@ -278,13 +277,12 @@ __global__ __launch_bounds__(256) void k_curv(Batch bt) {
   const float4* __restrict__ nrm = s.nrm;
   float2* __restrict__ cur = s.curv;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
-  const int n = sb.y * 256 + threadIdx.x;
-  if (n >= (int)s.N) return;
+  int n, gx, gy, gz;
+  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   float c = 0.f;
   uint32_t bits = 0x80000000u;
   const float4 nc = nrm[n];
   if (nc.w >= 0.f) {
-    const int gz = n / nxny, rem = n - gz * nxny, gy = rem / nx, gx = rem - gy * nx;
     const Nbr nb(gx, gy, gz, nx, ny, nz);
     float kappa = 0.f;
     bits = 0u;
@@ -332,17 +330,13 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   const int N = (int)s.N;
   const int nxny = nx * ny;
-  const int n = sb.y * 256 + threadIdx.x;
-  if (n >= N) return;
+  int n, gx, gy, gz;
+  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   const float rho0 = s.rho0;
   const T* __restrict__ sp_ = (const T*)src;
   T* __restrict__ dp_ = (T*)dst;
   const float2 cb = cur[n];
   const uint32_t bits = __float_as_uint(cb.y);
-  const int gz = n / nxny;
-  const int rem = n - gz * nxny;
-  const int gy = rem / nx;
-  const int gx = rem - gy * nx;
 
   if (bits & 0x80000000u) {
     if (MODE == MODE_FIELDS) {

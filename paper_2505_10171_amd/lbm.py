@@ -22,7 +22,8 @@ HIST_DOUBLES = 27
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_sync", "lbm_particles_sync",
            "lbm_fields", "lbm_fields2", "lbm_links", "lbm_mass", "lbm_dem_substeps", "lbm_destroy",
-           "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_use_graph"]
+           "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_use_graph",
+           "lbm_autotune", "lbm_set_tile"]
 PROFILE_KINDS = ("fused", "particles", "moments", "interface")
 
 
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.lbm_profile.argtypes = [vp, i32]
     L.lbm_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
     L.lbm_use_graph.argtypes = [vp, i32]
+    L.lbm_autotune.argtypes = [vp, i32, C.POINTER(i32)]
+    L.lbm_set_tile.argtypes = [vp, i32, i32]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = [vp]
@@ -244,6 +247,17 @@ class Context:
             rho.ctypes.data, u.ctypes.data, phi.ctypes.data, mask.ctypes.data, None, 0))
         return rho.reshape(shp), u.reshape((3,) + shp), phi.reshape(shp), mask.reshape(shp)
 
+    def phi_mask(self, sim: int = 0):
+        """Order parameter and solid mask only (nz, ny, nx)."""
+        c = self._cfg[sim]
+        shp = (c.nz, c.ny, c.nx)
+        N = c.nx * c.ny * c.nz
+        phi = np.zeros(N, np.float32)
+        mask = np.zeros(N, np.uint16)
+        self._check(load_library().lbm_fields(self.h, sim, LBM_F_PHI | LBM_F_MASK, None, None,
+                                              phi.ctypes.data, mask.ctypes.data, None, 0))
+        return phi.reshape(shp), mask.reshape(shp)
+
     def force(self, sim: int = 0):
         """Force per volume (CSF + body force), shape (nz, ny, nx, 3), float32."""
         c = self._cfg[sim]
@@ -302,6 +316,16 @@ class Context:
         cnt = (C.c_int64 * n)()
         self._check(load_library().lbm_profile_read(self.h, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(PROFILE_KINDS)}
+
+    def autotune(self, reps: int = 5):
+        """Pick the per-node block shape of every box class; returns the tile
+        width chosen per simulation (0 = consecutive nodes)."""
+        out = (C.c_int32 * self.n)()
+        self._check(load_library().lbm_autotune(self.h, int(reps), out))
+        return list(out)
+
+    def set_tile(self, sim: int, tile_x: int):
+        self._check(load_library().lbm_set_tile(self.h, int(sim), int(tile_x)))
 
     def use_graph(self, enable: bool = True):
         """Replay pairs of steps from a captured HIP graph (needs a non-null stream)."""
