@@ -121,6 +121,129 @@ def ensemble(args):
     print(json.dumps(out), flush=True)
 
 
+def scale_c3(args):
+    """The 512x256x192 slab workload with 500 spheres, FP32 and FP16 storage on
+    the same run: MLUPS of each, the roofline of k_fused for each, and the
+    per-field error of FP16 against FP32 after the timed steps; both against
+    the FP64 oracle after --c3-oracle-steps steps."""
+    import numpy as np
+    import torch
+    from paper_2505_10171_amd import workloads as W
+    from paper_2505_10171_amd.lbm import Simulation
+
+    def rel(a, b):
+        return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+    res = {}
+    fields = {}
+    for storage in ("fp32", "fp16"):
+        w = W.slab_c3(storage=storage)
+        cfg = w["cfg"]
+        N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+        sim = Simulation(cfg, w["phi0"], w["particles"])
+        n_fluid = int((sim.phi_mask()[1] == 0).sum())
+        sim.step(args.warmup)
+        sim.sync()
+        sim.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        sim.sync()
+        t1 = time.perf_counter()
+        prof = sim.profile_read()
+        sim.profile(False)
+        pop_b, ref_b = (2, 12) if storage == "fp16" else (4, 0)
+        alg = n_fluid * (19 * pop_b + 38 * pop_b + 24 + ref_b) + (N - n_fluid) * 8
+        t_f = prof["fused"][0] / max(prof["fused"][1], 1) * 1e-3
+        res[storage] = {"mlups": round(N * args.steps / (t1 - t0) / 1e6, 1),
+                        "ms_per_step": round((t1 - t0) * 1e3 / args.steps, 4),
+                        "k_fused_gbs": round(alg / t_f / 1e9, 1),
+                        "k_fused_frac": round(alg / t_f / (HBM_PEAK_GBS * 1e9), 4),
+                        "phase_ms_per_step": {k: round(v[0] / max(v[1], 1), 5)
+                                              for k, v in prof.items()}}
+        r, u, phi, mask = sim.fields()
+        fields[storage] = (r, u, phi, mask)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    a, b = fields["fp16"], fields["fp32"]
+    fl = b[3] == 0
+    res["fp16_vs_fp32_after_timed_steps"] = {
+        "rho": rel(a[0][fl], b[0][fl]), "u": rel(a[1][:, fl], b[1][:, fl]),
+        "phi": rel(a[2][fl], b[2][fl]), "masks_equal": bool(np.array_equal(a[3], b[3]))}
+    if args.c3_oracle_steps > 0:
+        from oracle.oracle import OracleSim
+        w = W.slab_c3()
+        o = OracleSim(w["cfg"], w["phi0"], w["particles"])
+        o.step(args.c3_oracle_steps)
+        ro, uo, po, mo = o.fields()
+        o.close()
+        fl = mo == 0
+        for storage in ("fp32", "fp16"):
+            w = W.slab_c3(storage=storage)
+            sim = Simulation(w["cfg"], w["phi0"], w["particles"])
+            sim.step(args.c3_oracle_steps)
+            r, u, phi, mask = sim.fields()
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+            res[f"{storage}_vs_oracle_{args.c3_oracle_steps}_steps"] = {
+                "rho": rel(r[fl], ro[fl]), "u": rel(u[:, fl], uo[:, fl]),
+                "phi": rel(phi[fl], po[fl]), "masks_equal": bool(np.array_equal(mask, mo))}
+    out = {"metric": "MLUPS (f+g+particles), FP32 vs FP16 storage", "value": res["fp32"]["mlups"],
+           "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "liquid slab 512x256x192, 500 spheres R=4"}, "c3": res}
+    print(json.dumps(out), flush=True)
+
+
+def surrogate(args):
+    """The surrogate trained on runs of the coupled method (committed data set of
+    4,096 training and 256 held-out runs of the uneven-box distribution) and
+    judged against the held-out plain runs.  Effective runs/hour: the plain
+    ensemble rate (timed here on 256 members) divided by the fraction of runs
+    the surrogate hands back to the plain method (confidence below 0.9), plus
+    its own inference time."""
+    import torch
+    from paper_2505_10171_amd import surrogate_eval as E
+    train = E.load(E.TRAIN_FILES)
+    held = E.load(E.HELDOUT_FILES)
+    res = E.train_and_evaluate(train, held, epochs=args.srg_epochs)
+    # plain method rate on the same GPU: the batched ensemble
+    from paper_2505_10171_amd import workloads as W
+    from paper_2505_10171_amd.lbm import Context
+    members = [W.ensemble_member_c4(4, i) for i in range(256)]
+    ctx = Context(members, stream=torch.cuda.Stream())
+    ctx.use_graph(True)
+    ctx.step(4)
+    ctx.sync()
+    t0 = time.perf_counter()
+    ctx.step(200)
+    ctx.sync()
+    ms_step = (time.perf_counter() - t0) * 1e3 / 200
+    ctx.close()
+    plain_rph = 256 * 3600.0 / (ms_step * 1e-3 * 5000)
+    n = len(held["label"])
+    f = res["fallback_fraction"]
+    t_surr = res["infer_us"] * 1e-6 * max(1.0, n / res["infer_batch"])
+    eff_rph = n * 3600.0 / (t_surr + f * n * 3600.0 / plain_rph)
+    out = {
+        "metric": "surrogate effective runs/hour with fallback (held-out plain runs as truth)",
+        "value": round(eff_rph, 1), "unit": "runs/hour", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "MLP 6-256x4-51 on 4,096 runs of the uneven-box ensemble, "
+                               "256 held-out runs", "epochs": args.srg_epochs},
+        "plain_runs_per_hour": round(plain_rph, 1),
+        "roofline": {"bound": "mfma", "achieved": res["infer_tflops"], "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(res["infer_tflops"] / 2500.0, 5),
+                     "kernel": "k_gemm (inference, batch %d)" % res["infer_batch"],
+                     "traffic": None},
+        "surrogate": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +258,12 @@ def main():
                     help="batched ensemble of uneven boxes (runs/hour) instead of the drop sweep")
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--gate-steps", type=int, default=20)
+    ap.add_argument("--surrogate", action="store_true",
+                    help="train and judge the surrogate on the committed runs of the method")
+    ap.add_argument("--srg-epochs", type=int, default=200)
+    ap.add_argument("--c3", action="store_true",
+                    help="512x256x192 slab with 500 spheres, FP32 vs FP16 storage")
+    ap.add_argument("--c3-oracle-steps", type=int, default=20)
     args = ap.parse_args()
     args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.gpus != 1:
@@ -144,6 +273,10 @@ def main():
 
     if args.ensemble:
         return ensemble(args)
+    if args.surrogate:
+        return surrogate(args)
+    if args.c3:
+        return scale_c3(args)
     import torch
     from paper_2505_10171_amd import workloads as W
     from paper_2505_10171_amd.lbm import Simulation

@@ -451,7 +451,7 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
       d.ref[0] = d.ref[1] = nullptr;
     }
     d.phi = (float*)(b + sh.L.off_phi);
-    d.nrm = (float4*)(b + sh.L.off_nrm);
+    d.nrm = (float*)(b + sh.L.off_nrm);
     d.curv = (float2*)(b + sh.L.off_cur);
     d.mask = (uint16_t*)(b + sh.L.off_mask);
     d.claim = (uint32_t*)(b + sh.L.off_claim);

@@ -143,7 +143,7 @@ struct SimDev {
   void* pops[2];       // ping-pong population buffers: 38 planes of N
   float2* ref[2];      // FP16 storage: per-node reference (rho, phi), ping-pong
   float* phi;          // order parameter of the current state (PHI_SOLID at solids)
-  float4* nrm;         // per node (n, |G|) of the current state; w = -1 at solids
+  float* nrm;          // 4 planes of N: n_x, n_y, n_z (NaN at solids), |G| (-1 at solids)
   float2* curv;        // per node (CSF coefficient, solid-neighbour bits as float)
   uint16_t* mask;      // 0 fluid, 1 wall, 2+p particle p; FRESH_BIT while refilling
   uint32_t* claim;     // per node: lowest particle claiming it in the new mask, ~0u none

@@ -226,11 +226,14 @@ struct Nbr {
 __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  float4* __restrict__ nrm = s.nrm;
+  float* __restrict__ NX = s.nrm;
+  const long long Nn = s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
-  float4 out = make_float4(0.f, 0.f, 0.f, -1.0f);  // w < 0 marks a solid node
+  // solid node: NaN normal (tells stencils the neighbour is solid) and |G| = -1
+  const float qnan = __int_as_float(0x7fc00000);
+  float4 out = make_float4(qnan, qnan, qnan, -1.0f);
   const float p0 = s.phi[n];
   if (p0 < PHI_SOLID_TEST) {
     const Nbr nb(gx, gy, gz, nx, ny, nz);
@@ -265,7 +268,10 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
     const float ig = 1.0f / fmaxf(g, EPS_G);
     out = make_float4(Gx * ig, Gy * ig, Gz * ig, g);
   }
-  nrm[n] = out;
+  NX[n] = out.x;
+  NX[Nn + n] = out.y;
+  NX[2 * Nn + n] = out.z;
+  NX[3 * Nn + n] = out.w;
 }
 
 // Curvature kappa = div n (same stencil and closure) and the CSF coefficient
@@ -274,32 +280,63 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
 __global__ __launch_bounds__(256) void k_curv(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  const float4* __restrict__ nrm = s.nrm;
+  // normal planes: x, y, z components (NaN at solid nodes), then |G|
+  const float* __restrict__ NX = s.nrm;
+  const float* __restrict__ NY = NX + s.N;
+  const float* __restrict__ NZ = NY + s.N;
+  const float* __restrict__ NG = NZ + s.N;
   float2* __restrict__ cur = s.curv;
-  const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
+  const int nx = s.nx, ny = s.ny, nz = s.nz;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   float c = 0.f;
   uint32_t bits = 0x80000000u;
-  const float4 nc = nrm[n];
-  if (nc.w >= 0.f) {
+  const float g0 = NG[n];
+  if (g0 >= 0.f) {
+    const float ncx = NX[n], ncy = NY[n], ncz = NZ[n];
     const Nbr nb(gx, gy, gz, nx, ny, nz);
     float kappa = 0.f;
     bits = 0u;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int i = pair_dir(q), o = opp(i);
-      float4 np_ = nrm[nb(i)];
-      float4 nm_ = nrm[nb(o)];
-      const bool sp = np_.w < 0.f, sm = nm_.w < 0.f;
-      if (sp) np_ = nc;
-      if (sm) nm_ = nc;
+      const int mp = nb(i), mm = nb(o);
+      // only the components c_i selects are loaded; a NaN marks a solid neighbour
+      float px = 0.f, py = 0.f, pz = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+      bool sp = false, sm = false;
+      if (cx(i) != 0) {
+        px = NX[mp];
+        mx = NX[mm];
+        sp |= px != px;
+        sm |= mx != mx;
+      }
+      if (cy(i) != 0) {
+        py = NY[mp];
+        my = NY[mm];
+        sp |= py != py;
+        sm |= my != my;
+      }
+      if (cz(i) != 0) {
+        pz = NZ[mp];
+        mz = NZ[mm];
+        sp |= pz != pz;
+        sm |= mz != mz;
+      }
+      if (sp) {
+        px = ncx;
+        py = ncy;
+        pz = ncz;
+      }
+      if (sm) {
+        mx = ncx;
+        my = ncy;
+        mz = ncz;
+      }
       kappa += 3.0f * wq(i) *
-               ((float)cx(i) * (np_.x - nm_.x) + (float)cy(i) * (np_.y - nm_.y) +
-                (float)cz(i) * (np_.z - nm_.z));
+               ((float)cx(i) * (px - mx) + (float)cy(i) * (py - my) + (float)cz(i) * (pz - mz));
       bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
     }
-    c = -0.5f * s.sigma * kappa * fmaxf(nc.w, EPS_G);
+    c = -0.5f * s.sigma * kappa * fmaxf(g0, EPS_G);
   }
   cur[n] = make_float2(c, __uint_as_float(bits));
 }
@@ -323,7 +360,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   const SimDev& s = bt.tab[sb.x];
   const void* __restrict__ src = s.pops[bt.cur];
   void* __restrict__ dst = s.pops[bt.cur ^ 1];
-  const float4* __restrict__ nrm = s.nrm;
+  const float* __restrict__ NX = s.nrm;
   const float2* __restrict__ cur = s.curv;
   const float2* __restrict__ rdec = s.ref[bt.rd];
   const float2* __restrict__ renc = s.ref[bt.rd ^ 1];
@@ -369,7 +406,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   const float Rn = STORE ? rdec[n].x : 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = IO::ld_d(sp_ + (unsigned)(i * N + n), wq(i) * rho0, wq(i) * Rn);
-  const float4 nc = nrm[n];
+  const float3 nc = make_float3(NX[n], NX[N + n], NX[2 * N + n]);
   const float phi = s.phi[n];
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll

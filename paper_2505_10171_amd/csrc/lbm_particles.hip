@@ -225,11 +225,11 @@ __global__ void k_capbox(Batch bt) {
     const int x = wrapi(org[0] + ix, s.nx), y = wrapi(org[1] + iy, s.ny), z = wrapi(org[2] + iz, s.nz);
     const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
     float4 v = make_float4(2.f, 0.f, 0.f, 0.f);  // phi = 2 marks a solid node
-    const float4 nr = s.nrm[n];
-    if (nr.w >= 0.f) {
+    const float gw = s.nrm[3 * s.N + n];
+    if (gw >= 0.f) {
       // G = n max(|G|, EPS_G): the colour gradient after the wetting rotation
-      const float gm = fmaxf(nr.w, EPS_G);
-      v = make_float4(s.phi[n], nr.x * gm, nr.y * gm, nr.z * gm);
+      const float gm = fmaxf(gw, EPS_G);
+      v = make_float4(s.phi[n], s.nrm[n] * gm, s.nrm[s.N + n] * gm, s.nrm[2 * s.N + n] * gm);
     }
     box[k] = v;
   }
@@ -252,14 +252,30 @@ __global__ __launch_bounds__(256) void k_capillary(Batch bt) {
   const double R = P.R, da = s.cap_dang;
   const double pref = s.cap_pref * (double)P.sin_t;
   const int na = s.cap_na, nph = s.cap_nphi;
+  // the polar and azimuthal grids are fixed: their sines and cosines once per
+  // workgroup (same arguments, same values as per point)
+  constexpr int TAB = 512;
+  __shared__ double t_sa[TAB], t_ca[TAB], t_sp[TAB], t_cp[TAB];
+  const bool tab = na <= TAB && nph <= TAB;
+  if (tab) {
+    for (int j = threadIdx.x; j < na; j += blockDim.x) sincos((j + 0.5) * da, &t_sa[j], &t_ca[j]);
+    for (int k = threadIdx.x; k < nph; k += blockDim.x) sincos(k * da, &t_sp[k], &t_cp[k]);
+  }
+  __syncthreads();
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < na * nph;
        idx += gridDim.x * blockDim.x) {
     const int j = idx / nph, k = idx % nph;
-    const double al = (j + 0.5) * da, ph = k * da;
     double sa, ca, sp, cp;
-    sincos(al, &sa, &ca);
-    sincos(ph, &sp, &cp);
+    if (tab) {
+      sa = t_sa[j];
+      ca = t_ca[j];
+      sp = t_sp[k];
+      cp = t_cp[k];
+    } else {
+      sincos((j + 0.5) * da, &sa, &ca);
+      sincos(k * da, &sp, &cp);
+    }
     const double sh[3] = {sa * cp, sa * sp, ca};
     const double xp[3] = {P.x[0] + R * sh[0], P.x[1] + R * sh[1], P.x[2] + R * sh[2]};
     const double f0 = floor(xp[0]), f1 = floor(xp[1]), f2 = floor(xp[2]);
@@ -364,17 +380,11 @@ __device__ inline void capped_spring(double k, double gam, double cap, double* x
 
 // Contact of particle i with one partner (normal spring-dashpot, sliding and
 // rolling friction after Luding's model as the paper describes it).
-__device__ bool contact(const SimDev& s, Contact* tab, int partner, double delta, const double* nh,
-                        const double* vi, const double* wi, const double* vj, const double* wj,
-                        double Rci, double Rcj, const double* armj, double mu, double mur,
-                        double dt, double* Fo, double* To) {
-  if (!(delta > 0.0)) {
-    Contact* sl = find_slot(tab, partner, false, &s.counters[1]);
-    if (sl) sl->partner = -100;
-    return false;
-  }
-  Contact* sl = find_slot(tab, partner, true, &s.counters[1]);
-  if (!sl) return false;
+// Force and torque of an active contact (delta > 0) whose spring state is sl.
+__device__ void contact_force(const SimDev& s, Contact* sl, double delta, const double* nh,
+                              const double* vi, const double* wi, const double* vj,
+                              const double* wj, double Rci, double Rcj, const double* armj,
+                              double mu, double mur, double dt, double* Fo, double* To) {
   double vrel[3];
   for (int d = 0; d < 3; ++d) vrel[d] = vi[d] - vj[d];
   const double ddot = -dot3(vrel, nh);
@@ -409,7 +419,6 @@ __device__ bool contact(const SimDev& s, Contact* tab, int partner, double delta
     Fo[d] = Fn * nh[d] + Ft[d];
     To[d] = Tt[d] + ap * Tr[d];
   }
-  return true;
 }
 
 __device__ inline void rel_vec(const SimDev& s, const double* a, const double* b, double* d) {
@@ -435,7 +444,7 @@ __device__ void quat_rotate(double* q, const double* th) {
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
 template <bool SH>
-__global__ __launch_bounds__(256) void k_dem(Batch bt) {
+__global__ __launch_bounds__(1024) void k_dem(Batch bt) {
   // one workgroup per simulation
   const SimDev& s = bt.tab[blockIdx.x];
   if (s.np == 0) return;
@@ -549,52 +558,89 @@ __global__ __launch_bounds__(256) void k_dem(Batch bt) {
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < np; i += nt) {
-      DevParticle& P = PP[i];
-      Contact* tab = CT + (long long)i * MAXC;
-      const double Rci = P.Rc;
-      const double zero[3] = {0, 0, 0};
-      double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0}, Fo[3], To[3];
-      if (s.has_wall) {
-        const double nb_[3] = {0, 0, 1}, nt_[3] = {0, 0, -1};
-        const double db = Rci - (P.x[2] - 0.5);
-        if (contact(s, tab, -1, db, nb_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r, dt,
-                    Fo, To))
-          for (int d = 0; d < 3; ++d) {
-            Fs[d] += Fo[d];
-            Ts[d] += To[d];
+    // contacts: one wave per particle, one lane per contact (lanes 0, 1: the
+    // wall and its underside, then the pair candidates in list order)
+    {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = nt >> 6;
+      const int nwall = s.has_wall ? 2 : 0;
+      for (int i = wv; i < np; i += nwv) {
+        DevParticle& P = PP[i];
+        Contact* tab = CT + (long long)i * MAXC;
+        const int* nbl = NB + (long long)i * MAXNB;
+        const double Rci = P.Rc;
+        // the candidate list ends at its first -1, or is full
+        const bool endm = lane >= MAXNB || nbl[lane < MAXNB ? lane : 0] < 0;
+        const unsigned long long em = __ballot(endm);
+        const int ncand = __ffsll((long long)em) - 1;
+        const int ntask = nwall + ncand;
+        const bool act = lane < ntask;
+        int partner = -100;
+        double delta = -1.0, Rcj = 0.0, mu = P.mu_s, mur = P.mu_r;
+        double nh[3] = {0, 0, 0}, vj[3] = {0, 0, 0}, wj[3] = {0, 0, 0}, arm[3] = {0, 0, 0};
+        if (act) {
+          if (lane < nwall) {
+            partner = lane == 0 ? -1 : -2;
+            delta = lane == 0 ? Rci - (P.x[2] - 0.5) : Rci - (((double)s.nz - 0.5) - P.x[2]);
+            nh[2] = lane == 0 ? 1.0 : -1.0;
+          } else {
+            const int j = nbl[lane - nwall];
+            const DevParticle& Pj = PP[j];
+            partner = j;
+            Rcj = Pj.Rc;
+            rel_vec(s, P.x, Pj.x, arm);
+            const double dist = sqrt(dot3(arm, arm));
+            delta = Rci + Rcj - dist;
+            if (dist > 0.0)
+              for (int d = 0; d < 3; ++d) nh[d] = arm[d] / dist;
+            for (int d = 0; d < 3; ++d) {
+              vj[d] = Pj.vp[d];
+              wj[d] = Pj.wp[d];
+            }
+            mu = 0.5 * (P.mu_s + Pj.mu_s);
+            mur = 0.5 * (P.mu_r + Pj.mu_r);
           }
-        const double dtp = Rci - (((double)s.nz - 0.5) - P.x[2]);
-        if (contact(s, tab, -2, dtp, nt_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r,
-                    dt, Fo, To))
-          for (int d = 0; d < 3; ++d) {
-            Fs[d] += Fo[d];
-            Ts[d] += To[d];
+        }
+        // existing spring of this pair (each partner holds at most one slot)
+        int slot = -1;
+        if (act)
+          for (int k = 0; k < MAXC; ++k)
+            if (tab[k].partner == partner) {
+              slot = k;
+              break;
+            }
+        // a contact that ended releases its slot
+        if (act && !(delta > 0.0) && slot >= 0) tab[slot].partner = -100;
+        __threadfence_block();
+        // a contact that began takes the first free slot, one lane after another
+        for (int l = 0; l < ntask; ++l) {
+          if (lane == l && delta > 0.0 && slot < 0) {
+            for (int k = 0; k < MAXC; ++k)
+              if (tab[k].partner == -100) {
+                slot = k;
+                break;
+              }
+            if (slot >= 0) {
+              tab[slot].partner = partner;
+              for (int d = 0; d < 3; ++d) tab[slot].xt[d] = tab[slot].xr[d] = 0.0;
+            } else {
+              atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+            }
           }
-      }
-      const int* nb = NB + (long long)i * MAXNB;
-      for (int q = 0; q < MAXNB; ++q) {
-        const int j = nb[q];
-        if (j < 0) break;
-        const DevParticle& Pj = PP[j];
-        const double Rcj = Pj.Rc;
-        double dx[3];
-        rel_vec(s, P.x, Pj.x, dx);
-        const double dist = sqrt(dot3(dx, dx));
-        const double delta = Rci + Rcj - dist;
-        double nh[3] = {0, 0, 0};
-        if (dist > 0.0)
-          for (int d = 0; d < 3; ++d) nh[d] = dx[d] / dist;
-        if (contact(s, tab, j, delta, nh, P.vp, P.wp, Pj.vp, Pj.wp, Rci, Rcj, dx,
-                    0.5 * (P.mu_s + Pj.mu_s), 0.5 * (P.mu_r + Pj.mu_r), dt, Fo, To))
+          __threadfence_block();
+        }
+        double F[6] = {0, 0, 0, 0, 0, 0};
+        if (act && delta > 0.0 && slot >= 0)
+          contact_force(s, &tab[slot], delta, nh, P.vp, P.wp, vj, wj, Rci, Rcj, arm, mu, mur, dt,
+                        F, F + 3);
+        // fixed-order sum over the wave
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+          for (int off = 32; off > 0; off >>= 1) F[c] += __shfl_xor(F[c], off, 64);
+        if (lane == 0)
           for (int d = 0; d < 3; ++d) {
-            Fs[d] += Fo[d];
-            Ts[d] += To[d];
+            P.Fcn[d] = F[d];
+            P.Tcn[d] = F[3 + d];
           }
-      }
-      for (int d = 0; d < 3; ++d) {
-        P.Fcn[d] = Fs[d];
-        P.Tcn[d] = Ts[d];
       }
     }
     __syncthreads();
@@ -699,9 +745,9 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
   if (need <= (size_t)max_lds && need <= 64 * 1024)
-    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(256), need, st, b);
+    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(1024), need, st, b);
   else
-    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(1024), 0, st, b);
   return hipGetLastError();
 }
 

@@ -144,6 +144,16 @@ class Surrogate:
         self._check(library().srg_sync(self.h))
 
 
+def he_init(seed: int, sizes=(6, 256, 256, 256, 256, 51)):
+    """He-normal weights and zero biases from numpy Generator(PCG64(seed))."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    ps = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        ps.append(g.normal(0.0, np.sqrt(2.0 / a), size=(a, b)))
+        ps.append(np.zeros(b))
+    return ps
+
+
 def flatten(params):
     """Canonical flat order of a list [W1, b1, ..., W5, b5] (W as in x out)."""
     return np.concatenate([np.asarray(p, np.float64).reshape(-1) for p in params]).astype(np.float32)
