@@ -152,7 +152,7 @@ def scale_c3(args):
         t1 = time.perf_counter()
         prof = sim.profile_read()
         sim.profile(False)
-        pop_b, ref_b = (2, 12) if storage == "fp16" else (4, 0)
+        pop_b, ref_b = (2, 8) if storage == "fp16" else (4, 0)
         alg = n_fluid * (19 * pop_b + 38 * pop_b + 24 + ref_b) + (N - n_fluid) * 8
         t_f = prof["fused"][0] / max(prof["fused"][1], 1) * 1e-3
         res[storage] = {"mlups": round(N * args.steps / (t1 - t0) / 1e6, 1),
@@ -317,11 +317,11 @@ def main():
     # populations read (the collision needs f only; the colour enters through
     # phi), all 38 populations written (4 B each, 2 B in FP16 storage), the
     # interface normal (12 B), the curvature term + solid-link word (8 B) and
-    # phi (4 B) read; FP16 adds the references: the node's own density for
-    # decoding (4 B) and the (rho, phi) references of the nodes written to
-    # (8 B per node).  Per solid node the link word.
+    # phi (4 B) read; FP16 adds the references (half2 per node): the node's own
+    # for decoding (4 B) and those of the nodes written to (4 B per node).  Per
+    # solid node the link word.
     pop_b = 2 if args.storage == "fp16" else 4
-    ref_b = 12 if args.storage == "fp16" else 0
+    ref_b = 8 if args.storage == "fp16" else 0
     alg_bytes = n_fluid * (19 * pop_b + 38 * pop_b + 12 + 8 + 4 + ref_b) + (N - n_fluid) * 8
     fused_ms, fused_n = prof["fused"]
     t_fused = fused_ms / max(fused_n, 1) * 1e-3

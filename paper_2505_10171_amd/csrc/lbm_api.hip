@@ -124,7 +124,7 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   L.off_pops0 = take(L.pop_bytes);
   L.off_pops1 = take(L.pop_bytes);
   // FP16 storage: two per-node references (rho, phi) (ping-pong)
-  const size_t ref_bytes = c.storage == LBM_STORE_FP16 ? 8 * (size_t)L.N : 0;
+  const size_t ref_bytes = c.storage == LBM_STORE_FP16 ? 4 * (size_t)L.N : 0;
   L.off_ref0 = take(ref_bytes);
   L.off_ref1 = take(ref_bytes);
   L.off_phi = take(4 * L.N);
@@ -445,8 +445,8 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.pops[0] = b + sh.L.off_pops0;
     d.pops[1] = b + sh.L.off_pops1;
     if (c.storage == LBM_STORE_FP16) {
-      d.ref[0] = (float2*)(b + sh.L.off_ref0);
-      d.ref[1] = (float2*)(b + sh.L.off_ref1);
+      d.ref[0] = (__half2*)(b + sh.L.off_ref0);
+      d.ref[1] = (__half2*)(b + sh.L.off_ref1);
     } else {
       d.ref[0] = d.ref[1] = nullptr;
     }

@@ -91,46 +91,90 @@ struct Contact {
 // bulk colour, and keep FP16's relative precision for them.  In the bulk of
 // either fluid (P = +-1, g = +-f) k is exactly 0, so g = +-f and phi = +-1 hold
 // exactly after decoding.
+// Global-memory view of a pointer.  Pointers read from the simulation table
+// are generic to the compiler; the hot kernels convert them once so that every
+// access compiles to a global (not flat) memory instruction.
+#define GLB __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLB T* gp(T* p) {
+  return (GLB T*)p;
+}
+
 template <int STORE>
 struct Codec;
 
+// iwr0 = 1 / (w_i rho0) (encoding multiplies by it)
 template <>
 struct Codec<0> {
   using T = float;
-  static __device__ __forceinline__ void ld(const T* pd, const T* pg, float, float, float,
-                                            float& d, float& g) {
+  template <class PD, class PG>
+  static __device__ __forceinline__ void ld(PD pd, PG pg, float, float, float, float& d, float& g) {
     d = *pd;
     g = *pg;
   }
-  static __device__ __forceinline__ float ld_d(const T* pd, float, float) { return *pd; }
-  static __device__ __forceinline__ void st(T* pd, T* pg, float, float, float, float d, float g) {
+  template <class PD>
+  static __device__ __forceinline__ float ld_d(PD pd, float, float) {
+    return *pd;
+  }
+  template <class PD, class PG>
+  static __device__ __forceinline__ void st(PD pd, PG pg, float, float, float, float, float d,
+                                            float g) {
     *pd = d;
     *pg = g;
   }
 };
 
+// wr0 = w_i rho0, iwr0 = 1 / wr0, wR = w_i R; values stored as raw FP16 bits
 template <>
 struct Codec<1> {
-  using T = __half;
-  static __device__ __forceinline__ float f_of(const T* pd, float wr0, float wR) {
-    return __fadd_rn(wR, __fmul_rn(wr0, __half2float(*pd)));
+  using T = uint16_t;
+  static __device__ __forceinline__ float h2f(uint16_t v) { return __half2float(__ushort_as_half(v)); }
+  static __device__ __forceinline__ uint16_t f2h(float v) {
+    return __half_as_ushort(__float2half_rn(v));
   }
-  static __device__ __forceinline__ void ld(const T* pd, const T* pg, float wr0, float wR, float P,
-                                            float& d, float& g) {
+  template <class PD>
+  static __device__ __forceinline__ float f_of(PD pd, float wr0, float wR) {
+    return __fadd_rn(wR, __fmul_rn(wr0, h2f(*pd)));
+  }
+  template <class PD, class PG>
+  static __device__ __forceinline__ void ld(PD pd, PG pg, float wr0, float wR, float P, float& d,
+                                            float& g) {
     const float f = f_of(pd, wr0, wR);
     d = __fsub_rn(f, wr0);
-    g = __fadd_rn(__fmul_rn(P, f), __fmul_rn(wr0, __half2float(*pg)));
+    g = __fadd_rn(__fmul_rn(P, f), __fmul_rn(wr0, h2f(*pg)));
   }
-  static __device__ __forceinline__ float ld_d(const T* pd, float wr0, float wR) {
+  template <class PD>
+  static __device__ __forceinline__ float ld_d(PD pd, float wr0, float wR) {
     return __fsub_rn(f_of(pd, wr0, wR), wr0);
   }
-  static __device__ __forceinline__ void st(T* pd, T* pg, float wr0, float wR, float P, float d,
-                                            float g) {
+  template <class PD, class PG>
+  static __device__ __forceinline__ void st(PD pd, PG pg, float wr0, float iwr0, float wR, float P,
+                                            float d, float g) {
     const float f = __fadd_rn(d, wr0);
-    *pd = __float2half_rn(__fdividef(f - wR, wr0));
-    *pg = __float2half_rn(__fdividef(__fsub_rn(g, __fmul_rn(P, f)), wr0));
+    *pd = f2h((f - wR) * iwr0);
+    *pg = f2h(__fsub_rn(g, __fmul_rn(P, f)) * iwr0);
   }
 };
+
+// FP16 reference (R, P) of a node as floats; both the encoder and the decoder
+// read it from the same stored pair
+__device__ __forceinline__ float2 ref_of(const __half2* r, long long n) {
+  return __half22float2(r[n]);
+}
+// the same from a global view of the pairs as 32-bit words
+__device__ __forceinline__ float2 ref_of(const GLB uint32_t* r, long long n) {
+  const uint32_t v = r[n];
+  return make_float2(__half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))),
+                     __half2float(__ushort_as_half((unsigned short)(v >> 16))));
+}
+__device__ __forceinline__ uint32_t ref_pack(float rho, float phi) {
+  return (uint32_t)__half_as_ushort(__float2half_rn(rho)) |
+         ((uint32_t)__half_as_ushort(__float2half_rn(phi)) << 16);
+}
+template <class T>
+__device__ __forceinline__ const GLB uint32_t* gref(T* p) {
+  return (const GLB uint32_t*)p;
+}
 
 struct SimDev {
   int nx, ny, nz, has_wall;
@@ -141,7 +185,7 @@ struct SimDev {
   float wall_neg_cos, wall_sin;
   // fields
   void* pops[2];       // ping-pong population buffers: 38 planes of N
-  float2* ref[2];      // FP16 storage: per-node reference (rho, phi), ping-pong
+  __half2* ref[2];     // FP16 storage: per-node reference (rho, phi), ping-pong
   float* phi;          // order parameter of the current state (PHI_SOLID at solids)
   float* nrm;          // 4 planes of N: n_x, n_y, n_z (NaN at solids), |G| (-1 at solids)
   float2* curv;        // per node (CSF coefficient, solid-neighbour bits as float)

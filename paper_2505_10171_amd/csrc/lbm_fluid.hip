@@ -76,21 +76,22 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   const int2 sb = batch_block(bt, blockIdx.x);
   const SimDev& s = bt.tab[sb.x];
   const void* __restrict__ pops = s.pops[bt.cur];
-  const float2* __restrict__ rdec = s.ref[bt.rd];
-  float2* __restrict__ rnext = s.ref[bt.rd ^ 1];
+  const __half2* __restrict__ rdec = s.ref[bt.rd];
+  __half2* __restrict__ rnext = s.ref[bt.rd ^ 1];
   const long long N = s.N;
   int n, gx, gy, gz;
   if (sb.y == 0 && threadIdx.x == 0) s.counters[0] = 0u;  // fresh list consumed
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
-  uint16_t m = s.mask[n];
+  GLB uint16_t* __restrict__ MASK = gp(s.mask);
+  uint16_t m = MASK[n];
   if (m & FRESH_BIT) {
     m = (uint16_t)(m & ~FRESH_BIT);
-    s.mask[n] = m;
+    MASK[n] = m;
   }
   float out = PHI_SOLID, rho = s.rho0;
   if (m == 0) {
-    const T* b = (const T*)pops;
-    const float2 R = STORE ? rdec[n] : make_float2(0.f, 0.f);
+    const GLB T* b = gp((const T*)pops);
+    const float2 R = STORE ? ref_of(gref(rdec), n) : make_float2(0.f, 0.f);
     // phi = sum g / sum f with f_i = d_i + w_i rho0 rounded exactly as the
     // recolouring forms it, so that a pure fluid (g_i = +-f_i) has phi = +-1
     // exactly and its colour stays segregated without rounding leakage
@@ -107,9 +108,9 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
     out = sg / rabs;
     rho = rabs;
   }
-  s.phi[n] = out;
+  gp(s.phi)[n] = out;
   // reference of the next encoding: this state's density and order parameter
-  if (STORE) rnext[n] = make_float2(rho, m == 0 ? out : 0.f);
+  if (STORE) gp((uint32_t*)rnext)[n] = ref_pack(rho, m == 0 ? out : 0.f);
 }
 
 // ------------------------------------------------------------ init kernels
@@ -131,22 +132,25 @@ __global__ void k_init_pops(SimDev s, void* pops) {
   if (n >= s.N) return;
   T* b = (T*)pops;
   float p0 = (s.mask[n] == 0) ? s.phi[n] : 0.f;
+  // FP16: encode with the stored (rounded) reference the decoder will read
+  const __half2 Rh = __floats2half2_rn(s.rho0, p0);
+  const float2 R0 = STORE ? __half22float2(Rh) : make_float2(s.rho0, p0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float wr0 = wq(i) * s.rho0;
-    IO::st(b + (long long)i * s.N + n, b + (long long)(Q + i) * s.N + n, wr0, wr0, p0, 0.f,
-           wr0 * p0);
+    IO::st(b + (long long)i * s.N + n, b + (long long)(Q + i) * s.N + n, wr0, 1.0f / wr0,
+           wq(i) * R0.x, R0.y, 0.f, wr0 * p0);
   }
   if (STORE) {
-    s.ref[0][n] = make_float2(s.rho0, p0);
-    s.ref[1][n] = make_float2(s.rho0, p0);
+    s.ref[0][n] = Rh;
+    s.ref[1][n] = Rh;
   }
 }
 
 // --------------------------------------------------------- global mass (FP64)
 template <int STORE>
 __global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__ pops,
-                                             const float2* __restrict__ rdec) {
+                                             const __half2* __restrict__ rdec) {
   using IO = Codec<STORE>;
   using T = typename IO::T;
   __shared__ double sh[2][256];
@@ -156,7 +160,7 @@ __global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__
        n += (long long)gridDim.x * blockDim.x) {
     if (s.mask[n] != 0) continue;
     double drho = 0.0, sg = 0.0;
-    const float2 R = STORE ? rdec[n] : make_float2(0.f, 0.f);
+    const float2 R = STORE ? ref_of(rdec, n) : make_float2(0.f, 0.f);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       float d, g;
@@ -226,7 +230,8 @@ struct Nbr {
 __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  float* __restrict__ NX = s.nrm;
+  GLB float* __restrict__ NX = gp(s.nrm);
+  const GLB float* __restrict__ PHI = gp((const float*)s.phi);
   const long long Nn = s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
   int n, gx, gy, gz;
@@ -234,7 +239,7 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   // solid node: NaN normal (tells stencils the neighbour is solid) and |G| = -1
   const float qnan = __int_as_float(0x7fc00000);
   float4 out = make_float4(qnan, qnan, qnan, -1.0f);
-  const float p0 = s.phi[n];
+  const float p0 = PHI[n];
   if (p0 < PHI_SOLID_TEST) {
     const Nbr nb(gx, gy, gz, nx, ny, nz);
     float Gx = 0.f, Gy = 0.f, Gz = 0.f;
@@ -242,8 +247,8 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int i = pair_dir(q);
-      float vp = s.phi[nb(i)];
-      float vm = s.phi[nb(opp(i))];
+      float vp = PHI[nb(i)];
+      float vm = PHI[nb(opp(i))];
       const bool sp = vp > PHI_SOLID_TEST, sm = vm > PHI_SOLID_TEST;
       solid |= sp | sm;
       vp = sp ? p0 : vp;
@@ -281,11 +286,11 @@ __global__ __launch_bounds__(256) void k_curv(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
   // normal planes: x, y, z components (NaN at solid nodes), then |G|
-  const float* __restrict__ NX = s.nrm;
-  const float* __restrict__ NY = NX + s.N;
-  const float* __restrict__ NZ = NY + s.N;
-  const float* __restrict__ NG = NZ + s.N;
-  float2* __restrict__ cur = s.curv;
+  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
+  const GLB float* __restrict__ NY = NX + s.N;
+  const GLB float* __restrict__ NZ = NY + s.N;
+  const GLB float* __restrict__ NG = NZ + s.N;
+  GLB float* __restrict__ cur = gp((float*)s.curv);
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
@@ -338,7 +343,8 @@ __global__ __launch_bounds__(256) void k_curv(Batch bt) {
     }
     c = -0.5f * s.sigma * kappa * fmaxf(g0, EPS_G);
   }
-  cur[n] = make_float2(c, __uint_as_float(bits));
+  cur[2 * n] = c;
+  cur[2 * n + 1] = __uint_as_float(bits);
 }
 
 // ------------------------------------------------------------- fused kernel
@@ -358,21 +364,21 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   using T = typename IO::T;
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  const void* __restrict__ src = s.pops[bt.cur];
-  void* __restrict__ dst = s.pops[bt.cur ^ 1];
-  const float* __restrict__ NX = s.nrm;
-  const float2* __restrict__ cur = s.curv;
-  const float2* __restrict__ rdec = s.ref[bt.rd];
-  const float2* __restrict__ renc = s.ref[bt.rd ^ 1];
+  const GLB T* __restrict__ sp_ = gp((const T*)s.pops[bt.cur]);
+  GLB T* __restrict__ dp_ = gp((T*)s.pops[bt.cur ^ 1]);
+  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
+  const GLB float* __restrict__ cur = gp((const float*)s.curv);
+  const GLB uint32_t* __restrict__ rdec = gref(s.ref[bt.rd]);
+  const GLB uint32_t* __restrict__ renc = gref(s.ref[bt.rd ^ 1]);
+  const GLB float* __restrict__ PHI = gp((const float*)s.phi);
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   const int N = (int)s.N;
   const int nxny = nx * ny;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   const float rho0 = s.rho0;
-  const T* __restrict__ sp_ = (const T*)src;
-  T* __restrict__ dp_ = (T*)dst;
-  const float2 cb = cur[n];
+  const float inv_rho0 = 1.0f / rho0;
+  const float2 cb = make_float2(cur[2 * n], cur[2 * n + 1]);
   const uint32_t bits = __float_as_uint(cb.y);
 
   if (bits & 0x80000000u) {
@@ -403,11 +409,11 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   // the collision needs the total populations only: the colour enters through
   // phi (moments pass) in the recolouring
   float d[Q];
-  const float Rn = STORE ? rdec[n].x : 0.f;
+  const float Rn = STORE ? ref_of(rdec, n).x : 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = IO::ld_d(sp_ + (unsigned)(i * N + n), wq(i) * rho0, wq(i) * Rn);
   const float3 nc = make_float3(NX[n], NX[N + n], NX[2 * N + n]);
-  const float phi = s.phi[n];
+  const float phi = PHI[n];
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -451,9 +457,9 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   // FP16: each population is encoded with the reference of the node that
   // stores it
   auto st_pop = [&](int i, int node, float dv, float gv) {
-    const float2 R = STORE ? renc[node] : make_float2(0.f, 0.f);
+    const float2 R = STORE ? ref_of(renc, node) : make_float2(0.f, 0.f);
     IO::st(dp_ + (unsigned)(i * N + node), dp_ + (unsigned)((Q + i) * N + node), wq(i) * rho0,
-           wq(i) * R.x, R.y, dv, gv);
+           inv_rho0 * (1.0f / wq(i)), wq(i) * R.x, R.y, dv, gv);
   };
   // push to the neighbour in direction i, or bounce back into direction opp(i)
   auto emit = [&](int i, float dv, float gv) {
@@ -514,8 +520,8 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
   const int p = sp.y;
   const void* __restrict__ src = s.pops[bt.cur];
   void* __restrict__ dst = s.pops[bt.cur ^ 1];
-  const float2* __restrict__ rdec = s.ref[bt.rd];
-  const float2* __restrict__ renc = s.ref[bt.rd ^ 1];
+  const __half2* __restrict__ rdec = s.ref[bt.rd];
+  const __half2* __restrict__ renc = s.ref[bt.rd ^ 1];
   const DevParticle& P = s.P[p];
   const int nx = s.nx, ny = s.ny, nz = s.nz, N = (int)s.N;
   const float rho0 = s.rho0;
@@ -547,14 +553,14 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
       const int o = opp(i);
       // f*_i bounced by k_fused into direction opp(i) at x (same weight w_i)
       const float wr0 = wq(o) * rho0;
-      const float2 Re = STORE ? renc[n] : make_float2(0.f, 0.f);
+      const float2 Re = STORE ? ref_of(renc, n) : make_float2(0.f, 0.f);
       const float wRe = wq(o) * Re.x;
       T* fo = dp_ + (unsigned)(o * N + n);
       T* go = dp_ + (unsigned)((Q + o) * N + n);
       float ds, gs;
       IO::ld(fo, go, wr0, wRe, Re.y, ds, gs);
       const float phi = s.phi[n];
-      const float Rd = STORE ? rdec[n].x : 0.f;
+      const float Rd = STORE ? ref_of(rdec, n).x : 0.f;
       float drho = 0.f;
 #pragma unroll
       for (int q = 0; q < Q; ++q) drho += IO::ld_d(sp_ + (unsigned)(q * N + n), wq(q) * rho0, wq(q) * Rd);
@@ -568,7 +574,7 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
       const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));  // c_opp . u_w
       const float corr = 6.0f * wq(i) * rho * cu;
       const float dso = ds + corr;
-      IO::st(fo, go, wr0, wRe, Re.y, dso, gs + phi * corr);
+      IO::st(fo, go, wr0, 1.0f / wr0, wRe, Re.y, dso, gs + phi * corr);
       const double wr = wqd(i) * (double)rho0;
       const double fin = (double)ds + wr;
       const double fout = (double)dso + wr;

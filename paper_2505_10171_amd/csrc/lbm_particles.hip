@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
   const SimDev& s = bt.tab[blockIdx.y];
   if (s.np == 0) return;
   void* pops = s.pops[bt.cur];
-  const float2* __restrict__ rdec = s.ref[bt.rd];
+  const __half2* __restrict__ rdec = s.ref[bt.rd];
   constexpr int PER = 14;
   __shared__ float sh_a[PER][18], sh_b[PER][18];
   __shared__ int sh_c[PER][18];
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
                                                (long long)s.ny * wrapi(z + cz(dir), s.nz));
         if (s.mask[m] == 0) {
           float drho = 0.f, sg = 0.f;
-          const float2 R = STORE ? rdec[m] : make_float2(0.f, 0.f);
+          const float2 R = STORE ? ref_of(rdec, m) : make_float2(0.f, 0.f);
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float d, g;
@@ -192,14 +192,14 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
       const float uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
       const float uu = ux * ux + uy * uy + uz * uz;
       const float rho = ra + rb;
-      const float2 Rn = STORE ? rdec[n] : make_float2(0.f, 0.f);
+      const float2 Rn = STORE ? ref_of(rdec, n) : make_float2(0.f, 0.f);
       for (int q = 0; q < Q; ++q) {
         const float cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
         const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
         const float dq = wq(q) * ((rho - s.rho0) + rho * poly);
         const float gq = wq(q) * (ra - rb) * (1.0f + poly);
         IO::st(b + (long long)q * N + n, b + (long long)(Q + q) * N + n, wq(q) * s.rho0,
-               wq(q) * Rn.x, Rn.y, dq, gq);
+               1.0f / (wq(q) * s.rho0), wq(q) * Rn.x, Rn.y, dq, gq);
       }
     }
     __syncthreads();
@@ -380,11 +380,17 @@ __device__ inline void capped_spring(double k, double gam, double cap, double* x
 
 // Contact of particle i with one partner (normal spring-dashpot, sliding and
 // rolling friction after Luding's model as the paper describes it).
-// Force and torque of an active contact (delta > 0) whose spring state is sl.
-__device__ void contact_force(const SimDev& s, Contact* sl, double delta, const double* nh,
-                              const double* vi, const double* wi, const double* vj,
-                              const double* wj, double Rci, double Rcj, const double* armj,
-                              double mu, double mur, double dt, double* Fo, double* To) {
+__device__ bool contact(const SimDev& s, Contact* tab, int partner, double delta, const double* nh,
+                        const double* vi, const double* wi, const double* vj, const double* wj,
+                        double Rci, double Rcj, const double* armj, double mu, double mur,
+                        double dt, double* Fo, double* To) {
+  if (!(delta > 0.0)) {
+    Contact* sl = find_slot(tab, partner, false, &s.counters[1]);
+    if (sl) sl->partner = -100;
+    return false;
+  }
+  Contact* sl = find_slot(tab, partner, true, &s.counters[1]);
+  if (!sl) return false;
   double vrel[3];
   for (int d = 0; d < 3; ++d) vrel[d] = vi[d] - vj[d];
   const double ddot = -dot3(vrel, nh);
@@ -419,6 +425,7 @@ __device__ void contact_force(const SimDev& s, Contact* sl, double delta, const 
     Fo[d] = Fn * nh[d] + Ft[d];
     To[d] = Tt[d] + ap * Tr[d];
   }
+  return true;
 }
 
 __device__ inline void rel_vec(const SimDev& s, const double* a, const double* b, double* d) {
@@ -444,7 +451,7 @@ __device__ void quat_rotate(double* q, const double* th) {
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
 template <bool SH>
-__global__ __launch_bounds__(1024) void k_dem(Batch bt) {
+__global__ __launch_bounds__(256) void k_dem(Batch bt) {
   // one workgroup per simulation
   const SimDev& s = bt.tab[blockIdx.x];
   if (s.np == 0) return;
@@ -558,89 +565,52 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
       }
     }
     __syncthreads();
-    // contacts: one wave per particle, one lane per contact (lanes 0, 1: the
-    // wall and its underside, then the pair candidates in list order)
-    {
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = nt >> 6;
-      const int nwall = s.has_wall ? 2 : 0;
-      for (int i = wv; i < np; i += nwv) {
-        DevParticle& P = PP[i];
-        Contact* tab = CT + (long long)i * MAXC;
-        const int* nbl = NB + (long long)i * MAXNB;
-        const double Rci = P.Rc;
-        // the candidate list ends at its first -1, or is full
-        const bool endm = lane >= MAXNB || nbl[lane < MAXNB ? lane : 0] < 0;
-        const unsigned long long em = __ballot(endm);
-        const int ncand = __ffsll((long long)em) - 1;
-        const int ntask = nwall + ncand;
-        const bool act = lane < ntask;
-        int partner = -100;
-        double delta = -1.0, Rcj = 0.0, mu = P.mu_s, mur = P.mu_r;
-        double nh[3] = {0, 0, 0}, vj[3] = {0, 0, 0}, wj[3] = {0, 0, 0}, arm[3] = {0, 0, 0};
-        if (act) {
-          if (lane < nwall) {
-            partner = lane == 0 ? -1 : -2;
-            delta = lane == 0 ? Rci - (P.x[2] - 0.5) : Rci - (((double)s.nz - 0.5) - P.x[2]);
-            nh[2] = lane == 0 ? 1.0 : -1.0;
-          } else {
-            const int j = nbl[lane - nwall];
-            const DevParticle& Pj = PP[j];
-            partner = j;
-            Rcj = Pj.Rc;
-            rel_vec(s, P.x, Pj.x, arm);
-            const double dist = sqrt(dot3(arm, arm));
-            delta = Rci + Rcj - dist;
-            if (dist > 0.0)
-              for (int d = 0; d < 3; ++d) nh[d] = arm[d] / dist;
-            for (int d = 0; d < 3; ++d) {
-              vj[d] = Pj.vp[d];
-              wj[d] = Pj.wp[d];
-            }
-            mu = 0.5 * (P.mu_s + Pj.mu_s);
-            mur = 0.5 * (P.mu_r + Pj.mu_r);
-          }
-        }
-        // existing spring of this pair (each partner holds at most one slot)
-        int slot = -1;
-        if (act)
-          for (int k = 0; k < MAXC; ++k)
-            if (tab[k].partner == partner) {
-              slot = k;
-              break;
-            }
-        // a contact that ended releases its slot
-        if (act && !(delta > 0.0) && slot >= 0) tab[slot].partner = -100;
-        __threadfence_block();
-        // a contact that began takes the first free slot, one lane after another
-        for (int l = 0; l < ntask; ++l) {
-          if (lane == l && delta > 0.0 && slot < 0) {
-            for (int k = 0; k < MAXC; ++k)
-              if (tab[k].partner == -100) {
-                slot = k;
-                break;
-              }
-            if (slot >= 0) {
-              tab[slot].partner = partner;
-              for (int d = 0; d < 3; ++d) tab[slot].xt[d] = tab[slot].xr[d] = 0.0;
-            } else {
-              atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
-            }
-          }
-          __threadfence_block();
-        }
-        double F[6] = {0, 0, 0, 0, 0, 0};
-        if (act && delta > 0.0 && slot >= 0)
-          contact_force(s, &tab[slot], delta, nh, P.vp, P.wp, vj, wj, Rci, Rcj, arm, mu, mur, dt,
-                        F, F + 3);
-        // fixed-order sum over the wave
-#pragma unroll
-        for (int c = 0; c < 6; ++c)
-          for (int off = 32; off > 0; off >>= 1) F[c] += __shfl_xor(F[c], off, 64);
-        if (lane == 0)
+    for (int i = threadIdx.x; i < np; i += nt) {
+      DevParticle& P = PP[i];
+      Contact* tab = CT + (long long)i * MAXC;
+      const double Rci = P.Rc;
+      const double zero[3] = {0, 0, 0};
+      double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0}, Fo[3], To[3];
+      if (s.has_wall) {
+        const double nb_[3] = {0, 0, 1}, nt_[3] = {0, 0, -1};
+        const double db = Rci - (P.x[2] - 0.5);
+        if (contact(s, tab, -1, db, nb_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r, dt,
+                    Fo, To))
           for (int d = 0; d < 3; ++d) {
-            P.Fcn[d] = F[d];
-            P.Tcn[d] = F[3 + d];
+            Fs[d] += Fo[d];
+            Ts[d] += To[d];
           }
+        const double dtp = Rci - (((double)s.nz - 0.5) - P.x[2]);
+        if (contact(s, tab, -2, dtp, nt_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r,
+                    dt, Fo, To))
+          for (int d = 0; d < 3; ++d) {
+            Fs[d] += Fo[d];
+            Ts[d] += To[d];
+          }
+      }
+      const int* nb = NB + (long long)i * MAXNB;
+      for (int q = 0; q < MAXNB; ++q) {
+        const int j = nb[q];
+        if (j < 0) break;
+        const DevParticle& Pj = PP[j];
+        const double Rcj = Pj.Rc;
+        double dx[3];
+        rel_vec(s, P.x, Pj.x, dx);
+        const double dist = sqrt(dot3(dx, dx));
+        const double delta = Rci + Rcj - dist;
+        double nh[3] = {0, 0, 0};
+        if (dist > 0.0)
+          for (int d = 0; d < 3; ++d) nh[d] = dx[d] / dist;
+        if (contact(s, tab, j, delta, nh, P.vp, P.wp, Pj.vp, Pj.wp, Rci, Rcj, dx,
+                    0.5 * (P.mu_s + Pj.mu_s), 0.5 * (P.mu_r + Pj.mu_r), dt, Fo, To))
+          for (int d = 0; d < 3; ++d) {
+            Fs[d] += Fo[d];
+            Ts[d] += To[d];
+          }
+      }
+      for (int d = 0; d < 3; ++d) {
+        P.Fcn[d] = Fs[d];
+        P.Tcn[d] = Ts[d];
       }
     }
     __syncthreads();
@@ -745,9 +715,9 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
   if (need <= (size_t)max_lds && need <= 64 * 1024)
-    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(1024), need, st, b);
+    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(256), need, st, b);
   else
-    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(1024), 0, st, b);
+    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

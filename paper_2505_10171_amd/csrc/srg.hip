@@ -5,9 +5,10 @@
 // workgroup, K in steps of 32 staged through LDS (both operands stored with K
 // contiguous, so each lane reads its eight-element fragment with one 16-byte
 // LDS load), and each of the four waves accumulating a 32x32 sub-tile with
-// four v_mfma_f32_16x16x32_bf16 per K step.  Transposed operands (W^T in dX,
-// X^T in dW) are transposed while staging.  Epilogues fuse the bias, the ReLU
-// and the ReLU derivative.
+// four v_mfma_f32_16x16x32_bf16 per K step.  The forward products read a BF16
+// copy of each weight matrix kept transposed (N x K), so both operands stage
+// with 16-byte copies; the backward products transpose W^T (dX) and X^T (dW)
+// while staging.  Epilogues fuse the bias, the ReLU and the ReLU derivative.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -212,6 +213,15 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   pb[i] = (bf16)pi;
 }
 
+// BF16 copy of a weight matrix W (K x N, FP32) stored transposed (N x K), the
+// layout the forward product stages without scattering
+__global__ void k_transpose_bf16(const float* __restrict__ W, int K, int N, bf16* __restrict__ Wt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * N) return;
+  const int n = t / K, k = t - n * K;
+  Wt[t] = (bf16)W[(long long)k * N + n];
+}
+
 __global__ void k_to_bf16(const float* __restrict__ p, bf16* __restrict__ pb, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) pb[i] = (bf16)p[i];
@@ -234,7 +244,8 @@ size_t aup(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
   size_t w_off[NL], b_off[NL], n_par;  // offsets (elements) in the padded vector
-  size_t off_p, off_g, off_m, off_v, off_pb, off_xall, off_lab, off_traj, off_perm, off_xb,
+  size_t t_off[NL], n_wt;              // transposed weight copies (N x K per layer)
+  size_t off_p, off_g, off_m, off_v, off_pb, off_pbt, off_xall, off_lab, off_traj, off_perm, off_xb,
       off_act[NL], off_y, off_dy, off_dz[2], off_acc, off_xin, off_yout, total;
 };
 
@@ -248,6 +259,12 @@ Layout make_layout(int max_batch, int max_train) {
     e += NOUT[l];
   }
   L.n_par = e;
+  size_t t = 0;
+  for (int l = 0; l < NL; ++l) {
+    L.t_off[l] = t;
+    t += (size_t)KIN[l] * NOUT[l];
+  }
+  L.n_wt = t;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -259,6 +276,7 @@ Layout make_layout(int max_batch, int max_train) {
   L.off_m = take(4 * e);
   L.off_v = take(4 * e);
   L.off_pb = take(2 * e);
+  L.off_pbt = take(2 * t);
   L.off_xall = take(2 * 32 * (size_t)max_train);
   L.off_lab = take(4 * (size_t)max_train);
   L.off_traj = take(4 * NTRAJ * (size_t)max_train);
@@ -295,6 +313,7 @@ struct srg_ctx {
   float* p() { return (float*)(ws + L.off_p); }
   float* g() { return (float*)(ws + L.off_g); }
   bf16* pb() { return (bf16*)(ws + L.off_pb); }
+  bf16* pbt() { return (bf16*)(ws + L.off_pbt); }
   bf16* act(int l) { return (bf16*)(ws + L.off_act[l]); }
 };
 
@@ -316,6 +335,8 @@ static int srg_err(srg_ctx* c, int code, const char* fmt, ...) {
       return srg_err((ctx), LBM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+static int refresh_transposed(srg_ctx* c);
+
 template <bool TA, bool TB, int EPI>
 static hipError_t gemm(hipStream_t st, int M, int N, int K, const bf16* A, int lda, const bf16* B,
                        int ldb, const float* bias, const bf16* act, int ldact, bf16* Cb, float* Cf,
@@ -334,15 +355,16 @@ static int forward(srg_ctx* c, const bf16* Xb, int B) {
   const bf16* in = Xb;
   int ld_in = 32;
   for (int l = 0; l < NL - 1; ++l) {
-    SCHK(c, (gemm<false, false, EPI_RELU_BF16>(st, B, NOUT[l], KIN[l], in, ld_in, pb + c->L.w_off[l],
-                                               NOUT[l], p + c->L.b_off[l], nullptr, 0,
-                                               c->act(l + 1), nullptr, 256)));
+    SCHK(c, (gemm<false, true, EPI_RELU_BF16>(st, B, NOUT[l], KIN[l], in, ld_in,
+                                              c->pbt() + c->L.t_off[l], KIN[l],
+                                              p + c->L.b_off[l], nullptr, 0, c->act(l + 1),
+                                              nullptr, 256)));
     in = c->act(l + 1);
     ld_in = 256;
   }
-  SCHK(c, (gemm<false, false, EPI_LINEAR_F32>(st, B, 64, 256, in, 256, pb + c->L.w_off[4], 64,
-                                              p + c->L.b_off[4], nullptr, 0, nullptr,
-                                              (float*)(c->ws + c->L.off_y), 64)));
+  SCHK(c, (gemm<false, true, EPI_LINEAR_F32>(st, B, 64, 256, in, 256, c->pbt() + c->L.t_off[4],
+                                             256, p + c->L.b_off[4], nullptr, 0, nullptr,
+                                             (float*)(c->ws + c->L.off_y), 64)));
   return LBM_OK;
 }
 
@@ -423,6 +445,7 @@ int srg_set_params(srg_ctx* c, const float* params) {
   hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((c->L.n_par + 255) / 256)), dim3(256), 0, c->stream,
                      c->p(), c->pb(), (long long)c->L.n_par);
   SCHK(c, hipGetLastError());
+  if (int rc = refresh_transposed(c)) return rc;
   c->step = 0;
   SCHK(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
@@ -474,6 +497,16 @@ int srg_set_train(srg_ctx* c, const float* X, const int32_t* label, const float*
   return LBM_OK;
 }
 
+static int refresh_transposed(srg_ctx* c) {
+  for (int l = 0; l < NL; ++l) {
+    const int n = KIN[l] * NOUT[l];
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                       c->p() + c->L.w_off[l], KIN[l], NOUT[l], c->pbt() + c->L.t_off[l]);
+  }
+  SCHK(c, hipGetLastError());
+  return LBM_OK;
+}
+
 static int adam(srg_ctx* c, float lr) {
   ++c->step;
   const float bc1 = 1.f - powf(0.9f, (float)c->step), bc2 = 1.f - powf(0.999f, (float)c->step);
@@ -481,7 +514,7 @@ static int adam(srg_ctx* c, float lr) {
                      c->p(), c->g(), (float*)(c->ws + c->L.off_m), (float*)(c->ws + c->L.off_v),
                      c->pb(), (long long)c->L.n_par, lr, bc1, bc2);
   SCHK(c, hipGetLastError());
-  return LBM_OK;
+  return refresh_transposed(c);
 }
 
 int srg_train(srg_ctx* c, int32_t epochs, int32_t batch, float lr, float w_traj, uint64_t seed,
