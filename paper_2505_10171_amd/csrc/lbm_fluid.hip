@@ -540,10 +540,22 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = t / 18, i = 1 + t - 18 * (t / 18);
   double acc[6] = {0, 0, 0, 0, 0, 0};
+  bool near = false;
+  int gx = 0, gy = 0, gz = 0;
   if (k < vol) {
-    const int gx = wrapi(lo[0] + k % w[0], nx);
-    const int gy = wrapi(lo[1] + (k / w[0]) % w[1], ny);
-    const int gz = wrapi(lo[2] + k / (w[0] * w[1]), nz);
+    gx = wrapi(lo[0] + k % w[0], nx);
+    gy = wrapi(lo[1] + (k / w[0]) % w[1], ny);
+    gz = wrapi(lo[2] + k / (w[0] * w[1]), nz);
+    // a fluid node with a link to p lies within R + sqrt(2) of its centre and
+    // not inside (R - 0.5 leaves room for rounding): others skip every load
+    const double dx = wrapd((double)gx - P.x[0], (double)nx);
+    const double dy = wrapd((double)gy - P.x[1], (double)ny);
+    const double dz = wrapd((double)gz - P.x[2], (double)nz);
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double rlo = P.R - 0.5, rhi = P.R + 1.5;
+    near = d2 < rhi * rhi && (rlo <= 0.0 || d2 >= rlo * rlo);
+  }
+  if (near) {
     const int n = gx + nx * (gy + ny * gz);
     const int m = wrapi(gx + cx(i), nx) + nx * (wrapi(gy + cy(i), ny) + ny * wrapi(gz + cz(i), nz));
     const uint16_t mn = s.mask[n], mm = s.mask[m];

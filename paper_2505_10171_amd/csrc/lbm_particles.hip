@@ -347,16 +347,24 @@ __device__ inline double dot3(const double* a, const double* b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// Slot of `partner` in a particle's contact table (created if asked and free
+// slots remain).  The scans read all MAXC entries without early exit so that
+// their loads issue together (the table may live in global memory).
 __device__ Contact* find_slot(Contact* t, int partner, bool create, uint32_t* status) {
-  for (int k = 0; k < MAXC; ++k)
-    if (t[k].partner == partner) return &t[k];
+  int found = -1, freek = -1;
+#pragma unroll
+  for (int k = MAXC - 1; k >= 0; --k) {
+    const int pk = t[k].partner;
+    if (pk == partner) found = k;
+    if (pk == -100) freek = k;
+  }
+  if (found >= 0) return &t[found];
   if (!create) return nullptr;
-  for (int k = 0; k < MAXC; ++k)
-    if (t[k].partner == -100) {
-      t[k].partner = partner;
-      for (int d = 0; d < 3; ++d) t[k].xt[d] = t[k].xr[d] = 0.0;
-      return &t[k];
-    }
+  if (freek >= 0) {
+    t[freek].partner = partner;
+    for (int d = 0; d < 3; ++d) t[freek].xt[d] = t[freek].xr[d] = 0.0;
+    return &t[freek];
+  }
   atomicOr(status, (uint32_t)ST_CONTACT_FULL);
   return nullptr;
 }
@@ -451,7 +459,7 @@ __device__ void quat_rotate(double* q, const double* th) {
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
 template <bool SH>
-__global__ __launch_bounds__(256) void k_dem(Batch bt) {
+__global__ __launch_bounds__(1024) void k_dem(Batch bt) {
   // one workgroup per simulation
   const SimDev& s = bt.tab[blockIdx.x];
   if (s.np == 0) return;
@@ -714,10 +722,12 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
   }
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
+  // one thread per particle where possible (many-particle boxes get 1024)
+  const unsigned nt = np_max > 256 ? 1024u : 256u;
   if (need <= (size_t)max_lds && need <= 64 * 1024)
-    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(256), need, st, b);
+    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(nt), need, st, b);
   else
-    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(nt), 0, st, b);
   return hipGetLastError();
 }
 
