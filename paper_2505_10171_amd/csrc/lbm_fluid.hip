@@ -510,18 +510,18 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
 // particle over the nodes of its bounding box grown by one.
 template <int STORE>
 __global__ __launch_bounds__(256) void k_links(Batch bt) {
-  // one thread per (node of the particle's box, direction 1..18); runs after
-  // k_fused, before the buffers swap: src holds the state it read, dst the
-  // state it wrote
+  // one thread per node of the particle's box; runs after k_fused, before the
+  // buffers swap: src holds the state it read, dst the state it wrote
   using IO = Codec<STORE>;
   using T = typename IO::T;
   const int2 sp = batch_particle(bt, blockIdx.y);
   const SimDev& s = bt.tab[sp.x];
   const int p = sp.y;
-  const void* __restrict__ src = s.pops[bt.cur];
-  void* __restrict__ dst = s.pops[bt.cur ^ 1];
-  const __half2* __restrict__ rdec = s.ref[bt.rd];
-  const __half2* __restrict__ renc = s.ref[bt.rd ^ 1];
+  const GLB T* __restrict__ sp_ = gp((const T*)s.pops[bt.cur]);
+  GLB T* __restrict__ dp_ = gp((T*)s.pops[bt.cur ^ 1]);
+  const GLB uint32_t* __restrict__ rdec = gref(s.ref[bt.rd]);
+  const GLB uint32_t* __restrict__ renc = gref(s.ref[bt.rd ^ 1]);
+  const GLB uint16_t* __restrict__ MASK = gp((const uint16_t*)s.mask);
   const DevParticle& P = s.P[p];
   const int nx = s.nx, ny = s.ny, nz = s.nz, N = (int)s.N;
   const float rho0 = s.rho0;
@@ -537,70 +537,82 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
     }
   }
   const int vol = w[0] * w[1] * w[2];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = t / 18, i = 1 + t - 18 * (t / 18);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  bool near = false;
-  int gx = 0, gy = 0, gz = 0;
+  bool any = false;
   if (k < vol) {
-    gx = wrapi(lo[0] + k % w[0], nx);
-    gy = wrapi(lo[1] + (k / w[0]) % w[1], ny);
-    gz = wrapi(lo[2] + k / (w[0] * w[1]), nz);
+    const int gx = wrapi(lo[0] + k % w[0], nx);
+    const int gy = wrapi(lo[1] + (k / w[0]) % w[1], ny);
+    const int gz = wrapi(lo[2] + k / (w[0] * w[1]), nz);
     // a fluid node with a link to p lies within R + sqrt(2) of its centre and
-    // not inside (R - 0.5 leaves room for rounding): others skip every load
+    // not inside (R - 0.5 leaves room for rounding): others load nothing
     const double dx = wrapd((double)gx - P.x[0], (double)nx);
     const double dy = wrapd((double)gy - P.x[1], (double)ny);
     const double dz = wrapd((double)gz - P.x[2], (double)nz);
     const double d2 = dx * dx + dy * dy + dz * dz;
     const double rlo = P.R - 0.5, rhi = P.R + 1.5;
-    near = d2 < rhi * rhi && (rlo <= 0.0 || d2 >= rlo * rlo);
-  }
-  if (near) {
     const int n = gx + nx * (gy + ny * gz);
-    const int m = wrapi(gx + cx(i), nx) + nx * (wrapi(gy + cy(i), ny) + ny * wrapi(gz + cz(i), nz));
-    const uint16_t mn = s.mask[n], mm = s.mask[m];
-    if (mn == 0 && mm == (uint16_t)(2 + p)) {
-      const T* __restrict__ sp_ = (const T*)src;
-      T* __restrict__ dp_ = (T*)dst;
-      const int o = opp(i);
-      // f*_i bounced by k_fused into direction opp(i) at x (same weight w_i)
-      const float wr0 = wq(o) * rho0;
-      const float2 Re = STORE ? ref_of(renc, n) : make_float2(0.f, 0.f);
-      const float wRe = wq(o) * Re.x;
-      T* fo = dp_ + (unsigned)(o * N + n);
-      T* go = dp_ + (unsigned)((Q + o) * N + n);
-      float ds, gs;
-      IO::ld(fo, go, wr0, wRe, Re.y, ds, gs);
-      const float phi = s.phi[n];
-      const float Rd = STORE ? ref_of(rdec, n).x : 0.f;
-      float drho = 0.f;
+    if (d2 < rhi * rhi && (rlo <= 0.0 || d2 >= rlo * rlo) && MASK[n] == 0) {
+      const Nbr nb(gx, gy, gz, nx, ny, nz);
+      const uint16_t me = (uint16_t)(2 + p);
+      uint32_t lm = 0;  // bit i: the neighbour in direction i is a solid node of p
 #pragma unroll
-      for (int q = 0; q < Q; ++q) drho += IO::ld_d(sp_ + (unsigned)(q * N + n), wq(q) * rho0, wq(q) * Rd);
-      const float rho = rho0 + drho;
-      const double rx = wrapd((double)gx + 0.5 * cx(i) - P.x[0], (double)nx);
-      const double ry = wrapd((double)gy + 0.5 * cy(i) - P.x[1], (double)ny);
-      const double rz = wrapd((double)gz + 0.5 * cz(i) - P.x[2], (double)nz);
-      const double uwx = P.v[0] + (P.w[1] * rz - P.w[2] * ry);
-      const double uwy = P.v[1] + (P.w[2] * rx - P.w[0] * rz);
-      const double uwz = P.v[2] + (P.w[0] * ry - P.w[1] * rx);
-      const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));  // c_opp . u_w
-      const float corr = 6.0f * wq(i) * rho * cu;
-      const float dso = ds + corr;
-      IO::st(fo, go, wr0, 1.0f / wr0, wRe, Re.y, dso, gs + phi * corr);
-      const double wr = wqd(i) * (double)rho0;
-      const double fin = (double)ds + wr;
-      const double fout = (double)dso + wr;
-      const double dPx = (cx(i) - uwx) * fin - (-cx(i) - uwx) * fout;
-      const double dPy = (cy(i) - uwy) * fin - (-cy(i) - uwy) * fout;
-      const double dPz = (cz(i) - uwz) * fin - (-cz(i) - uwz) * fout;
-      acc[0] = dPx;
-      acc[1] = dPy;
-      acc[2] = dPz;
-      acc[3] = ry * dPz - rz * dPy;
-      acc[4] = rz * dPx - rx * dPz;
-      acc[5] = rx * dPy - ry * dPx;
+      for (int i = 1; i < Q; ++i) lm |= (MASK[nb(i)] == me) ? (1u << i) : 0u;
+      if (lm) {
+        any = true;
+        const float2 Re = STORE ? ref_of(renc, n) : make_float2(0.f, 0.f);
+        const float Rd = STORE ? ref_of(rdec, n).x : 0.f;
+        const float phi = gp((const float*)s.phi)[n];
+        float drho = 0.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          drho += IO::ld_d(sp_ + (unsigned)(q * N + n), wq(q) * rho0, wq(q) * Rd);
+        const float rho = rho0 + drho;
+        // f*_i was bounced by k_fused into direction opp(i) at x: all of them
+        // loaded first, then corrected and stored
+        float ds[Q], gs[Q];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          ds[i] = gs[i] = 0.f;
+          if (lm & (1u << i)) {
+            const int o = opp(i);
+            IO::ld(dp_ + (unsigned)(o * N + n), dp_ + (unsigned)((Q + o) * N + n), wq(o) * rho0,
+                   wq(o) * Re.x, Re.y, ds[i], gs[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          if (!(lm & (1u << i))) continue;
+          const int o = opp(i);
+          const float wr0 = wq(o) * rho0;
+          const double rx = wrapd((double)gx + 0.5 * cx(i) - P.x[0], (double)nx);
+          const double ry = wrapd((double)gy + 0.5 * cy(i) - P.x[1], (double)ny);
+          const double rz = wrapd((double)gz + 0.5 * cz(i) - P.x[2], (double)nz);
+          const double uwx = P.v[0] + (P.w[1] * rz - P.w[2] * ry);
+          const double uwy = P.v[1] + (P.w[2] * rx - P.w[0] * rz);
+          const double uwz = P.v[2] + (P.w[0] * ry - P.w[1] * rx);
+          const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));  // c_opp . u_w
+          const float corr = 6.0f * wq(i) * rho * cu;
+          const float dso = ds[i] + corr;
+          IO::st(dp_ + (unsigned)(o * N + n), dp_ + (unsigned)((Q + o) * N + n), wr0, 1.0f / wr0,
+                 wq(o) * Re.x, Re.y, dso, gs[i] + phi * corr);
+          const double wr = wqd(i) * (double)rho0;
+          const double fin = (double)ds[i] + wr;
+          const double fout = (double)dso + wr;
+          const double dPx = (cx(i) - uwx) * fin - (-cx(i) - uwx) * fout;
+          const double dPy = (cy(i) - uwy) * fin - (-cy(i) - uwy) * fout;
+          const double dPz = (cz(i) - uwz) * fin - (-cz(i) - uwz) * fout;
+          acc[0] += dPx;
+          acc[1] += dPy;
+          acc[2] += dPz;
+          acc[3] += ry * dPz - rz * dPy;
+          acc[4] += rz * dPx - rx * dPz;
+          acc[5] += rx * dPy - ry * dPx;
+        }
+      }
     }
   }
+  if (!__syncthreads_or(any)) return;  // no link in this block
   // wave reduction, then across the block's waves
 #pragma unroll
   for (int c = 0; c < 6; ++c)
@@ -658,7 +670,7 @@ hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipS
   if (np_rows == 0) return hipSuccess;
   // the box of k_links spans at most 2 R + 6 nodes per axis, R <= (Bmask - 5) / 2
   const long long B = Bmax + 1;
-  const dim3 grid((unsigned)((B * B * B * 18 + 255) / 256), np_rows);
+  const dim3 grid((unsigned)((B * B * B + 255) / 256), np_rows);
   if (storage == 0)
     hipLaunchKernelGGL(k_links<0>, grid, dim3(256), 0, st, b);
   else
