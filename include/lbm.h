@@ -180,8 +180,9 @@ int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]);
  * collision-duration rule dt_DEM ~ t_c / 45). */
 int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out);
 
-/* Per-phase timing for benchmarks.  lbm_profile(ctx, 1) starts (or restarts)
- * recording HIP events on the context's stream around each step's phases:
+/* Per-phase timing for benchmarks.  lbm_profile(ctx, k), k >= 1, starts (or
+ * restarts) recording HIP events on the context's stream around the phases of
+ * every k-th step (k = 1: every step):
  * kind 0 the fused collide-stream kernel, kind 1 the particle kernels
  * (capillary, DEM, mask update, refill), kind 2 the order-parameter kernel,
  * kind 3 the interface kernel (normal and curvature);

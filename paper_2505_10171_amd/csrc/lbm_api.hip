@@ -217,6 +217,8 @@ constexpr int PROF_KINDS = 4;  // 0 k_fused, 1 particle kernels, 2 k_moments, 3 
 constexpr int PROF_EVENTS = PROF_KINDS + 1;
 struct Profiler {
   bool on = false;
+  int every = 1;           // time every k-th step
+  long long step_no = 0;
   hipEvent_t ev[PROF_RING][PROF_EVENTS];
   bool pending[PROF_RING];
   int next = 0;
@@ -652,7 +654,7 @@ int lbm_step(lbm_ctx* ctx, int32_t n_steps) {
   }
   for (int t = 0; t < n_steps; ++t) {
     int slot = -1;
-    if (P.on) {
+    if (P.on && (P.step_no++ % P.every) == 0) {
       slot = P.next;
       P.next = (P.next + 1) % PROF_RING;
       int rc = prof_harvest(ctx, slot);
@@ -753,6 +755,11 @@ int lbm_profile(lbm_ctx* ctx, int32_t enable) {
   if (!ctx) return LBM_EINVAL;
   if (ctx->err) return LBM_ESTATE;
   Profiler& P = ctx->prof;
+  if (enable < 0) return set_err(ctx, LBM_EINVAL, "profile interval must be >= 0");
+  if (enable) {
+    P.every = enable;
+    P.step_no = 0;
+  }
   if (enable && !P.on) {
     for (int r = 0; r < PROF_RING; ++r) {
       for (int k = 0; k < PROF_EVENTS; ++k) HIPCHK(ctx, hipEventCreate(&P.ev[r][k]));

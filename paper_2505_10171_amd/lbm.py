@@ -305,8 +305,9 @@ class Context:
         self._check(load_library().lbm_mass(self.h, sim, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
-    def profile(self, enable: bool = True):
-        self._check(load_library().lbm_profile(self.h, 1 if enable else 0))
+    def profile(self, enable: bool = True, every: int = 1):
+        """Time the phases of every `every`-th step with HIP events (off: enable=False)."""
+        self._check(load_library().lbm_profile(self.h, int(every) if enable else 0))
 
     def profile_read(self):
         """{kind: (total_ms, launches)} for the fused, particle, moments and
