@@ -153,3 +153,30 @@ def test_autotuned_block_shapes_give_the_same_results():
             assert max(err.values()) <= 1e-6, (tx, i, err)
         c.close()
         d.close()
+
+
+def test_uneven_box_members_in_one_context_against_oracle():
+    """Four members of the uneven-box ensemble distribution (cubic boxes of the
+    benchmark's sizes, one sphere each) batched in one context with graph
+    replay, 20 steps, each against the oracle."""
+    import torch
+    from paper_2505_10171_amd.lbm import Context
+    ms, seen = [], set()
+    for i in range(64):  # one member per box size
+        m = W.ensemble_member_c4(4, i)
+        if m["cfg"]["nx"] not in seen:
+            seen.add(m["cfg"]["nx"])
+            ms.append(m)
+        if len(ms) == 4:
+            break
+    ens = Context(ms, stream=torch.cuda.Stream())
+    ens.use_graph(True)
+    ens.step(20)
+    for i, m in enumerate(ms):
+        o = OracleSim(m["cfg"], m["phi0"], m["particles"])
+        o.step(20)
+        e = field_errors(ens, o, sim_g=i)
+        print("member L =", m["cfg"]["nx"], {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        for v in e.values():
+            assert v <= 1e-5, (i, e)
+        o.close()

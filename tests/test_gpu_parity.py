@@ -256,3 +256,26 @@ def test_fp16_storage_free_drop():
     e = dict(rho=rel_l2(rg, ro), u=rel_l2(ug, uo), phi=rel_l2(pg, po))
     print("FP16 free drop", {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
     assert e["u"] <= 1e-3, e
+
+
+def test_full_size_slab_c3_parity():
+    """The 512x256x192 slab with its 500 spheres (the throughput-at-scale
+    workload) at full size for two steps against the oracle: masks bit-exact,
+    FP32 fields within 1e-5, particle forces within 1e-5 of their scale."""
+    w = W.slab_c3()
+    g = _gpu(w["cfg"], w["phi0"], w["particles"])
+    o = OracleSim(w["cfg"], w["phi0"], w["particles"])
+    g.step(2)
+    o.step(2)
+    _compare_fields(g, o, label="C3 full size, 2 steps")
+    pg, po = g.particles(), o.particles()
+    R = max(p["R"] for p in w["particles"])
+    for k in ("F_hyd", "T_hyd", "F_cap", "F_con", "x", "v"):
+        a = np.array([p[k] for p in pg])
+        b = np.array([p[k] for p in po])
+        scale = np.abs(b).max()
+        if k.startswith("T_"):
+            scale = max(scale, R * np.abs(np.array([p["F_" + k[2:]] for p in po])).max())
+        assert np.abs(a - b).max() <= 1e-5 * scale, (k, np.abs(a - b).max(), scale)
+    g.close()
+    o.close()
