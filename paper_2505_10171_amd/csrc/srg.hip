@@ -128,6 +128,80 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
     }
 }
 
+// Forward product on larger tiles: C[M x N] = A[M x K] * B^T with A and B both
+// K-contiguous (B stored N x K), M and N multiples of 128, K of 32.  A
+// workgroup computes a 128x128 tile, each wave a 64x64 sub-tile (16 MFMAs per
+// K step); the next K step's tiles are fetched into registers while the
+// current one is multiplied.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const bf16* __restrict__ A,
+                                                  int lda, const bf16* __restrict__ B, int ldb,
+                                                  const float* __restrict__ bias,
+                                                  bf16* __restrict__ Cb, float* __restrict__ Cf,
+                                                  int ldc) {
+  constexpr int LD = 40;
+  __shared__ __attribute__((aligned(16))) bf16 As[128 * LD];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[128 * LD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * 128, n0 = blockIdx.x * 128;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // staging: thread t moves rows r0 and r0 + 64 of both tiles, chunk kc
+  const int r0 = t >> 2, kc = (t & 3) * 8;
+  const bf16* a0 = A + (long long)(m0 + r0) * lda + kc;
+  const bf16* a1 = A + (long long)(m0 + r0 + 64) * lda + kc;
+  const bf16* b0 = B + (long long)(n0 + r0) * ldb + kc;
+  const bf16* b1 = B + (long long)(n0 + r0 + 64) * ldb + kc;
+  bf16x8 pa0 = *(const bf16x8*)a0, pa1 = *(const bf16x8*)a1;
+  bf16x8 pb0 = *(const bf16x8*)b0, pb1 = *(const bf16x8*)b1;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    __syncthreads();
+    *(bf16x8*)(As + r0 * LD + kc) = pa0;
+    *(bf16x8*)(As + (r0 + 64) * LD + kc) = pa1;
+    *(bf16x8*)(Bs + r0 * LD + kc) = pb0;
+    *(bf16x8*)(Bs + (r0 + 64) * LD + kc) = pb1;
+    __syncthreads();
+    if (k0 + 32 < K) {  // next tiles in flight during this step's products
+      pa0 = *(const bf16x8*)(a0 + k0 + 32);
+      pa1 = *(const bf16x8*)(a1 + k0 + 32);
+      pb0 = *(const bf16x8*)(b0 + k0 + 32);
+      pb1 = *(const bf16x8*)(b1 + k0 + 32);
+    }
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)(As + (wm + i * 16 + fr) * LD + fk);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8*)(Bs + (wn + j * 16 + fr) * LD + fk);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn + j * 16 + (lane & 15);
+      const float bn = bias[n];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const long long o = (long long)m * ldc + n;
+        const float c = acc[i][j][r] + bn;
+        if (EPI == EPI_RELU_BF16)
+          Cb[o] = (bf16)fmaxf(c, 0.f);
+        else
+          Cf[o] = c;
+      }
+    }
+}
+
 // rows of the training set picked by the permutation, as padded BF16 inputs
 __global__ void k_gather(const bf16* __restrict__ Xall, const int* __restrict__ perm, int off,
                          int B, bf16* __restrict__ Xb) {
@@ -355,10 +429,17 @@ static int forward(srg_ctx* c, const bf16* Xb, int B) {
   const bf16* in = Xb;
   int ld_in = 32;
   for (int l = 0; l < NL - 1; ++l) {
-    SCHK(c, (gemm<false, true, EPI_RELU_BF16>(st, B, NOUT[l], KIN[l], in, ld_in,
-                                              c->pbt() + c->L.t_off[l], KIN[l],
-                                              p + c->L.b_off[l], nullptr, 0, c->act(l + 1),
-                                              nullptr, 256)));
+    if (B % 128 == 0 && NOUT[l] % 128 == 0) {
+      hipLaunchKernelGGL((k_gemm_big<EPI_RELU_BF16>), dim3(NOUT[l] / 128, B / 128), dim3(256), 0,
+                         st, B, NOUT[l], KIN[l], in, ld_in, c->pbt() + c->L.t_off[l], KIN[l],
+                         p + c->L.b_off[l], c->act(l + 1), nullptr, 256);
+      SCHK(c, hipGetLastError());
+    } else {
+      SCHK(c, (gemm<false, true, EPI_RELU_BF16>(st, B, NOUT[l], KIN[l], in, ld_in,
+                                                c->pbt() + c->L.t_off[l], KIN[l],
+                                                p + c->L.b_off[l], nullptr, 0, c->act(l + 1),
+                                                nullptr, 256)));
+    }
     in = c->act(l + 1);
     ld_in = 256;
   }
