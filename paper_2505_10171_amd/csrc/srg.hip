@@ -27,6 +27,7 @@ namespace srg {
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int NL = 5;                                  // layers
 constexpr int KIN[NL] = {32, 256, 256, 256, 256};      // padded fan-in
@@ -130,9 +131,10 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
 
 // Forward product on larger tiles: C[M x N] = A[M x K] * B^T with A and B both
 // K-contiguous (B stored N x K), M and N multiples of 128, K of 32.  A
-// workgroup computes a 128x128 tile, each wave a 64x64 sub-tile (16 MFMAs per
-// K step); the next K step's tiles are fetched into registers while the
-// current one is multiplied.
+// workgroup computes a 128x128 tile, each wave a 64x64 sub-tile with
+// v_mfma_f32_32x32x16_bf16 (twice the FLOPs per LDS fragment of the 16x16x32
+// form); the next K step's tiles are fetched into registers while the current
+// one is multiplied.
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const bf16* __restrict__ A,
                                                   int lda, const bf16* __restrict__ B, int ldb,
@@ -145,11 +147,13 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const bf1
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * 128, n0 = blockIdx.x * 128;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
-  f32x4 acc[4][4];
+  f32x16 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
   // staging: thread t moves rows r0 and r0 + 64 of both tiles, chunk kc
   const int r0 = t >> 2, kc = (t & 3) * 8;
   const bf16* a0 = A + (long long)(m0 + r0) * lda + kc;
@@ -158,7 +162,8 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const bf1
   const bf16* b1 = B + (long long)(n0 + r0 + 64) * ldb + kc;
   bf16x8 pa0 = *(const bf16x8*)a0, pa1 = *(const bf16x8*)a1;
   bf16x8 pb0 = *(const bf16x8*)b0, pb1 = *(const bf16x8*)b1;
-  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  // 32x32x16 fragments: lane l holds row (col) l % 32, K elements (l / 32) * 8 .. + 7
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
   for (int k0 = 0; k0 < K; k0 += 32) {
     __syncthreads();
     *(bf16x8*)(As + r0 * LD + kc) = pa0;
@@ -172,26 +177,30 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const bf1
       pb0 = *(const bf16x8*)(b0 + k0 + 32);
       pb1 = *(const bf16x8*)(b1 + k0 + 32);
     }
-    bf16x8 a[4], b[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)(As + (wm + i * 16 + fr) * LD + fk);
+    for (int ks = 0; ks < 32; ks += 16) {
+      bf16x8 a[2], b[2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8*)(Bs + (wn + j * 16 + fr) * LD + fk);
+      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)(As + (wm + i * 32 + fr) * LD + ks + fk);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)(Bs + (wn + j * 32 + fr) * LD + ks + fk);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
   }
+  // lane l holds rows (r / 4) * 8 + (l / 32) * 4 + r % 4 (r = 0..15) of column l % 32
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + wn + j * 16 + (lane & 15);
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + j * 32 + (lane & 31);
       const float bn = bias[n];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         const long long o = (long long)m * ldc + n;
         const float c = acc[i][j][r] + bn;
         if (EPI == EPI_RELU_BF16)
