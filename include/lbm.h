@@ -56,10 +56,13 @@ enum lbm_status {
 };
 
 enum lbm_storage {
-  LBM_STORE_FP32 = 0, /* populations stored as FP32 deviations f - w rho0, g  */
-  LBM_STORE_FP16 = 1  /* FP16: h = (f - w R)/(w rho0), k = (g - P f)/(w rho0)
-                         with (R, P) the node's density and order parameter
-                         of the previous step; FP32 arithmetic               */
+  LBM_STORE_FP32 = 0, /* total populations stored as FP32 deviations f - w rho0 */
+  LBM_STORE_FP16 = 1  /* FP16: h = (f - w R)/(w rho0) with R the node's density
+                         of the previous state; FP32 arithmetic.  Either way
+                         the colour is held as the per-node order parameter:
+                         the colour populations after the recolouring are a
+                         function of f, rho, phi and the interface normal of
+                         the node they left, and are rebuilt from them      */
 };
 
 enum lbm_field_bits {
@@ -67,9 +70,8 @@ enum lbm_field_bits {
   LBM_F_U = 2u,    /* velocity with half the force (velocity eq.)   (float) */
   LBM_F_PHI = 4u,  /* order parameter (order-parameter eq.)         (float) */
   LBM_F_MASK = 8u, /* solid mask                                 (uint16_t) */
-  LBM_F_POPS = 16u, /* raw stored populations: 38 planes of N values in the
-                       storage type.  FP32: 19 planes of f - w rho0, then 19
-                       of g = f^a - f^b.  FP16: the encoded pairs (h, g/f)
+  LBM_F_POPS = 16u, /* raw stored populations: 19 planes of N values in the
+                       storage type.  FP32: f - w rho0.  FP16: the encoded h
                        of LBM_STORE_FP16 (the reference densities are
                        internal)                                           */
   LBM_F_FORCE = 32u  /* force per volume: CSF surface tension (CSF eq.) plus
@@ -79,7 +81,7 @@ enum lbm_field_bits {
 /* One simulation, in lattice units.  Defaults in brackets follow the paper's
  * parameter table. */
 typedef struct {
-  int32_t nx, ny, nz;   /* lattice size; nz >= 3                             */
+  int32_t nx, ny, nz;   /* lattice size; nz >= 3, 19 nx ny nz < 2^32        */
   int32_t has_wall;     /* 1: node plane z = 0 is a solid wall [1]           */
   double rho0;          /* reference density [0.05]                          */
   double tau_a, tau_b;  /* relaxation times of fluids a and b (> 1/2) [1, 1] */
@@ -129,7 +131,7 @@ size_t lbm_workspace_bytes(const lbm_config* cfg, int32_t n_sims,
  * values, or NULL for phi = +1 everywhere) and the particles (per simulation
  * cfg[s].n_particles host records, state at rest is allowed), sets the fluid at
  * rest with f_a = w rho0 (1+phi0)/2, f_b = w rho0 (1-phi0)/2, builds the solid
- * mask and computes the first moments.  The workspace must be 256-byte aligned
+ * mask and the first moments (rho0, phi0).  The workspace must be 256-byte aligned
  * and at least lbm_workspace_bytes long (LBM_EINVAL / LBM_ENOMEM otherwise).
  * hip_stream is a hipStream_t (NULL: the null stream).  On success *out owns the
  * context. */
@@ -156,7 +158,7 @@ int lbm_particles_sync(lbm_ctx* ctx, int32_t sim, int32_t dir, lbm_particle* par
                        double* history, int32_t max_steps, int32_t* n_hist);
 
 /* Copy fields of simulation sim (bits of lbm_field_bits).  rho, phi: N floats;
- * u: 3N floats; mask: N uint16; pops: 38N values of the storage type.  Solid
+ * u: 3N floats; mask: N uint16; pops: 19N values of the storage type.  Solid
  * nodes report rho = phi = 0 and u = the solid's surface velocity.  Buffers are
  * host memory unless dst_is_device.  Synchronous. */
 int lbm_fields(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, float* phi,

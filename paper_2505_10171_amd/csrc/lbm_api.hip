@@ -28,13 +28,16 @@ hipError_t launch_interface(const Batch& b, unsigned nblk, hipStream_t st);
 hipError_t launch_fused(const Batch& b, int storage, unsigned nblk, int mode, float* orho,
                         float* ou, float* ophi, float* oF, hipStream_t st);
 hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipStream_t st);
-hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, hipStream_t st);
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, hipStream_t st);
 hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
 hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
-hipError_t launch_mass(const SimDev& s, const void* pops, int rd, hipStream_t st);
+hipError_t launch_mass(const SimDev& s, const float* rp, hipStream_t st);
 hipError_t launch_mask_update(const Batch& b, int np_rows, int Bmax, bool with_release,
                               hipStream_t st);
-hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, hipStream_t st);
+hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int mode,
+                         hipStream_t st);
+// kernel modes (lbm_fluid.hip, lbm_particles.hip): in a step, or between steps
+constexpr int MOM_STEP = 0, MOM_BOUNDARY = 1, REFILL_STEP = 0, REFILL_BOUNDARY = 1;
 hipError_t launch_capillary(const Batch& b, int np_rows, int cap_B, int npts, hipStream_t st);
 hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st);
 }  // namespace lbm
@@ -52,7 +55,7 @@ struct SimLayout {
   long long N;
   int np, Bmask, Bcap, hist_cap;
   size_t pop_bytes, fresh_cap;
-  size_t off_pops0, off_pops1, off_ref0, off_ref1, off_phi, off_nrm, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
+  size_t off_pops0, off_pops1, off_rp0, off_rp1, off_nrm, off_csrc, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
       off_counters, off_P, off_ct, off_nb, off_hist, off_capbox, off_caporg, off_mass, off_step;
   size_t total;
 };
@@ -69,7 +72,8 @@ bool valid_config(const lbm_config& c, char* msg, size_t len) {
     return false;
   };
   if (c.nx < 1 || c.ny < 1 || c.nz < 3) return fail("lattice must be nx, ny >= 1 and nz >= 3");
-  if ((long long)c.nx * c.ny * c.nz > (1ll << 31) - 1) return fail("lattice too large");
+  // population offsets are 32-bit: 19 planes of N values
+  if ((long long)c.nx * c.ny * c.nz * 19 > 0xFFFFFFFFll) return fail("lattice too large");
   if (!(c.rho0 > 0.0)) return fail("rho0 must be positive");
   if (!(c.tau_a > 0.5) || !(c.tau_b > 0.5)) return fail("relaxation times must exceed 1/2");
   if (!(c.sigma >= 0.0) || !(c.beta >= 0.0)) return fail("sigma and beta must be >= 0");
@@ -113,7 +117,7 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   L.Bmask = (int)ceil(2.0 * Rmax) + 4;
   L.Bcap = (int)ceil(2.0 * Rmax) + 3;
   L.hist_cap = L.np > 0 ? hist_cap : 0;
-  L.pop_bytes = (size_t)38 * L.N * (c.storage == LBM_STORE_FP16 ? 2 : 4);
+  L.pop_bytes = (size_t)19 * L.N * (c.storage == LBM_STORE_FP16 ? 2 : 4);
   L.fresh_cap = L.np > 0 ? (size_t)L.np * L.Bmask * L.Bmask * L.Bmask : 0;
   size_t o = align_up(base);
   auto take = [&](size_t bytes) {
@@ -123,12 +127,11 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   };
   L.off_pops0 = take(L.pop_bytes);
   L.off_pops1 = take(L.pop_bytes);
-  // FP16 storage: two per-node references (rho, phi) (ping-pong)
-  const size_t ref_bytes = c.storage == LBM_STORE_FP16 ? 4 * (size_t)L.N : 0;
-  L.off_ref0 = take(ref_bytes);
-  L.off_ref1 = take(ref_bytes);
-  L.off_phi = take(4 * L.N);
+  // per-node moments (rho, phi) of the current and the previous state
+  L.off_rp0 = take(8 * L.N);
+  L.off_rp1 = take(8 * L.N);
   L.off_nrm = take(16 * L.N);
+  L.off_csrc = take(16 * L.N);
   L.off_cur = take(8 * L.N);
   L.off_mask = take(2 * L.N);
   L.off_claim = take(4 * L.N);
@@ -352,9 +355,9 @@ static int post_dem_pipeline(lbm_ctx* ctx, int si, bool with_release) {
   const Batch b = batch_one(ctx, si);
   if (s.np > 0) {
     HIPCHK(ctx, launch_mask_update(b, s.np, sh.L.Bmask, with_release, ctx->stream));
-    HIPCHK(ctx, launch_refill(b, ctx->storage, s.fresh_cap, ctx->stream));
+    HIPCHK(ctx, launch_refill(b, ctx->storage, s.fresh_cap, REFILL_BOUNDARY, ctx->stream));
   }
-  HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), ctx->stream));
+  HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), MOM_BOUNDARY, ctx->stream));
   return LBM_OK;
 }
 
@@ -446,14 +449,10 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     char* b = ctx->ws;
     d.pops[0] = b + sh.L.off_pops0;
     d.pops[1] = b + sh.L.off_pops1;
-    if (c.storage == LBM_STORE_FP16) {
-      d.ref[0] = (__half2*)(b + sh.L.off_ref0);
-      d.ref[1] = (__half2*)(b + sh.L.off_ref1);
-    } else {
-      d.ref[0] = d.ref[1] = nullptr;
-    }
-    d.phi = (float*)(b + sh.L.off_phi);
-    d.nrm = (float*)(b + sh.L.off_nrm);
+    d.rp[0] = (float*)(b + sh.L.off_rp0);
+    d.rp[1] = (float*)(b + sh.L.off_rp1);
+    d.nrm = (v4f*)(b + sh.L.off_nrm);
+    d.csrc = (v4f*)(b + sh.L.off_csrc);
     d.curv = (float2*)(b + sh.L.off_cur);
     d.mask = (uint16_t*)(b + sh.L.off_mask);
     d.claim = (uint32_t*)(b + sh.L.off_claim);
@@ -509,14 +508,14 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     if (hipMemsetAsync(d.counters, 0, 64, st) != hipSuccess ||
         hipMemsetAsync(d.step_counter, 0, sizeof(unsigned long long), st) != hipSuccess)
       return fail(LBM_EHIP, "counter initialisation failed");
-    // phi0 staged in the phi field
+    // phi0 staged in the phi plane of rp[0]
     if (phi0 && phi0[si]) {
-      if (hipMemcpyAsync(d.phi, phi0[si], sizeof(float) * d.N, hipMemcpyHostToDevice, st) !=
+      if (hipMemcpyAsync(d.rp[0] + d.N, phi0[si], sizeof(float) * d.N, hipMemcpyHostToDevice, st) !=
           hipSuccess)
         return fail(LBM_EHIP, "phi0 upload failed");
     } else {
       std::vector<float> ones(d.N, 1.0f);
-      if (hipMemcpyAsync(d.phi, ones.data(), sizeof(float) * d.N, hipMemcpyHostToDevice, st) !=
+      if (hipMemcpyAsync(d.rp[0] + d.N, ones.data(), sizeof(float) * d.N, hipMemcpyHostToDevice, st) !=
               hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         return fail(LBM_EHIP, "phi0 upload failed");
@@ -542,8 +541,6 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
       return fail(LBM_EHIP, "mask build failed");
     if (launch_init_pops(d, d.pops[0], st) != hipSuccess)
       return fail(LBM_EHIP, "population init failed");
-    if (launch_moments(b1, ctx->storage, sim_blocks(d), st) != hipSuccess)
-      return fail(LBM_EHIP, "moments failed");
   }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(LBM_EHIP, "synchronise failed");
   *out = ctx;
@@ -584,10 +581,10 @@ static int step_once(lbm_ctx* ctx, int slot) {
     HIPCHK(ctx, launch_capillary(a, ctx->np_rows, ctx->cap_B, ctx->npts, st));
     HIPCHK(ctx, launch_dem(a, ctx->np_max, st));
     HIPCHK(ctx, launch_mask_update(a, ctx->np_rows, ctx->Bmax, true, st));
-    HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, st));
+    HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, REFILL_STEP, st));
   }
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], st));
-  HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, st));
+  HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, MOM_STEP, st));
   if (slot >= 0) {
     HIPCHK(ctx, hipEventRecord(P.ev[slot][4], st));
     P.pending[slot] = true;
@@ -692,6 +689,16 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
   const int n_sims = (int)ctx->sims.size();
+  struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void release() {
+      if (p) (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    ~DevBuf() { release(); }
+  } save;
   int rc = LBM_OK;
   for (int si = 0; si < n_sims && rc == LBM_OK; ++si) {
     SimDev& d = ctx->sims[si].d;
@@ -701,6 +708,16 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
     for (auto& kv : cache)
       if (kv.first == key) best = kv.second;
     if (best < 0) {
+      // the timed moments pass rewrites the current moments: kept aside and
+      // put back afterwards
+      const size_t rp_bytes = 8 * (size_t)d.N;
+      if (save.bytes < rp_bytes) {
+        save.release();
+        HIPCHK(ctx, hipMalloc(&save.p, rp_bytes));
+        save.bytes = rp_bytes;
+      }
+      float* rp_cur = d.rp[ctx->rd ^ 1];
+      HIPCHK(ctx, hipMemcpyAsync(save.p, rp_cur, rp_bytes, hipMemcpyDeviceToDevice, st));
       float best_ms = 1e30f;
       for (int c : cand) {
         if (c > 0 && c > 2 * d.nx) continue;  // over half the tile idle
@@ -713,7 +730,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
           if (r == 1) HIPCHK(ctx, hipEventRecord(e0, st));
           HIPCHK(ctx, launch_interface(b1, nb, st));
           HIPCHK(ctx, launch_fused(b1, ctx->storage, nb, 0, nullptr, nullptr, nullptr, nullptr, st));
-          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, st));
+          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, MOM_STEP, st));
         }
         HIPCHK(ctx, hipEventRecord(e1, st));
         HIPCHK(ctx, hipEventSynchronize(e1));
@@ -723,6 +740,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
           best = c;
         }
       }
+      HIPCHK(ctx, hipMemcpyAsync(rp_cur, save.p, rp_bytes, hipMemcpyDeviceToDevice, st));
       cache.emplace_back(key, best);
     }
     set_tile(d, best);
@@ -731,6 +749,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
+  HIPCHK(ctx, hipStreamSynchronize(st));  // before the saved copy is freed
   return upload_tables(ctx, 0);
 }
 
@@ -989,7 +1008,7 @@ int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]) {
   if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
   SimDev& d = sh->d;
   HIPCHK(ctx, hipMemsetAsync(d.mass_acc, 0, 2 * sizeof(double), ctx->stream));
-  HIPCHK(ctx, launch_mass(d, d.pops[ctx->cur], ctx->rd, ctx->stream));
+  HIPCHK(ctx, launch_mass(d, d.rp[ctx->rd ^ 1], ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(out, d.mass_acc, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   return lbm_sync(ctx);
 }

@@ -78,23 +78,25 @@ struct Contact {
 
 // ------------------------------------------------------------- simulation
 // ------------------------------------------------------ population codecs
-// Every population i of a node is held as a pair (d, g): d = f_i - w_i rho0 the
-// deviation of the total population from rest, g = f^a_i - f^b_i the colour
-// population.  Arguments: wr0 = w_i rho0; for FP16 the node's reference
-// (R, P) enters as wR = w_i R and P.
+// Only the total populations f_i are stored.  The colour populations are not:
+// after the recolouring every streamed colour population is the source node's
+// order parameter times f_i plus its segregation term, so the moments pass
+// rebuilds them from f_i and the per-node (rho, phi, n) of the state that
+// collided.  Kernels work with d = f_i - w_i rho0.  Arguments: wr0 = w_i rho0,
+// iwr0 = 1 / wr0, wR = w_i R with R the reference density of the node that
+// stores the population (FP16 only).
 //
-// FP32: d and g stored as they are.
-// FP16: h = (f - w_i R) / wr0 and k = (g - P f) / wr0, with (R, P) the node's
-// density and order parameter of the previous step.  h and k then hold only
-// the parts of f and g that the previous state does not predict (velocity,
-// non-equilibrium, interface motion), not the Laplace pressure offset or the
-// bulk colour, and keep FP16's relative precision for them.  In the bulk of
-// either fluid (P = +-1, g = +-f) k is exactly 0, so g = +-f and phi = +-1 hold
-// exactly after decoding.
+// FP32: d stored as it is.
+// FP16: h = (f - w_i R) / wr0, R the node's density of the previous state: h
+// holds only the part of f that the previous density does not predict
+// (velocity, non-equilibrium), not the Laplace pressure offset, and keeps
+// FP16's relative precision for it.
 // Global-memory view of a pointer.  Pointers read from the simulation table
 // are generic to the compiler; the hot kernels convert them once so that every
 // access compiles to a global (not flat) memory instruction.
 #define GLB __attribute__((address_space(1)))
+// four floats as one 16-byte load or store (a clang vector, usable through GLB)
+typedef float v4f __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ GLB T* gp(T* p) {
   return (GLB T*)p;
@@ -103,28 +105,20 @@ __device__ __forceinline__ GLB T* gp(T* p) {
 template <int STORE>
 struct Codec;
 
-// iwr0 = 1 / (w_i rho0) (encoding multiplies by it)
 template <>
 struct Codec<0> {
   using T = float;
-  template <class PD, class PG>
-  static __device__ __forceinline__ void ld(PD pd, PG pg, float, float, float, float& d, float& g) {
-    d = *pd;
-    g = *pg;
-  }
   template <class PD>
-  static __device__ __forceinline__ float ld_d(PD pd, float, float) {
+  static __device__ __forceinline__ float ld(PD pd, float, float) {
     return *pd;
   }
-  template <class PD, class PG>
-  static __device__ __forceinline__ void st(PD pd, PG pg, float, float, float, float, float d,
-                                            float g) {
+  template <class PD>
+  static __device__ __forceinline__ void st(PD pd, float, float, float, float d) {
     *pd = d;
-    *pg = g;
   }
 };
 
-// wr0 = w_i rho0, iwr0 = 1 / wr0, wR = w_i R; values stored as raw FP16 bits
+// values stored as raw FP16 bits
 template <>
 struct Codec<1> {
   using T = uint16_t;
@@ -133,48 +127,15 @@ struct Codec<1> {
     return __half_as_ushort(__float2half_rn(v));
   }
   template <class PD>
-  static __device__ __forceinline__ float f_of(PD pd, float wr0, float wR) {
-    return __fadd_rn(wR, __fmul_rn(wr0, h2f(*pd)));
-  }
-  template <class PD, class PG>
-  static __device__ __forceinline__ void ld(PD pd, PG pg, float wr0, float wR, float P, float& d,
-                                            float& g) {
-    const float f = f_of(pd, wr0, wR);
-    d = __fsub_rn(f, wr0);
-    g = __fadd_rn(__fmul_rn(P, f), __fmul_rn(wr0, h2f(*pg)));
+  static __device__ __forceinline__ float ld(PD pd, float wr0, float wR) {
+    return __fsub_rn(__fadd_rn(wR, __fmul_rn(wr0, h2f(*pd))), wr0);
   }
   template <class PD>
-  static __device__ __forceinline__ float ld_d(PD pd, float wr0, float wR) {
-    return __fsub_rn(f_of(pd, wr0, wR), wr0);
-  }
-  template <class PD, class PG>
-  static __device__ __forceinline__ void st(PD pd, PG pg, float wr0, float iwr0, float wR, float P,
-                                            float d, float g) {
+  static __device__ __forceinline__ void st(PD pd, float wr0, float iwr0, float wR, float d) {
     const float f = __fadd_rn(d, wr0);
     *pd = f2h((f - wR) * iwr0);
-    *pg = f2h(__fsub_rn(g, __fmul_rn(P, f)) * iwr0);
   }
 };
-
-// FP16 reference (R, P) of a node as floats; both the encoder and the decoder
-// read it from the same stored pair
-__device__ __forceinline__ float2 ref_of(const __half2* r, long long n) {
-  return __half22float2(r[n]);
-}
-// the same from a global view of the pairs as 32-bit words
-__device__ __forceinline__ float2 ref_of(const GLB uint32_t* r, long long n) {
-  const uint32_t v = r[n];
-  return make_float2(__half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))),
-                     __half2float(__ushort_as_half((unsigned short)(v >> 16))));
-}
-__device__ __forceinline__ uint32_t ref_pack(float rho, float phi) {
-  return (uint32_t)__half_as_ushort(__float2half_rn(rho)) |
-         ((uint32_t)__half_as_ushort(__float2half_rn(phi)) << 16);
-}
-template <class T>
-__device__ __forceinline__ const GLB uint32_t* gref(T* p) {
-  return (const GLB uint32_t*)p;
-}
 
 struct SimDev {
   int nx, ny, nz, has_wall;
@@ -184,10 +145,15 @@ struct SimDev {
   float body[3];
   float wall_neg_cos, wall_sin;
   // fields
-  void* pops[2];       // ping-pong population buffers: 38 planes of N
-  __half2* ref[2];     // FP16 storage: per-node reference (rho, phi), ping-pong
-  float* phi;          // order parameter of the current state (PHI_SOLID at solids)
-  float* nrm;          // 4 planes of N: n_x, n_y, n_z (NaN at solids), |G| (-1 at solids)
+  void* pops[2];       // ping-pong population buffers: 19 planes of N (f only)
+  // per-node moments of a state, 2 planes of N: rho, then phi (rho0 and
+  // PHI_SOLID at solids); rp[rd ^ 1] belongs to the state in pops[cur], rp[rd]
+  // to the state before it (the FP16 reference of pops[cur])
+  float* rp[2];
+  v4f* nrm;            // per node (n_x, n_y, n_z, |G|); (NaN, NaN, NaN, -1) at solids
+  // per node colour source of the state about to collide: (phi, r n_x, r n_y,
+  // r n_z) with r = beta rho (1 - phi^2) / 2; NaN in r n at solids
+  v4f* csrc;
   float2* curv;        // per node (CSF coefficient, solid-neighbour bits as float)
   uint16_t* mask;      // 0 fluid, 1 wall, 2+p particle p; FRESH_BIT while refilling
   uint32_t* claim;     // per node: lowest particle claiming it in the new mask, ~0u none
@@ -250,8 +216,8 @@ enum StatusBits : uint32_t { ST_UNSTABLE = 1u, ST_CONTACT_FULL = 2u, ST_FRESH_FU
 // simulation s (blk[nsim] the total).  Particle kernels run one grid row per
 // particle; pmap[row] = (simulation, particle).  With nsim == 1 the tables are
 // not read: the block index is the simulation's own and row = particle.
-// cur: population buffer holding the current state; rd: FP16 reference buffer
-// it is encoded with (both uniform over the batch).
+// cur: population buffer holding the current state; rd: moments buffer of the
+// state before it (both uniform over the batch).
 struct Batch {
   const SimDev* tab;
   const uint32_t* blk;
@@ -277,6 +243,73 @@ __device__ __forceinline__ int2 batch_block(const Batch& b, int g) {
 // (simulation, particle) of grid row r
 __device__ __forceinline__ int2 batch_particle(const Batch& b, int r) {
   return b.nsim == 1 ? make_int2(0, r) : b.pmap[r];
+}
+
+// wrapped neighbour offsets of node (x, y, z): index of x + c is
+// X[1+cx] + Y[1+cy] + Z[1+cz]
+struct Nbr {
+  int X[3], Y[3], Z[3];
+  __device__ __forceinline__ Nbr(int gx, int gy, int gz, int nx, int ny, int nz) {
+    const int nxny = nx * ny;
+    X[0] = gx == 0 ? nx - 1 : gx - 1;
+    X[1] = gx;
+    X[2] = gx == nx - 1 ? 0 : gx + 1;
+    Y[0] = (gy == 0 ? ny - 1 : gy - 1) * nx;
+    Y[1] = gy * nx;
+    Y[2] = (gy == ny - 1 ? 0 : gy + 1) * nx;
+    Z[0] = (gz == 0 ? nz - 1 : gz - 1) * nxny;
+    Z[1] = gz * nxny;
+    Z[2] = (gz == nz - 1 ? 0 : gz + 1) * nxny;
+  }
+  __device__ __forceinline__ int operator()(int i) const {
+    return X[1 + cx(i)] + Y[1 + cy(i)] + Z[1 + cz(i)];
+  }
+};
+
+// offset of population i of node n in the plane layout (19 N < 2^32)
+__device__ __forceinline__ unsigned pidx(int i, int N, int n) {
+  return (unsigned)i * (unsigned)N + (unsigned)n;
+}
+
+// Moments of the post-stream state at fluid node n (order-parameter eq.), with
+// the colour populations rebuilt from the state that collided.  The
+// recolouring (recolouring eqs.) gave the population leaving x' in direction i
+// the colour difference f^a_i - f^b_i = phi' f*_i + r' w_i (c_i . n'), with
+// r' = beta rho' (1 - phi'^2) / 2 = 2 beta rho_a' rho_b' / rho'.  So f_i at x
+// carries that of its source: x' = x - c_i if that node was fluid when the
+// state streamed (its colour source is not NaN), else x itself, whose
+// f*_opp(i) was bounced back (the moving-wall term of the bounce-back eqs. is
+// coloured by phi(x) as well), giving phi(x) f_i - r(x) w_i (c_i . n(x)).
+// CS: colour sources (phi, r n) of the state that collided; Rd: the FP16
+// reference density of the stored populations at n.  Returns rabs = sum f_i,
+// with f_i = d_i + w_i rho0 rounded as the collision formed it, and sg = sum of
+// the colour differences: in the bulk of either fluid (phi' = +-1, r' = 0)
+// sg = +-rabs exactly.
+template <int STORE, class PT>
+__device__ __forceinline__ void rebuild_moments(PT pops, const GLB v4f* CS, int N, int n,
+                                                const Nbr& nb, float rho0, float Rd, float& rabs,
+                                                float& sg) {
+  using IO = Codec<STORE>;
+  const v4f own = CS[n];
+  {
+    const float wr0 = wq(0) * rho0;
+    const float f = IO::ld(pops + (unsigned)n, wr0, wq(0) * Rd) + wr0;
+    rabs = f;
+    sg = own.x * f;
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const v4f c = CS[nb(opp(i))];
+    const bool solid = c.y != c.y;
+    const float wr0 = wq(i) * rho0;
+    const float f = IO::ld(pops + pidx(i, N, n), wr0, wq(i) * Rd) + wr0;
+    const float ts = (float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w;
+    const float to = (float)cx(i) * own.y + (float)cy(i) * own.z + (float)cz(i) * own.w;
+    const float ph = solid ? own.x : c.x;
+    const float t = solid ? -to : ts;
+    rabs += f;
+    sg += ph * f + wq(i) * t;
+  }
 }
 
 __host__ __device__ inline int wrapi(int a, int n) {

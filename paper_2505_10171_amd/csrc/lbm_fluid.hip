@@ -1,17 +1,18 @@
 // lbm_fluid.hip -- lattice kernels of liblbm for gfx950.
 //
-// Storage: structure-of-arrays populations, 38 planes of N values (19 planes of
-// the total f, then 19 of the colour difference g = f_a - f_b), x-fastest.  FP32
-// storage keeps the deviation d_i = f_i - w_i rho0 (so that the small velocity
-// survives FP32 rounding); FP16 storage keeps the scaled offsets
-// h_i = f_i / (w_i rho0) - 1 and k_i = g_i / (w_i rho0).  All arithmetic is FP32;
-// momentum exchange sums are FP64.
+// Storage: structure-of-arrays populations, 19 planes of N values of the total
+// f, x-fastest; the colour is carried by the per-node order parameter and the
+// colour populations are rebuilt by the moments pass (see rebuild_moments).
+// FP32 storage keeps the deviation d_i = f_i - w_i rho0 (so that the small
+// velocity survives FP32 rounding); FP16 storage keeps
+// h_i = (f_i - w_i R) / (w_i rho0) with R the node's density of the previous
+// state.  All arithmetic is FP32; momentum exchange sums are FP64.
 //
-// A step of the fluid runs three kernels: k_moments (order parameter of the
-// post-stream state), k_interface (interface normal and CSF coefficient, an LDS
-// z-march over phi and the mask) and k_fused (collision, force, recolouring,
-// streaming, bounce-back and momentum exchange, one thread per node, reading and
-// writing every population exactly once).
+// A step of the fluid runs k_normal and k_curv (interface normal, curvature
+// and CSF coefficient from phi), k_fused (collision, force, streaming and
+// bounce-back of f, one thread per node, reading and writing every population
+// exactly once), k_links (moving-wall terms and momentum exchange at particle
+// links) and k_moments (density and order parameter of the post-stream state).
 #include "lbm_device.h"
 
 namespace lbm {
@@ -65,52 +66,56 @@ __host__ __device__ constexpr int pair_dir(int k) {
   return t[k];
 }
 
+// XCD-aware block order: consecutive dispatches go round-robin over the 8 XCDs;
+// give each XCD a contiguous range of blocks so that data shared by neighbouring
+// blocks (halo reads, pushed populations) meets in the same L2.
+__device__ __forceinline__ int xcd_tile(int lin, int nblk) {
+  if ((nblk & 7) == 0) {
+    const int per = nblk >> 3;
+    return (lin & 7) * per + (lin >> 3);
+  }
+  return lin;
+}
+
 // ------------------------------------------------------------- moments kernel
-// Order parameter phi = sum g / rho of every fluid node (order-parameter eq.),
-// after the refill of fresh nodes; clears their FRESH mark.  Solid nodes get
-// the sentinel PHI_SOLID, so stencils can tell solids from phi alone.
-template <int STORE>
+// Density and order parameter phi = sum g / rho (order-parameter eq.) of every
+// fluid node of the post-stream state into rp[rd ^ 1], the colour populations
+// rebuilt from the state that collided (its colour sources).  Runs
+// after the refill, which has written the moments of the fresh nodes; clears
+// their FRESH mark.  Solid nodes get (rho0, PHI_SOLID), so that stencils can
+// tell solids from phi alone.  MOM_BOUNDARY (between steps, after the mask
+// changed with the populations in place): fluid nodes keep their moments.
+enum { MOM_STEP = 0, MOM_BOUNDARY = 1 };
+template <int STORE, int MODE>
 __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   using IO = Codec<STORE>;
   using T = typename IO::T;
-  const int2 sb = batch_block(bt, blockIdx.x);
+  const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  const void* __restrict__ pops = s.pops[bt.cur];
-  const __half2* __restrict__ rdec = s.ref[bt.rd];
-  __half2* __restrict__ rnext = s.ref[bt.rd ^ 1];
-  const long long N = s.N;
+  const int N = (int)s.N;
   int n, gx, gy, gz;
   if (sb.y == 0 && threadIdx.x == 0) s.counters[0] = 0u;  // fresh list consumed
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   GLB uint16_t* __restrict__ MASK = gp(s.mask);
-  uint16_t m = MASK[n];
-  if (m & FRESH_BIT) {
-    m = (uint16_t)(m & ~FRESH_BIT);
-    MASK[n] = m;
+  GLB float* __restrict__ RN = gp(s.rp[bt.rd ^ 1]);
+  const uint16_t m = MASK[n];
+  if (m & FRESH_BIT) {  // refilled node: moments written by the refill
+    MASK[n] = (uint16_t)(m & ~FRESH_BIT);
+    return;
   }
-  float out = PHI_SOLID, rho = s.rho0;
-  if (m == 0) {
-    const GLB T* b = gp((const T*)pops);
-    const float2 R = STORE ? ref_of(gref(rdec), n) : make_float2(0.f, 0.f);
-    // phi = sum g / sum f with f_i = d_i + w_i rho0 rounded exactly as the
-    // recolouring forms it, so that a pure fluid (g_i = +-f_i) has phi = +-1
-    // exactly and its colour stays segregated without rounding leakage
-    float rabs = 0.f, sg = 0.f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const float wr0 = wq(i) * s.rho0;
-      float d, g;
-      IO::ld(b + (long long)i * N + n, b + (long long)(Q + i) * N + n, wr0, wq(i) * R.x, R.y, d,
-             g);
-      rabs += d + wr0;
-      sg += g;
-    }
-    out = sg / rabs;
-    rho = rabs;
+  if (m != 0) {
+    RN[n] = s.rho0;
+    RN[N + n] = PHI_SOLID;
+    return;
   }
-  gp(s.phi)[n] = out;
-  // reference of the next encoding: this state's density and order parameter
-  if (STORE) gp((uint32_t*)rnext)[n] = ref_pack(rho, m == 0 ? out : 0.f);
+  if (MODE == MOM_BOUNDARY) return;
+  const Nbr nb(gx, gy, gz, s.nx, s.ny, s.nz);
+  float rabs, sg;
+  const float Rd = STORE ? gp((const float*)s.rp[bt.rd])[n] : 0.f;
+  rebuild_moments<STORE>(gp((const T*)s.pops[bt.cur]), gp((const v4f*)s.csrc), N, n, nb, s.rho0, Rd,
+                         rabs, sg);
+  RN[n] = rabs;
+  RN[N + n] = sg / rabs;
 }
 
 // ------------------------------------------------------------ init kernels
@@ -122,8 +127,8 @@ __global__ void k_init_mask(SimDev s) {
   s.claim[n] = 0xFFFFFFFFu;
 }
 
-// fluid at rest: f = w rho0, g = w rho0 phi0 (phi0 staged in s.phi); FP16
-// references (rho0, phi0)
+// fluid at rest: f = w rho0 (d = 0), moments (rho0, phi0) in both moment
+// buffers (phi0 staged in the phi plane of rp[0]; (rho0, PHI_SOLID) at solids)
 template <int STORE>
 __global__ void k_init_pops(SimDev s, void* pops) {
   using IO = Codec<STORE>;
@@ -131,45 +136,28 @@ __global__ void k_init_pops(SimDev s, void* pops) {
   long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= s.N) return;
   T* b = (T*)pops;
-  float p0 = (s.mask[n] == 0) ? s.phi[n] : 0.f;
-  // FP16: encode with the stored (rounded) reference the decoder will read
-  const __half2 Rh = __floats2half2_rn(s.rho0, p0);
-  const float2 R0 = STORE ? __half22float2(Rh) : make_float2(s.rho0, p0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float wr0 = wq(i) * s.rho0;
-    IO::st(b + (long long)i * s.N + n, b + (long long)(Q + i) * s.N + n, wr0, 1.0f / wr0,
-           wq(i) * R0.x, R0.y, 0.f, wr0 * p0);
+    IO::st(b + (long long)i * s.N + n, wr0, 1.0f / wr0, wr0, 0.f);
   }
-  if (STORE) {
-    s.ref[0][n] = Rh;
-    s.ref[1][n] = Rh;
+  const float p0 = (s.mask[n] == 0) ? s.rp[0][s.N + n] : PHI_SOLID;
+  for (int k = 0; k < 2; ++k) {
+    s.rp[k][n] = s.rho0;
+    s.rp[k][s.N + n] = p0;
   }
 }
 
 // --------------------------------------------------------- global mass (FP64)
-template <int STORE>
-__global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__ pops,
-                                             const __half2* __restrict__ rdec) {
-  using IO = Codec<STORE>;
-  using T = typename IO::T;
+// masses of fluids a and b, sum of rho (1 +- phi) / 2 over fluid nodes, from
+// the moments rp (rho plane, phi plane) of the current state
+__global__ __launch_bounds__(256) void k_mass(SimDev s, const float* __restrict__ rp) {
   __shared__ double sh[2][256];
   double a = 0.0, b = 0.0;
-  const T* p = (const T*)pops;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < s.N;
        n += (long long)gridDim.x * blockDim.x) {
     if (s.mask[n] != 0) continue;
-    double drho = 0.0, sg = 0.0;
-    const float2 R = STORE ? ref_of(rdec, n) : make_float2(0.f, 0.f);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      float d, g;
-      IO::ld(p + (long long)i * s.N + n, p + (long long)(Q + i) * s.N + n, wq(i) * s.rho0,
-             wq(i) * R.x, R.y, d, g);
-      drho += (double)d;
-      sg += (double)g;
-    }
-    double rho = (double)s.rho0 + drho;
+    const double rho = (double)rp[n], sg = rho * (double)rp[s.N + n];
     a += 0.5 * (rho + sg);
     b += 0.5 * (rho - sg);
   }
@@ -191,54 +179,25 @@ __global__ __launch_bounds__(256) void k_mass(SimDev s, const void* __restrict__
 
 enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 
-// XCD-aware block order: consecutive dispatches go round-robin over the 8 XCDs;
-// give each XCD a contiguous range of blocks so that data shared by neighbouring
-// blocks (halo reads, pushed populations) meets in the same L2.
-__device__ __forceinline__ int xcd_tile(int lin, int nblk) {
-  if ((nblk & 7) == 0) {
-    const int per = nblk >> 3;
-    return (lin & 7) * per + (lin >> 3);
-  }
-  return lin;
-}
-
 // ------------------------------------------------------ interface kernels
-// wrapped neighbour offsets of node (x, y, z): index of x + c is
-// X[1+cx] + Y[1+cy] + Z[1+cz]
-struct Nbr {
-  int X[3], Y[3], Z[3];
-  __device__ __forceinline__ Nbr(int gx, int gy, int gz, int nx, int ny, int nz) {
-    const int nxny = nx * ny;
-    X[0] = gx == 0 ? nx - 1 : gx - 1;
-    X[1] = gx;
-    X[2] = gx == nx - 1 ? 0 : gx + 1;
-    Y[0] = (gy == 0 ? ny - 1 : gy - 1) * nx;
-    Y[1] = gy * nx;
-    Y[2] = (gy == ny - 1 ? 0 : gy + 1) * nx;
-    Z[0] = (gz == 0 ? nz - 1 : gz - 1) * nxny;
-    Z[1] = gz * nxny;
-    Z[2] = (gz == nz - 1 ? 0 : gz + 1) * nxny;
-  }
-  __device__ __forceinline__ int operator()(int i) const {
-    return X[1 + cx(i)] + Y[1 + cy(i)] + Z[1 + cz(i)];
-  }
-};
-
 // Colour gradient G = 3 sum_i w_i c_i phi(x + c_i) (isotropic stencil, the value
 // at x for solid neighbours), the geometric wetting rotation next to solids, and
-// the normal n = G / max(|G|, EPS_G); written as (n, |G|).
+// the normal n = G / max(|G|, EPS_G); written as (n, |G|), and the node's
+// colour source (phi, r n), r = beta rho (1 - phi^2) / 2, for the moments pass.
 __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  GLB float* __restrict__ NX = gp(s.nrm);
-  const GLB float* __restrict__ PHI = gp((const float*)s.phi);
-  const long long Nn = s.N;
+  GLB v4f* __restrict__ NRM = gp(s.nrm);
+  GLB v4f* __restrict__ CS = gp(s.csrc);
+  const GLB float* __restrict__ RHO = gp((const float*)s.rp[bt.rd ^ 1]);
+  const GLB float* __restrict__ PHI = RHO + s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   // solid node: NaN normal (tells stencils the neighbour is solid) and |G| = -1
   const float qnan = __int_as_float(0x7fc00000);
-  float4 out = make_float4(qnan, qnan, qnan, -1.0f);
+  v4f out = {qnan, qnan, qnan, -1.0f};
+  v4f cs = {PHI_SOLID, qnan, qnan, qnan};
   const float p0 = PHI[n];
   if (p0 < PHI_SOLID_TEST) {
     const Nbr nb(gx, gy, gz, nx, ny, nz);
@@ -271,12 +230,12 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
     }
     const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
     const float ig = 1.0f / fmaxf(g, EPS_G);
-    out = make_float4(Gx * ig, Gy * ig, Gz * ig, g);
+    out = v4f{Gx * ig, Gy * ig, Gz * ig, g};
+    const float r = 0.5f * s.beta * RHO[n] * (1.0f - p0) * (1.0f + p0);
+    cs = v4f{p0, r * out.x, r * out.y, r * out.z};
   }
-  NX[n] = out.x;
-  NX[Nn + n] = out.y;
-  NX[2 * Nn + n] = out.z;
-  NX[3 * Nn + n] = out.w;
+  NRM[n] = out;
+  CS[n] = cs;
 }
 
 // Curvature kappa = div n (same stencil and closure) and the CSF coefficient
@@ -285,63 +244,31 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
 __global__ __launch_bounds__(256) void k_curv(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  // normal planes: x, y, z components (NaN at solid nodes), then |G|
-  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
-  const GLB float* __restrict__ NY = NX + s.N;
-  const GLB float* __restrict__ NZ = NY + s.N;
-  const GLB float* __restrict__ NG = NZ + s.N;
+  // normals (n, |G|); NaN n at solid nodes
+  const GLB v4f* __restrict__ NRM = gp((const v4f*)s.nrm);
   GLB float* __restrict__ cur = gp((float*)s.curv);
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   float c = 0.f;
   uint32_t bits = 0x80000000u;
-  const float g0 = NG[n];
-  if (g0 >= 0.f) {
-    const float ncx = NX[n], ncy = NY[n], ncz = NZ[n];
+  const v4f n0 = NRM[n];
+  if (n0.w >= 0.f) {
     const Nbr nb(gx, gy, gz, nx, ny, nz);
     float kappa = 0.f;
     bits = 0u;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int i = pair_dir(q), o = opp(i);
-      const int mp = nb(i), mm = nb(o);
-      // only the components c_i selects are loaded; a NaN marks a solid neighbour
-      float px = 0.f, py = 0.f, pz = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
-      bool sp = false, sm = false;
-      if (cx(i) != 0) {
-        px = NX[mp];
-        mx = NX[mm];
-        sp |= px != px;
-        sm |= mx != mx;
-      }
-      if (cy(i) != 0) {
-        py = NY[mp];
-        my = NY[mm];
-        sp |= py != py;
-        sm |= my != my;
-      }
-      if (cz(i) != 0) {
-        pz = NZ[mp];
-        mz = NZ[mm];
-        sp |= pz != pz;
-        sm |= mz != mz;
-      }
-      if (sp) {
-        px = ncx;
-        py = ncy;
-        pz = ncz;
-      }
-      if (sm) {
-        mx = ncx;
-        my = ncy;
-        mz = ncz;
-      }
+      v4f p = NRM[nb(i)], m = NRM[nb(o)];
+      const bool sp = p.x != p.x, sm = m.x != m.x;
+      if (sp) p = n0;
+      if (sm) m = n0;
       kappa += 3.0f * wq(i) *
-               ((float)cx(i) * (px - mx) + (float)cy(i) * (py - my) + (float)cz(i) * (pz - mz));
+               ((float)cx(i) * (p.x - m.x) + (float)cy(i) * (p.y - m.y) + (float)cz(i) * (p.z - m.z));
       bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
     }
-    c = -0.5f * s.sigma * kappa * fmaxf(g0, EPS_G);
+    c = -0.5f * s.sigma * kappa * fmaxf(n0.w, EPS_G);
   }
   cur[2 * n] = c;
   cur[2 * n + 1] = __uint_as_float(bits);
@@ -352,9 +279,11 @@ __global__ __launch_bounds__(256) void k_curv(Batch bt) {
 // on the total f (MRT + Guo forcing; the printed relaxation vector gives omega
 // to every even and omega' = 8(2-omega)/(8-omega) to every odd non-conserved
 // moment -- the two-relaxation-time operator computed here), the force c n +
-// body force on fluid a, the recolouring of f* into the two colours, push
-// streaming, and half-way bounce-back at every solid link.  At particle links
-// the moving-wall term and the momentum exchange are added by k_links.
+// body force on fluid a, push streaming, and half-way bounce-back at every
+// solid link.  The recolouring of f* into the two colours is not stored: the
+// next moments pass rebuilds it from phi, rho and n of this state.  At
+// particle links the moving-wall term and the momentum exchange are added by
+// k_links.
 template <int STORE, int MODE>
 __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out_rho,
                                               float* __restrict__ out_u,
@@ -366,14 +295,14 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   const SimDev& s = bt.tab[sb.x];
   const GLB T* __restrict__ sp_ = gp((const T*)s.pops[bt.cur]);
   GLB T* __restrict__ dp_ = gp((T*)s.pops[bt.cur ^ 1]);
-  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
+  const GLB v4f* __restrict__ NRM = gp((const v4f*)s.nrm);
   const GLB float* __restrict__ cur = gp((const float*)s.curv);
-  const GLB uint32_t* __restrict__ rdec = gref(s.ref[bt.rd]);
-  const GLB uint32_t* __restrict__ renc = gref(s.ref[bt.rd ^ 1]);
-  const GLB float* __restrict__ PHI = gp((const float*)s.phi);
+  // moments of this state (rho, phi planes) and of the one before it; FP16
+  // decodes with the latter's density and encodes with the former's
+  const GLB float* __restrict__ RM = gp((const float*)s.rp[bt.rd ^ 1]);
+  const GLB float* __restrict__ RP = gp((const float*)s.rp[bt.rd]);
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   const int N = (int)s.N;
-  const int nxny = nx * ny;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   const float rho0 = s.rho0;
@@ -406,14 +335,12 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
     return;
   }
   const Nbr nb(gx, gy, gz, nx, ny, nz);
-  // the collision needs the total populations only: the colour enters through
-  // phi (moments pass) in the recolouring
   float d[Q];
-  const float Rn = STORE ? ref_of(rdec, n).x : 0.f;
+  const float Rn = STORE ? RP[n] : 0.f;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = IO::ld_d(sp_ + (unsigned)(i * N + n), wq(i) * rho0, wq(i) * Rn);
-  const float3 nc = make_float3(NX[n], NX[N + n], NX[2 * N + n]);
-  const float phi = PHI[n];
+  for (int i = 0; i < Q; ++i) d[i] = IO::ld(sp_ + pidx(i, N, n), wq(i) * rho0, wq(i) * Rn);
+  const v4f nc = NRM[n];
+  const float phi = RM[N + n];
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -452,29 +379,26 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   const float om2 = 8.0f * (2.0f - om) / (8.0f - om);
   const float cfs = 1.0f - 0.5f * om, cfa = 1.0f - 0.5f * om2;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
-  const float recl = 0.5f * s.beta * rho * (1.0f - phi) * (1.0f + phi);
 
-  // FP16: each population is encoded with the reference of the node that
+  // FP16: each population is encoded with the density of the node that
   // stores it
-  auto st_pop = [&](int i, int node, float dv, float gv) {
-    const float2 R = STORE ? ref_of(renc, node) : make_float2(0.f, 0.f);
-    IO::st(dp_ + (unsigned)(i * N + node), dp_ + (unsigned)((Q + i) * N + node), wq(i) * rho0,
-           inv_rho0 * (1.0f / wq(i)), wq(i) * R.x, R.y, dv, gv);
+  auto st_pop = [&](int i, int node, float dv) {
+    const float R = STORE ? RM[node] : 0.f;
+    IO::st(dp_ + pidx(i, N, node), wq(i) * rho0, inv_rho0 * (1.0f / wq(i)), wq(i) * R, dv);
   };
   // push to the neighbour in direction i, or bounce back into direction opp(i)
-  auto emit = [&](int i, float dv, float gv) {
+  auto emit = [&](int i, float dv) {
     if (bits & (1u << i))
-      st_pop(opp(i), n, dv, gv);
+      st_pop(opp(i), n, dv);
     else
-      st_pop(i, nb(i), dv, gv);
+      st_pop(i, nb(i), dv);
   };
 
   {
     const float w0 = wq(0);
     const float deq = w0 * (drho - 1.5f * rho * uu);
     const float fb = w0 * (-3.0f * uF);
-    const float ds = d[0] - om * (d[0] - deq) + cfs * fb;
-    st_pop(0, n, ds, phi * (ds + w0 * rho0));
+    st_pop(0, n, d[0] - om * (d[0] - deq) + cfs * fb);
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -491,19 +415,15 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
     const float an = 0.5f * (d[i] - d[o]) - eqa;
     const float common = -om * sy + cfs * fs;
     const float anti = -om2 * an + cfa * fa2;
-    const float ds_i = d[i] + common + anti;
-    const float ds_o = d[o] + common - anti;
-    const float cn = (float)cx(i) * nc.x + (float)cy(i) * nc.y + (float)cz(i) * nc.z;
-    const float rc = recl * w * cn;
-    const float wr0 = w * rho0;
-    emit(i, ds_i, phi * (ds_i + wr0) + rc);
-    emit(o, ds_o, phi * (ds_o + wr0) - rc);
+    emit(i, d[i] + common + anti);
+    emit(o, d[o] + common - anti);
   }
 }
 
 // Moving-wall correction and momentum exchange on particle links, after
 // k_fused has bounced f*_i back into direction opp(i) at the fluid node x:
-// f_opp(x) += 6 w_i rho(x) (c_opp . u_w), g_opp(x) += phi(x) * the same, with
+// f_opp(x) += 6 w_i rho(x) (c_opp . u_w) (its colour share phi(x) is added by
+// the moments pass, as for every bounced population), with
 // u_w = V + Omega x (x + c_i/2 - X) (half-way bounce-back eqs.), and the
 // momentum given to the particle dP = (c_i - u_w) f*_i - (c_opp - u_w) f_opp
 // (hydrodynamic force eqs.), summed in FP64 per particle.  One grid row per
@@ -517,10 +437,10 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
   const int2 sp = batch_particle(bt, blockIdx.y);
   const SimDev& s = bt.tab[sp.x];
   const int p = sp.y;
-  const GLB T* __restrict__ sp_ = gp((const T*)s.pops[bt.cur]);
   GLB T* __restrict__ dp_ = gp((T*)s.pops[bt.cur ^ 1]);
-  const GLB uint32_t* __restrict__ rdec = gref(s.ref[bt.rd]);
-  const GLB uint32_t* __restrict__ renc = gref(s.ref[bt.rd ^ 1]);
+  // moments of the state that collided: rho(x), and the FP16 reference of the
+  // populations k_fused wrote
+  const GLB float* __restrict__ RM = gp((const float*)s.rp[bt.rd ^ 1]);
   const GLB uint16_t* __restrict__ MASK = gp((const uint16_t*)s.mask);
   const DevParticle& P = s.P[p];
   const int nx = s.nx, ny = s.ny, nz = s.nz, N = (int)s.N;
@@ -560,24 +480,17 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
       for (int i = 1; i < Q; ++i) lm |= (MASK[nb(i)] == me) ? (1u << i) : 0u;
       if (lm) {
         any = true;
-        const float2 Re = STORE ? ref_of(renc, n) : make_float2(0.f, 0.f);
-        const float Rd = STORE ? ref_of(rdec, n).x : 0.f;
-        const float phi = gp((const float*)s.phi)[n];
-        float drho = 0.f;
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-          drho += IO::ld_d(sp_ + (unsigned)(q * N + n), wq(q) * rho0, wq(q) * Rd);
-        const float rho = rho0 + drho;
+        const float rho = RM[n];
+        const float Re = STORE ? rho : 0.f;
         // f*_i was bounced by k_fused into direction opp(i) at x: all of them
         // loaded first, then corrected and stored
-        float ds[Q], gs[Q];
+        float ds[Q];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          ds[i] = gs[i] = 0.f;
+          ds[i] = 0.f;
           if (lm & (1u << i)) {
             const int o = opp(i);
-            IO::ld(dp_ + (unsigned)(o * N + n), dp_ + (unsigned)((Q + o) * N + n), wq(o) * rho0,
-                   wq(o) * Re.x, Re.y, ds[i], gs[i]);
+            ds[i] = IO::ld(dp_ + pidx(o, N, n), wq(o) * rho0, wq(o) * Re);
           }
         }
 #pragma unroll
@@ -594,8 +507,7 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
           const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));  // c_opp . u_w
           const float corr = 6.0f * wq(i) * rho * cu;
           const float dso = ds[i] + corr;
-          IO::st(dp_ + (unsigned)(o * N + n), dp_ + (unsigned)((Q + o) * N + n), wr0, 1.0f / wr0,
-                 wq(o) * Re.x, Re.y, dso, gs[i] + phi * corr);
+          IO::st(dp_ + pidx(o, N, n), wr0, 1.0f / wr0, wq(o) * Re, dso);
           const double wr = wqd(i) * (double)rho0;
           const double fin = (double)ds[i] + wr;
           const double fout = (double)dso + wr;
@@ -678,11 +590,15 @@ hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, hipStream_t st) {
-  if (storage == 0)
-    hipLaunchKernelGGL(k_moments<0>, dim3(nblk), dim3(256), 0, st, b);
+// mode: MOM_STEP (in a step, after the refill) or MOM_BOUNDARY (between steps)
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, hipStream_t st) {
+  const dim3 grid(nblk);
+  if (mode == MOM_BOUNDARY)
+    hipLaunchKernelGGL((k_moments<0, MOM_BOUNDARY>), grid, dim3(256), 0, st, b);
+  else if (storage == 0)
+    hipLaunchKernelGGL((k_moments<0, MOM_STEP>), grid, dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL(k_moments<1>, dim3(nblk), dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_moments<1, MOM_STEP>), grid, dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
@@ -699,13 +615,11 @@ hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_mass(const SimDev& s, const void* pops, int rd, hipStream_t st) {
+// rp: moments (rho plane, phi plane) of the current state
+hipError_t launch_mass(const SimDev& s, const float* rp, hipStream_t st) {
   unsigned nb = nblocks(s.N, 256);
   if (nb > 4096) nb = 4096;
-  if (s.storage == 0)
-    hipLaunchKernelGGL(k_mass<0>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
-  else
-    hipLaunchKernelGGL(k_mass<1>, dim3(nb), dim3(256), 0, st, s, pops, s.ref[rd]);
+  hipLaunchKernelGGL(k_mass, dim3(nb), dim3(256), 0, st, s, rp);
   return hipGetLastError();
 }
 

@@ -116,8 +116,13 @@ __global__ void k_cover(Batch bt) {
 
 // Refilling (refilling eqs.): f_a, f_b of a fresh node = equilibria of the mean
 // neighbour densities (fluid, not fresh, D3Q19 neighbours; rho0/2 each if none)
-// at the surface velocity of the particle that uncovered it.
-template <int STORE>
+// at the surface velocity of the particle that uncovered it.  Stored are the
+// total f and the node's moments (rho, phi) in rp[rd ^ 1].  The neighbour
+// densities are those of the post-stream state: in a step (REFILL_STEP) rebuilt
+// from the state that collided, as the moments pass does; between steps
+// (REFILL_BOUNDARY) the current moments rp[rd ^ 1].
+enum { REFILL_STEP = 0, REFILL_BOUNDARY = 1 };
+template <int STORE, int MODE>
 __global__ __launch_bounds__(256) void k_refill(Batch bt) {
   // one thread per (fresh node, neighbour direction): 14 fresh nodes per
   // block; grid row = simulation
@@ -125,14 +130,14 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
   using T = typename IO::T;
   const SimDev& s = bt.tab[blockIdx.y];
   if (s.np == 0) return;
-  void* pops = s.pops[bt.cur];
-  const __half2* __restrict__ rdec = s.ref[bt.rd];
+  T* b = (T*)s.pops[bt.cur];
+  const GLB float* RO = gp((const float*)s.rp[bt.rd]);
+  float* RN = s.rp[bt.rd ^ 1];
   constexpr int PER = 14;
   __shared__ float sh_a[PER][18], sh_b[PER][18];
   __shared__ int sh_c[PER][18];
-  T* b = (T*)pops;
   const uint32_t cnt = min(s.counters[0], s.fresh_cap);
-  const long long N = s.N;
+  const int N = (int)s.N;
   const int slot = threadIdx.x / 18, dir = threadIdx.x % 18 + 1;
   for (uint32_t base = blockIdx.x * PER; base < cnt; base += gridDim.x * PER) {
     const uint32_t k = base + slot;
@@ -140,24 +145,21 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
       float ra = 0.f, rb = 0.f;
       int c = 0;
       if (k < cnt) {
-        const long long n = s.fresh[k];
-        const int x = (int)(n % s.nx), y = (int)((n / s.nx) % s.ny),
-                  z = (int)(n / ((long long)s.nx * s.ny));
-        const long long m = (long long)wrapi(x + cx(dir), s.nx) +
-                            (long long)s.nx * ((long long)wrapi(y + cy(dir), s.ny) +
-                                               (long long)s.ny * wrapi(z + cz(dir), s.nz));
+        const int n = (int)s.fresh[k];
+        const int x = n % s.nx, y = (n / s.nx) % s.ny, z = n / (s.nx * s.ny);
+        const int mx = wrapi(x + cx(dir), s.nx), my = wrapi(y + cy(dir), s.ny),
+                  mz = wrapi(z + cz(dir), s.nz);
+        const int m = mx + s.nx * (my + s.ny * mz);
         if (s.mask[m] == 0) {
-          float drho = 0.f, sg = 0.f;
-          const float2 R = STORE ? ref_of(rdec, m) : make_float2(0.f, 0.f);
-#pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            float d, g;
-            IO::ld(b + (long long)q * N + m, b + (long long)(Q + q) * N + m, wq(q) * s.rho0,
-                   wq(q) * R.x, R.y, d, g);
-            drho += d;
-            sg += g;
+          float rho, sg;
+          if (MODE == REFILL_STEP) {
+            const Nbr nbm(mx, my, mz, s.nx, s.ny, s.nz);
+            rebuild_moments<STORE>(gp((const T*)b), gp((const v4f*)s.csrc), N, m, nbm, s.rho0,
+                                   STORE ? RO[m] : 0.f, rho, sg);
+          } else {
+            rho = RN[m];
+            sg = rho * RN[N + m];
           }
-          const float rho = s.rho0 + drho;
           ra = 0.5f * (rho + sg);
           rb = 0.5f * (rho - sg);
           c = 1;
@@ -177,10 +179,9 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
         sb += sh_b[threadIdx.x][i];
         c += sh_c[threadIdx.x][i];
       }
-      const long long n = s.fresh[kk];
+      const int n = (int)s.fresh[kk];
       const int p = (int)s.fresh_own[kk];
-      const int x = (int)(n % s.nx), y = (int)((n / s.nx) % s.ny),
-                z = (int)(n / ((long long)s.nx * s.ny));
+      const int x = n % s.nx, y = (n / s.nx) % s.ny, z = n / (s.nx * s.ny);
       const float ra = c ? sa / c : 0.5f * s.rho0;
       const float rb = c ? sb / c : 0.5f * s.rho0;
       const DevParticle& P = s.P[p];
@@ -192,15 +193,17 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
       const float uz = (float)(P.v[2] + P.w[0] * ry - P.w[1] * rx);
       const float uu = ux * ux + uy * uy + uz * uz;
       const float rho = ra + rb;
-      const float2 Rn = STORE ? ref_of(rdec, n) : make_float2(0.f, 0.f);
+      // FP16: encoded with the reference the decoders of this state use
+      const float Rn = STORE ? RO[n] : 0.f;
       for (int q = 0; q < Q; ++q) {
         const float cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
         const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
         const float dq = wq(q) * ((rho - s.rho0) + rho * poly);
-        const float gq = wq(q) * (ra - rb) * (1.0f + poly);
-        IO::st(b + (long long)q * N + n, b + (long long)(Q + q) * N + n, wq(q) * s.rho0,
-               1.0f / (wq(q) * s.rho0), wq(q) * Rn.x, Rn.y, dq, gq);
+        IO::st(b + (long long)q * N + n, wq(q) * s.rho0, 1.0f / (wq(q) * s.rho0), wq(q) * Rn, dq);
       }
+      // f^a - f^b = (ra - rb) / rho f: the order parameter of the node
+      RN[n] = rho;
+      RN[N + n] = (ra - rb) / rho;
     }
     __syncthreads();
   }
@@ -220,16 +223,18 @@ __global__ void k_capbox(Batch bt) {
   for (int k = 0; k < 3; ++k) org[k] = (int)floor(P.x[k] - P.R);
   if (blockIdx.x == 0 && threadIdx.x < 3) s.capbox_org[3 * p + threadIdx.x] = org[threadIdx.x];
   float4* box = s.capbox + (long long)p * B * B * B;
+  // phi of the state that collided this step (the buffers have swapped)
+  const float* PHI = s.rp[bt.rd] + s.N;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < B * B * B; k += gridDim.x * blockDim.x) {
     const int ix = k % B, iy = (k / B) % B, iz = k / (B * B);
     const int x = wrapi(org[0] + ix, s.nx), y = wrapi(org[1] + iy, s.ny), z = wrapi(org[2] + iz, s.nz);
     const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
     float4 v = make_float4(2.f, 0.f, 0.f, 0.f);  // phi = 2 marks a solid node
-    const float gw = s.nrm[3 * s.N + n];
-    if (gw >= 0.f) {
+    const v4f nr = s.nrm[n];
+    if (nr.w >= 0.f) {
       // G = n max(|G|, EPS_G): the colour gradient after the wetting rotation
-      const float gm = fmaxf(gw, EPS_G);
-      v = make_float4(s.phi[n], s.nrm[n] * gm, s.nrm[s.N + n] * gm, s.nrm[2 * s.N + n] * gm);
+      const float gm = fmaxf(nr.w, EPS_G);
+      v = make_float4(PHI[n], nr.x * gm, nr.y * gm, nr.z * gm);
     }
     box[k] = v;
   }
@@ -687,16 +692,26 @@ hipError_t launch_mask_update(const Batch& b, int np_rows, int Bmax, bool with_r
 }
 
 // fresh_cap_max: the largest fresh-list capacity of the batch
-hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, hipStream_t st) {
+// fresh_cap_max: the largest fresh-list capacity of the batch; mode REFILL_STEP
+// (in a step) or REFILL_BOUNDARY (between steps)
+hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int mode,
+                         hipStream_t st) {
   if (fresh_cap_max == 0) return hipSuccess;
   unsigned nb = (unsigned)((fresh_cap_max + 13) / 14);
   if (nb > 128) nb = 128;
   if (nb == 0) nb = 1;
   const dim3 grid(nb, b.nsim);
-  if (storage == 0)
-    hipLaunchKernelGGL(k_refill<0>, grid, dim3(256), 0, st, b);
-  else
-    hipLaunchKernelGGL(k_refill<1>, grid, dim3(256), 0, st, b);
+  if (storage == 0) {
+    if (mode == REFILL_STEP)
+      hipLaunchKernelGGL((k_refill<0, REFILL_STEP>), grid, dim3(256), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_refill<0, REFILL_BOUNDARY>), grid, dim3(256), 0, st, b);
+  } else {
+    if (mode == REFILL_STEP)
+      hipLaunchKernelGGL((k_refill<1, REFILL_STEP>), grid, dim3(256), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_refill<1, REFILL_BOUNDARY>), grid, dim3(256), 0, st, b);
+  }
   return hipGetLastError();
 }
 

@@ -284,10 +284,10 @@ class Context:
         c = self._cfg[sim]
         N = c.nx * c.ny * c.nz
         dt = np.float16 if c.storage == LBM_STORE_FP16 else np.float32
-        out = np.zeros(38 * N, dt)
+        out = np.zeros(19 * N, dt)
         self._check(load_library().lbm_fields(self.h, sim, LBM_F_POPS, None, None, None, None,
                                               out.ctypes.data, 0))
-        return out.reshape(38, N)
+        return out.reshape(19, N)
 
     def links(self, sim: int = 0):
         L = load_library()
