@@ -153,7 +153,7 @@ def scale_c3(args):
         prof = sim.profile_read()
         sim.profile(False)
         pop_b, ref_b = (2, 8) if storage == "fp16" else (4, 0)
-        alg = n_fluid * (19 * pop_b + 38 * pop_b + 24 + ref_b) + (N - n_fluid) * 8
+        alg = n_fluid * (38 * pop_b + 24 + ref_b) + (N - n_fluid) * 8
         t_f = prof["fused"][0] / max(prof["fused"][1], 1) * 1e-3
         res[storage] = {"mlups": round(N * args.steps / (t1 - t0) / 1e6, 1),
                         "ms_per_step": round((t1 - t0) * 1e3 / args.steps, 4),
@@ -315,23 +315,23 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     mlups = N * args.steps / (t1 - t0) / 1e6
 
-    # algorithmic bytes of one k_fused launch.  Per fluid node: the 19 total
-    # populations read (the collision needs f only; the colour enters through
-    # phi), all 38 populations written (4 B each, 2 B in FP16 storage), the
-    # interface normal (12 B), the curvature term + solid-link word (8 B) and
-    # phi (4 B) read; FP16 adds the references (half2 per node): the node's own
-    # for decoding (4 B) and those of the nodes written to (4 B per node).  Per
-    # solid node the link word.
+    # algorithmic bytes of one k_fused launch.  Per fluid node: the 19 stored
+    # populations read and written once (4 B each, 2 B in FP16 storage; the
+    # colour is not stored), the interface normal (12 B), the curvature term +
+    # solid-link word (8 B) and phi (4 B) read; FP16 adds the reference
+    # densities: the node's previous one for decoding (4 B) and the current one
+    # of the nodes written to (4 B per node).  Per solid node the link word.
     pop_b = 2 if args.storage == "fp16" else 4
     ref_b = 8 if args.storage == "fp16" else 0
-    alg_bytes = n_fluid * (19 * pop_b + 38 * pop_b + 12 + 8 + 4 + ref_b) + (N - n_fluid) * 8
+    alg_bytes = n_fluid * (38 * pop_b + 12 + 8 + 4 + ref_b) + (N - n_fluid) * 8
     fused_ms, fused_n = prof["fused"]
     t_fused = fused_ms / max(fused_n, 1) * 1e-3
     achieved = alg_bytes / t_fused / 1e9
     traffic = traffic_from_profile() if args.storage == "fp32" else None
-    # whole-step effective fraction: B_alg per node-step (populations r+w, phi
-    # w+r, mask r) at the measured MLUPS
-    b_alg_node = 38 * pop_b * 2 + 8 + 2
+    # whole-step effective fraction: B_alg per node-step (populations read and
+    # written by the collision and read by the moments pass, moments written,
+    # mask read) at the measured MLUPS
+    b_alg_node = 19 * pop_b * 3 + 8 + 2
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),

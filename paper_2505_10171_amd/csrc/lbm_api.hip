@@ -28,7 +28,8 @@ hipError_t launch_interface(const Batch& b, unsigned nblk, hipStream_t st);
 hipError_t launch_fused(const Batch& b, int storage, unsigned nblk, int mode, float* orho,
                         float* ou, float* ophi, float* oF, hipStream_t st);
 hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipStream_t st);
-hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, hipStream_t st);
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, size_t lds,
+                          hipStream_t st);
 hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
 hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
 hipError_t launch_mass(const SimDev& s, const float* rp, hipStream_t st);
@@ -248,6 +249,7 @@ struct lbm_ctx {
   unsigned nblk = 0;
   int np_rows = 0, np_max = 0, Bmax = 0, cap_B = 0, npts = 0;
   size_t fresh_cap_max = 0;
+  size_t mom_lds = 0;  // LDS of the moments pass: the largest tile halo of the batch
   // graph replay of a pair of steps (captured with cur == graph_cur)
   bool use_graph = false;
   hipGraphExec_t graph_exec = nullptr;
@@ -269,6 +271,13 @@ static void set_tile(SimDev& d, int tx) {
   while ((1 << d.tile_lx) < tx) ++d.tile_lx;
   d.tiles_x = (d.nx + tx - 1) / tx;
   d.tiles_y = (d.ny + (256 / tx) - 1) / (256 / tx);
+}
+
+// LDS of the moments pass for one simulation: colour sources of its x-y tile
+// grown by one node in x, y and z (none for blocks of consecutive nodes)
+static size_t moments_lds_bytes(const SimDev& d) {
+  if (d.tile_x == 0) return 0;
+  return (size_t)(d.tile_x + 2) * (256 / d.tile_x + 2) * 3 * sizeof(v4f);
 }
 
 static Batch batch_all(const lbm_ctx* c) {
@@ -321,9 +330,11 @@ static int upload_tables(lbm_ctx* ctx, size_t off) {
   std::vector<int2> pmap;
   ctx->np_max = ctx->Bmax = ctx->cap_B = ctx->npts = 0;
   ctx->fresh_cap_max = 0;
+  ctx->mom_lds = 0;
   for (int si = 0; si < n_sims; ++si) {
     const SimHost& sh = ctx->sims[si];
     tab[si] = sh.d;
+    ctx->mom_lds = std::max(ctx->mom_lds, moments_lds_bytes(sh.d));
     const unsigned long long nb = (unsigned long long)blk[si] + sim_blocks(sh.d);
     if (nb > 0x7fffffffull) return set_err(ctx, LBM_EINVAL, "too many lattice nodes in one context");
     blk[si + 1] = (uint32_t)nb;
@@ -357,7 +368,7 @@ static int post_dem_pipeline(lbm_ctx* ctx, int si, bool with_release) {
     HIPCHK(ctx, launch_mask_update(b, s.np, sh.L.Bmask, with_release, ctx->stream));
     HIPCHK(ctx, launch_refill(b, ctx->storage, s.fresh_cap, REFILL_BOUNDARY, ctx->stream));
   }
-  HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), MOM_BOUNDARY, ctx->stream));
+  HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), MOM_BOUNDARY, 0, ctx->stream));
   return LBM_OK;
 }
 
@@ -584,7 +595,7 @@ static int step_once(lbm_ctx* ctx, int slot) {
     HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, REFILL_STEP, st));
   }
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], st));
-  HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, MOM_STEP, st));
+  HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, MOM_STEP, ctx->mom_lds, st));
   if (slot >= 0) {
     HIPCHK(ctx, hipEventRecord(P.ev[slot][4], st));
     P.pending[slot] = true;
@@ -730,7 +741,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
           if (r == 1) HIPCHK(ctx, hipEventRecord(e0, st));
           HIPCHK(ctx, launch_interface(b1, nb, st));
           HIPCHK(ctx, launch_fused(b1, ctx->storage, nb, 0, nullptr, nullptr, nullptr, nullptr, st));
-          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, MOM_STEP, st));
+          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, MOM_STEP, moments_lds_bytes(d), st));
         }
         HIPCHK(ctx, hipEventRecord(e1, st));
         HIPCHK(ctx, hipEventSynchronize(e1));

@@ -280,36 +280,43 @@ __device__ __forceinline__ unsigned pidx(int i, int N, int n) {
 // state streamed (its colour source is not NaN), else x itself, whose
 // f*_opp(i) was bounced back (the moving-wall term of the bounce-back eqs. is
 // coloured by phi(x) as well), giving phi(x) f_i - r(x) w_i (c_i . n(x)).
-// CS: colour sources (phi, r n) of the state that collided; Rd: the FP16
+// Colour sources (phi, r n) of the state that collided; Rd: the FP16
 // reference density of the stored populations at n.  Returns rabs = sum f_i,
 // with f_i = d_i + w_i rho0 rounded as the collision formed it, and sg = sum of
 // the colour differences: in the bulk of either fluid (phi' = +-1, r' = 0)
 // sg = +-rabs exactly.
-template <int STORE, class PT>
-__device__ __forceinline__ void rebuild_moments(PT pops, const GLB v4f* CS, int N, int n,
-                                                const Nbr& nb, float rho0, float Rd, float& rabs,
-                                                float& sg) {
+// CSRC(i): colour source of x - c_i (i = 1..18), own: that of x.
+template <int STORE, class PT, class CSRC>
+__device__ __forceinline__ void rebuild_moments(PT pops, CSRC cs_src, const v4f own, int N, int n,
+                                                float rho0, float Rd, float& rabs, float& sg) {
   using IO = Codec<STORE>;
-  const v4f own = CS[n];
-  {
-    const float wr0 = wq(0) * rho0;
-    const float f = IO::ld(pops + (unsigned)n, wr0, wq(0) * Rd) + wr0;
-    rabs = f;
-    sg = own.x * f;
-  }
+  // all populations first, so that their loads are in flight together
+  float f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = IO::ld(pops + pidx(i, N, n), wq(i) * rho0, wq(i) * Rd);
+  rabs = f[0] + wq(0) * rho0;
+  sg = own.x * rabs;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    const v4f c = CS[nb(opp(i))];
+    const v4f c = cs_src(i);
     const bool solid = c.y != c.y;
-    const float wr0 = wq(i) * rho0;
-    const float f = IO::ld(pops + pidx(i, N, n), wr0, wq(i) * Rd) + wr0;
+    const float fi = f[i] + wq(i) * rho0;
     const float ts = (float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w;
     const float to = (float)cx(i) * own.y + (float)cy(i) * own.z + (float)cz(i) * own.w;
     const float ph = solid ? own.x : c.x;
     const float t = solid ? -to : ts;
-    rabs += f;
-    sg += ph * f + wq(i) * t;
+    rabs += fi;
+    sg += ph * fi + wq(i) * t;
   }
+}
+
+// the same with the colour sources read from the global array CS
+template <int STORE, class PT>
+__device__ __forceinline__ void rebuild_moments(PT pops, const GLB v4f* CS, int N, int n,
+                                                const Nbr& nb, float rho0, float Rd, float& rabs,
+                                                float& sg) {
+  rebuild_moments<STORE>(
+      pops, [&](int i) { return CS[nb(opp(i))]; }, CS[n], N, n, rho0, Rd, rabs, sg);
 }
 
 __host__ __device__ inline int wrapi(int a, int n) {

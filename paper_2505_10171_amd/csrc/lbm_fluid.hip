@@ -86,36 +86,102 @@ __device__ __forceinline__ int xcd_tile(int lin, int nblk) {
 // tell solids from phi alone.  MOM_BOUNDARY (between steps, after the mask
 // changed with the populations in place): fluid nodes keep their moments.
 enum { MOM_STEP = 0, MOM_BOUNDARY = 1 };
+// Blocks of x-y tiles stage the colour sources of the tile grown by one node
+// in x, y and z in LDS (dynamic size (tx + 2)(ty + 2) 3 x 16 B); blocks of
+// consecutive nodes read them from global memory.
 template <int STORE, int MODE>
 __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   using IO = Codec<STORE>;
   using T = typename IO::T;
+  extern __shared__ __attribute__((aligned(16))) char mom_smem[];
+  v4f* halo = (v4f*)mom_smem;
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
   const int N = (int)s.N;
-  int n, gx, gy, gz;
+  const int nx = s.nx, ny = s.ny, nz = s.nz;
   if (sb.y == 0 && threadIdx.x == 0) s.counters[0] = 0u;  // fresh list consumed
-  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
+  const GLB v4f* __restrict__ CS = gp((const v4f*)s.csrc);
+  const bool tiled = MODE == MOM_STEP && s.tile_x != 0;
+  int lx = 0, ly = 0, HX = 0, HY = 0, n, gx, gy, gz;
+  bool in;
+  if (tiled) {
+    const int tx = s.tile_x, ty = 256 >> s.tile_lx;
+    const int bx = sb.y % s.tiles_x, r = sb.y / s.tiles_x;
+    const int x0 = bx * tx, y0 = (r % s.tiles_y) * ty;
+    gz = r / s.tiles_y;
+    HX = tx + 2;
+    HY = ty + 2;
+    const int HP = HX * HY;
+    // every load of the halo in flight before the first LDS store (at most
+    // 3 (256 + 2) 3 = 2322 records: 10 per thread)
+    constexpr int KMAX = 10;
+    // (k + 1/2) / HP in FP32 is within 1e-6 of its value (k < 2^12), far from
+    // the next integer (>= 1 / (2 HP)): the floor is exact
+    const float iHP = 1.0f / (float)HP, iHX = 1.0f / (float)HX;
+    v4f hv[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int k = (int)threadIdx.x + 256 * j;
+      if (k < 3 * HP) {
+        const int hz = (int)(((float)k + 0.5f) * iHP), rem = k - hz * HP;
+        const int hy = (int)(((float)rem + 0.5f) * iHX), hx = rem - hy * HX;
+        // periodic wrap of the halo; positions past a partial tile's end are
+        // never read and only kept in bounds
+        int x = x0 - 1 + hx, y = y0 - 1 + hy, z = gz - 1 + hz;
+        x = x < 0 ? x + nx : x;
+        x = x >= nx ? x - nx : x;
+        x = min(x, nx - 1);
+        y = y < 0 ? y + ny : y;
+        y = y >= ny ? y - ny : y;
+        y = min(y, ny - 1);
+        z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+        hv[j] = CS[x + nx * (y + ny * z)];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int k = (int)threadIdx.x + 256 * j;
+      if (k < 3 * HP) halo[k] = hv[j];
+    }
+    __syncthreads();
+    lx = (int)threadIdx.x & (tx - 1);
+    ly = (int)threadIdx.x >> s.tile_lx;
+    gx = x0 + lx;
+    gy = y0 + ly;
+    in = gx < nx && gy < ny;
+    n = gx + nx * (gy + ny * gz);
+  } else {
+    in = tile_node(s, sb.y, n, gx, gy, gz);
+  }
+  if (!in) return;
   GLB uint16_t* __restrict__ MASK = gp(s.mask);
   GLB float* __restrict__ RN = gp(s.rp[bt.rd ^ 1]);
   const uint16_t m = MASK[n];
+  // the sums are formed before the mask is examined, so that every load of
+  // the node is in flight at once (at solid and fresh nodes they go unused)
+  float rabs = 0.f, sg = 0.f;
+  if (MODE == MOM_STEP) {
+    const float Rd = STORE ? gp((const float*)s.rp[bt.rd])[n] : 0.f;
+    const GLB T* pops = gp((const T*)s.pops[bt.cur]);
+    if (tiled) {
+      const int c0 = (lx + 1) + HX * ((ly + 1) + HY);
+      rebuild_moments<STORE>(
+          pops, [&](int i) { return halo[c0 - cx(i) - HX * (cy(i) + HY * cz(i))]; }, halo[c0], N,
+          n, s.rho0, Rd, rabs, sg);
+    } else {
+      const Nbr nb(gx, gy, gz, nx, ny, nz);
+      rebuild_moments<STORE>(pops, CS, N, n, nb, s.rho0, Rd, rabs, sg);
+    }
+  }
   if (m & FRESH_BIT) {  // refilled node: moments written by the refill
     MASK[n] = (uint16_t)(m & ~FRESH_BIT);
-    return;
-  }
-  if (m != 0) {
+  } else if (m != 0) {
     RN[n] = s.rho0;
     RN[N + n] = PHI_SOLID;
-    return;
+  } else if (MODE == MOM_STEP) {
+    RN[n] = rabs;
+    RN[N + n] = sg / rabs;
   }
-  if (MODE == MOM_BOUNDARY) return;
-  const Nbr nb(gx, gy, gz, s.nx, s.ny, s.nz);
-  float rabs, sg;
-  const float Rd = STORE ? gp((const float*)s.rp[bt.rd])[n] : 0.f;
-  rebuild_moments<STORE>(gp((const T*)s.pops[bt.cur]), gp((const v4f*)s.csrc), N, n, nb, s.rho0, Rd,
-                         rabs, sg);
-  RN[n] = rabs;
-  RN[N + n] = sg / rabs;
 }
 
 // ------------------------------------------------------------ init kernels
@@ -199,15 +265,22 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   v4f out = {qnan, qnan, qnan, -1.0f};
   v4f cs = {PHI_SOLID, qnan, qnan, qnan};
   const float p0 = PHI[n];
+  // neighbour values loaded before the node's own is examined
+  const Nbr nb(gx, gy, gz, nx, ny, nz);
+  float vpl[9], vml[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    vpl[q] = PHI[nb(pair_dir(q))];
+    vml[q] = PHI[nb(opp(pair_dir(q)))];
+  }
   if (p0 < PHI_SOLID_TEST) {
-    const Nbr nb(gx, gy, gz, nx, ny, nz);
     float Gx = 0.f, Gy = 0.f, Gz = 0.f;
     bool solid = false;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int i = pair_dir(q);
-      float vp = PHI[nb(i)];
-      float vm = PHI[nb(opp(i))];
+      float vp = vpl[q];
+      float vm = vml[q];
       const bool sp = vp > PHI_SOLID_TEST, sm = vm > PHI_SOLID_TEST;
       solid |= sp | sm;
       vp = sp ? p0 : vp;
@@ -253,14 +326,21 @@ __global__ __launch_bounds__(256) void k_curv(Batch bt) {
   float c = 0.f;
   uint32_t bits = 0x80000000u;
   const v4f n0 = NRM[n];
+  // neighbour normals loaded before the node's own is examined
+  const Nbr nb(gx, gy, gz, nx, ny, nz);
+  v4f npl[9], nml[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    npl[q] = NRM[nb(pair_dir(q))];
+    nml[q] = NRM[nb(opp(pair_dir(q)))];
+  }
   if (n0.w >= 0.f) {
-    const Nbr nb(gx, gy, gz, nx, ny, nz);
     float kappa = 0.f;
     bits = 0u;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int i = pair_dir(q), o = opp(i);
-      v4f p = NRM[nb(i)], m = NRM[nb(o)];
+      v4f p = npl[q], m = nml[q];
       const bool sp = p.x != p.x, sm = m.x != m.x;
       if (sp) p = n0;
       if (sm) m = n0;
@@ -590,15 +670,17 @@ hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipS
   return hipGetLastError();
 }
 
-// mode: MOM_STEP (in a step, after the refill) or MOM_BOUNDARY (between steps)
-hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, hipStream_t st) {
+// mode: MOM_STEP (in a step, after the refill) or MOM_BOUNDARY (between steps);
+// lds: dynamic LDS bytes, the largest tile halo of the batch (0 if none tiled)
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, size_t lds,
+                          hipStream_t st) {
   const dim3 grid(nblk);
   if (mode == MOM_BOUNDARY)
     hipLaunchKernelGGL((k_moments<0, MOM_BOUNDARY>), grid, dim3(256), 0, st, b);
   else if (storage == 0)
-    hipLaunchKernelGGL((k_moments<0, MOM_STEP>), grid, dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_moments<0, MOM_STEP>), grid, dim3(256), lds, st, b);
   else
-    hipLaunchKernelGGL((k_moments<1, MOM_STEP>), grid, dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_moments<1, MOM_STEP>), grid, dim3(256), lds, st, b);
   return hipGetLastError();
 }
 
