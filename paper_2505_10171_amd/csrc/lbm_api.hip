@@ -28,7 +28,7 @@ hipError_t launch_interface(const Batch& b, unsigned nblk, hipStream_t st);
 hipError_t launch_fused(const Batch& b, int storage, unsigned nblk, int mode, float* orho,
                         float* ou, float* ophi, float* oF, hipStream_t st);
 hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipStream_t st);
-hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, size_t lds,
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, unsigned mnblk, int mode,
                           hipStream_t st);
 hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
 hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
@@ -245,11 +245,12 @@ struct lbm_ctx {
   // batch tables (in the workspace) and their host-side extents
   SimDev* d_tab = nullptr;
   uint32_t* d_blk = nullptr;
+  uint32_t* d_mblk = nullptr;
   int2* d_pmap = nullptr;
   unsigned nblk = 0;
   int np_rows = 0, np_max = 0, Bmax = 0, cap_B = 0, npts = 0;
   size_t fresh_cap_max = 0;
-  size_t mom_lds = 0;  // LDS of the moments pass: the largest tile halo of the batch
+  unsigned mnblk = 0;  // blocks of the moments pass over the batch
   // graph replay of a pair of steps (captured with cur == graph_cur)
   bool use_graph = false;
   hipGraphExec_t graph_exec = nullptr;
@@ -273,23 +274,29 @@ static void set_tile(SimDev& d, int tx) {
   d.tiles_y = (d.ny + (256 / tx) - 1) / (256 / tx);
 }
 
-// LDS of the moments pass for one simulation: colour sources of its x-y tile
-// grown by one node in x, y and z (none for blocks of consecutive nodes)
-static size_t moments_lds_bytes(const SimDev& d) {
-  if (d.tile_x == 0) return 0;
-  return (size_t)(d.tile_x + 2) * (256 / d.tile_x + 2) * 3 * sizeof(v4f);
+// tiling of the moments pass: the widest of 64, 32, 16 that the box fills
+static void set_mom_tiling(SimDev& d) {
+  d.mtile_x = d.nx >= 64 ? 64 : (d.nx >= 32 ? 32 : 16);
+  d.mtile_lx = d.mtile_x == 64 ? 6 : (d.mtile_x == 32 ? 5 : 4);
+  const int ty = 256 / d.mtile_x;
+  d.mtiles_x = (d.nx + d.mtile_x - 1) / d.mtile_x;
+  d.mtiles_y = (d.ny + ty - 1) / ty;
+  d.mtiles_z = (d.nz + MOM_KZ - 1) / MOM_KZ;
+}
+static unsigned mom_blocks(const SimDev& d) {
+  return (unsigned)((long long)d.mtiles_x * d.mtiles_y * d.mtiles_z);
 }
 
 static Batch batch_all(const lbm_ctx* c) {
-  return Batch{c->d_tab, c->d_blk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd};
+  return Batch{c->d_tab, c->d_blk, c->d_mblk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd};
 }
 static Batch batch_one(const lbm_ctx* c, int si) {
-  return Batch{c->d_tab + si, nullptr, nullptr, 1, c->cur, c->rd};
+  return Batch{c->d_tab + si, nullptr, nullptr, nullptr, 1, c->cur, c->rd};
 }
 
 // workspace tail holding the batch tables
 static size_t batch_tables_bytes(int n_sims, long long np_total) {
-  return align_up(sizeof(SimDev) * (size_t)n_sims) + align_up(4 * (size_t)(n_sims + 1)) +
+  return align_up(sizeof(SimDev) * (size_t)n_sims) + 2 * align_up(4 * (size_t)(n_sims + 1)) +
          align_up(8 * (size_t)std::max<long long>(np_total, 1));
 }
 
@@ -323,18 +330,21 @@ static int upload_tables(lbm_ctx* ctx, size_t off) {
     b += align_up(sizeof(SimDev) * (size_t)n_sims);
     ctx->d_blk = (uint32_t*)b;
     b += align_up(4 * (size_t)(n_sims + 1));
+    ctx->d_mblk = (uint32_t*)b;
+    b += align_up(4 * (size_t)(n_sims + 1));
     ctx->d_pmap = (int2*)b;
   }
   std::vector<SimDev> tab(n_sims);
-  std::vector<uint32_t> blk(n_sims + 1, 0);
+  std::vector<uint32_t> blk(n_sims + 1, 0), mblk(n_sims + 1, 0);
   std::vector<int2> pmap;
   ctx->np_max = ctx->Bmax = ctx->cap_B = ctx->npts = 0;
   ctx->fresh_cap_max = 0;
-  ctx->mom_lds = 0;
   for (int si = 0; si < n_sims; ++si) {
     const SimHost& sh = ctx->sims[si];
     tab[si] = sh.d;
-    ctx->mom_lds = std::max(ctx->mom_lds, moments_lds_bytes(sh.d));
+    const unsigned long long mb = (unsigned long long)mblk[si] + mom_blocks(sh.d);
+    if (mb > 0x7fffffffull) return set_err(ctx, LBM_EINVAL, "too many lattice nodes in one context");
+    mblk[si + 1] = (uint32_t)mb;
     const unsigned long long nb = (unsigned long long)blk[si] + sim_blocks(sh.d);
     if (nb > 0x7fffffffull) return set_err(ctx, LBM_EINVAL, "too many lattice nodes in one context");
     blk[si + 1] = (uint32_t)nb;
@@ -348,10 +358,12 @@ static int upload_tables(lbm_ctx* ctx, size_t off) {
     }
   }
   ctx->nblk = blk[n_sims];
+  ctx->mnblk = mblk[n_sims];
   ctx->np_rows = (int)pmap.size();
   hipStream_t st = ctx->stream;
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_tab, tab.data(), sizeof(SimDev) * n_sims, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_blk, blk.data(), 4 * (size_t)(n_sims + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_mblk, mblk.data(), 4 * (size_t)(n_sims + 1), hipMemcpyHostToDevice, st));
   if (!pmap.empty())
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_pmap, pmap.data(), 8 * pmap.size(), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
@@ -368,7 +380,7 @@ static int post_dem_pipeline(lbm_ctx* ctx, int si, bool with_release) {
     HIPCHK(ctx, launch_mask_update(b, s.np, sh.L.Bmask, with_release, ctx->stream));
     HIPCHK(ctx, launch_refill(b, ctx->storage, s.fresh_cap, REFILL_BOUNDARY, ctx->stream));
   }
-  HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), MOM_BOUNDARY, 0, ctx->stream));
+  HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), 0, MOM_BOUNDARY, ctx->stream));
   return LBM_OK;
 }
 
@@ -446,6 +458,7 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.nz = c.nz;
     d.has_wall = c.has_wall ? 1 : 0;
     d.N = sh.L.N;
+    set_mom_tiling(d);
     d.storage = c.storage;
     d.np = c.n_particles;
     d.rho0 = (float)c.rho0;
@@ -462,7 +475,7 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.pops[1] = b + sh.L.off_pops1;
     d.rp[0] = (float*)(b + sh.L.off_rp0);
     d.rp[1] = (float*)(b + sh.L.off_rp1);
-    d.nrm = (v4f*)(b + sh.L.off_nrm);
+    d.nrm = (float*)(b + sh.L.off_nrm);
     d.csrc = (v4f*)(b + sh.L.off_csrc);
     d.curv = (float2*)(b + sh.L.off_cur);
     d.mask = (uint16_t*)(b + sh.L.off_mask);
@@ -595,7 +608,7 @@ static int step_once(lbm_ctx* ctx, int slot) {
     HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, REFILL_STEP, st));
   }
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], st));
-  HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, MOM_STEP, ctx->mom_lds, st));
+  HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, ctx->mnblk, MOM_STEP, st));
   if (slot >= 0) {
     HIPCHK(ctx, hipEventRecord(P.ev[slot][4], st));
     P.pending[slot] = true;
@@ -741,7 +754,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
           if (r == 1) HIPCHK(ctx, hipEventRecord(e0, st));
           HIPCHK(ctx, launch_interface(b1, nb, st));
           HIPCHK(ctx, launch_fused(b1, ctx->storage, nb, 0, nullptr, nullptr, nullptr, nullptr, st));
-          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, MOM_STEP, moments_lds_bytes(d), st));
+          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, mom_blocks(d), MOM_STEP, st));
         }
         HIPCHK(ctx, hipEventRecord(e1, st));
         HIPCHK(ctx, hipEventSynchronize(e1));

@@ -7,6 +7,9 @@
 
 namespace lbm {
 
+// planes one block of the moments pass marches through
+constexpr int MOM_KZ = 4;
+
 // ---------------------------------------------------------------- lattice
 // D3Q19: rest, +-x, +-y, +-z, (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1).
 constexpr int Q = 19;
@@ -150,7 +153,7 @@ struct SimDev {
   // PHI_SOLID at solids); rp[rd ^ 1] belongs to the state in pops[cur], rp[rd]
   // to the state before it (the FP16 reference of pops[cur])
   float* rp[2];
-  v4f* nrm;            // per node (n_x, n_y, n_z, |G|); (NaN, NaN, NaN, -1) at solids
+  float* nrm;          // 4 planes of N: n_x, n_y, n_z (NaN at solids), |G| (-1 at solids)
   // per node colour source of the state about to collide: (phi, r n_x, r n_y,
   // r n_z) with r = beta rho (1 - phi^2) / 2; NaN in r n at solids
   v4f* csrc;
@@ -181,6 +184,11 @@ struct SimDev {
   // consecutive nodes per block; otherwise an x-y tile of tile_x by
   // 256 / tile_x nodes (tile_x = 1 << tile_lx), tiles_x by tiles_y per plane
   int tile_x, tile_lx, tiles_x, tiles_y;
+  // blocks of the moments pass: x-y tiles of mtile_x (16, 32 or 64) by
+  // 256 / mtile_x nodes
+  // (mtile_x = 1 << mtile_lx), each over MOM_KZ planes; mtiles_x by mtiles_y
+  // by mtiles_z of them
+  int mtile_x, mtile_lx, mtiles_x, mtiles_y, mtiles_z;
 };
 
 // lattice node of thread threadIdx.x in block lb of simulation s; false if the
@@ -221,23 +229,28 @@ enum StatusBits : uint32_t { ST_UNSTABLE = 1u, ST_CONTACT_FULL = 2u, ST_FRESH_FU
 struct Batch {
   const SimDev* tab;
   const uint32_t* blk;
+  const uint32_t* mblk;  // as blk, for the blocks of the moments pass
   const int2* pmap;
   int nsim;
   int cur, rd;
 };
 
-// (simulation, block within it) of global block g
-__device__ __forceinline__ int2 batch_block(const Batch& b, int g) {
+// (simulation, block within it) of global block g, given the block prefix blk
+__device__ __forceinline__ int2 batch_block_in(const Batch& b, const uint32_t* blk, int g) {
   if (b.nsim == 1) return make_int2(0, g);
   int lo = 0, hi = b.nsim;  // blk[lo] <= g < blk[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if ((int)b.blk[mid] <= g)
+    if ((int)blk[mid] <= g)
       lo = mid;
     else
       hi = mid;
   }
-  return make_int2(lo, g - (int)b.blk[lo]);
+  return make_int2(lo, g - (int)blk[lo]);
+}
+// the per-node kernels' blocks
+__device__ __forceinline__ int2 batch_block(const Batch& b, int g) {
+  return batch_block_in(b, b.blk, g);
 }
 
 // (simulation, particle) of grid row r
@@ -285,38 +298,55 @@ __device__ __forceinline__ unsigned pidx(int i, int N, int n) {
 // with f_i = d_i + w_i rho0 rounded as the collision formed it, and sg = sum of
 // the colour differences: in the bulk of either fluid (phi' = +-1, r' = 0)
 // sg = +-rabs exactly.
-// CSRC(i): colour source of x - c_i (i = 1..18), own: that of x.
-template <int STORE, class PT, class CSRC>
-__device__ __forceinline__ void rebuild_moments(PT pops, CSRC cs_src, const v4f own, int N, int n,
-                                                float rho0, float Rd, float& rabs, float& sg) {
+// The node's populations f_i - w_i rho0 (decoded with the reference density Rd).
+template <int STORE, class PT>
+__device__ __forceinline__ void load_pops(PT pops, int N, int n, float rho0, float Rd, float* d) {
   using IO = Codec<STORE>;
-  // all populations first, so that their loads are in flight together
-  float f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = IO::ld(pops + pidx(i, N, n), wq(i) * rho0, wq(i) * Rd);
-  rabs = f[0] + wq(0) * rho0;
-  sg = own.x * rabs;
+  for (int i = 0; i < Q; ++i) d[i] = IO::ld(pops + pidx(i, N, n), wq(i) * rho0, wq(i) * Rd);
+}
+
+// The sums from the populations d; CSRC(i): colour source of x - c_i
+// (i = 1..18), own: that of x.
+template <class CSRC>
+__device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v4f own, float rho0,
+                                            float& rabs, float& sg) {
+  rabs = d[0] + wq(0) * rho0;
+  const float sg0 = own.x * rabs;
+  // every source fluid: no selects.  A solid source carries NaN in r n, which
+  // turns the sum to NaN; only then the sum is redone with the bounce rule.
+  sg = sg0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const v4f c = cs_src(i);
-    const bool solid = c.y != c.y;
-    const float fi = f[i] + wq(i) * rho0;
-    const float ts = (float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w;
-    const float to = (float)cx(i) * own.y + (float)cy(i) * own.z + (float)cz(i) * own.w;
-    const float ph = solid ? own.x : c.x;
-    const float t = solid ? -to : ts;
+    const float fi = d[i] + wq(i) * rho0;
     rabs += fi;
-    sg += ph * fi + wq(i) * t;
+    sg += c.x * fi + wq(i) * ((float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w);
+  }
+  if (sg != sg) {
+    sg = sg0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const v4f c = cs_src(i);
+      const bool solid = c.y != c.y;
+      const float fi = d[i] + wq(i) * rho0;
+      const float ts = (float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w;
+      const float to = (float)cx(i) * own.y + (float)cy(i) * own.z + (float)cz(i) * own.w;
+      const float ph = solid ? own.x : c.x;
+      const float t = solid ? -to : ts;
+      sg += ph * fi + wq(i) * t;
+    }
   }
 }
 
-// the same with the colour sources read from the global array CS
+// both, with the colour sources read from the global array CS
 template <int STORE, class PT>
 __device__ __forceinline__ void rebuild_moments(PT pops, const GLB v4f* CS, int N, int n,
                                                 const Nbr& nb, float rho0, float Rd, float& rabs,
                                                 float& sg) {
-  rebuild_moments<STORE>(
-      pops, [&](int i) { return CS[nb(opp(i))]; }, CS[n], N, n, rho0, Rd, rabs, sg);
+  float d[Q];
+  load_pops<STORE>(pops, N, n, rho0, Rd, d);
+  colour_sums(d, [&](int i) { return CS[nb(opp(i))]; }, CS[n], rho0, rabs, sg);
 }
 
 __host__ __device__ inline int wrapi(int a, int n) {

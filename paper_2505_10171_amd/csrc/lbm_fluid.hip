@@ -66,6 +66,9 @@ __host__ __device__ constexpr int pair_dir(int k) {
   return t[k];
 }
 
+// index of halo record j of thread t
+__device__ __forceinline__ int k_of(int t, int j) { return t + 256 * j; }
+
 // XCD-aware block order: consecutive dispatches go round-robin over the 8 XCDs;
 // give each XCD a contiguous range of blocks so that data shared by neighbouring
 // blocks (halo reads, pushed populations) meets in the same L2.
@@ -80,107 +83,121 @@ __device__ __forceinline__ int xcd_tile(int lin, int nblk) {
 // ------------------------------------------------------------- moments kernel
 // Density and order parameter phi = sum g / rho (order-parameter eq.) of every
 // fluid node of the post-stream state into rp[rd ^ 1], the colour populations
-// rebuilt from the state that collided (its colour sources).  Runs
-// after the refill, which has written the moments of the fresh nodes; clears
-// their FRESH mark.  Solid nodes get (rho0, PHI_SOLID), so that stencils can
-// tell solids from phi alone.  MOM_BOUNDARY (between steps, after the mask
-// changed with the populations in place): fluid nodes keep their moments.
-enum { MOM_STEP = 0, MOM_BOUNDARY = 1 };
-// Blocks of x-y tiles stage the colour sources of the tile grown by one node
-// in x, y and z in LDS (dynamic size (tx + 2)(ty + 2) 3 x 16 B); blocks of
-// consecutive nodes read them from global memory.
-template <int STORE, int MODE>
+// rebuilt from the state that collided (its colour sources).  Runs after the
+// refill, which has written the moments of the fresh nodes; clears their FRESH
+// mark.  Solid nodes get (rho0, PHI_SOLID), so that stencils can tell solids
+// from phi alone.
+//
+// A block takes an x-y tile of the simulation's moments tiling and marches up
+// MOM_KZ planes.  The colour sources of three planes of the tile grown by one
+// node sit in an LDS ring; the next plane's sources are loaded while the
+// current plane is summed.
+constexpr int MOM_HALO = 66 * 6;  // largest tile plane grown by one: (64 + 2)(4 + 2)
+template <int STORE>
 __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   using IO = Codec<STORE>;
   using T = typename IO::T;
-  extern __shared__ __attribute__((aligned(16))) char mom_smem[];
-  v4f* halo = (v4f*)mom_smem;
-  const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
+  __shared__ v4f ring[3][MOM_HALO];
+  const int2 sb = batch_block_in(bt, bt.mblk, blockIdx.x);
   const SimDev& s = bt.tab[sb.x];
   const int N = (int)s.N;
-  const int nx = s.nx, ny = s.ny, nz = s.nz;
+  const int nx = s.nx, ny = s.ny, nz = s.nz, P = nx * ny;
   if (sb.y == 0 && threadIdx.x == 0) s.counters[0] = 0u;  // fresh list consumed
   const GLB v4f* __restrict__ CS = gp((const v4f*)s.csrc);
-  const bool tiled = MODE == MOM_STEP && s.tile_x != 0;
-  int lx = 0, ly = 0, HX = 0, HY = 0, n, gx, gy, gz;
-  bool in;
-  if (tiled) {
-    const int tx = s.tile_x, ty = 256 >> s.tile_lx;
-    const int bx = sb.y % s.tiles_x, r = sb.y / s.tiles_x;
-    const int x0 = bx * tx, y0 = (r % s.tiles_y) * ty;
-    gz = r / s.tiles_y;
-    HX = tx + 2;
-    HY = ty + 2;
-    const int HP = HX * HY;
-    // every load of the halo in flight before the first LDS store (at most
-    // 3 (256 + 2) 3 = 2322 records: 10 per thread)
-    constexpr int KMAX = 10;
-    // (k + 1/2) / HP in FP32 is within 1e-6 of its value (k < 2^12), far from
-    // the next integer (>= 1 / (2 HP)): the floor is exact
-    const float iHP = 1.0f / (float)HP, iHX = 1.0f / (float)HX;
-    v4f hv[KMAX];
+  const GLB T* __restrict__ pops = gp((const T*)s.pops[bt.cur]);
+  const GLB float* __restrict__ RO = gp((const float*)s.rp[bt.rd]);
+  GLB float* __restrict__ RN = gp(s.rp[bt.rd ^ 1]);
+  GLB uint16_t* __restrict__ MASK = gp(s.mask);
+  const int tx = s.mtile_x, ty = 256 >> s.mtile_lx, HX = tx + 2, HY = ty + 2;
+  const int bx = sb.y % s.mtiles_x, r = sb.y / s.mtiles_x;
+  const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * MOM_KZ;
+  const int kz = min(MOM_KZ, nz - z0);
+  const int t = (int)threadIdx.x;
+  const int lx = t & (tx - 1), ly = t >> s.mtile_lx;
+  const int gx = bx * tx + lx, gy = by * ty + ly;
+  const bool in = gx < nx && gy < ny;
+  // this thread's halo records of a plane: t and t + 256 (a plane has at
+  // most 396); past a partial tile's end they are only kept in bounds
+  int hoff[2];
+  bool hon[2];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      const int k = (int)threadIdx.x + 256 * j;
-      if (k < 3 * HP) {
-        const int hz = (int)(((float)k + 0.5f) * iHP), rem = k - hz * HP;
-        const int hy = (int)(((float)rem + 0.5f) * iHX), hx = rem - hy * HX;
-        // periodic wrap of the halo; positions past a partial tile's end are
-        // never read and only kept in bounds
-        int x = x0 - 1 + hx, y = y0 - 1 + hy, z = gz - 1 + hz;
-        x = x < 0 ? x + nx : x;
-        x = x >= nx ? x - nx : x;
-        x = min(x, nx - 1);
-        y = y < 0 ? y + ny : y;
-        y = y >= ny ? y - ny : y;
-        y = min(y, ny - 1);
-        z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
-        hv[j] = CS[x + nx * (y + ny * z)];
+  for (int j = 0; j < 2; ++j) {
+    const int k = t + 256 * j;
+    hon[j] = k < HX * HY;
+    const int hy = k / HX, hx = k - hy * HX;
+    int x = bx * tx - 1 + hx, y = by * ty - 1 + hy;
+    x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    hoff[j] = hon[j] ? min(x, nx - 1) + nx * min(y, ny - 1) : 0;
+  }
+  auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+  // planes z0 - 1 and z0 into the ring
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz) {
+    const int zp = zwrap(z0 - 1 + dz);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (hon[j]) ring[(z0 + 2 + dz) % 3][k_of(t, j)] = CS[hoff[j] + P * zp];
+  }
+  // sources of plane z + 1 are loaded one plane ahead; the node's populations
+  // at the top of its plane, in flight across the barrier
+  v4f nxt[2];
+  auto fetch_sources = [&](int z) {
+    const int zp = zwrap(z + 1);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) nxt[j] = hon[j] ? CS[hoff[j] + P * zp] : v4f{0.f, 0.f, 0.f, 0.f};
+  };
+  fetch_sources(z0);
+  for (int zz = 0; zz < kz; ++zz) {
+    const int z = z0 + zz;
+    const int n = gx + nx * (gy + ny * z);
+    float d[Q];
+    uint16_t m = 0;
+    if (in) {
+      m = MASK[n];
+      load_pops<STORE>(pops, N, n, s.rho0, STORE ? RO[n] : 0.f, d);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (hon[j]) ring[(z + 1) % 3][k_of(t, j)] = nxt[j];
+    __syncthreads();
+    if (zz + 1 < kz) fetch_sources(z + 1);
+    if (in) {
+      const int c0 = (lx + 1) + HX * (ly + 1);
+      float rabs, sg;
+      colour_sums(
+          d, [&](int i) { return ring[(z + 3 - cz(i)) % 3][c0 - cx(i) - HX * cy(i)]; },
+          ring[z % 3][c0], s.rho0, rabs, sg);
+      if (m & FRESH_BIT) {  // refilled node: moments written by the refill
+        MASK[n] = (uint16_t)(m & ~FRESH_BIT);
+      } else if (m != 0) {
+        RN[n] = s.rho0;
+        RN[N + n] = PHI_SOLID;
+      } else {
+        RN[n] = rabs;
+        RN[N + n] = sg / rabs;
       }
     }
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      const int k = (int)threadIdx.x + 256 * j;
-      if (k < 3 * HP) halo[k] = hv[j];
-    }
     __syncthreads();
-    lx = (int)threadIdx.x & (tx - 1);
-    ly = (int)threadIdx.x >> s.tile_lx;
-    gx = x0 + lx;
-    gy = y0 + ly;
-    in = gx < nx && gy < ny;
-    n = gx + nx * (gy + ny * gz);
-  } else {
-    in = tile_node(s, sb.y, n, gx, gy, gz);
   }
-  if (!in) return;
-  GLB uint16_t* __restrict__ MASK = gp(s.mask);
-  GLB float* __restrict__ RN = gp(s.rp[bt.rd ^ 1]);
-  const uint16_t m = MASK[n];
-  // the sums are formed before the mask is examined, so that every load of
-  // the node is in flight at once (at solid and fresh nodes they go unused)
-  float rabs = 0.f, sg = 0.f;
-  if (MODE == MOM_STEP) {
-    const float Rd = STORE ? gp((const float*)s.rp[bt.rd])[n] : 0.f;
-    const GLB T* pops = gp((const T*)s.pops[bt.cur]);
-    if (tiled) {
-      const int c0 = (lx + 1) + HX * ((ly + 1) + HY);
-      rebuild_moments<STORE>(
-          pops, [&](int i) { return halo[c0 - cx(i) - HX * (cy(i) + HY * cz(i))]; }, halo[c0], N,
-          n, s.rho0, Rd, rabs, sg);
-    } else {
-      const Nbr nb(gx, gy, gz, nx, ny, nz);
-      rebuild_moments<STORE>(pops, CS, N, n, nb, s.rho0, Rd, rabs, sg);
-    }
-  }
-  if (m & FRESH_BIT) {  // refilled node: moments written by the refill
-    MASK[n] = (uint16_t)(m & ~FRESH_BIT);
+}
+
+// Between steps, after the mask changed with the populations in place (and
+// the refill of fresh nodes): solid nodes get (rho0, PHI_SOLID), fresh nodes
+// lose their mark, fluid nodes keep their moments.
+__global__ __launch_bounds__(256) void k_moments_boundary(Batch bt) {
+  const int2 sb = batch_block(bt, blockIdx.x);
+  const SimDev& s = bt.tab[sb.x];
+  int n, gx, gy, gz;
+  if (sb.y == 0 && threadIdx.x == 0) s.counters[0] = 0u;
+  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
+  const uint16_t m = s.mask[n];
+  if (m & FRESH_BIT) {
+    s.mask[n] = (uint16_t)(m & ~FRESH_BIT);
   } else if (m != 0) {
+    float* RN = s.rp[bt.rd ^ 1];
     RN[n] = s.rho0;
-    RN[N + n] = PHI_SOLID;
-  } else if (MODE == MOM_STEP) {
-    RN[n] = rabs;
-    RN[N + n] = sg / rabs;
+    RN[s.N + n] = PHI_SOLID;
   }
 }
 
@@ -248,13 +265,14 @@ enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 // ------------------------------------------------------ interface kernels
 // Colour gradient G = 3 sum_i w_i c_i phi(x + c_i) (isotropic stencil, the value
 // at x for solid neighbours), the geometric wetting rotation next to solids, and
-// the normal n = G / max(|G|, EPS_G); written as (n, |G|), and the node's
+// the normal n = G / max(|G|, EPS_G); written as the planes (n, |G|), and the node's
 // colour source (phi, r n), r = beta rho (1 - phi^2) / 2, for the moments pass.
 __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  GLB v4f* __restrict__ NRM = gp(s.nrm);
+  GLB float* __restrict__ NX = gp(s.nrm);
   GLB v4f* __restrict__ CS = gp(s.csrc);
+  const long long Nn = s.N;
   const GLB float* __restrict__ RHO = gp((const float*)s.rp[bt.rd ^ 1]);
   const GLB float* __restrict__ PHI = RHO + s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
@@ -307,7 +325,10 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
     const float r = 0.5f * s.beta * RHO[n] * (1.0f - p0) * (1.0f + p0);
     cs = v4f{p0, r * out.x, r * out.y, r * out.z};
   }
-  NRM[n] = out;
+  NX[n] = out.x;
+  NX[Nn + n] = out.y;
+  NX[2 * Nn + n] = out.z;
+  NX[3 * Nn + n] = out.w;
   CS[n] = cs;
 }
 
@@ -317,38 +338,58 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
 __global__ __launch_bounds__(256) void k_curv(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
-  // normals (n, |G|); NaN n at solid nodes
-  const GLB v4f* __restrict__ NRM = gp((const v4f*)s.nrm);
+  // normal planes: x, y, z components (NaN at solid nodes), then |G|
+  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
+  const GLB float* __restrict__ NY = NX + s.N;
+  const GLB float* __restrict__ NZ = NY + s.N;
+  const GLB float* __restrict__ NG = NZ + s.N;
   GLB float* __restrict__ cur = gp((float*)s.curv);
   const int nx = s.nx, ny = s.ny, nz = s.nz;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   float c = 0.f;
   uint32_t bits = 0x80000000u;
-  const v4f n0 = NRM[n];
-  // neighbour normals loaded before the node's own is examined
+  const float g0 = NG[n];
+  const float ncx = NX[n], ncy = NY[n], ncz = NZ[n];
+  // only the components c_i selects are loaded (a NaN marks a solid
+  // neighbour), all before the node's own value is examined
   const Nbr nb(gx, gy, gz, nx, ny, nz);
-  v4f npl[9], nml[9];
+  float P[9][3], M[9][3];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    npl[q] = NRM[nb(pair_dir(q))];
-    nml[q] = NRM[nb(opp(pair_dir(q)))];
+    const int i = pair_dir(q), mp = nb(i), mm = nb(opp(i));
+    P[q][0] = cx(i) != 0 ? NX[mp] : 0.f;
+    M[q][0] = cx(i) != 0 ? NX[mm] : 0.f;
+    P[q][1] = cy(i) != 0 ? NY[mp] : 0.f;
+    M[q][1] = cy(i) != 0 ? NY[mm] : 0.f;
+    P[q][2] = cz(i) != 0 ? NZ[mp] : 0.f;
+    M[q][2] = cz(i) != 0 ? NZ[mm] : 0.f;
   }
-  if (n0.w >= 0.f) {
+  if (g0 >= 0.f) {
     float kappa = 0.f;
     bits = 0u;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int i = pair_dir(q), o = opp(i);
-      v4f p = npl[q], m = nml[q];
-      const bool sp = p.x != p.x, sm = m.x != m.x;
-      if (sp) p = n0;
-      if (sm) m = n0;
+      float px = P[q][0], py = P[q][1], pz = P[q][2];
+      float mx = M[q][0], my = M[q][1], mz = M[q][2];
+      const bool sp = (px != px) | (py != py) | (pz != pz);
+      const bool sm = (mx != mx) | (my != my) | (mz != mz);
+      if (sp) {
+        px = ncx;
+        py = ncy;
+        pz = ncz;
+      }
+      if (sm) {
+        mx = ncx;
+        my = ncy;
+        mz = ncz;
+      }
       kappa += 3.0f * wq(i) *
-               ((float)cx(i) * (p.x - m.x) + (float)cy(i) * (p.y - m.y) + (float)cz(i) * (p.z - m.z));
+               ((float)cx(i) * (px - mx) + (float)cy(i) * (py - my) + (float)cz(i) * (pz - mz));
       bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
     }
-    c = -0.5f * s.sigma * kappa * fmaxf(n0.w, EPS_G);
+    c = -0.5f * s.sigma * kappa * fmaxf(g0, EPS_G);
   }
   cur[2 * n] = c;
   cur[2 * n + 1] = __uint_as_float(bits);
@@ -375,7 +416,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   const SimDev& s = bt.tab[sb.x];
   const GLB T* __restrict__ sp_ = gp((const T*)s.pops[bt.cur]);
   GLB T* __restrict__ dp_ = gp((T*)s.pops[bt.cur ^ 1]);
-  const GLB v4f* __restrict__ NRM = gp((const v4f*)s.nrm);
+  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
   const GLB float* __restrict__ cur = gp((const float*)s.curv);
   // moments of this state (rho, phi planes) and of the one before it; FP16
   // decodes with the latter's density and encodes with the former's
@@ -419,7 +460,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   const float Rn = STORE ? RP[n] : 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = IO::ld(sp_ + pidx(i, N, n), wq(i) * rho0, wq(i) * Rn);
-  const v4f nc = NRM[n];
+  const float3 nc = make_float3(NX[n], NX[N + n], NX[2 * N + n]);
   const float phi = RM[N + n];
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
@@ -670,17 +711,17 @@ hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipS
   return hipGetLastError();
 }
 
-// mode: MOM_STEP (in a step, after the refill) or MOM_BOUNDARY (between steps);
-// lds: dynamic LDS bytes, the largest tile halo of the batch (0 if none tiled)
-hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, int mode, size_t lds,
+// mode MOM_STEP (in a step, after the refill; mnblk blocks of the moments
+// tiling) or MOM_BOUNDARY (between steps; nblk per-node blocks)
+enum { MOM_STEP = 0, MOM_BOUNDARY = 1 };
+hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, unsigned mnblk, int mode,
                           hipStream_t st) {
-  const dim3 grid(nblk);
   if (mode == MOM_BOUNDARY)
-    hipLaunchKernelGGL((k_moments<0, MOM_BOUNDARY>), grid, dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_moments_boundary, dim3(nblk), dim3(256), 0, st, b);
   else if (storage == 0)
-    hipLaunchKernelGGL((k_moments<0, MOM_STEP>), grid, dim3(256), lds, st, b);
+    hipLaunchKernelGGL(k_moments<0>, dim3(mnblk), dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL((k_moments<1, MOM_STEP>), grid, dim3(256), lds, st, b);
+    hipLaunchKernelGGL(k_moments<1>, dim3(mnblk), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -230,11 +230,11 @@ __global__ void k_capbox(Batch bt) {
     const int x = wrapi(org[0] + ix, s.nx), y = wrapi(org[1] + iy, s.ny), z = wrapi(org[2] + iz, s.nz);
     const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
     float4 v = make_float4(2.f, 0.f, 0.f, 0.f);  // phi = 2 marks a solid node
-    const v4f nr = s.nrm[n];
-    if (nr.w >= 0.f) {
+    const float gw = s.nrm[3 * s.N + n];
+    if (gw >= 0.f) {
       // G = n max(|G|, EPS_G): the colour gradient after the wetting rotation
-      const float gm = fmaxf(nr.w, EPS_G);
-      v = make_float4(PHI[n], nr.x * gm, nr.y * gm, nr.z * gm);
+      const float gm = fmaxf(gw, EPS_G);
+      v = make_float4(PHI[n], s.nrm[n] * gm, s.nrm[s.N + n] * gm, s.nrm[2 * s.N + n] * gm);
     }
     box[k] = v;
   }
