@@ -70,10 +70,12 @@ enum lbm_field_bits {
   LBM_F_U = 2u,    /* velocity with half the force (velocity eq.)   (float) */
   LBM_F_PHI = 4u,  /* order parameter (order-parameter eq.)         (float) */
   LBM_F_MASK = 8u, /* solid mask                                 (uint16_t) */
-  LBM_F_POPS = 16u, /* raw stored populations: 19 planes of N values in the
-                       storage type.  FP32: f - w rho0.  FP16: the encoded h
-                       of LBM_STORE_FP16 (the reference densities are
-                       internal)                                           */
+  LBM_F_POPS = 16u, /* raw stored populations, 19 per node in the storage
+                       type, in blocks of 64 nodes: value i of node n at
+                       (n / 64) 19 64 + 64 i + n % 64, the last block padded
+                       (19 ceil(N / 64) 64 values).  FP32: f - w rho0.
+                       FP16: the encoded h of LBM_STORE_FP16 (the reference
+                       densities are internal)                             */
   LBM_F_FORCE = 32u  /* force per volume: CSF surface tension (CSF eq.) plus
                        the body force on fluid a                    (float) */
 };
@@ -81,7 +83,7 @@ enum lbm_field_bits {
 /* One simulation, in lattice units.  Defaults in brackets follow the paper's
  * parameter table. */
 typedef struct {
-  int32_t nx, ny, nz;   /* lattice size; nz >= 3, 19 nx ny nz < 2^32        */
+  int32_t nx, ny, nz;   /* lattice size; nz >= 3, 19 (nx ny nz + 63) < 2^32 */
   int32_t has_wall;     /* 1: node plane z = 0 is a solid wall [1]           */
   double rho0;          /* reference density [0.05]                          */
   double tau_a, tau_b;  /* relaxation times of fluids a and b (> 1/2) [1, 1] */
@@ -158,7 +160,7 @@ int lbm_particles_sync(lbm_ctx* ctx, int32_t sim, int32_t dir, lbm_particle* par
                        double* history, int32_t max_steps, int32_t* n_hist);
 
 /* Copy fields of simulation sim (bits of lbm_field_bits).  rho, phi: N floats;
- * u: 3N floats; mask: N uint16; pops: 19N values of the storage type.  Solid
+ * u: 3N floats; mask: N uint16; pops: 19 ceil(N/64) 64 values of the storage type.  Solid
  * nodes report rho = phi = 0 and u = the solid's surface velocity.  Buffers are
  * host memory unless dst_is_device.  Synchronous. */
 int lbm_fields(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, float* phi,

@@ -73,8 +73,8 @@ bool valid_config(const lbm_config& c, char* msg, size_t len) {
     return false;
   };
   if (c.nx < 1 || c.ny < 1 || c.nz < 3) return fail("lattice must be nx, ny >= 1 and nz >= 3");
-  // population offsets are 32-bit: 19 planes of N values
-  if ((long long)c.nx * c.ny * c.nz * 19 > 0xFFFFFFFFll) return fail("lattice too large");
+  // population offsets are 32-bit: 19 values per node (padded to 64 nodes)
+  if (((long long)c.nx * c.ny * c.nz + 63) * 19 > 0xFFFFFFFFll) return fail("lattice too large");
   if (!(c.rho0 > 0.0)) return fail("rho0 must be positive");
   if (!(c.tau_a > 0.5) || !(c.tau_b > 0.5)) return fail("relaxation times must exceed 1/2");
   if (!(c.sigma >= 0.0) || !(c.beta >= 0.0)) return fail("sigma and beta must be >= 0");
@@ -118,7 +118,9 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   L.Bmask = (int)ceil(2.0 * Rmax) + 4;
   L.Bcap = (int)ceil(2.0 * Rmax) + 3;
   L.hist_cap = L.np > 0 ? hist_cap : 0;
-  L.pop_bytes = (size_t)19 * L.N * (c.storage == LBM_STORE_FP16 ? 2 : 4);
+  // populations in blocks of 64 nodes (the last one padded)
+  L.pop_bytes = (size_t)19 * ((L.N + POP_BLOCK - 1) / POP_BLOCK * POP_BLOCK) *
+                (c.storage == LBM_STORE_FP16 ? 2 : 4);
   L.fresh_cap = L.np > 0 ? (size_t)L.np * L.Bmask * L.Bmask * L.Bmask : 0;
   size_t o = align_up(base);
   auto take = [&](size_t bytes) {

@@ -1,8 +1,9 @@
 // lbm_fluid.hip -- lattice kernels of liblbm for gfx950.
 //
-// Storage: structure-of-arrays populations, 19 planes of N values of the total
-// f, x-fastest; the colour is carried by the per-node order parameter and the
-// colour populations are rebuilt by the moments pass (see rebuild_moments).
+// Storage: the 19 total populations f of each node, in blocks of 64 nodes (19
+// runs of 64 values; see pidx).  The colour is carried by the per-node order
+// parameter; the colour populations are rebuilt by the moments pass (see
+// rebuild_moments).
 // FP32 storage keeps the deviation d_i = f_i - w_i rho0 (so that the small
 // velocity survives FP32 rounding); FP16 storage keeps
 // h_i = (f_i - w_i R) / (w_i rho0) with R the node's density of the previous
@@ -222,7 +223,7 @@ __global__ void k_init_pops(SimDev s, void* pops) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float wr0 = wq(i) * s.rho0;
-    IO::st(b + (long long)i * s.N + n, wr0, 1.0f / wr0, wr0, 0.f);
+    IO::st(b + pidx(i, (int)s.N, (int)n), wr0, 1.0f / wr0, wr0, 0.f);
   }
   const float p0 = (s.mask[n] == 0) ? s.rp[0][s.N + n] : PHI_SOLID;
   for (int k = 0; k < 2; ++k) {

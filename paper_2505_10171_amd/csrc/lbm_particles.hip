@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
         const float cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
         const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
         const float dq = wq(q) * ((rho - s.rho0) + rho * poly);
-        IO::st(b + (long long)q * N + n, wq(q) * s.rho0, 1.0f / (wq(q) * s.rho0), wq(q) * Rn, dq);
+        IO::st(b + pidx(q, N, n), wq(q) * s.rho0, 1.0f / (wq(q) * s.rho0), wq(q) * Rn, dq);
       }
       // f^a - f^b = (ra - rb) / rho f: the order parameter of the node
       RN[n] = rho;

@@ -284,10 +284,12 @@ class Context:
         c = self._cfg[sim]
         N = c.nx * c.ny * c.nz
         dt = np.float16 if c.storage == LBM_STORE_FP16 else np.float32
-        out = np.zeros(19 * N, dt)
+        Np = (N + 63) // 64 * 64
+        out = np.zeros(19 * Np, dt)
         self._check(load_library().lbm_fields(self.h, sim, LBM_F_POPS, None, None, None, None,
                                               out.ctypes.data, 0))
-        return out.reshape(19, N)
+        # blocks of 64 nodes, 19 runs of 64 values each -> 19 planes of N
+        return out.reshape(Np // 64, 19, 64).transpose(1, 0, 2).reshape(19, Np)[:, :N]
 
     def links(self, sim: int = 0):
         L = load_library()
