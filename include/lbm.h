@@ -197,12 +197,14 @@ int lbm_profile(lbm_ctx* ctx, int32_t enable);
 int lbm_profile_read(lbm_ctx* ctx, double* total_ms, int64_t* launches, int32_t n_kinds);
 
 /* Block-shape autotuner for the per-node kernels (256 threads per block: 256
- * consecutive nodes, or x-y tiles of 256 x 1 .. 16 x 16 nodes).  For each box
- * class of the context it times `reps` passes of the per-node kernels with
- * every shape on the current state (which it leaves unchanged) and keeps the
- * fastest; results are identical with any shape.  chosen (nullable, one per
- * simulation) receives the tile width (0 = consecutive nodes).  Choices are
- * cached in the process per (GPU architecture, box size, storage). */
+ * consecutive nodes, or x-y tiles of 256 x 1 .. 16 x 16 nodes; the moments pass
+ * keeps its own tiling).  For each box class of the context it times `reps`
+ * passes of the per-node kernels with every shape on the current state and
+ * keeps the fastest; results are identical with any shape.  The state is left
+ * unchanged: the moments the timing rewrites (8 bytes per node) are kept in
+ * host memory meanwhile.  chosen (nullable, one per simulation) receives the
+ * tile width (0 = consecutive nodes).  Choices are cached in the process per
+ * (GPU architecture, box size, storage).  Synchronous. */
 int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen);
 
 /* Set the block shape of one simulation by hand (tile width 0, 16, 32, 64,

@@ -715,16 +715,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
   const int n_sims = (int)ctx->sims.size();
-  struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    void release() {
-      if (p) (void)hipFree(p);
-      p = nullptr;
-      bytes = 0;
-    }
-    ~DevBuf() { release(); }
-  } save;
+  std::vector<float> save;  // host copy of the moments the timing rewrites
   int rc = LBM_OK;
   for (int si = 0; si < n_sims && rc == LBM_OK; ++si) {
     SimDev& d = ctx->sims[si].d;
@@ -734,16 +725,13 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
     for (auto& kv : cache)
       if (kv.first == key) best = kv.second;
     if (best < 0) {
-      // the timed moments pass rewrites the current moments: kept aside and
-      // put back afterwards
+      // the timed moments pass rewrites the current moments: kept aside in
+      // host memory (the library allocates no device memory) and put back
       const size_t rp_bytes = 8 * (size_t)d.N;
-      if (save.bytes < rp_bytes) {
-        save.release();
-        HIPCHK(ctx, hipMalloc(&save.p, rp_bytes));
-        save.bytes = rp_bytes;
-      }
+      save.resize(2 * (size_t)d.N);
       float* rp_cur = d.rp[ctx->rd ^ 1];
-      HIPCHK(ctx, hipMemcpyAsync(save.p, rp_cur, rp_bytes, hipMemcpyDeviceToDevice, st));
+      HIPCHK(ctx, hipMemcpyAsync(save.data(), rp_cur, rp_bytes, hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
       float best_ms = 1e30f;
       for (int c : cand) {
         if (c > 0 && c > 2 * d.nx) continue;  // over half the tile idle
@@ -766,7 +754,8 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
           best = c;
         }
       }
-      HIPCHK(ctx, hipMemcpyAsync(rp_cur, save.p, rp_bytes, hipMemcpyDeviceToDevice, st));
+      HIPCHK(ctx, hipMemcpyAsync(rp_cur, save.data(), rp_bytes, hipMemcpyHostToDevice, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
       cache.emplace_back(key, best);
     }
     set_tile(d, best);
@@ -775,7 +764,6 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  HIPCHK(ctx, hipStreamSynchronize(st));  // before the saved copy is freed
   return upload_tables(ctx, 0);
 }
 
