@@ -56,7 +56,7 @@ struct SimLayout {
   long long N;
   int np, Bmask, Bcap, hist_cap;
   size_t pop_bytes, fresh_cap;
-  size_t off_pops0, off_pops1, off_rp0, off_rp1, off_nrm, off_csrc, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
+  size_t off_pops0, off_pops1, off_rp0, off_rp1, off_nrm, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
       off_counters, off_P, off_ct, off_nb, off_hist, off_capbox, off_caporg, off_mass, off_step;
   size_t total;
 };
@@ -134,7 +134,6 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   L.off_rp0 = take(8 * L.N);
   L.off_rp1 = take(8 * L.N);
   L.off_nrm = take(16 * L.N);
-  L.off_csrc = take(16 * L.N);
   L.off_cur = take(8 * L.N);
   L.off_mask = take(2 * L.N);
   L.off_claim = take(4 * L.N);
@@ -478,7 +477,6 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.rp[0] = (float*)(b + sh.L.off_rp0);
     d.rp[1] = (float*)(b + sh.L.off_rp1);
     d.nrm = (float*)(b + sh.L.off_nrm);
-    d.csrc = (v4f*)(b + sh.L.off_csrc);
     d.curv = (float2*)(b + sh.L.off_cur);
     d.mask = (uint16_t*)(b + sh.L.off_mask);
     d.claim = (uint32_t*)(b + sh.L.off_claim);

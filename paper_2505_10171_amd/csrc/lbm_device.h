@@ -154,9 +154,7 @@ struct SimDev {
   // to the state before it (the FP16 reference of pops[cur])
   float* rp[2];
   float* nrm;          // 4 planes of N: n_x, n_y, n_z (NaN at solids), |G| (-1 at solids)
-  // per node colour source of the state about to collide: (phi, r n_x, r n_y,
-  // r n_z) with r = beta rho (1 - phi^2) / 2; NaN in r n at solids
-  v4f* csrc;
+
   float2* curv;        // per node (CSF coefficient, solid-neighbour bits as float)
   uint16_t* mask;      // 0 fluid, 1 wall, 2+p particle p; FRESH_BIT while refilling
   uint32_t* claim;     // per node: lowest particle claiming it in the new mask, ~0u none
@@ -344,14 +342,26 @@ __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v
   }
 }
 
-// both, with the colour sources read from the global array CS
+// Colour source (phi, r n_x, r n_y, r n_z) of node m of the state that
+// collided, r = beta rho (1 - phi^2) / 2, from its moments RO (rho plane, phi
+// plane) and normal planes NX; NaN in r n at a solid node (its normal is NaN).
+__device__ __forceinline__ v4f colour_source(const GLB float* RO, const GLB float* NX, int N,
+                                             int m, float hb) {
+  const float rho = RO[m], phi = RO[N + m];
+  const float r = hb * rho * (1.0f - phi) * (1.0f + phi);
+  return v4f{phi, r * NX[m], r * NX[N + m], r * NX[2 * N + m]};
+}
+
+// both, for one node, with the colour sources read from the global planes
 template <int STORE, class PT>
-__device__ __forceinline__ void rebuild_moments(PT pops, const GLB v4f* CS, int N, int n,
-                                                const Nbr& nb, float rho0, float Rd, float& rabs,
-                                                float& sg) {
+__device__ __forceinline__ void rebuild_moments(PT pops, const GLB float* RO, const GLB float* NX,
+                                                int N, int n, const Nbr& nb, float rho0, float hb,
+                                                float Rd, float& rabs, float& sg) {
   float d[Q];
   load_pops<STORE>(pops, N, n, rho0, Rd, d);
-  colour_sums(d, [&](int i) { return CS[nb(opp(i))]; }, CS[n], rho0, rabs, sg);
+  colour_sums(
+      d, [&](int i) { return colour_source(RO, NX, N, nb(opp(i)), hb); },
+      colour_source(RO, NX, N, n, hb), rho0, rabs, sg);
 }
 
 __host__ __device__ inline int wrapi(int a, int n) {

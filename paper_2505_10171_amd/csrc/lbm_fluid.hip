@@ -84,7 +84,8 @@ __device__ __forceinline__ int xcd_tile(int lin, int nblk) {
 // ------------------------------------------------------------- moments kernel
 // Density and order parameter phi = sum g / rho (order-parameter eq.) of every
 // fluid node of the post-stream state into rp[rd ^ 1], the colour populations
-// rebuilt from the state that collided (its colour sources).  Runs after the
+// rebuilt from the state that collided (the colour source (phi, r n) of each
+// node, formed from its moments and normal).  Runs after the
 // refill, which has written the moments of the fresh nodes; clears their FRESH
 // mark.  Solid nodes get (rho0, PHI_SOLID), so that stencils can tell solids
 // from phi alone.
@@ -104,7 +105,8 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   const int N = (int)s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz, P = nx * ny;
   if (sb.y == 0 && threadIdx.x == 0) s.counters[0] = 0u;  // fresh list consumed
-  const GLB v4f* __restrict__ CS = gp((const v4f*)s.csrc);
+  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
+  const float hb = 0.5f * s.beta;
   const GLB T* __restrict__ pops = gp((const T*)s.pops[bt.cur]);
   const GLB float* __restrict__ RO = gp((const float*)s.rp[bt.rd]);
   GLB float* __restrict__ RN = gp(s.rp[bt.rd ^ 1]);
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
     const int zp = zwrap(z0 - 1 + dz);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      if (hon[j]) ring[(z0 + 2 + dz) % 3][k_of(t, j)] = CS[hoff[j] + P * zp];
+      if (hon[j]) ring[(z0 + 2 + dz) % 3][k_of(t, j)] = colour_source(RO, NX, N, hoff[j] + P * zp, hb);
   }
   // sources of plane z + 1 are loaded one plane ahead; the node's populations
   // at the top of its plane, in flight across the barrier
@@ -146,7 +148,8 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   auto fetch_sources = [&](int z) {
     const int zp = zwrap(z + 1);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) nxt[j] = hon[j] ? CS[hoff[j] + P * zp] : v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j)
+      nxt[j] = hon[j] ? colour_source(RO, NX, N, hoff[j] + P * zp, hb) : v4f{0.f, 0.f, 0.f, 0.f};
   };
   fetch_sources(z0);
   for (int zz = 0; zz < kz; ++zz) {
@@ -266,23 +269,19 @@ enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 // ------------------------------------------------------ interface kernels
 // Colour gradient G = 3 sum_i w_i c_i phi(x + c_i) (isotropic stencil, the value
 // at x for solid neighbours), the geometric wetting rotation next to solids, and
-// the normal n = G / max(|G|, EPS_G); written as the planes (n, |G|), and the node's
-// colour source (phi, r n), r = beta rho (1 - phi^2) / 2, for the moments pass.
+// the normal n = G / max(|G|, EPS_G); written as the planes (n, |G|).
 __global__ __launch_bounds__(256) void k_normal(Batch bt) {
   const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
   const SimDev& s = bt.tab[sb.x];
   GLB float* __restrict__ NX = gp(s.nrm);
-  GLB v4f* __restrict__ CS = gp(s.csrc);
   const long long Nn = s.N;
-  const GLB float* __restrict__ RHO = gp((const float*)s.rp[bt.rd ^ 1]);
-  const GLB float* __restrict__ PHI = RHO + s.N;
+  const GLB float* __restrict__ PHI = gp((const float*)s.rp[bt.rd ^ 1]) + s.N;
   const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
   int n, gx, gy, gz;
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   // solid node: NaN normal (tells stencils the neighbour is solid) and |G| = -1
   const float qnan = __int_as_float(0x7fc00000);
   v4f out = {qnan, qnan, qnan, -1.0f};
-  v4f cs = {PHI_SOLID, qnan, qnan, qnan};
   const float p0 = PHI[n];
   // neighbour values loaded before the node's own is examined
   const Nbr nb(gx, gy, gz, nx, ny, nz);
@@ -323,14 +322,11 @@ __global__ __launch_bounds__(256) void k_normal(Batch bt) {
     const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
     const float ig = 1.0f / fmaxf(g, EPS_G);
     out = v4f{Gx * ig, Gy * ig, Gz * ig, g};
-    const float r = 0.5f * s.beta * RHO[n] * (1.0f - p0) * (1.0f + p0);
-    cs = v4f{p0, r * out.x, r * out.y, r * out.z};
   }
   NX[n] = out.x;
   NX[Nn + n] = out.y;
   NX[2 * Nn + n] = out.z;
   NX[3 * Nn + n] = out.w;
-  CS[n] = cs;
 }
 
 // Curvature kappa = div n (same stencil and closure) and the CSF coefficient

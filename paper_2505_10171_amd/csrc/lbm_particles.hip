@@ -154,8 +154,8 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
           float rho, sg;
           if (MODE == REFILL_STEP) {
             const Nbr nbm(mx, my, mz, s.nx, s.ny, s.nz);
-            rebuild_moments<STORE>(gp((const T*)b), gp((const v4f*)s.csrc), N, m, nbm, s.rho0,
-                                   STORE ? RO[m] : 0.f, rho, sg);
+            rebuild_moments<STORE>(gp((const T*)b), RO, gp((const float*)s.nrm), N, m, nbm,
+                                   s.rho0, 0.5f * s.beta, STORE ? RO[m] : 0.f, rho, sg);
           } else {
             rho = RN[m];
             sg = rho * RN[N + m];

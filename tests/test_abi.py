@@ -87,11 +87,11 @@ def test_workspace_sizing_and_validation():
     c = (lbm.LbmConfig * 1)(lbm.make_config(cfg, 0))
     nb = L.lbm_workspace_bytes(c, 1, None, 0)
     N = 64 * 32 * 16
-    # per node besides the two 19-plane population buffers: moments (rho, phi)
-    # of two states 16 B, interface normal 16 B, colour source 16 B, curvature
-    # term + solid-link bits 8 B, mask 2 B, claim 4 B
-    assert nb >= 2 * 19 * 4 * N + 62 * N
-    assert nb < 2 * 19 * 4 * N + 64 * N + 4096
+    # per node besides the two population buffers (19 values per node, padded
+    # to 64 nodes): moments (rho, phi) of two states 16 B, interface normal
+    # 16 B, curvature term + solid-link bits 8 B, mask 2 B, claim 4 B
+    assert nb >= 2 * 19 * 4 * N + 46 * N
+    assert nb < 2 * 19 * 4 * N + 48 * N + 64 * 19 * 4 * 2 + 4096
     bad = dict(cfg, tau_a=0.5)
     c = (lbm.LbmConfig * 1)(lbm.make_config(bad, 0))
     assert L.lbm_workspace_bytes(c, 1, None, 0) == 0
@@ -100,7 +100,7 @@ def test_workspace_sizing_and_validation():
     assert L.lbm_workspace_bytes(c, 1, None, 0) == 0
     # FP16 storage halves the population bytes
     c16 = (lbm.LbmConfig * 1)(lbm.make_config(dict(cfg, storage="fp16"), 0))
-    assert L.lbm_workspace_bytes(c16, 1, None, 0) < 0.5 * (nb - 62 * N) + 64 * N + 4096
+    assert L.lbm_workspace_bytes(c16, 1, None, 0) < 0.5 * (nb - 46 * N) + 48 * N + 4096
 
 
 def test_error_paths_without_gpu():
