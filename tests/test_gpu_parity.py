@@ -84,6 +84,20 @@ def test_drop_ragged_lattice_no_particles():
     _compare_fields(g, o, label="ragged 37x29x23")
 
 
+@pytest.mark.parametrize("shape", [(10, 6, 5), (12, 3, 7), (70, 9, 9)])
+def test_tiny_and_partial_boxes(shape):
+    """Boxes narrower than every block tile (x < 16, y < 4), a z extent that
+    leaves a partial plane march, and an x extent one past the widest tile."""
+    nx, ny, nz = shape
+    cfg = W.config(nx, ny, nz, theta_wall_deg=70.0, sigma=0.01, body_force=(3e-6, 0.0, 0.0))
+    phi0 = W.drop_phi0(nx, ny, nz, (0.45 * nx, 0.5 * ny, 0.5), 0.4 * min(nx, 2 * nz))
+    g = _gpu(cfg, phi0, [])
+    o = OracleSim(cfg, phi0, [])
+    g.step(40)
+    o.step(40)
+    _compare_fields(g, o, label=f"box {shape}")
+
+
 def test_drop_free_periodic():
     cfg = W.config(24, 20, 28, has_wall=0, sigma=0.01, tau_a=0.8, tau_b=1.4)
     phi0 = W.drop_phi0(24, 20, 28, (11.5, 9.5, 13.5), 7.0)
