@@ -24,7 +24,7 @@
 #include "lbm_device.h"
 
 namespace lbm {
-hipError_t launch_interface(const Batch& b, unsigned nblk, hipStream_t st);
+hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipStream_t st);
 hipError_t launch_fused(const Batch& b, int storage, unsigned nblk, int mode, float* orho,
                         float* ou, float* ophi, float* oF, hipStream_t st);
 hipError_t launch_links(const Batch& b, int storage, int np_rows, int Bmax, hipStream_t st);
@@ -593,7 +593,7 @@ static int step_once(lbm_ctx* ctx, int slot) {
   hipStream_t st = ctx->stream;
   const Batch b = batch_all(ctx);
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][0], st));
-  HIPCHK(ctx, launch_interface(b, ctx->nblk, st));
+  HIPCHK(ctx, launch_interface(b, ctx->nblk, ctx->mnblk, st));
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][1], st));
   HIPCHK(ctx, launch_fused(b, ctx->storage, ctx->nblk, 0, nullptr, nullptr, nullptr, nullptr, st));
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], st));
@@ -740,7 +740,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
         float ms = 0.f;
         for (int r = 0; r <= reps; ++r) {  // the first pass warms up
           if (r == 1) HIPCHK(ctx, hipEventRecord(e0, st));
-          HIPCHK(ctx, launch_interface(b1, nb, st));
+          HIPCHK(ctx, launch_interface(b1, nb, mom_blocks(d), st));
           HIPCHK(ctx, launch_fused(b1, ctx->storage, nb, 0, nullptr, nullptr, nullptr, nullptr, st));
           HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, mom_blocks(d), MOM_STEP, st));
         }
@@ -963,7 +963,7 @@ int lbm_fields2(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, 
     float* ou = scratch + 2 * N;
     float* oF = scratch + 5 * N;
     const Batch b1 = batch_one(ctx, sim);
-    HIPCHK(ctx, launch_interface(b1, sim_blocks(d), ctx->stream));
+    HIPCHK(ctx, launch_interface(b1, sim_blocks(d), mom_blocks(d), ctx->stream));
     HIPCHK(ctx, launch_fused(b1, ctx->storage, sim_blocks(d), 1, orho, ou, ophi, oF, ctx->stream));
     if ((what & LBM_F_FORCE) && force)
       HIPCHK(ctx, hipMemcpyAsync(force, oF, 12 * N, kind, ctx->stream));

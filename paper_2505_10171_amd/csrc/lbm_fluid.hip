@@ -271,62 +271,104 @@ enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 // at x for solid neighbours), the geometric wetting rotation next to solids, and
 // the normal n = G / max(|G|, EPS_G); written as the planes (n, |G|).
 __global__ __launch_bounds__(256) void k_normal(Batch bt) {
-  const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
+  // blocks follow the moments tiling: an x-y tile marching MOM_KZ planes, phi
+  // of three planes of the tile grown by one node in an LDS ring
+  __shared__ float ring[3][MOM_HALO];
+  const int2 sb = batch_block_in(bt, bt.mblk, blockIdx.x);
   const SimDev& s = bt.tab[sb.x];
   GLB float* __restrict__ NX = gp(s.nrm);
-  const long long Nn = s.N;
+  const int N = (int)s.N;
   const GLB float* __restrict__ PHI = gp((const float*)s.rp[bt.rd ^ 1]) + s.N;
-  const int nx = s.nx, ny = s.ny, nz = s.nz, nxny = nx * ny;
-  int n, gx, gy, gz;
-  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
-  // solid node: NaN normal (tells stencils the neighbour is solid) and |G| = -1
+  const int nx = s.nx, ny = s.ny, nz = s.nz, P = nx * ny;
+  const int tx = s.mtile_x, ty = 256 >> s.mtile_lx, HX = tx + 2, HY = ty + 2;
+  const int bx = sb.y % s.mtiles_x, r = sb.y / s.mtiles_x;
+  const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * MOM_KZ;
+  const int kz = min(MOM_KZ, nz - z0);
+  const int t = (int)threadIdx.x;
+  const int lx = t & (tx - 1), ly = t >> s.mtile_lx;
+  const int gx = bx * tx + lx, gy = by * ty + ly;
+  const bool in = gx < nx && gy < ny;
+  int hoff[2];
+  bool hon[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int k = t + 256 * j;
+    hon[j] = k < HX * HY;
+    const int hy = k / HX, hx = k - hy * HX;
+    int x = bx * tx - 1 + hx, y = by * ty - 1 + hy;
+    x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    hoff[j] = hon[j] ? min(x, nx - 1) + nx * min(y, ny - 1) : 0;
+  }
+  auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz) {
+    const int zp = zwrap(z0 - 1 + dz);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (hon[j]) ring[(z0 + 2 + dz) % 3][k_of(t, j)] = PHI[hoff[j] + P * zp];
+  }
+  float nxt[2];
+  auto fetch = [&](int z) {
+    const int zp = zwrap(z + 1);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) nxt[j] = hon[j] ? PHI[hoff[j] + P * zp] : 0.f;
+  };
+  fetch(z0);
   const float qnan = __int_as_float(0x7fc00000);
-  v4f out = {qnan, qnan, qnan, -1.0f};
-  const float p0 = PHI[n];
-  // neighbour values loaded before the node's own is examined
-  const Nbr nb(gx, gy, gz, nx, ny, nz);
-  float vpl[9], vml[9];
+  for (int zz = 0; zz < kz; ++zz) {
+    const int z = z0 + zz;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    vpl[q] = PHI[nb(pair_dir(q))];
-    vml[q] = PHI[nb(opp(pair_dir(q)))];
-  }
-  if (p0 < PHI_SOLID_TEST) {
-    float Gx = 0.f, Gy = 0.f, Gz = 0.f;
-    bool solid = false;
+    for (int j = 0; j < 2; ++j)
+      if (hon[j]) ring[(z + 1) % 3][k_of(t, j)] = nxt[j];
+    __syncthreads();
+    if (zz + 1 < kz) fetch(z + 1);
+    if (in) {
+      const int c0 = (lx + 1) + HX * (ly + 1);
+      const int n = gx + nx * (gy + ny * z);
+      // solid node: NaN normal (tells stencils the neighbour is solid), |G| = -1
+      v4f out = {qnan, qnan, qnan, -1.0f};
+      const float p0 = ring[z % 3][c0];
+      if (p0 < PHI_SOLID_TEST) {
+        float Gx = 0.f, Gy = 0.f, Gz = 0.f;
+        bool solid = false;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const int i = pair_dir(q);
-      float vp = vpl[q];
-      float vm = vml[q];
-      const bool sp = vp > PHI_SOLID_TEST, sm = vm > PHI_SOLID_TEST;
-      solid |= sp | sm;
-      vp = sp ? p0 : vp;
-      vm = sm ? p0 : vm;
-      const float d = 3.0f * wq(i) * (vp - vm);
-      Gx += (float)cx(i) * d;
-      Gy += (float)cy(i) * d;
-      Gz += (float)cz(i) * d;
-    }
-    if (solid) {
-      // identify the solid: the lowest-index neighbouring particle, else the wall
-      int minp = 0x7fffffff;
-      bool wall = false;
-      for (int i = 1; i < Q; ++i) {
-        const uint16_t m = s.mask[nb(i)];
-        if (m >= 2) minp = min(minp, (int)m - 2);
-        else if (m == 1) wall = true;
+        for (int q = 0; q < 9; ++q) {
+          const int i = pair_dir(q);
+          float vp = ring[(z + 3 + cz(i)) % 3][c0 + cx(i) + HX * cy(i)];
+          float vm = ring[(z + 3 - cz(i)) % 3][c0 - cx(i) - HX * cy(i)];
+          const bool sp = vp > PHI_SOLID_TEST, sm = vm > PHI_SOLID_TEST;
+          solid |= sp | sm;
+          vp = sp ? p0 : vp;
+          vm = sm ? p0 : vm;
+          const float d = 3.0f * wq(i) * (vp - vm);
+          Gx += (float)cx(i) * d;
+          Gy += (float)cy(i) * d;
+          Gz += (float)cz(i) * d;
+        }
+        if (solid) {
+          // identify the solid: the lowest-index neighbouring particle, else the wall
+          const Nbr nb(gx, gy, z, nx, ny, nz);
+          int minp = 0x7fffffff;
+          bool wall = false;
+          for (int i = 1; i < Q; ++i) {
+            const uint16_t m = s.mask[nb(i)];
+            if (m >= 2) minp = min(minp, (int)m - 2);
+            else if (m == 1) wall = true;
+          }
+          wetting_rotate(s, gx, gy, z, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
+        }
+        const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
+        const float ig = 1.0f / fmaxf(g, EPS_G);
+        out = v4f{Gx * ig, Gy * ig, Gz * ig, g};
       }
-      wetting_rotate(s, gx, gy, gz, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
+      NX[n] = out.x;
+      NX[N + n] = out.y;
+      NX[2 * N + n] = out.z;
+      NX[3 * N + n] = out.w;
     }
-    const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
-    const float ig = 1.0f / fmaxf(g, EPS_G);
-    out = v4f{Gx * ig, Gy * ig, Gz * ig, g};
+    __syncthreads();
   }
-  NX[n] = out.x;
-  NX[Nn + n] = out.y;
-  NX[2 * Nn + n] = out.z;
-  NX[3 * Nn + n] = out.w;
 }
 
 // Curvature kappa = div n (same stencil and closure) and the CSF coefficient
@@ -671,8 +713,9 @@ static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 
 // Batched launchers: one launch over every simulation of the batch.
 // nblk: total 256-node blocks; np_rows: total particle rows; Bmax: the largest
 // mask-box side of the batch.
-hipError_t launch_interface(const Batch& b, unsigned nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_normal, dim3(nblk), dim3(256), 0, st, b);
+// nblk: per-node blocks; mnblk: blocks of the moments tiling (k_normal)
+hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_normal, dim3(mnblk), dim3(256), 0, st, b);
   hipLaunchKernelGGL(k_curv, dim3(nblk), dim3(256), 0, st, b);
   return hipGetLastError();
 }
