@@ -460,6 +460,27 @@ __device__ void quat_rotate(double* q, const double* th) {
   for (int k = 0; k < 4; ++k) q[k] = r[k] / nq;
 }
 
+// dst[0, n) = src[0, n) by the whole workgroup, eight loads per thread issued
+// before their stores (one memory round trip per 8 blockDim values, not one per
+// value)
+__device__ __forceinline__ void stage_in(double* dst, const double* src, size_t n) {
+  constexpr int U = 8;
+  const size_t nt = blockDim.x;
+  for (size_t base = 0; base < n; base += U * nt) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t k = base + u * nt + threadIdx.x;
+      v[u] = k < n ? src[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t k = base + u * nt + threadIdx.x;
+      if (k < n) dst[k] = v[u];
+    }
+  }
+}
+
 // One workgroup per simulation.  Fluid forces (momentum exchange + capillary)
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
@@ -483,8 +504,9 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
     PP = (DevParticle*)lp;
     CT = (Contact*)lc;
     NB = (int*)(lc + wC);
-    for (size_t k = threadIdx.x; k < wP; k += blockDim.x) lp[k] = ((const double*)s.P)[k];
-    for (size_t k = threadIdx.x; k < wC; k += blockDim.x) lc[k] = ((const double*)s.ct)[k];
+    // eight loads in flight per thread before their LDS stores
+    stage_in(lp, (const double*)s.P, wP);
+    stage_in(lc, (const double*)s.ct, wC);
     __syncthreads();
   }
   const int np = s.np;
