@@ -211,6 +211,118 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const bf1
     }
 }
 
+// Whole forward pass of 128 rows per workgroup.  The activations (128 x 256
+// BF16, 64 KB) stay in LDS through the five layers; the transposed weights
+// (N x K per layer) come from L2 as B fragments of v_mfma_f32_32x32x16_bf16,
+// the next K step's in flight while the current one is multiplied.  Row r of
+// the activations keeps its 16-byte chunk c at position c ^ (r % 32), so that
+// the 32 rows of an A fragment read distinct banks.
+struct MlpArgs {
+  const bf16* W[NL];    // transposed weights of each layer (NOUT x KIN)
+  const float* b[NL];   // biases
+};
+
+__device__ __forceinline__ bf16* mlp_row(bf16* act, int row, int chunk) {
+  return act + row * 256 + ((chunk ^ (row & 31)) << 3);
+}
+
+// hidden layer: act (128 x K) -> relu(act W^T + b) (128 x 256), in place;
+// wave w computes columns [64 w, 64 w + 64) of all 128 rows
+template <int K>
+__device__ __forceinline__ void mlp_hidden(bf16* act, const bf16* __restrict__ W,
+                                           const float* __restrict__ bias, int w, int lane) {
+  const int fr = lane & 31, fk = lane >> 5;
+  f32x16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  const bf16* b0 = W + (long long)(64 * w + fr) * K + fk * 8;
+  const bf16* b1 = W + (long long)(64 * w + 32 + fr) * K + fk * 8;
+  bf16x8 nb0 = *(const bf16x8*)b0, nb1 = *(const bf16x8*)b1;
+#pragma unroll 2
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x8 cb0 = nb0, cb1 = nb1;
+    if (k0 + 16 < K) {
+      nb0 = *(const bf16x8*)(b0 + k0 + 16);
+      nb1 = *(const bf16x8*)(b1 + k0 + 16);
+    }
+    const int ch = (k0 >> 3) + fk;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bf16x8 a = *(const bf16x8*)mlp_row(act, 32 * i + fr, ch);
+      acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, cb0, acc[i][0], 0, 0, 0);
+      acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, cb1, acc[i][1], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave is done reading this layer's inputs
+  // lane l holds rows (r / 4) * 8 + (l / 32) * 4 + r % 4 of column l % 32
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = 64 * w + 32 * j + fr;
+    const float bn = bias[n];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * i + (r >> 2) * 8 + fk * 4 + (r & 3);
+        mlp_row(act, row, n >> 3)[n & 7] = (bf16)fmaxf(acc[i][j][r] + bn, 0.f);
+      }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_mlp(const bf16* __restrict__ Xb, MlpArgs a,
+                                             float* __restrict__ Y) {
+  __shared__ __attribute__((aligned(16))) bf16 act[128 * 256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.x * 128;
+  // padded inputs: 128 rows of 4 chunks
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = t + 256 * j, row = q >> 2, ch = q & 3;
+    *(bf16x8*)mlp_row(act, row, ch) = *(const bf16x8*)(Xb + (long long)(m0 + row) * 32 + ch * 8);
+  }
+  __syncthreads();
+  mlp_hidden<32>(act, a.W[0], a.b[0], w, lane);
+  mlp_hidden<256>(act, a.W[1], a.b[1], w, lane);
+  mlp_hidden<256>(act, a.W[2], a.b[2], w, lane);
+  mlp_hidden<256>(act, a.W[3], a.b[3], w, lane);
+  // output layer: 64 padded columns; wave w takes rows [32 w, 32 w + 32)
+  const int fr = lane & 31, fk = lane >> 5;
+  f32x16 acc[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+  const bf16* b0 = a.W[4] + (long long)fr * 256 + fk * 8;
+  const bf16* b1 = a.W[4] + (long long)(32 + fr) * 256 + fk * 8;
+  bf16x8 nb0 = *(const bf16x8*)b0, nb1 = *(const bf16x8*)b1;
+#pragma unroll 2
+  for (int k0 = 0; k0 < 256; k0 += 16) {
+    const bf16x8 cb0 = nb0, cb1 = nb1;
+    if (k0 + 16 < 256) {
+      nb0 = *(const bf16x8*)(b0 + k0 + 16);
+      nb1 = *(const bf16x8*)(b1 + k0 + 16);
+    }
+    const bf16x8 av = *(const bf16x8*)mlp_row(act, 32 * w + fr, (k0 >> 3) + fk);
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, cb0, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, cb1, acc[1], 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = 32 * j + fr;
+    const float bn = a.b[4][n];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * w + (r >> 2) * 8 + fk * 4 + (r & 3);
+      Y[(long long)(m0 + row) * 64 + n] = acc[j][r] + bn;
+    }
+  }
+}
+
 // rows of the training set picked by the permutation, as padded BF16 inputs
 __global__ void k_gather(const bf16* __restrict__ Xall, const int* __restrict__ perm, int off,
                          int B, bf16* __restrict__ Xb) {
@@ -430,11 +542,23 @@ static hipError_t gemm(hipStream_t st, int M, int N, int K, const bf16* A, int l
   return hipGetLastError();
 }
 
-// forward over B rows of packed inputs Xb: activations act[1..4], output Y
-static int forward(srg_ctx* c, const bf16* Xb, int B) {
+// forward over B rows of packed inputs Xb: output Y, and the activations
+// act[1..4] that the backward pass needs when keep (training)
+static int forward(srg_ctx* c, const bf16* Xb, int B, bool keep) {
   hipStream_t st = c->stream;
   const float* p = c->p();
   const bf16* pb = c->pb();
+  if (!keep && B % 128 == 0) {  // the whole pass in one kernel, activations in LDS
+    MlpArgs a;
+    for (int l = 0; l < NL; ++l) {
+      a.W[l] = c->pbt() + c->L.t_off[l];
+      a.b[l] = p + c->L.b_off[l];
+    }
+    hipLaunchKernelGGL(k_mlp, dim3(B / 128), dim3(256), 0, st, Xb, a,
+                       (float*)(c->ws + c->L.off_y));
+    SCHK(c, hipGetLastError());
+    return LBM_OK;
+  }
   const bf16* in = Xb;
   int ld_in = 32;
   for (int l = 0; l < NL - 1; ++l) {
@@ -628,7 +752,7 @@ int srg_train(srg_ctx* c, int32_t epochs, int32_t batch, float lr, float w_traj,
       hipLaunchKernelGGL(k_gather, dim3((batch * 4 + 255) / 256), dim3(256), 0, c->stream,
                          (const bf16*)(c->ws + c->L.off_xall), dperm, b * batch, batch, Xb);
       SCHK(c, hipGetLastError());
-      int rc = forward(c, Xb, batch);
+      int rc = forward(c, Xb, batch, true);
       if (rc) return rc;
       hipLaunchKernelGGL(k_loss, dim3((batch + 255) / 256), dim3(256), 0, c->stream,
                          (const float*)(c->ws + c->L.off_y), dperm, b * batch, batch,
@@ -671,7 +795,7 @@ int srg_gradients(srg_ctx* c, const float* X, const int32_t* label, const float*
   SCHK(c, hipMemcpyAsync(dtr, traj, 4 * (size_t)NTRAJ * n, hipMemcpyHostToDevice, c->stream));
   float* acc = (float*)(c->ws + c->L.off_acc);
   SCHK(c, hipMemsetAsync(acc, 0, 4, c->stream));
-  int rc = forward(c, Xb, n);
+  int rc = forward(c, Xb, n, true);
   if (rc) return rc;
   hipLaunchKernelGGL(k_loss, dim3((n + 255) / 256), dim3(256), 0, c->stream,
                      (const float*)(c->ws + c->L.off_y), (const int*)nullptr, 0, n, dlab, dtr, w_traj,
@@ -709,7 +833,7 @@ int srg_predict(srg_ctx* c, const float* X, int32_t n, float* y, int32_t src_is_
     SCHK(c, hipGetLastError());
     if (mp > m)  // zero the padding rows of the input block
       SCHK(c, hipMemsetAsync(Xb + (size_t)m * 32, 0, 2 * 32 * (size_t)(mp - m), c->stream));
-    int rc = forward(c, Xb, mp);
+    int rc = forward(c, Xb, mp, false);
     if (rc) return rc;
     float* dst = dst_is_device ? y + (size_t)r0 * SRG_OUT : yout;
     hipLaunchKernelGGL(k_unpack_outputs, dim3((m * SRG_OUT + 255) / 256), dim3(256), 0, c->stream,
