@@ -201,7 +201,7 @@ def scale_c3(args):
 def surrogate(args):
     """The surrogate trained on runs of the coupled method (committed data set of
     4,096 training and 256 held-out runs of the uneven-box distribution) and
-    judged against the held-out plain runs.  Effective runs/hour: the plain
+    checked against the held-out plain runs.  Effective runs/hour: the plain
     ensemble rate (timed here on 256 members) divided by the fraction of runs
     the surrogate hands back to the plain method (confidence below 0.9), plus
     its own inference time."""
@@ -259,7 +259,7 @@ def main():
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--gate-steps", type=int, default=20)
     ap.add_argument("--surrogate", action="store_true",
-                    help="train and judge the surrogate on the committed runs of the method")
+                    help="train and evaluate the surrogate on the committed runs of the method")
     ap.add_argument("--srg-epochs", type=int, default=200)
     ap.add_argument("--c3", action="store_true",
                     help="512x256x192 slab with 500 spheres, FP32 vs FP16 storage")
