@@ -59,6 +59,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"liblbm.so not found at {path}: build it with "
                           "`python -m paper_2505_10171_amd.build` (hipcc, gfx950)")
+    # torch first: it may bring its own HIP runtime, and the library must bind
+    # to that same runtime (device pointers and streams come from torch).
+    # Loaded the other way round, a process holds two runtimes and the first
+    # copy into torch memory fails.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     L.lbm_workspace_bytes.restype = sz
