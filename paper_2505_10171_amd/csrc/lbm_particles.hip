@@ -741,7 +741,10 @@ hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int 
 hipError_t launch_capillary(const Batch& b, int np_rows, int cap_B, int npts, hipStream_t st) {
   if (np_rows == 0) return hipSuccess;
   hipLaunchKernelGGL(k_capbox, dim3(box_blocks(cap_B), np_rows), dim3(256), 0, st, b);
-  const unsigned split = (unsigned)std::max(1, std::min(64, npts / (256 * 4)));
+  // workgroups per particle: four points per thread, or down to one where
+  // few particles leave the GPU idle (about 2,048 workgroups in all)
+  const int wide = std::min(npts / 256, (2048 + np_rows - 1) / np_rows);
+  const unsigned split = (unsigned)std::max(1, std::min(64, std::max(npts / (256 * 4), wide)));
   hipLaunchKernelGGL(k_capillary, dim3(split, np_rows), dim3(256), 0, st, b);
   return hipGetLastError();
 }
