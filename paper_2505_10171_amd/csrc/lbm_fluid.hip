@@ -632,27 +632,26 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
     const double d2 = dx * dx + dy * dy + dz * dz;
     const double rlo = P.R - 0.5, rhi = P.R + 1.5;
     const int n = gx + nx * (gy + ny * gz);
-    if (d2 < rhi * rhi && (rlo <= 0.0 || d2 >= rlo * rlo) && MASK[n] == 0) {
+    if (d2 < rhi * rhi && (rlo <= 0.0 || d2 >= rlo * rlo)) {
+      // the node's and its neighbours' masks, its density and the 18
+      // populations that bounce-back may have written, all in one round trip
       const Nbr nb(gx, gy, gz, nx, ny, nz);
       const uint16_t me = (uint16_t)(2 + p);
+      const uint16_t m0 = MASK[n];
       uint32_t lm = 0;  // bit i: the neighbour in direction i is a solid node of p
 #pragma unroll
       for (int i = 1; i < Q; ++i) lm |= (MASK[nb(i)] == me) ? (1u << i) : 0u;
+      const float rho = RM[n];
+      const float Re = STORE ? rho : 0.f;
+      float ds[Q];
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const int o = opp(i);
+        ds[i] = IO::ld(dp_ + pidx(o, N, n), wq(o) * rho0, wq(o) * Re);
+      }
+      if (m0 != 0) lm = 0;
       if (lm) {
         any = true;
-        const float rho = RM[n];
-        const float Re = STORE ? rho : 0.f;
-        // f*_i was bounced by k_fused into direction opp(i) at x: all of them
-        // loaded first, then corrected and stored
-        float ds[Q];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          ds[i] = 0.f;
-          if (lm & (1u << i)) {
-            const int o = opp(i);
-            ds[i] = IO::ld(dp_ + pidx(o, N, n), wq(o) * rho0, wq(o) * Re);
-          }
-        }
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
           if (!(lm & (1u << i))) continue;
