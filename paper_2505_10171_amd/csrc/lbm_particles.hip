@@ -713,7 +713,6 @@ hipError_t launch_mask_update(const Batch& b, int np_rows, int Bmax, bool with_r
   return hipGetLastError();
 }
 
-// fresh_cap_max: the largest fresh-list capacity of the batch
 // fresh_cap_max: the largest fresh-list capacity of the batch; mode REFILL_STEP
 // (in a step) or REFILL_BOUNDARY (between steps)
 hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int mode,
