@@ -212,26 +212,53 @@ __global__ __launch_bounds__(256) void k_gemm_big(int M, int N, int K, const bf1
 }
 
 // Whole forward pass of 128 rows per workgroup.  The activations (128 x 256
-// BF16, 64 KB) stay in LDS through the five layers; the transposed weights
-// (N x K per layer) come from L2 as B fragments of v_mfma_f32_32x32x16_bf16,
-// the next K step's in flight while the current one is multiplied.  Row r of
-// the activations keeps its 16-byte chunk c at position c ^ (r % 32), so that
-// the 32 rows of an A fragment read distinct banks.
+// BF16, 64 KB) stay in LDS through the five layers.  The transposed weights
+// (N x K per layer) are staged in LDS in slices of 64 K values, shared by the
+// four waves; all slices of a layer are requested at its start and staged in
+// turn.  Products use v_mfma_f32_32x32x16_bf16.  Row r of the activations
+// keeps its 16-byte chunk c at position c ^ (r % 32), so that the 32 rows of an
+// A fragment read distinct banks; weight-slice rows are padded to 144 bytes.
 struct MlpArgs {
   const bf16* W[NL];    // transposed weights of each layer (NOUT x KIN)
   const float* b[NL];   // biases
 };
 
+constexpr int MLP_KS = 64;           // K values per weight slice
+constexpr int MLP_LDW = MLP_KS + 8;  // LDS row of a weight slice (BF16)
+// dynamic LDS: activations, then two weight slices of up to 256 rows
+constexpr size_t MLP_LDS = (size_t)128 * 256 * 2 + (size_t)2 * 256 * MLP_LDW * 2;
+
 __device__ __forceinline__ bf16* mlp_row(bf16* act, int row, int chunk) {
   return act + row * 256 + ((chunk ^ (row & 31)) << 3);
+}
+
+// slice s of W (NN x K) into registers: 16-byte chunks q = t + 256 j
+template <int K, int NN>
+__device__ __forceinline__ void mlp_fetch(const bf16* __restrict__ W, int s, int t, bf16x8* v) {
+  constexpr int KS = K < MLP_KS ? K : MLP_KS, CPR = KS / 8, TOT = NN * CPR;
+#pragma unroll
+  for (int j = 0; j < (TOT + 255) / 256; ++j) {
+    const int q = t + 256 * j;
+    if (q < TOT) v[j] = *(const bf16x8*)(W + (long long)(q / CPR) * K + s * KS + (q % CPR) * 8);
+  }
+}
+template <int K, int NN>
+__device__ __forceinline__ void mlp_stage(bf16* wb, int t, const bf16x8* v) {
+  constexpr int KS = K < MLP_KS ? K : MLP_KS, CPR = KS / 8, TOT = NN * CPR;
+#pragma unroll
+  for (int j = 0; j < (TOT + 255) / 256; ++j) {
+    const int q = t + 256 * j;
+    if (q < TOT) *(bf16x8*)(wb + (q / CPR) * MLP_LDW + (q % CPR) * 8) = v[j];
+  }
 }
 
 // hidden layer: act (128 x K) -> relu(act W^T + b) (128 x 256), in place;
 // wave w computes columns [64 w, 64 w + 64) of all 128 rows
 template <int K>
-__device__ __forceinline__ void mlp_hidden(bf16* act, const bf16* __restrict__ W,
-                                           const float* __restrict__ bias, int w, int lane) {
-  const int fr = lane & 31, fk = lane >> 5;
+__device__ __forceinline__ void mlp_hidden(bf16* act, bf16* wbuf, const bf16* __restrict__ W,
+                                           const float* __restrict__ bias, int t) {
+  constexpr int KS = K < MLP_KS ? K : MLP_KS, NS = K / KS;
+  const int lane = t & 63, w = t >> 6, fr = lane & 31, fk = lane >> 5;
   f32x16 acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -239,25 +266,34 @@ __device__ __forceinline__ void mlp_hidden(bf16* act, const bf16* __restrict__ W
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-  const bf16* b0 = W + (long long)(64 * w + fr) * K + fk * 8;
-  const bf16* b1 = W + (long long)(64 * w + 32 + fr) * K + fk * 8;
-  bf16x8 nb0 = *(const bf16x8*)b0, nb1 = *(const bf16x8*)b1;
-#pragma unroll 2
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bf16x8 cb0 = nb0, cb1 = nb1;
-    if (k0 + 16 < K) {
-      nb0 = *(const bf16x8*)(b0 + k0 + 16);
-      nb1 = *(const bf16x8*)(b1 + k0 + 16);
-    }
-    const int ch = (k0 >> 3) + fk;
+  // every slice of the layer requested at once (one wave per SIMD leaves the
+  // registers for it); each is staged when its turn comes
+  bf16x8 v[NS][8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const bf16x8 a = *(const bf16x8*)mlp_row(act, 32 * i + fr, ch);
-      acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, cb0, acc[i][0], 0, 0, 0);
-      acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, cb1, acc[i][1], 0, 0, 0);
+  for (int sl = 0; sl < NS; ++sl) mlp_fetch<K, 256>(W, sl, t, v[sl]);
+  mlp_stage<K, 256>(wbuf, t, v[0]);
+  __syncthreads();
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const bf16* wb = wbuf + (sl & 1) * 256 * MLP_LDW;
+#pragma unroll
+    for (int ks = 0; ks < KS; ks += 16) {
+      const bf16x8 b0 = *(const bf16x8*)(wb + (64 * w + fr) * MLP_LDW + ks + fk * 8);
+      const bf16x8 b1 = *(const bf16x8*)(wb + (64 * w + 32 + fr) * MLP_LDW + ks + fk * 8);
+      const int ch = ((sl * KS + ks) >> 3) + fk;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bf16x8 a = *(const bf16x8*)mlp_row(act, 32 * i + fr, ch);
+        acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[i][0], 0, 0, 0);
+        acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[i][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave is done with this slice (and, last, with act)
+    if (sl + 1 < NS) {
+      mlp_stage<K, 256>(wbuf + ((sl + 1) & 1) * 256 * MLP_LDW, t, v[sl + 1]);
+      __syncthreads();
     }
   }
-  __syncthreads();  // every wave is done reading this layer's inputs
   // lane l holds rows (r / 4) * 8 + (l / 32) * 4 + r % 4 of column l % 32
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -276,7 +312,9 @@ __device__ __forceinline__ void mlp_hidden(bf16* act, const bf16* __restrict__ W
 
 __global__ __launch_bounds__(256) void k_mlp(const bf16* __restrict__ Xb, MlpArgs a,
                                              float* __restrict__ Y) {
-  __shared__ __attribute__((aligned(16))) bf16 act[128 * 256];
+  extern __shared__ __attribute__((aligned(16))) bf16 mlp_lds[];
+  bf16* act = mlp_lds;
+  bf16* wbuf = mlp_lds + 128 * 256;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.x * 128;
   // padded inputs: 128 rows of 4 chunks
@@ -286,10 +324,10 @@ __global__ __launch_bounds__(256) void k_mlp(const bf16* __restrict__ Xb, MlpArg
     *(bf16x8*)mlp_row(act, row, ch) = *(const bf16x8*)(Xb + (long long)(m0 + row) * 32 + ch * 8);
   }
   __syncthreads();
-  mlp_hidden<32>(act, a.W[0], a.b[0], w, lane);
-  mlp_hidden<256>(act, a.W[1], a.b[1], w, lane);
-  mlp_hidden<256>(act, a.W[2], a.b[2], w, lane);
-  mlp_hidden<256>(act, a.W[3], a.b[3], w, lane);
+  mlp_hidden<32>(act, wbuf, a.W[0], a.b[0], t);
+  mlp_hidden<256>(act, wbuf, a.W[1], a.b[1], t);
+  mlp_hidden<256>(act, wbuf, a.W[2], a.b[2], t);
+  mlp_hidden<256>(act, wbuf, a.W[3], a.b[3], t);
   // output layer: 64 padded columns; wave w takes rows [32 w, 32 w + 32)
   const int fr = lane & 31, fk = lane >> 5;
   f32x16 acc[2];
@@ -297,19 +335,29 @@ __global__ __launch_bounds__(256) void k_mlp(const bf16* __restrict__ Xb, MlpArg
   for (int j = 0; j < 2; ++j)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
-  const bf16* b0 = a.W[4] + (long long)fr * 256 + fk * 8;
-  const bf16* b1 = a.W[4] + (long long)(32 + fr) * 256 + fk * 8;
-  bf16x8 nb0 = *(const bf16x8*)b0, nb1 = *(const bf16x8*)b1;
-#pragma unroll 2
-  for (int k0 = 0; k0 < 256; k0 += 16) {
-    const bf16x8 cb0 = nb0, cb1 = nb1;
-    if (k0 + 16 < 256) {
-      nb0 = *(const bf16x8*)(b0 + k0 + 16);
-      nb1 = *(const bf16x8*)(b1 + k0 + 16);
+  constexpr int NS4 = 256 / MLP_KS;
+  bf16x8 v[NS4][8];
+#pragma unroll
+  for (int sl = 0; sl < NS4; ++sl) mlp_fetch<256, 64>(a.W[4], sl, t, v[sl]);
+  mlp_stage<256, 64>(wbuf, t, v[0]);
+  __syncthreads();
+#pragma unroll
+  for (int sl = 0; sl < NS4; ++sl) {
+    const bf16* wb = wbuf + (sl & 1) * 256 * MLP_LDW;
+#pragma unroll
+    for (int ks = 0; ks < MLP_KS; ks += 16) {
+      const bf16x8 b0 = *(const bf16x8*)(wb + fr * MLP_LDW + ks + fk * 8);
+      const bf16x8 b1 = *(const bf16x8*)(wb + (32 + fr) * MLP_LDW + ks + fk * 8);
+      const bf16x8 av =
+          *(const bf16x8*)mlp_row(act, 32 * w + fr, ((sl * MLP_KS + ks) >> 3) + fk);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc[1], 0, 0, 0);
     }
-    const bf16x8 av = *(const bf16x8*)mlp_row(act, 32 * w + fr, (k0 >> 3) + fk);
-    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, cb0, acc[0], 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, cb1, acc[1], 0, 0, 0);
+    __syncthreads();
+    if (sl + 1 < NS4) {
+      mlp_stage<256, 64>(wbuf + ((sl + 1) & 1) * 256 * MLP_LDW, t, v[sl + 1]);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -554,7 +602,13 @@ static int forward(srg_ctx* c, const bf16* Xb, int B, bool keep) {
       a.W[l] = c->pbt() + c->L.t_off[l];
       a.b[l] = p + c->L.b_off[l];
     }
-    hipLaunchKernelGGL(k_mlp, dim3(B / 128), dim3(256), 0, st, Xb, a,
+    static bool lds_set = false;  // above 64 KB of LDS needs the attribute once
+    if (!lds_set) {
+      SCHK(c, hipFuncSetAttribute((const void*)k_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)MLP_LDS));
+      lds_set = true;
+    }
+    hipLaunchKernelGGL(k_mlp, dim3(B / 128), dim3(256), MLP_LDS, st, Xb, a,
                        (float*)(c->ws + c->L.off_y));
     SCHK(c, hipGetLastError());
     return LBM_OK;
