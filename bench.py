@@ -237,7 +237,7 @@ def surrogate(args):
         "plain_runs_per_hour": round(plain_rph, 1),
         "roofline": {"bound": "mfma", "achieved": res["infer_tflops"], "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": round(res["infer_tflops"] / 2500.0, 5),
-                     "kernel": "k_gemm (inference, batch %d)" % res["infer_batch"],
+                     "kernel": "k_mlp (inference, batch %d)" % res["infer_batch"],
                      "traffic": None},
         "surrogate": res,
     }

@@ -310,18 +310,28 @@ __device__ __forceinline__ void mlp_hidden(bf16* act, bf16* wbuf, const bf16* __
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_mlp(const bf16* __restrict__ Xb, MlpArgs a,
-                                             float* __restrict__ Y) {
+// X: n x 6 FP32 rows, y: n x 51 FP32 rows; rows from n on are computed on zero
+// inputs and not written
+__global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ X, int n, MlpArgs a,
+                                             float* __restrict__ y) {
   extern __shared__ __attribute__((aligned(16))) bf16 mlp_lds[];
   bf16* act = mlp_lds;
   bf16* wbuf = mlp_lds + 128 * 256;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.x * 128;
-  // padded inputs: 128 rows of 4 chunks
+  // inputs padded to 32 features: 128 rows of 4 chunks, the features in chunk 0
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = t + 256 * j, row = q >> 2, ch = q & 3;
-    *(bf16x8*)mlp_row(act, row, ch) = *(const bf16x8*)(Xb + (long long)(m0 + row) * 32 + ch * 8);
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (bf16)0.f;
+    if (ch == 0 && m0 + row < n) {
+      const float* x = X + (long long)(m0 + row) * SRG_IN;
+#pragma unroll
+      for (int e = 0; e < SRG_IN; ++e) v[e] = (bf16)x[e];
+    }
+    *(bf16x8*)mlp_row(act, row, ch) = v;
   }
   __syncthreads();
   mlp_hidden<32>(act, wbuf, a.W[0], a.b[0], t);
@@ -361,12 +371,13 @@ __global__ __launch_bounds__(256) void k_mlp(const bf16* __restrict__ Xb, MlpArg
   }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const int n = 32 * j + fr;
-    const float bn = a.b[4][n];
+    const int col = 32 * j + fr;
+    if (col >= SRG_OUT) continue;
+    const float bn = a.b[4][col];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = 32 * w + (r >> 2) * 8 + fk * 4 + (r & 3);
-      Y[(long long)(m0 + row) * 64 + n] = acc[j][r] + bn;
+      const int row = m0 + 32 * w + (r >> 2) * 8 + fk * 4 + (r & 3);
+      if (row < n) y[(long long)row * SRG_OUT + col] = acc[j][r] + bn;
     }
   }
 }
@@ -378,14 +389,6 @@ __global__ void k_gather(const bf16* __restrict__ Xall, const int* __restrict__ 
   if (t >= B * 4) return;
   const int r = t >> 2, c = (t & 3) * 8;
   *(bf16x8*)(Xb + (long long)r * 32 + c) = *(const bf16x8*)(Xall + (long long)perm[off + r] * 32 + c);
-}
-
-// FP32 inputs (n x 6) -> padded BF16 rows (n x 32)
-__global__ void k_pack_inputs(const float* __restrict__ X, int n, bf16* __restrict__ Xb) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * 32) return;
-  const int r = t >> 5, c = t & 31;
-  Xb[t] = (bf16)(c < SRG_IN ? X[(long long)r * SRG_IN + c] : 0.f);
 }
 
 // loss and its gradient dL/dy (B x 64, BF16, zero in the padding); loss sum in
@@ -431,13 +434,34 @@ __global__ void k_loss(const float* __restrict__ Y, const int* __restrict__ perm
   if ((threadIdx.x & 63) == 0) atomicAdd(acc, l);
 }
 
-// column sums of a BF16 matrix (bias gradient): one thread per column
-__global__ void k_colsum(const bf16* __restrict__ D, int M, int N, int ld, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// column sums of a BF16 matrix (bias gradient).  A workgroup takes 64 columns;
+// its 16 waves take interleaved groups of 8 rows (eight loads in flight per
+// lane), then the 16 partial sums of a column are added in a fixed order.
+constexpr int COLSUM_WAVES = 16;
+__global__ __launch_bounds__(64 * COLSUM_WAVES) void k_colsum(const bf16* __restrict__ D, int M,
+                                                              int N, int ld,
+                                                              float* __restrict__ out) {
+  __shared__ float part[COLSUM_WAVES][64];
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += (float)D[(long long)m * ld + n];
-  out[n] = s;
+  if (n < N) {
+    for (int m0 = 8 * w; m0 < M; m0 += 8 * COLSUM_WAVES) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = m0 + u < M ? (float)D[(long long)(m0 + u) * ld + n] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+  }
+  part[w][c] = s;
+  __syncthreads();
+  if (w == 0 && n < N) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < COLSUM_WAVES; ++q) t += part[q][c];
+    out[n] = t;
+  }
 }
 
 // Adam on the whole parameter vector; refreshes the BF16 copy
@@ -468,14 +492,6 @@ __global__ void k_transpose_bf16(const float* __restrict__ W, int K, int N, bf16
 __global__ void k_to_bf16(const float* __restrict__ p, bf16* __restrict__ pb, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) pb[i] = (bf16)p[i];
-}
-
-// y (n x 51) from the padded FP32 output rows (n x 64)
-__global__ void k_unpack_outputs(const float* __restrict__ Y, int n, float* __restrict__ y) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * SRG_OUT) return;
-  const int r = t / SRG_OUT, c = t - r * SRG_OUT;
-  y[t] = Y[(long long)r * 64 + c];
 }
 
 }  // namespace srg
@@ -590,29 +606,31 @@ static hipError_t gemm(hipStream_t st, int M, int N, int K, const bf16* A, int l
   return hipGetLastError();
 }
 
-// forward over B rows of packed inputs Xb: output Y, and the activations
-// act[1..4] that the backward pass needs when keep (training)
-static int forward(srg_ctx* c, const bf16* Xb, int B, bool keep) {
+// inference over n rows of FP32 inputs X (n x 6) to y (n x 51), both on the
+// device: the whole pass in one kernel, the activations in LDS
+static int infer(srg_ctx* c, const float* X, int n, float* y) {
+  MlpArgs a;
+  for (int l = 0; l < NL; ++l) {
+    a.W[l] = c->pbt() + c->L.t_off[l];
+    a.b[l] = c->p() + c->L.b_off[l];
+  }
+  static bool lds_set = false;  // above 64 KB of LDS needs the attribute once
+  if (!lds_set) {
+    SCHK(c, hipFuncSetAttribute((const void*)k_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)MLP_LDS));
+    lds_set = true;
+  }
+  hipLaunchKernelGGL(k_mlp, dim3((n + 127) / 128), dim3(256), MLP_LDS, c->stream, X, n, a, y);
+  SCHK(c, hipGetLastError());
+  return LBM_OK;
+}
+
+// training forward over B rows of packed inputs Xb: output Y and the
+// activations act[1..4] that the backward pass reads
+static int forward(srg_ctx* c, const bf16* Xb, int B) {
   hipStream_t st = c->stream;
   const float* p = c->p();
   const bf16* pb = c->pb();
-  if (!keep && B % 128 == 0) {  // the whole pass in one kernel, activations in LDS
-    MlpArgs a;
-    for (int l = 0; l < NL; ++l) {
-      a.W[l] = c->pbt() + c->L.t_off[l];
-      a.b[l] = p + c->L.b_off[l];
-    }
-    static bool lds_set = false;  // above 64 KB of LDS needs the attribute once
-    if (!lds_set) {
-      SCHK(c, hipFuncSetAttribute((const void*)k_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)MLP_LDS));
-      lds_set = true;
-    }
-    hipLaunchKernelGGL(k_mlp, dim3(B / 128), dim3(256), MLP_LDS, st, Xb, a,
-                       (float*)(c->ws + c->L.off_y));
-    SCHK(c, hipGetLastError());
-    return LBM_OK;
-  }
   const bf16* in = Xb;
   int ld_in = 32;
   for (int l = 0; l < NL - 1; ++l) {
@@ -650,8 +668,8 @@ static int backward(srg_ctx* c, const bf16* Xb, int B) {
     // dW_l = a_in^T dz  (KIN x NOUT)
     SCHK(c, (gemm<true, false, EPI_F32>(st, KIN[l], NOUT[l], B, a_in, ld_in, dz, ld_dz, nullptr,
                                         nullptr, 0, nullptr, g + c->L.w_off[l], NOUT[l])));
-    hipLaunchKernelGGL(k_colsum, dim3((NOUT[l] + 255) / 256), dim3(256), 0, st, dz, B, NOUT[l],
-                       ld_dz, g + c->L.b_off[l]);
+    hipLaunchKernelGGL(k_colsum, dim3((NOUT[l] + 63) / 64), dim3(64 * COLSUM_WAVES), 0, st, dz, B,
+                       NOUT[l], ld_dz, g + c->L.b_off[l]);
     SCHK(c, hipGetLastError());
     if (l > 0) {
       // dz_{l-1} = (dz W_l^T) * relu'(a_in)
@@ -806,7 +824,7 @@ int srg_train(srg_ctx* c, int32_t epochs, int32_t batch, float lr, float w_traj,
       hipLaunchKernelGGL(k_gather, dim3((batch * 4 + 255) / 256), dim3(256), 0, c->stream,
                          (const bf16*)(c->ws + c->L.off_xall), dperm, b * batch, batch, Xb);
       SCHK(c, hipGetLastError());
-      int rc = forward(c, Xb, batch, true);
+      int rc = forward(c, Xb, batch);
       if (rc) return rc;
       hipLaunchKernelGGL(k_loss, dim3((batch + 255) / 256), dim3(256), 0, c->stream,
                          (const float*)(c->ws + c->L.off_y), dperm, b * batch, batch,
@@ -849,7 +867,7 @@ int srg_gradients(srg_ctx* c, const float* X, const int32_t* label, const float*
   SCHK(c, hipMemcpyAsync(dtr, traj, 4 * (size_t)NTRAJ * n, hipMemcpyHostToDevice, c->stream));
   float* acc = (float*)(c->ws + c->L.off_acc);
   SCHK(c, hipMemsetAsync(acc, 0, 4, c->stream));
-  int rc = forward(c, Xb, n, true);
+  int rc = forward(c, Xb, n);
   if (rc) return rc;
   hipLaunchKernelGGL(k_loss, dim3((n + 255) / 256), dim3(256), 0, c->stream,
                      (const float*)(c->ws + c->L.off_y), (const int*)nullptr, 0, n, dlab, dtr, w_traj,
@@ -871,28 +889,18 @@ int srg_predict(srg_ctx* c, const float* X, int32_t n, float* y, int32_t src_is_
                 int32_t dst_is_device) {
   if (!c || !X || !y || n < 1) return LBM_EINVAL;
   if (c->err) return LBM_ESTATE;
-  bf16* Xb = (bf16*)(c->ws + c->L.off_xb);
   float* xin = (float*)(c->ws + c->L.off_xin);
   float* yout = (float*)(c->ws + c->L.off_yout);
   for (int r0 = 0; r0 < n; r0 += c->max_batch) {
     const int m = std::min(c->max_batch, n - r0);
-    const int mp = (m + 63) / 64 * 64;  // rows beyond m are computed and discarded
     const float* src = X + (size_t)r0 * SRG_IN;
     if (!src_is_device) {
       SCHK(c, hipMemcpyAsync(xin, src, 4 * (size_t)SRG_IN * m, hipMemcpyHostToDevice, c->stream));
       src = xin;
     }
-    hipLaunchKernelGGL(k_pack_inputs, dim3((mp * 32 + 255) / 256), dim3(256), 0, c->stream, src, m,
-                       Xb);
-    SCHK(c, hipGetLastError());
-    if (mp > m)  // zero the padding rows of the input block
-      SCHK(c, hipMemsetAsync(Xb + (size_t)m * 32, 0, 2 * 32 * (size_t)(mp - m), c->stream));
-    int rc = forward(c, Xb, mp, false);
-    if (rc) return rc;
     float* dst = dst_is_device ? y + (size_t)r0 * SRG_OUT : yout;
-    hipLaunchKernelGGL(k_unpack_outputs, dim3((m * SRG_OUT + 255) / 256), dim3(256), 0, c->stream,
-                       (const float*)(c->ws + c->L.off_y), m, dst);
-    SCHK(c, hipGetLastError());
+    int rc = infer(c, src, m, dst);
+    if (rc) return rc;
     if (!dst_is_device) {
       SCHK(c, hipMemcpyAsync(y + (size_t)r0 * SRG_OUT, yout, 4 * (size_t)SRG_OUT * m,
                              hipMemcpyDeviceToHost, c->stream));

@@ -56,6 +56,23 @@ def test_forward_matches_reference():
     assert rel(y2, S.forward(ref, bf16(X2))[0]) <= 2e-2
 
 
+def test_device_predict_ragged_rows():
+    """Device-resident inputs and outputs at row counts that leave a partial
+    128-row tile: every output row matches the reference and nothing past the
+    last row is written."""
+    import torch
+    s, ps, ref, Xr, X, lab, tr = _setup()
+    for n in (1, 127, 129, 300):
+        Xh = np.random.default_rng(100 + n).standard_normal((n, 6)).astype(np.float32)
+        Xd = torch.from_numpy(Xh).to("cuda")
+        Yd = torch.full((n + 3, 51), 7.0, device="cuda")
+        s.predict_device(Xd, Yd)
+        s.sync()
+        Y = Yd.cpu().numpy()
+        assert rel(Y[:n], S.forward(ref, bf16(Xh))[0]) <= 2e-2, n
+        assert np.all(Y[n:] == 7.0), n
+
+
 def test_gradients_match_reference():
     from paper_2505_10171_amd.surrogate import unflatten
     s, ps, ref, Xr, X, lab, tr = _setup()
