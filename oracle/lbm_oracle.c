@@ -337,7 +337,10 @@ static void moments_node(const orc_sim *s, int64_t n) {
 /* reading: the wetting rotation turns G about the direction of its tangential
  * part G_t = G - (G.n_s) n_s; where |G_t| <= EPS_GT (the interface parallel to
  * the solid, or G_t below what single precision resolves) the axis is not
- * defined and G is left unrotated */
+ * defined and G is left unrotated.  The rotation fades in between the
+ * thresholds and twice their value (see wetting_node), so that G stays a
+ * continuous function of phi: a switch at a hard threshold would let a
+ * last-bit difference in |G_t| or |G| turn G by up to 90 degrees. */
 #define EPS_GT 1e-4
 /* capillary direction m = n_s - (n.n_s) n is skipped below this length */
 #define EPS_T 1e-3
@@ -350,7 +353,9 @@ static void moments_node(const orc_sim *s, int64_t n) {
  * n.n_s = -cos(theta): the paper's n_+ with theta -> pi - theta.  Writing
  * n* = cos(a*) n_s + sin(a*) t^, n_+ = cos(theta) n_s + sin(theta) t^ is always
  * at least as close to n* as n_-, so n_+ is taken; if |G_t| <= EPS_GT the
- * direction is left unchanged.  |G| is kept. */
+ * direction is left unchanged.  |G| is kept where the rotation applies in full
+ * (|G_t| >= 2 EPS_GT and |G| >= 2 EPS_G); below that, G moves from the
+ * unrotated towards the rotated vector in proportion to the weight w. */
 static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, double G[3]) {
   int solid_p = -1, has_wall = 0;
   for (int i = 1; i < Q; ++i) {
@@ -384,7 +389,13 @@ static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, doubl
   double tn = norm3(t);
   if (!(tn > EPS_GT)) return;
   double ct = -cos(theta), st = sin(theta);
-  for (int k = 0; k < 3; ++k) G[k] = g * (ct * ns[k] + st * t[k] / tn);
+  /* weight of the rotated gradient: 0 at the thresholds, 1 from twice them */
+  double wt = tn / EPS_GT - 1.0, wg = g / EPS_G - 1.0;
+  double w = (wt < 1.0 ? wt : 1.0) * (wg < 1.0 ? wg : 1.0);
+  for (int k = 0; k < 3; ++k) {
+    double r = g * (ct * ns[k] + st * t[k] / tn);
+    G[k] = w >= 1.0 ? r : G[k] + w * (r - G[k]);
+  }
 }
 
 static void prepare(orc_sim *s) {

@@ -25,6 +25,9 @@ namespace lbm {
 // t = n* - (n*.n_s) n_s.  The solid is the lowest-index neighbouring particle,
 // else the wall.  Applied inside the diffuse interface (|G| > EPS_G); left
 // unchanged if the tangential part |G - (G.n_s) n_s| <= EPS_GT (axis undefined).
+// Between those thresholds and twice their value the rotated vector is blended
+// in with weight w = min(1, |t|/EPS_GT - 1) min(1, |G|/EPS_G - 1), so that G is
+// continuous in phi (no last-bit difference can switch the rotation on or off).
 __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, int gz, int minp,
                                                bool wall_nb, float& Gx, float& Gy, float& Gz) {
   float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
@@ -55,9 +58,19 @@ __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, 
   float tn = sqrtf(tx * tx + ty * ty + tz * tz);
   if (!(tn > EPS_GT)) return;
   float it = 1.0f / tn;
-  Gx = g * (nc * nsx + ns * tx * it);
-  Gy = g * (nc * nsy + ns * ty * it);
-  Gz = g * (nc * nsz + ns * tz * it);
+  const float rx = g * (nc * nsx + ns * tx * it);
+  const float ry = g * (nc * nsy + ns * ty * it);
+  const float rz = g * (nc * nsz + ns * tz * it);
+  const float w = fminf(1.0f, tn / EPS_GT - 1.0f) * fminf(1.0f, g / EPS_G - 1.0f);
+  if (w >= 1.0f) {
+    Gx = rx;
+    Gy = ry;
+    Gz = rz;
+  } else {
+    Gx += w * (rx - Gx);
+    Gy += w * (ry - Gy);
+    Gz += w * (rz - Gz);
+  }
 }
 
 // One direction of each opposite pair: +x, +y, +z, (1,1,0), (1,-1,0), (1,0,1),
