@@ -481,24 +481,94 @@ __device__ __forceinline__ void stage_in(double* dst, const double* src, size_t 
   }
 }
 
+// What a particle's contacts read of it: centre, contact radius, predicted
+// velocities and friction coefficients (96 bytes).
+struct DemView {
+  double x[3], Rc, vp[3], mu_s, wp[3], mu_r;
+};
+
+// Where the DEM keeps its data for one lattice step:
+// DEM_GLOBAL  particle records, contact tables and candidate lists in global
+//             memory;
+// DEM_SHARED  all three staged in LDS and written back at the end;
+// DEM_VIEW    records and contact tables in global memory, but the view of
+//             every particle (DemView) and the candidate lists (16-bit) in LDS,
+//             so that the all-pairs candidate search and the neighbour reads
+//             of the contact loop wait on LDS; the view is refreshed by its
+//             owner after each predictor update.
+enum DemMode { DEM_GLOBAL = 0, DEM_SHARED = 1, DEM_VIEW = 2 };
+constexpr uint16_t NB16_END = 0xFFFF;
+constexpr size_t DEM_VIEW_LDS = 160 * 1024;  // LDS a gfx950 workgroup can have
+
+// Contact forces and torques on one particle from the walls and from its
+// candidates.  T is the record type the particle data is read from (DevParticle
+// or DemView: the same field names); cand(q) is the q-th candidate or -1 past
+// the last; rec(j) is particle j's record.
+template <class T, class Cand, class Rec>
+__device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, const T& me,
+                                             Cand cand, Rec rec, double dt, double* Fs,
+                                             double* Ts) {
+  const double Rci = me.Rc;
+  const double zero[3] = {0, 0, 0};
+  double Fo[3], To[3];
+  if (s.has_wall) {
+    const double nb_[3] = {0, 0, 1}, nt_[3] = {0, 0, -1};
+    const double db = Rci - (me.x[2] - 0.5);
+    if (contact(s, tab, -1, db, nb_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
+                dt, Fo, To))
+      for (int d = 0; d < 3; ++d) {
+        Fs[d] += Fo[d];
+        Ts[d] += To[d];
+      }
+    const double dtp = Rci - (((double)s.nz - 0.5) - me.x[2]);
+    if (contact(s, tab, -2, dtp, nt_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
+                dt, Fo, To))
+      for (int d = 0; d < 3; ++d) {
+        Fs[d] += Fo[d];
+        Ts[d] += To[d];
+      }
+  }
+  for (int q = 0; q < MAXNB; ++q) {
+    const int j = cand(q);
+    if (j < 0) break;
+    const T& pj = rec(j);
+    const double Rcj = pj.Rc;
+    double dx[3];
+    rel_vec(s, me.x, pj.x, dx);
+    const double dist = sqrt(dot3(dx, dx));
+    const double delta = Rci + Rcj - dist;
+    double nh[3] = {0, 0, 0};
+    if (dist > 0.0)
+      for (int d = 0; d < 3; ++d) nh[d] = dx[d] / dist;
+    if (contact(s, tab, j, delta, nh, me.vp, me.wp, pj.vp, pj.wp, Rci, Rcj, dx,
+                0.5 * (me.mu_s + pj.mu_s), 0.5 * (me.mu_r + pj.mu_r), dt, Fo, To))
+      for (int d = 0; d < 3; ++d) {
+        Fs[d] += Fo[d];
+        Ts[d] += To[d];
+      }
+  }
+}
+
 // One workgroup per simulation.  Fluid forces (momentum exchange + capillary)
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
-template <bool SH>
+template <int MODE>
 __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
   // one workgroup per simulation
   const SimDev& s = bt.tab[blockIdx.x];
   if (s.np == 0) return;
-  // SH: particle records, contact tables and candidate lists staged in LDS
-  // for the whole lattice step (dependent FP64 chains then wait on LDS, not
-  // on L2/HBM), written back at the end
   extern __shared__ double dem_lds[];
   DevParticle* PP = s.P;
   Contact* CT = s.ct;
   int* NB = s.nb;
+  DemView* V = nullptr;
+  uint16_t* NB16 = nullptr;
   const size_t wP = (size_t)s.np * sizeof(DevParticle) / 8;
   const size_t wC = (size_t)s.np * MAXC * sizeof(Contact) / 8;
-  if (SH) {
+  if (MODE == DEM_SHARED) {
+    // particle records, contact tables and candidate lists in LDS for the
+    // whole lattice step (dependent FP64 chains then wait on LDS, not on
+    // L2/HBM), written back at the end
     double* lp = dem_lds;
     double* lc = lp + wP;
     PP = (DevParticle*)lp;
@@ -509,10 +579,21 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
     stage_in(lc, (const double*)s.ct, wC);
     __syncthreads();
   }
+  if (MODE == DEM_VIEW) {
+    V = (DemView*)dem_lds;
+    NB16 = (uint16_t*)(V + s.np);
+  }
   const int np = s.np;
   const int nt = blockDim.x;
   const double dt = 1.0 / s.n_sub;
   const double skin = 1.5;
+  // what the pair search and the contacts read of particle j
+  auto rec = [&](int j) -> decltype(auto) {
+    if constexpr (MODE == DEM_VIEW)
+      return (const DemView&)V[j];
+    else
+      return (const DevParticle&)PP[j];
+  };
   // per-step set-up
   // fluid force and torque: mean of this and the previous lattice step (the
   // averaging of the Verlet update over the previous and current step)
@@ -540,34 +621,62 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
     P.Ff[2] -= P.g_p;
     P.Ro = P.R;
     P.havep = 1;
+    if (MODE == DEM_VIEW) {
+      DemView& v = V[i];
+      for (int d = 0; d < 3; ++d) v.x[d] = P.x[d];
+      v.Rc = P.Rc;
+      v.mu_s = P.mu_s;
+      v.mu_r = P.mu_r;
+    }
   }
   __syncthreads();
   // pair candidates within Rc_i + Rc_j + skin (ascending index)
   for (int i = threadIdx.x; i < np; i += nt) {
-    const DevParticle& P = PP[i];
+    const auto& me = rec(i);
     int* nb = NB + (long long)i * MAXNB;
+    uint16_t* nb16 = NB16 + (long long)i * MAXNB;
     int c = 0;
-    for (int j = 0; j < np; ++j) {
-      if (j == i) continue;
-      const DevParticle& Pj = PP[j];
-      double dx[3];
-      rel_vec(s, P.x, Pj.x, dx);
-      const double lim = P.Rc + Pj.Rc + skin;
-      if (dot3(dx, dx) < lim * lim) {
-        if (c < MAXNB)
-          nb[c++] = j;
-        else
+    // 32 partners per pass: the tests only set bits (no stores between the
+    // loads), then the hits are appended in ascending order
+    for (int j0 = 0; j0 < np; j0 += 32) {
+      const int jn = min(32, np - j0);
+      uint32_t hit = 0;
+#pragma unroll 4
+      for (int u = 0; u < jn; ++u) {
+        const int j = j0 + u;
+        const auto& pj = rec(j);
+        double dx[3];
+        rel_vec(s, me.x, pj.x, dx);
+        const double lim = me.Rc + pj.Rc + skin;
+        if (j != i && dot3(dx, dx) < lim * lim) hit |= 1u << u;
+      }
+      while (hit) {
+        const int j = j0 + __builtin_ctz(hit);
+        hit &= hit - 1;
+        if (c < MAXNB) {
+          if (MODE == DEM_VIEW)
+            nb16[c++] = (uint16_t)j;
+          else
+            nb[c++] = j;
+        } else {
           atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+        }
       }
     }
-    if (c < MAXNB) nb[c] = -1;
+    if (c < MAXNB) {
+      if (MODE == DEM_VIEW)
+        nb16[c] = NB16_END;
+      else
+        nb[c] = -1;
+    }
     // free pair springs whose partner is out of range
     Contact* tab = CT + (long long)i * MAXC;
     for (int k = 0; k < MAXC; ++k) {
       const int pt = tab[k].partner;
       if (pt < 0) continue;
       bool found = false;
-      for (int q = 0; q < c && q < MAXNB; ++q) found |= (nb[q] == pt);
+      for (int q = 0; q < c && q < MAXNB; ++q)
+        found |= (MODE == DEM_VIEW ? (int)nb16[q] : nb[q]) == pt;
       if (!found) tab[k].partner = -100;
     }
   }
@@ -598,50 +707,32 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
         else if (P.x[d] < 0.0)
           P.x[d] += L[d];
       }
+      if (MODE == DEM_VIEW) {
+        DemView& v = V[i];
+        for (int d = 0; d < 3; ++d) {
+          v.x[d] = P.x[d];
+          v.vp[d] = P.vp[d];
+          v.wp[d] = P.wp[d];
+        }
+      }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < np; i += nt) {
       DevParticle& P = PP[i];
       Contact* tab = CT + (long long)i * MAXC;
-      const double Rci = P.Rc;
-      const double zero[3] = {0, 0, 0};
-      double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0}, Fo[3], To[3];
-      if (s.has_wall) {
-        const double nb_[3] = {0, 0, 1}, nt_[3] = {0, 0, -1};
-        const double db = Rci - (P.x[2] - 0.5);
-        if (contact(s, tab, -1, db, nb_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r, dt,
-                    Fo, To))
-          for (int d = 0; d < 3; ++d) {
-            Fs[d] += Fo[d];
-            Ts[d] += To[d];
-          }
-        const double dtp = Rci - (((double)s.nz - 0.5) - P.x[2]);
-        if (contact(s, tab, -2, dtp, nt_, P.vp, P.wp, zero, zero, Rci, 0.0, zero, P.mu_s, P.mu_r,
-                    dt, Fo, To))
-          for (int d = 0; d < 3; ++d) {
-            Fs[d] += Fo[d];
-            Ts[d] += To[d];
-          }
-      }
-      const int* nb = NB + (long long)i * MAXNB;
-      for (int q = 0; q < MAXNB; ++q) {
-        const int j = nb[q];
-        if (j < 0) break;
-        const DevParticle& Pj = PP[j];
-        const double Rcj = Pj.Rc;
-        double dx[3];
-        rel_vec(s, P.x, Pj.x, dx);
-        const double dist = sqrt(dot3(dx, dx));
-        const double delta = Rci + Rcj - dist;
-        double nh[3] = {0, 0, 0};
-        if (dist > 0.0)
-          for (int d = 0; d < 3; ++d) nh[d] = dx[d] / dist;
-        if (contact(s, tab, j, delta, nh, P.vp, P.wp, Pj.vp, Pj.wp, Rci, Rcj, dx,
-                    0.5 * (P.mu_s + Pj.mu_s), 0.5 * (P.mu_r + Pj.mu_r), dt, Fo, To))
-          for (int d = 0; d < 3; ++d) {
-            Fs[d] += Fo[d];
-            Ts[d] += To[d];
-          }
+      double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0};
+      if constexpr (MODE == DEM_VIEW) {
+        const uint16_t* nb16 = NB16 + (long long)i * MAXNB;
+        dem_contacts(
+            s, tab, V[i],
+            [&](int q) {
+              const uint16_t u = nb16[q];
+              return u == NB16_END ? -1 : (int)u;
+            },
+            rec, dt, Fs, Ts);
+      } else {
+        const int* nb = NB + (long long)i * MAXNB;
+        dem_contacts(s, tab, P, [&](int q) { return nb[q]; }, rec, dt, Fs, Ts);
       }
       for (int d = 0; d < 3; ++d) {
         P.Fcn[d] = Fs[d];
@@ -690,7 +781,7 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
     }
   }
   __syncthreads();
-  if (SH) {
+  if (MODE == DEM_SHARED) {
     for (size_t k = threadIdx.x; k < wP; k += blockDim.x) ((double*)s.P)[k] = dem_lds[k];
     for (size_t k = threadIdx.x; k < wC; k += blockDim.x) ((double*)s.ct)[k] = dem_lds[wP + k];
   }
@@ -761,12 +852,23 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
   }
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
+  const size_t need_view = (size_t)np_max * (sizeof(DemView) + MAXNB * sizeof(uint16_t));
   // one thread per particle where possible (many-particle boxes get 1024)
   const unsigned nt = np_max > 256 ? 1024u : 256u;
-  if (need <= (size_t)max_lds && need <= 64 * 1024)
-    hipLaunchKernelGGL(k_dem<true>, dim3(b.nsim), dim3(nt), need, st, b);
-  else
-    hipLaunchKernelGGL(k_dem<false>, dim3(b.nsim), dim3(nt), 0, st, b);
+  if (need <= (size_t)max_lds && need <= 64 * 1024) {
+    hipLaunchKernelGGL(k_dem<DEM_SHARED>, dim3(b.nsim), dim3(nt), need, st, b);
+  } else if (need_view <= DEM_VIEW_LDS && np_max < NB16_END) {
+    static bool lds_set = false;  // above 64 KB of LDS needs the attribute once
+    if (!lds_set) {
+      const hipError_t e = hipFuncSetAttribute(
+          (const void*)k_dem<DEM_VIEW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEM_VIEW_LDS);
+      if (e != hipSuccess) return e;
+      lds_set = true;
+    }
+    hipLaunchKernelGGL(k_dem<DEM_VIEW>, dim3(b.nsim), dim3(nt), need_view, st, b);
+  } else {
+    hipLaunchKernelGGL(k_dem<DEM_GLOBAL>, dim3(b.nsim), dim3(nt), 0, st, b);
+  }
   return hipGetLastError();
 }
 

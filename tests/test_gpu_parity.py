@@ -272,6 +272,47 @@ def test_fp16_storage_free_drop():
     assert e["u"] <= 1e-3, e
 
 
+@pytest.mark.parametrize("n_side", [5, 8, 35])
+def test_packed_spheres_in_contact(n_side):
+    """A layer of n_side^2 spheres (R = 2, contact radius 3) on the wall, packed
+    closer than their contact diameter, with jittered positions and random
+    velocities and spins: every sphere presses on its neighbours and on the
+    wall from the first sub-step, so normal, sliding and rolling springs all
+    act.  25 spheres keep the DEM's data in LDS, 64 keep only the contact view
+    there, 1,225 keep everything in global memory."""
+    g0 = W.rng(77, n_side)
+    L = 6 * n_side - 2                    # spacing L / n_side < 2 Rc = 6
+    cfg = W.config(L, L, 16, theta_wall_deg=90.0)
+    phi0 = W.slab_phi0(L, L, 16, 8.0)
+    R = 2.0
+    Rc = R + cfg["delta_R"]
+    sp = L / n_side
+    parts = []
+    for a in range(n_side):
+        for b in range(n_side):
+            x = ((a + 0.5) * sp + g0.uniform(-0.1, 0.1), (b + 0.5) * sp + g0.uniform(-0.1, 0.1),
+                 0.5 + Rc - 0.1 + g0.uniform(-0.05, 0.05))
+            parts.append(W.particle(x, R, theta_deg=90.0, mu_s=0.5, mu_r=0.05, sigma=cfg["sigma"],
+                                    v=tuple(g0.uniform(-0.01, 0.01, 3)),
+                                    w=tuple(g0.uniform(-0.005, 0.005, 3))))
+    g = _gpu(cfg, phi0, parts)
+    o = OracleSim(cfg, phi0, parts)
+    g.step(3)
+    o.step(3)
+    _compare_fields(g, o, label=f"{n_side}^2 packed spheres, 3 steps")
+    pg, po = g.particles(), o.particles()
+    assert np.abs(np.array([p["F_con"] for p in po])).max() > 0.1  # the contacts do act
+    for k in ("F_con", "T_con", "x", "v", "w"):
+        a = np.array([p[k] for p in pg])
+        b = np.array([p[k] for p in po])
+        scale = np.abs(b).max()
+        if k == "T_con":
+            scale = max(scale, R * np.abs(np.array([p["F_con"] for p in po])).max())
+        assert np.abs(a - b).max() <= 1e-5 * scale, (k, np.abs(a - b).max(), scale)
+    g.close()
+    o.close()
+
+
 def test_full_size_slab_c3_parity():
     """The 512x256x192 slab with its 500 spheres (the throughput-at-scale
     workload) at full size for two steps against the oracle: masks bit-exact,
