@@ -549,10 +549,44 @@ __device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, cons
   }
 }
 
+// The pair tests of the DEM's candidate search spread over the GPU (boxes with
+// up to 32 MAXNB particles): thread (i, w) tests particle i against partners
+// 32 w .. 32 w + 31 (centre distance, minimum image, below Rc_i + Rc_j + skin)
+// and stores the hit mask as word w of row i of the candidate-list buffer
+// (MAXNB words per particle), which k_dem turns into the candidate list.
+// Positions and contact radii are those k_dem starts the step from (its
+// set-up changes neither).  Grid (ceil(np_max ceil(np_max / 32) / 256), nsim).
+__global__ __launch_bounds__(256) void k_dem_search(Batch bt) {
+  const SimDev& s = bt.tab[blockIdx.y];
+  const int np = s.np;
+  const int nw = (np + 31) / 32;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)np * nw) return;
+  // consecutive lanes take consecutive particles of one partner word, so the
+  // partner reads are the same address across the wave
+  const int i = (int)(t % np), w = (int)(t / np);
+  const DevParticle* PP = s.P;
+  const double skin = 1.5;
+  const double xi[3] = {PP[i].x[0], PP[i].x[1], PP[i].x[2]};
+  const double Rci = PP[i].Rc;
+  const int j0 = 32 * w, jn = min(32, np - j0);
+  uint32_t hit = 0;
+#pragma unroll 4
+  for (int u = 0; u < jn; ++u) {
+    const int j = j0 + u;
+    const double xj[3] = {PP[j].x[0], PP[j].x[1], PP[j].x[2]};
+    double dx[3];
+    rel_vec(s, xi, xj, dx);
+    const double lim = Rci + PP[j].Rc + skin;
+    if (j != i && dot3(dx, dx) < lim * lim) hit |= 1u << u;
+  }
+  ((uint32_t*)s.nb)[(long long)i * MAXNB + w] = hit;
+}
+
 // One workgroup per simulation.  Fluid forces (momentum exchange + capillary)
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
-template <int MODE>
+template <int MODE, bool PRE>
 __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
   // one workgroup per simulation
   const SimDev& s = bt.tab[blockIdx.x];
@@ -636,9 +670,30 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
     int* nb = NB + (long long)i * MAXNB;
     uint16_t* nb16 = NB16 + (long long)i * MAXNB;
     int c = 0;
+    if (PRE) {
+      // the pair tests were made by k_dem_search: row i of the candidate-list
+      // buffer holds one hit mask per 32 partners; all words loaded at once
+      const uint32_t* hm = (const uint32_t*)NB + (long long)i * MAXNB;
+      const int nw = (np + 31) / 32;
+      uint32_t words[MAXNB];
+#pragma unroll
+      for (int w = 0; w < MAXNB; ++w) words[w] = w < nw ? hm[w] : 0u;
+#pragma unroll
+      for (int w = 0; w < MAXNB; ++w) {
+        uint32_t hit = words[w];
+        while (hit) {
+          const int j = 32 * w + __builtin_ctz(hit);
+          hit &= hit - 1;
+          if (c < MAXNB)
+            nb16[c++] = (uint16_t)j;
+          else
+            atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+        }
+      }
+    }
     // 32 partners per pass: the tests only set bits (no stores between the
     // loads), then the hits are appended in ascending order
-    for (int j0 = 0; j0 < np; j0 += 32) {
+    for (int j0 = 0; j0 < (PRE ? 0 : np); j0 += 32) {
       const int jn = min(32, np - j0);
       uint32_t hit = 0;
 #pragma unroll 4
@@ -856,18 +911,28 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
   // one thread per particle where possible (many-particle boxes get 1024)
   const unsigned nt = np_max > 256 ? 1024u : 256u;
   if (need <= (size_t)max_lds && need <= 64 * 1024) {
-    hipLaunchKernelGGL(k_dem<DEM_SHARED>, dim3(b.nsim), dim3(nt), need, st, b);
+    hipLaunchKernelGGL((k_dem<DEM_SHARED, false>), dim3(b.nsim), dim3(nt), need, st, b);
   } else if (need_view <= DEM_VIEW_LDS && np_max < NB16_END) {
     static bool lds_set = false;  // above 64 KB of LDS needs the attribute once
     if (!lds_set) {
-      const hipError_t e = hipFuncSetAttribute(
-          (const void*)k_dem<DEM_VIEW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEM_VIEW_LDS);
-      if (e != hipSuccess) return e;
+      for (const void* f : {(const void*)k_dem<DEM_VIEW, false>, (const void*)k_dem<DEM_VIEW, true>}) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEM_VIEW_LDS);
+        if (e != hipSuccess) return e;
+      }
       lds_set = true;
     }
-    hipLaunchKernelGGL(k_dem<DEM_VIEW>, dim3(b.nsim), dim3(nt), need_view, st, b);
+    if (np_max <= 32 * MAXNB) {
+      // the pair tests on many CUs first; the hit masks fit the list buffer
+      const long long nw = (np_max + 31) / 32;
+      const unsigned gx = (unsigned)(((long long)np_max * nw + 255) / 256);
+      hipLaunchKernelGGL(k_dem_search, dim3(gx, b.nsim), dim3(256), 0, st, b);
+      hipLaunchKernelGGL((k_dem<DEM_VIEW, true>), dim3(b.nsim), dim3(nt), need_view, st, b);
+    } else {
+      hipLaunchKernelGGL((k_dem<DEM_VIEW, false>), dim3(b.nsim), dim3(nt), need_view, st, b);
+    }
   } else {
-    hipLaunchKernelGGL(k_dem<DEM_GLOBAL>, dim3(b.nsim), dim3(nt), 0, st, b);
+    hipLaunchKernelGGL((k_dem<DEM_GLOBAL, false>), dim3(b.nsim), dim3(nt), 0, st, b);
   }
   return hipGetLastError();
 }

@@ -272,14 +272,15 @@ def test_fp16_storage_free_drop():
     assert e["u"] <= 1e-3, e
 
 
-@pytest.mark.parametrize("n_side", [5, 8, 35])
+@pytest.mark.parametrize("n_side", [5, 8, 28, 35])
 def test_packed_spheres_in_contact(n_side):
     """A layer of n_side^2 spheres (R = 2, contact radius 3) on the wall, packed
     closer than their contact diameter, with jittered positions and random
     velocities and spins: every sphere presses on its neighbours and on the
     wall from the first sub-step, so normal, sliding and rolling springs all
-    act.  25 spheres keep the DEM's data in LDS, 64 keep only the contact view
-    there, 1,225 keep everything in global memory."""
+    act.  25 spheres keep the DEM's data in LDS; 64 keep the contact view
+    there, their pair tests spread over the GPU; 784 keep the contact view and
+    search in one workgroup; 1,225 keep everything in global memory."""
     g0 = W.rng(77, n_side)
     L = 6 * n_side - 2                    # spacing L / n_side < 2 Rc = 6
     cfg = W.config(L, L, 16, theta_wall_deg=90.0)
