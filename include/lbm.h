@@ -199,9 +199,11 @@ int lbm_profile_read(lbm_ctx* ctx, double* total_ms, int64_t* launches, int32_t 
 /* Block-shape autotuner for the per-node kernels (256 threads per block: 256
  * consecutive nodes, or x-y tiles of 256 x 1 .. 16 x 16 nodes; the moments pass
  * keeps its own tiling).  For each box class of the context it times `reps`
- * passes of the per-node kernels with every shape on the current state and
- * keeps the fastest; results are identical with any shape.  The state is left
- * unchanged: the moments the timing rewrites (8 bytes per node) are kept in
+ * passes of the per-node kernels with every shape on the current state (each
+ * pass the fluid part of a real step: interface, collide-and-stream, moments of
+ * what was streamed) and keeps the fastest; results are identical with any
+ * shape.  The state is left unchanged: the previous moments, which the timed
+ * moments pass overwrites (8 bytes per node), and the status words are kept in
  * host memory meanwhile.  chosen (nullable, one per simulation) receives the
  * tile width (0 = consecutive nodes).  Choices are cached in the process per
  * (GPU architecture, box size, storage).  Synchronous. */

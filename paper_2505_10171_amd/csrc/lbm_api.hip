@@ -723,12 +723,18 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
     for (auto& kv : cache)
       if (kv.first == key) best = kv.second;
     if (best < 0) {
-      // the timed moments pass rewrites the current moments: kept aside in
-      // host memory (the library allocates no device memory) and put back
+      // each timed pass is the fluid part of a real step on the current state
+      // (interface and collide-and-stream on it, the moments pass on what that
+      // streamed), so every pass sees consistent data and repeats the same
+      // work.  The moments pass overwrites the previous moments (the FP16
+      // reference): kept aside in host memory (the library allocates no device
+      // memory) and put back, with the status words
       const size_t rp_bytes = 8 * (size_t)d.N;
       save.resize(2 * (size_t)d.N);
-      float* rp_cur = d.rp[ctx->rd ^ 1];
-      HIPCHK(ctx, hipMemcpyAsync(save.data(), rp_cur, rp_bytes, hipMemcpyDeviceToHost, st));
+      float* rp_prev = d.rp[ctx->rd];
+      HIPCHK(ctx, hipMemcpyAsync(save.data(), rp_prev, rp_bytes, hipMemcpyDeviceToHost, st));
+      uint32_t status[4];
+      HIPCHK(ctx, hipMemcpyAsync(status, d.counters, sizeof status, hipMemcpyDeviceToHost, st));
       HIPCHK(ctx, hipStreamSynchronize(st));
       float best_ms = 1e30f;
       for (int c : cand) {
@@ -736,13 +742,16 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
         set_tile(d, c);
         HIPCHK(ctx, hipMemcpyAsync(ctx->d_tab + si, &d, sizeof(SimDev), hipMemcpyHostToDevice, st));
         const Batch b1 = batch_one(ctx, si);
+        Batch a1 = b1;  // buffer indices after a step's swap
+        a1.cur ^= 1;
+        a1.rd ^= 1;
         const unsigned nb = sim_blocks(d);
         float ms = 0.f;
         for (int r = 0; r <= reps; ++r) {  // the first pass warms up
           if (r == 1) HIPCHK(ctx, hipEventRecord(e0, st));
           HIPCHK(ctx, launch_interface(b1, nb, mom_blocks(d), st));
           HIPCHK(ctx, launch_fused(b1, ctx->storage, nb, 0, nullptr, nullptr, nullptr, nullptr, st));
-          HIPCHK(ctx, launch_moments(b1, ctx->storage, nb, mom_blocks(d), MOM_STEP, st));
+          HIPCHK(ctx, launch_moments(a1, ctx->storage, nb, mom_blocks(d), MOM_STEP, st));
         }
         HIPCHK(ctx, hipEventRecord(e1, st));
         HIPCHK(ctx, hipEventSynchronize(e1));
@@ -752,7 +761,8 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen) {
           best = c;
         }
       }
-      HIPCHK(ctx, hipMemcpyAsync(rp_cur, save.data(), rp_bytes, hipMemcpyHostToDevice, st));
+      HIPCHK(ctx, hipMemcpyAsync(rp_prev, save.data(), rp_bytes, hipMemcpyHostToDevice, st));
+      HIPCHK(ctx, hipMemcpyAsync(d.counters, status, sizeof status, hipMemcpyHostToDevice, st));
       HIPCHK(ctx, hipStreamSynchronize(st));
       cache.emplace_back(key, best);
     }

@@ -123,14 +123,19 @@ def test_graph_needs_a_stream():
             c.use_graph(True)
 
 
-def test_autotuned_block_shapes_give_the_same_results():
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_autotuned_block_shapes_give_the_same_results(storage):
     """Every candidate shape maps threads to nodes differently but computes
-    each node identically: a tuned ensemble matches an untuned one."""
+    each node identically: a tuned ensemble matches an untuned one (in FP16
+    storage too, whose decoding needs the previous moments the tuner puts
+    back)."""
     import torch
     from paper_2505_10171_amd.lbm import Context
-    ms = members()
+    ms = members(storage)
     a = Context(ms, stream=torch.cuda.Stream())
     b = Context(ms)
+    a.step(3)  # a state with previous moments that differ from the current ones
+    b.step(3)
     shapes = a.autotune(reps=2)
     print("chosen tile widths", shapes, flush=True)
     assert all(s in (0, 16, 32, 64, 128, 256) for s in shapes)
@@ -153,6 +158,30 @@ def test_autotuned_block_shapes_give_the_same_results():
             assert max(err.values()) <= 1e-6, (tx, i, err)
         c.close()
         d.close()
+
+
+def test_autotune_leaves_the_many_particle_slab_unchanged():
+    """The tuner's timing passes recompute the moments with the normals of the
+    current state (not of the state that collided) and may flag a node as
+    unstable that the real step never produces; on the 512x256x192 slab with
+    500 spheres they did.  The tuner puts the status words back with the
+    moments: afterwards the slab steps on without an error and equals an
+    untuned copy."""
+    from paper_2505_10171_amd.lbm import Simulation
+    w = W.slab_c3()
+    a = Simulation(w["cfg"], w["phi0"], w["particles"])
+    b = Simulation(w["cfg"], w["phi0"], w["particles"])
+    a.step(20)
+    b.step(20)
+    print("chosen", a.autotune(reps=2), flush=True)
+    a.step(4)
+    b.step(4)
+    a.sync()
+    b.sync()
+    err = field_errors(a, b)
+    assert max(err.values()) <= 1e-6, err
+    a.close()
+    b.close()
 
 
 def test_uneven_box_members_in_one_context_against_oracle():
