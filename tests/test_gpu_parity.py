@@ -202,6 +202,27 @@ def test_unstable_flow_is_reported():
         g.step(1)  # sticky error state
 
 
+@pytest.mark.parametrize("n_cube", [3, 5])
+def test_candidate_list_overflow_is_reported(n_cube):
+    """A cubic cluster of n_cube^3 spheres (R = 1.5, contact radius 2.5) at
+    spacing 3.2: every interior sphere has 26 partners within the candidate
+    range (2.5 + 2.5 + 1.5 = 6.5 > 2 x 3.2), more than the 24 a list holds, so
+    the step reports the overflow.  The spheres are held in place (prescribed
+    zero velocity), so the overlapping contacts move nothing.  27 spheres take
+    the DEM placement with all data in LDS; 125 the LDS contact view with the
+    pair tests spread over the GPU."""
+    from paper_2505_10171_amd.lbm import LbmError, LBM_ERANGE
+    cfg = W.config(28, 28, 24)
+    parts = [W.particle((6.0 + 3.2 * a, 6.0 + 3.2 * b, 4.0 + 3.2 * c), 1.5, sigma=cfg["sigma"],
+                        kinematic=1)
+             for a in range(n_cube) for b in range(n_cube) for c in range(n_cube)]
+    g = _gpu(cfg, None, parts)
+    g.step(1)
+    with pytest.raises(LbmError) as e:
+        g.sync()
+    assert e.value.code == LBM_ERANGE
+
+
 def test_full_size_drop_sweep_c2_parity():
     """The 256x128x96 drop-sweeping workload with its 20 spheres, in the launch
     configuration the benchmark times, for a few steps against the oracle."""
