@@ -259,6 +259,15 @@ __global__ __launch_bounds__(256) void k_capillary(Batch bt) {
   const int na = s.cap_na, nph = s.cap_nphi;
   // the polar and azimuthal grids are fixed: their sines and cosines once per
   // workgroup (same arguments, same values as per point)
+  // a particle whose box holds no node with |G| near EPS_G or above gets no
+  // force: every point's G is a convex combination of corner values, so it
+  // would fail the |G| > EPS_G test below (the 0.99 margin covers rounding)
+  bool iface = false;
+  for (int k = threadIdx.x; k < B * B * B; k += blockDim.x) {
+    const float4 v = box[k];
+    iface |= v.x <= 1.5f && v.y * v.y + v.z * v.z + v.w * v.w > (0.99f * EPS_G) * (0.99f * EPS_G);
+  }
+  if (!__syncthreads_or(iface)) return;
   constexpr int TAB = 512;
   __shared__ double t_sa[TAB], t_ca[TAB], t_sp[TAB], t_cp[TAB];
   const bool tab = na <= TAB && nph <= TAB;
@@ -302,15 +311,17 @@ __global__ __launch_bounds__(256) void k_capillary(Batch bt) {
       Gz += w * (double)v.w;
     }
     if (!(W > 0.0)) continue;
-    phi /= W;
-    Gx /= W;
-    Gy /= W;
-    Gz /= W;
+    const double iW = 1.0 / W;
+    phi *= iW;
+    Gx *= iW;
+    Gy *= iW;
+    Gz *= iW;
     const double wgt = 1.0 - phi * phi;
     if (!(wgt > 0.0)) continue;
     const double g = sqrt(Gx * Gx + Gy * Gy + Gz * Gz);
     if (!(g > (double)EPS_G)) continue;
-    const double nx_ = Gx / g, ny_ = Gy / g, nz_ = Gz / g;
+    const double ig = 1.0 / g;
+    const double nx_ = Gx * ig, ny_ = Gy * ig, nz_ = Gz * ig;
     const double a = nx_ * sh[0] + ny_ * sh[1] + nz_ * sh[2];
     const double mx = sh[0] - a * nx_, my = sh[1] - a * ny_, mz = sh[2] - a * nz_;
     const double mn = sqrt(mx * mx + my * my + mz * mz);
@@ -889,7 +900,8 @@ hipError_t launch_capillary(const Batch& b, int np_rows, int cap_B, int npts, hi
   // workgroups per particle: four points per thread, or down to one where
   // few particles leave the GPU idle (about 2,048 workgroups in all)
   const int wide = std::min(npts / 256, (2048 + np_rows - 1) / np_rows);
-  const unsigned split = (unsigned)std::max(1, std::min(64, std::max(npts / (256 * 4), wide)));
+  const int many = std::max(1, (4096 + np_rows - 1) / np_rows);
+  const unsigned split = (unsigned)std::max(1, std::min(64, std::max(std::min(npts / (256 * 4), many), wide)));
   hipLaunchKernelGGL(k_capillary, dim3(split, np_rows), dim3(256), 0, st, b);
   return hipGetLastError();
 }
