@@ -10,7 +10,10 @@ T7  the flat colour interface at rest obeys the discrete recolouring balance
     phi(z) - phi(z+1) = beta/2 (2 - phi(z)^2 - phi(z+1)^2), so sum(1 - phi^2) = 2/beta;
 T8  a free drop holds the Laplace jump c_s^2 (rho_in - rho_out) = 2 sigma / R
     (CSF surface tension eq.);
-T9  a drop on the wall takes the prescribed contact angle (geometric wetting).
+T9  a drop on the wall takes the prescribed contact angle (geometric wetting);
+    the wetting rotation of the colour gradient at a wall node is a continuous
+    function of the gradient across the threshold below which its axis is
+    undefined (unrotated well below it, fully rotated well above it).
 """
 import numpy as np
 import pytest
@@ -191,3 +194,35 @@ def test_T9_contact_angle_flat_wall(theta):
     rho, u, phi, mask = s.fields()
     th = _cap_angle(phi[:, 0, :])
     assert abs(th - theta) < 6.0, th
+
+
+def test_T9_wetting_rotation_is_continuous_across_its_threshold():
+    """phi linear in z (slope 0.01) and in x (slope b): at a node next to the
+    wall the gradient is nearly normal to it, and b sweeps its tangential part
+    through the threshold 1e-4 below which the rotation axis is undefined.
+    With a 90-degree wall the rotation turns G into the wall plane.  Below the
+    threshold G must stay unrotated, well above it G must lie in the plane, and
+    in between G must move continuously: no step between neighbouring b may
+    exceed a few times |G| / threshold times the step in b (a hard switch
+    would jump by about |G| at once)."""
+    nx, ny, nz = 16, 4, 8
+    cfg = W.config(nx, ny, nz, theta_wall_deg=90.0, sigma=0.01)
+    z, y, x = np.meshgrid(np.arange(nz, dtype=float), np.arange(ny, dtype=float),
+                          np.arange(nx, dtype=float), indexing="ij")
+    bs = np.linspace(0.5e-4, 2.9e-4, 61)
+    out = []
+    for b in bs:
+        phi0 = (-0.5 + 0.01 * z + b * (x - 8.0)).astype(np.float32)
+        s = OracleSim(cfg, phi0, [])
+        G, _ = s.grad_force()
+        out.append(G[1, 1, 8].copy())  # node (8, 1, 1): its -z neighbour is the wall
+        s.close()
+    out = np.array(out)
+    g = np.linalg.norm(out, axis=1)
+    # lowest b: tangential part below the threshold, G along the wall normal
+    assert out[0, 0] < 0.02 * out[0, 2] and out[0, 2] > 0
+    # highest b: fully rotated into the wall plane
+    assert abs(out[-1, 2]) <= 1e-12 * g[-1] and out[-1, 0] > 0.99 * g[-1]
+    # continuity: G is Lipschitz in b with a constant set by |G| / threshold
+    step = np.abs(np.diff(out, axis=0)).max()
+    assert step <= 3.0 * g.max() / 1e-4 * (bs[1] - bs[0]), step
