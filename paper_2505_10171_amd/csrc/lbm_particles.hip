@@ -701,31 +701,32 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
             atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
         }
       }
-    }
-    // 32 partners per pass: the tests only set bits (no stores between the
-    // loads), then the hits are appended in ascending order
-    for (int j0 = 0; j0 < (PRE ? 0 : np); j0 += 32) {
-      const int jn = min(32, np - j0);
-      uint32_t hit = 0;
+    } else {
+      // 32 partners per pass: the tests only set bits (no stores between the
+      // loads), then the hits are appended in ascending order
+      for (int j0 = 0; j0 < np; j0 += 32) {
+        const int jn = min(32, np - j0);
+        uint32_t hit = 0;
 #pragma unroll 4
-      for (int u = 0; u < jn; ++u) {
-        const int j = j0 + u;
-        const auto& pj = rec(j);
-        double dx[3];
-        rel_vec(s, me.x, pj.x, dx);
-        const double lim = me.Rc + pj.Rc + skin;
-        if (j != i && dot3(dx, dx) < lim * lim) hit |= 1u << u;
-      }
-      while (hit) {
-        const int j = j0 + __builtin_ctz(hit);
-        hit &= hit - 1;
-        if (c < MAXNB) {
-          if (MODE == DEM_VIEW)
-            nb16[c++] = (uint16_t)j;
-          else
-            nb[c++] = j;
-        } else {
-          atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+        for (int u = 0; u < jn; ++u) {
+          const int j = j0 + u;
+          const auto& pj = rec(j);
+          double dx[3];
+          rel_vec(s, me.x, pj.x, dx);
+          const double lim = me.Rc + pj.Rc + skin;
+          if (j != i && dot3(dx, dx) < lim * lim) hit |= 1u << u;
+        }
+        while (hit) {
+          const int j = j0 + __builtin_ctz(hit);
+          hit &= hit - 1;
+          if (c < MAXNB) {
+            if (MODE == DEM_VIEW)
+              nb16[c++] = (uint16_t)j;
+            else
+              nb[c++] = j;
+          } else {
+            atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+          }
         }
       }
     }
