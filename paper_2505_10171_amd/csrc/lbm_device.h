@@ -8,7 +8,7 @@
 namespace lbm {
 
 // planes one block of the moments pass marches through
-constexpr int MOM_KZ = 4;
+constexpr int MOM_KZ = 6;
 
 // ---------------------------------------------------------------- lattice
 // D3Q19: rest, +-x, +-y, +-z, (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1).
