@@ -471,22 +471,23 @@ __device__ void quat_rotate(double* q, const double* th) {
   for (int k = 0; k < 4; ++k) q[k] = r[k] / nq;
 }
 
-// dst[0, n) = src[0, n) by the whole workgroup, eight loads per thread issued
-// before their stores (one memory round trip per 8 blockDim values, not one per
-// value)
-__device__ __forceinline__ void stage_in(double* dst, const double* src, size_t n) {
-  constexpr int U = 8;
-  const size_t nt = blockDim.x;
-  for (size_t base = 0; base < n; base += U * nt) {
+// dst[0, n1 + n2) = src1[0, n1) followed by src2[0, n2), by the whole
+// workgroup: 20 loads per thread issued before their stores, so that a small
+// box's particle records and contact tables arrive in one memory round trip
+__device__ __forceinline__ void stage_in(double* dst, const double* src1, int n1,
+                                         const double* src2, int n2) {
+  constexpr int U = 20;
+  const int nt = (int)blockDim.x, n = n1 + n2;
+  for (int base = (int)threadIdx.x; base < n; base += U * nt) {
     double v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const size_t k = base + u * nt + threadIdx.x;
-      v[u] = k < n ? src[k] : 0.0;
+      const int k = base + u * nt;
+      v[u] = k < n1 ? src1[k] : (k < n ? src2[k - n1] : 0.0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const size_t k = base + u * nt + threadIdx.x;
+      const int k = base + u * nt;
       if (k < n) dst[k] = v[u];
     }
   }
@@ -619,9 +620,8 @@ __global__ __launch_bounds__(1024) void k_dem(Batch bt) {
     PP = (DevParticle*)lp;
     CT = (Contact*)lc;
     NB = (int*)(lc + wC);
-    // eight loads in flight per thread before their LDS stores
-    stage_in(lp, (const double*)s.P, wP);
-    stage_in(lc, (const double*)s.ct, wC);
+    // records and contact tables in one pass (lc follows lp)
+    stage_in(lp, (const double*)s.P, (int)wP, (const double*)s.ct, (int)wC);
     __syncthreads();
   }
   if (MODE == DEM_VIEW) {
