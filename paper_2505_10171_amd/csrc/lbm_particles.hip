@@ -364,13 +364,14 @@ __device__ inline double dot3(const double* a, const double* b) {
 }
 
 // Slot of `partner` in a particle's contact table (created if asked and free
-// slots remain).  The scans read all MAXC entries without early exit so that
-// their loads issue together (the table may live in global memory).
-__device__ Contact* find_slot(Contact* t, int partner, bool create, uint32_t* status) {
+// slots remain).  ids holds the table's partner ids in registers (the caller
+// loads them once per contact phase) and is kept in step with the table.
+__device__ __forceinline__ Contact* find_slot(Contact* t, int* ids, int partner, bool create,
+                                              uint32_t* status) {
   int found = -1, freek = -1;
 #pragma unroll
   for (int k = MAXC - 1; k >= 0; --k) {
-    const int pk = t[k].partner;
+    const int pk = ids[k];
     if (pk == partner) found = k;
     if (pk == -100) freek = k;
   }
@@ -378,6 +379,9 @@ __device__ Contact* find_slot(Contact* t, int partner, bool create, uint32_t* st
   if (!create) return nullptr;
   if (freek >= 0) {
     t[freek].partner = partner;
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k)
+      if (k == freek) ids[k] = partner;
     for (int d = 0; d < 3; ++d) t[freek].xt[d] = t[freek].xr[d] = 0.0;
     return &t[freek];
   }
@@ -404,16 +408,22 @@ __device__ inline void capped_spring(double k, double gam, double cap, double* x
 
 // Contact of particle i with one partner (normal spring-dashpot, sliding and
 // rolling friction after Luding's model as the paper describes it).
-__device__ bool contact(const SimDev& s, Contact* tab, int partner, double delta, const double* nh,
-                        const double* vi, const double* wi, const double* vj, const double* wj,
-                        double Rci, double Rcj, const double* armj, double mu, double mur,
-                        double dt, double* Fo, double* To) {
+__device__ __forceinline__ bool contact(const SimDev& s, Contact* tab, int* ids, int partner,
+                                        double delta, const double* nh, const double* vi,
+                                        const double* wi, const double* vj, const double* wj,
+                                        double Rci, double Rcj, const double* armj, double mu,
+                                        double mur, double dt, double* Fo, double* To) {
   if (!(delta > 0.0)) {
-    Contact* sl = find_slot(tab, partner, false, &s.counters[1]);
-    if (sl) sl->partner = -100;
+    Contact* sl = find_slot(tab, ids, partner, false, &s.counters[1]);
+    if (sl) {
+      sl->partner = -100;
+#pragma unroll
+      for (int k = 0; k < MAXC; ++k)
+        if (ids[k] == partner) ids[k] = -100;
+    }
     return false;
   }
-  Contact* sl = find_slot(tab, partner, true, &s.counters[1]);
+  Contact* sl = find_slot(tab, ids, partner, true, &s.counters[1]);
   if (!sl) return false;
   double vrel[3];
   for (int d = 0; d < 3; ++d) vrel[d] = vi[d] - vj[d];
@@ -523,17 +533,23 @@ __device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, cons
   const double Rci = me.Rc;
   const double zero[3] = {0, 0, 0};
   double Fo[3], To[3];
+  // partner ids of the contact table in registers for the whole phase (the
+  // table is written only by this thread): one memory round trip, not one per
+  // contact evaluated
+  int ids[MAXC];
+#pragma unroll
+  for (int k = 0; k < MAXC; ++k) ids[k] = tab[k].partner;
   if (s.has_wall) {
     const double nb_[3] = {0, 0, 1}, nt_[3] = {0, 0, -1};
     const double db = Rci - (me.x[2] - 0.5);
-    if (contact(s, tab, -1, db, nb_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
+    if (contact(s, tab, ids, -1, db, nb_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
                 dt, Fo, To))
       for (int d = 0; d < 3; ++d) {
         Fs[d] += Fo[d];
         Ts[d] += To[d];
       }
     const double dtp = Rci - (((double)s.nz - 0.5) - me.x[2]);
-    if (contact(s, tab, -2, dtp, nt_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
+    if (contact(s, tab, ids, -2, dtp, nt_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
                 dt, Fo, To))
       for (int d = 0; d < 3; ++d) {
         Fs[d] += Fo[d];
@@ -552,7 +568,7 @@ __device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, cons
     double nh[3] = {0, 0, 0};
     if (dist > 0.0)
       for (int d = 0; d < 3; ++d) nh[d] = dx[d] / dist;
-    if (contact(s, tab, j, delta, nh, me.vp, me.wp, pj.vp, pj.wp, Rci, Rcj, dx,
+    if (contact(s, tab, ids, j, delta, nh, me.vp, me.wp, pj.vp, pj.wp, Rci, Rcj, dx,
                 0.5 * (me.mu_s + pj.mu_s), 0.5 * (me.mu_r + pj.mu_r), dt, Fo, To))
       for (int d = 0; d < 3; ++d) {
         Fs[d] += Fo[d];
