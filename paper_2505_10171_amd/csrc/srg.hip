@@ -630,7 +630,6 @@ static int infer(srg_ctx* c, const float* X, int n, float* y) {
 static int forward(srg_ctx* c, const bf16* Xb, int B) {
   hipStream_t st = c->stream;
   const float* p = c->p();
-  const bf16* pb = c->pb();
   const bf16* in = Xb;
   int ld_in = 32;
   for (int l = 0; l < NL - 1; ++l) {
