@@ -614,8 +614,8 @@ __global__ __launch_bounds__(256) void k_dem_search(Batch bt) {
 // One workgroup per simulation.  Fluid forces (momentum exchange + capillary)
 // are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
 // new positions with the predicted velocities; gravity is the downward g_p.
-template <int MODE, bool PRE>
-__global__ __launch_bounds__(1024) void k_dem(Batch bt) {
+template <int MODE, bool PRE, int NT>
+__global__ __launch_bounds__(NT) void k_dem(Batch bt) {
   // one workgroup per simulation
   const SimDev& s = bt.tab[blockIdx.x];
   if (s.np == 0) return;
@@ -937,14 +937,18 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
   const size_t need_view = (size_t)np_max * (sizeof(DemView) + MAXNB * sizeof(uint16_t));
-  // one thread per particle where possible (many-particle boxes get 1024)
-  const unsigned nt = np_max > 256 ? 1024u : 256u;
+  // one thread per particle where possible; the launch bound follows the
+  // block size, so that boxes of up to 512 particles keep their contact-phase
+  // values in registers (1,024 threads leave 128 VGPRs a lane)
+  const unsigned nt = np_max > 512 ? 1024u : (np_max > 256 ? 512u : 256u);
   if (need <= (size_t)max_lds && need <= 64 * 1024) {
-    hipLaunchKernelGGL((k_dem<DEM_SHARED, false>), dim3(b.nsim), dim3(nt), need, st, b);
+    hipLaunchKernelGGL((k_dem<DEM_SHARED, false, 256>), dim3(b.nsim), dim3(nt), need, st, b);
   } else if (need_view <= DEM_VIEW_LDS && np_max < NB16_END) {
     static bool lds_set = false;  // above 64 KB of LDS needs the attribute once
     if (!lds_set) {
-      for (const void* f : {(const void*)k_dem<DEM_VIEW, false>, (const void*)k_dem<DEM_VIEW, true>}) {
+      for (const void* f : {(const void*)k_dem<DEM_VIEW, false, 1024>,
+                            (const void*)k_dem<DEM_VIEW, true, 512>,
+                            (const void*)k_dem<DEM_VIEW, true, 1024>}) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEM_VIEW_LDS);
         if (e != hipSuccess) return e;
@@ -956,12 +960,16 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
       const long long nw = (np_max + 31) / 32;
       const unsigned gx = (unsigned)(((long long)np_max * nw + 255) / 256);
       hipLaunchKernelGGL(k_dem_search, dim3(gx, b.nsim), dim3(256), 0, st, b);
-      hipLaunchKernelGGL((k_dem<DEM_VIEW, true>), dim3(b.nsim), dim3(nt), need_view, st, b);
+      if (nt <= 512)
+        hipLaunchKernelGGL((k_dem<DEM_VIEW, true, 512>), dim3(b.nsim), dim3(nt), need_view, st, b);
+      else
+        hipLaunchKernelGGL((k_dem<DEM_VIEW, true, 1024>), dim3(b.nsim), dim3(nt), need_view, st,
+                           b);
     } else {
-      hipLaunchKernelGGL((k_dem<DEM_VIEW, false>), dim3(b.nsim), dim3(nt), need_view, st, b);
+      hipLaunchKernelGGL((k_dem<DEM_VIEW, false, 1024>), dim3(b.nsim), dim3(nt), need_view, st, b);
     }
   } else {
-    hipLaunchKernelGGL((k_dem<DEM_GLOBAL, false>), dim3(b.nsim), dim3(nt), 0, st, b);
+    hipLaunchKernelGGL((k_dem<DEM_GLOBAL, false, 1024>), dim3(b.nsim), dim3(nt), 0, st, b);
   }
   return hipGetLastError();
 }
