@@ -329,32 +329,36 @@ static void moments_node(const orc_sim *s, int64_t n) {
   s->phi[n] = (ra - rb) / (ra + rb);
 }
 
-/* reading: the interface normal is n = G / max(|G|, EPS_G).  Inside the
- * diffuse interface (|G| > EPS_G, within about five nodes of its centre) this
+/* reading: the interface normal is n = G / max(|G|, eps_g).  Inside the
+ * diffuse interface (|G| > eps_g, within about five nodes of its centre) this
  * is the unit normal; outside it fades continuously to zero with G, so that
- * rounding noise in a nearly uniform phi cannot turn into an O(1) normal. */
-#define EPS_G 1e-4
-/* reading: the wetting rotation turns G about the direction of its tangential
- * part G_t = G - (G.n_s) n_s; where |G_t| <= EPS_GT (the interface parallel to
+ * rounding noise in a nearly uniform phi cannot turn into an O(1) normal.
+ * reading: the wetting rotation turns G about the direction of its tangential
+ * part G_t = G - (G.n_s) n_s; where |G_t| <= eps_gt (the interface parallel to
  * the solid, or G_t below what single precision resolves) the axis is not
  * defined and G is left unrotated.  The rotation fades in between the
  * thresholds and twice their value (see wetting_node), so that G stays a
  * continuous function of phi: a switch at a hard threshold would let a
- * last-bit difference in |G_t| or |G| turn G by up to 90 degrees. */
-#define EPS_GT 1e-4
+ * last-bit difference in |G_t| or |G| turn G by up to 90 degrees.
+ * The paper itself normalises G without a threshold and rotates it at every
+ * boundary node of the interface.  orc_set_regularisation replaces these
+ * values, so that the tests can run that plain method (thresholds near zero,
+ * no fade-in) beside the regularised one and bound the difference. */
+static double eps_g = 1e-4, eps_gt = 1e-4;
+static int wet_blend = 1;
 /* capillary direction m = n_s - (n.n_s) n is skipped below this length */
 #define EPS_T 1e-3
 
 /* S3, geometric wetting (wetting-condition eq. for n_pm).
  * reading: it is applied at every fluid node that has at least one solid
- * D3Q19 neighbour and lies in the diffuse interface, |G| > EPS_G.  The solid is the lowest-index particle
+ * D3Q19 neighbour and lies in the diffuse interface, |G| > eps_g.  The solid is the lowest-index particle
  * among the neighbours, else the wall.  theta is measured through fluid a
  * (phi = +1), so with n_s the outward solid normal the target is
  * n.n_s = -cos(theta): the paper's n_+ with theta -> pi - theta.  Writing
  * n* = cos(a*) n_s + sin(a*) t^, n_+ = cos(theta) n_s + sin(theta) t^ is always
- * at least as close to n* as n_-, so n_+ is taken; if |G_t| <= EPS_GT the
+ * at least as close to n* as n_-, so n_+ is taken; if |G_t| <= eps_gt the
  * direction is left unchanged.  |G| is kept where the rotation applies in full
- * (|G_t| >= 2 EPS_GT and |G| >= 2 EPS_G); below that, G moves from the
+ * (|G_t| >= 2 eps_gt and |G| >= 2 eps_g, or always without the fade-in); below that, G moves from the
  * unrotated towards the rotated vector in proportion to the weight w. */
 static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, double G[3]) {
   int solid_p = -1, has_wall = 0;
@@ -369,7 +373,7 @@ static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, doubl
   }
   if (solid_p < 0 && !has_wall) return;
   double g = norm3(G);
-  if (!(g > EPS_G)) return;
+  if (!(g > eps_g)) return;
   double ns[3], theta;
   if (solid_p >= 0) {
     double xp[3] = {(double)x, (double)y, (double)z}, d[3];
@@ -387,11 +391,11 @@ static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, doubl
   double a = dot3(G, ns);
   double t[3] = {G[0] - a * ns[0], G[1] - a * ns[1], G[2] - a * ns[2]};
   double tn = norm3(t);
-  if (!(tn > EPS_GT)) return;
+  if (!(tn > eps_gt)) return;
   double ct = -cos(theta), st = sin(theta);
   /* weight of the rotated gradient: 0 at the thresholds, 1 from twice them */
-  double wt = tn / EPS_GT - 1.0, wg = g / EPS_G - 1.0;
-  double w = (wt < 1.0 ? wt : 1.0) * (wg < 1.0 ? wg : 1.0);
+  double wt = tn / eps_gt - 1.0, wg = g / eps_g - 1.0;
+  double w = wet_blend ? (wt < 1.0 ? wt : 1.0) * (wg < 1.0 ? wg : 1.0) : 1.0;
   for (int k = 0; k < 3; ++k) {
     double r = g * (ct * ns[k] + st * t[k] / tn);
     G[k] = w >= 1.0 ? r : G[k] + w * (r - G[k]);
@@ -428,7 +432,7 @@ static void prepare(orc_sim *s) {
     }
     wetting_node(s, n, x, y, z, G);
     double g = norm3(G);
-    double den = g > EPS_G ? g : EPS_G;
+    double den = g > eps_g ? g : eps_g;
     for (int k = 0; k < 3; ++k) nr[k] = G[k] / den;
   }
   /* S5 - S7
@@ -540,7 +544,7 @@ static void capillary(orc_sim *s) {
         double wgt = 1.0 - ph_i * ph_i;
         if (!(wgt > 0.0)) continue;
         double g = norm3(Gi);
-        if (!(g > EPS_G)) continue;
+        if (!(g > eps_g)) continue;
         double nn[3] = {Gi[0] / g, Gi[1] / g, Gi[2] / g};
         double a = dot3(nn, sh);
         double mv[3] = {sh[0] - a * nn[0], sh[1] - a * nn[1], sh[2] - a * nn[2]};
@@ -1204,6 +1208,18 @@ void orc_collide(const double *f, const double *feq, const double *Fb, double om
   mrt_collide(f, feq, Fb, omega, out);
 }
 double orc_omega(const orc_config *c, double phi) { return local_omega(c, phi); }
+/* thresholds of the normal and the wetting rotation, and whether the rotation
+ * fades in (1) or switches on at once (0); see the readings at eps_g */
+void orc_set_regularisation(double g, double gt, int blend) {
+  eps_g = g;
+  eps_gt = gt;
+  wet_blend = blend ? 1 : 0;
+}
+void orc_get_regularisation(double *g, double *gt, int *blend) {
+  *g = eps_g;
+  *gt = eps_gt;
+  *blend = wet_blend;
+}
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -5,8 +5,9 @@ lattice Boltzmann + DEM step of arXiv 2505.10171 (see lbm_oracle.c for the step
 list and every reading of the paper it takes).  Nothing in the product library
 imports this module.
 
-Parity unpinned: the capillary-force sum (capillary-force eq.) has no closed
-form to check against beyond its symmetry and sign; its tests pin only those.
+The capillary-force sum (capillary-force eq.) is pinned by the paper's
+detachment benchmark (oracle/detachment.py): the largest force on a sphere
+pulled out of a liquid layer against Scheludko's closed form.
 """
 import ctypes as C
 import os
@@ -76,6 +77,8 @@ def lib():
         L.orc_omega.argtypes = [C.POINTER(OrcConfig), C.c_double]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_regularisation.argtypes = [C.c_double, C.c_double, C.c_int]
+        L.orc_get_regularisation.argtypes = [dp, dp, C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -279,3 +282,30 @@ def num_threads():
 
 def set_num_threads(n):
     lib().orc_set_num_threads(int(n))
+
+
+def get_regularisation():
+    """(eps_g, eps_gt, blend): the normal's threshold, the wetting rotation's
+    tangential threshold, and whether the rotation fades in."""
+    g, gt, b = C.c_double(), C.c_double(), C.c_int()
+    lib().orc_get_regularisation(C.byref(g), C.byref(gt), C.byref(b))
+    return g.value, gt.value, b.value
+
+
+class regularisation:
+    """Context manager that runs the oracle with other interface thresholds
+    (for instance the plain method: thresholds near zero, no fade-in) and
+    restores the previous ones on exit.  Applies to every simulation stepped
+    inside the block."""
+
+    def __init__(self, eps_g, eps_gt, blend):
+        self.new = (float(eps_g), float(eps_gt), int(blend))
+
+    def __enter__(self):
+        self.old = get_regularisation()
+        lib().orc_set_regularisation(*self.new)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_regularisation(*self.old)
+        return False
