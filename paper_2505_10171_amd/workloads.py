@@ -168,3 +168,67 @@ def ensemble_member_c4(seed: int, index: int, storage: str = "fp32"):
     parts = [particle(px, Rp, theta_deg=th, mu_s=mu_s, mu_r=mu_r, sigma=cfg["sigma"])]
     return dict(name=f"ensemble member {index}: L={L}", cfg=cfg, phi0=phi0, particles=parts,
                 steps=5000, params=dict(mu_s=mu_s, mu_r=mu_r, R_d=Rd, f_x=fx, theta_p=th, R_p=Rp))
+
+
+# Relaxation times of the paper's drop-particle runs (Table 1): rho_f = 0.05,
+# eta = 0.0273 for the drop and 0.00273 for the air, tau = 1/2 + 3 eta / rho_f.
+# Fluid a (phi = +1) is the drop here, fluid b the air.
+TAU_DROP = 0.5 + 3.0 * 0.0273 / 0.05   # 2.138
+TAU_AIR = 0.5 + 3.0 * 0.00273 / 0.05   # 0.6638
+
+
+def table1_n1(seed: int = 5, R_p: float = 10.0, drop_ratio: float = 5.0, bond: float = 1.25,
+              theta_p: float = 92.0, theta_s: float = 100.0, mu_s: float = 0.5,
+              mu_r: float = 0.05, sigma: float = 0.01, nx: int = 400, ny: int = 181,
+              nz: int = 71, storage: str = "fp32"):
+    """The paper's drop-particle workload (section "Simulation setup and
+    parameters", Table 1): 400x181x71 lattice, particle radius 10, drop radius
+    5 R_p as a hemisphere on the wall, viscosity ratio 10 (drop tau 2.138, air
+    0.664), particle contact angle 90-95 degrees, wall 90-110 degrees, body
+    force on the drop from the Bond number Bo = f R_d^2 / sigma, downward force
+    5.23 sigma R_p on the particle; the particle rests on the wall in front of
+    the drop, offset in y by a seeded jitter of +-0.5."""
+    g = rng(seed, 0)
+    R_d = drop_ratio * R_p
+    f_x = bond * sigma / (R_d * R_d)
+    cfg = config(nx, ny, nz, tau_a=TAU_DROP, tau_b=TAU_AIR, sigma=sigma,
+                 theta_wall_deg=theta_s, body_force=(f_x, 0.0, 0.0), storage=storage)
+    xd, yd = 0.25 * nx, 0.5 * (ny - 1)
+    phi0 = drop_phi0(nx, ny, nz, (xd, yd, 0.5), R_d)
+    Rc = R_p + cfg["delta_R"]
+    x = (xd + R_d + Rc + 2.0, yd + g.uniform(-0.5, 0.5), 0.5 + Rc)
+    parts = [particle(x, R_p, theta_deg=theta_p, mu_s=mu_s, mu_r=mu_r, sigma=sigma)]
+    return dict(name=f"drop-particle (Table 1) {nx}x{ny}x{nz}, R_p={R_p:g}, R_d={R_d:g}",
+                cfg=cfg, phi0=phi0, particles=parts, steps=20000,
+                params=dict(Bo=bond, f_x=f_x, R_d=R_d))
+
+
+def table1_reduced(seed: int = 6, storage: str = "fp32"):
+    """The Table 1 fluids and angles on a 64x48x32 box with R_p = 6 and a drop
+    of radius 2 R_p whose contact line touches the particle: a parity case at
+    viscosity ratio 10 that the oracle finishes in seconds."""
+    w = table1_n1(seed=seed, R_p=6.0, drop_ratio=2.0, nx=64, ny=48, nz=32, storage=storage)
+    # the particle starts at the drop's contact line, so that the interface
+    # meets it within the compared steps
+    p = w["particles"][0]
+    xd = 0.25 * 64
+    p["x"] = (xd + 12.0 + 4.0, p["x"][1], p["x"][2])
+    w["steps"] = 100
+    return w
+
+
+def drop_meets_sphere(seed: int = 7, storage: str = "fp32"):
+    """The drop-sweeping workload reduced to 96x64x40: a 110-degree wall, a drop
+    of radius 15 pushed along x by 5e-6, and one free sphere of radius 5 (contact
+    angle 60 degrees, mu_s 0.4, mu_r 0.04) placed where the drop's advancing
+    contact line reaches it within the first steps."""
+    g = rng(seed, 0)
+    nx, ny, nz = 96, 64, 40
+    cfg = config(nx, ny, nz, theta_wall_deg=110.0, body_force=(5e-6, 0.0, 0.0), storage=storage)
+    R_d, xd, yd = 15.0, 30.0, 32.0
+    phi0 = drop_phi0(nx, ny, nz, (xd, yd, 0.5), R_d)
+    R, Rc = 5.0, 5.0 + cfg["delta_R"]
+    x = (xd + R_d + 2.0, yd + g.uniform(-1.0, 1.0), 0.5 + Rc)
+    parts = [particle(x, R, theta_deg=60.0, mu_s=0.4, mu_r=0.04, g_p=10.0 * cfg["sigma"] * R,
+                      sigma=cfg["sigma"])]
+    return dict(name="drop meets sphere 96x64x40", cfg=cfg, phi0=phi0, particles=parts, steps=200)

@@ -209,3 +209,37 @@ def test_uneven_box_members_in_one_context_against_oracle():
         for v in e.values():
             assert v <= 1e-5, (i, e)
         o.close()
+
+
+@pytest.mark.timeout(900)
+def test_ensemble_error_gate_full_runs():
+    """The runs/hour figure's error gate over whole runs: eight members of the
+    256-member benchmark ensemble (uneven cubic boxes, one sphere each) stepped
+    together in one context with graph replay for the full 5,000 steps, in FP32
+    and FP16 storage; the two 48^3 members among them against the FP64 oracle
+    run for the same 5,000 steps: relative L2 of u and phi within 1e-3."""
+    from parity_util import oracle_runs_parallel, rel_l2 as rl
+    from paper_2505_10171_amd.lbm import Context
+    import torch
+    idx = list(range(8))
+    gate = [i for i in idx if W.ensemble_member_c4(4, i)["cfg"]["nx"] == 48]
+    assert len(gate) == 2
+    steps = W.ensemble_member_c4(4, 0)["steps"]
+    ref = oracle_runs_parallel([(W.ensemble_member_c4(4, i)["cfg"], W.ensemble_member_c4(4, i)["phi0"],
+                                 W.ensemble_member_c4(4, i)["particles"]) for i in gate], steps)
+    for storage in ("fp32", "fp16"):
+        ms = [W.ensemble_member_c4(4, i, storage=storage) for i in idx]
+        ens = Context(ms, stream=torch.cuda.Stream())
+        ens.use_graph(True)
+        ens.step(steps)
+        ens.sync()
+        for k, i in enumerate(gate):
+            rg, ug, pg, mg = ens.fields(i)
+            ro, uo, po, mo = ref[k]
+            fl = mo == 0
+            same_mask = bool(np.array_equal(mg, mo))
+            eu, ep = rl(ug[:, fl & (mg == 0)], uo[:, fl & (mg == 0)]), rl(pg[fl & (mg == 0)], po[fl & (mg == 0)])
+            print(f"{storage} member {i} (L=48) after {steps} steps: u {eu:.2e} phi {ep:.2e} "
+                  f"masks equal {same_mask}", flush=True)
+            assert eu <= 1e-3 and ep <= 1e-3, (storage, i, eu, ep)
+        ens.close()
