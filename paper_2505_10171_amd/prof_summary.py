@@ -8,7 +8,7 @@
 table (calls, average and total duration, share of GPU time per kernel).
 
 ``counters`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs into HBM
-bytes per launch of one kernel.  Both runs must contain one plain device copy of
+bytes per launch of each kernel named (``--kernel`` regex, repeatable).  Both runs must contain one plain device copy of
 known size (the largest ``__amd_rocclr_copyBuffer`` dispatch): each counter is
 scaled by (copy bytes / what the same counter reads for that copy), which
 calibrates the counter's unit and coverage on this chip.  The summary records a
@@ -70,7 +70,9 @@ def _per_kernel(path, counter):
     return vals, probe
 
 
-def counters(fetch, write, kernel, probe_bytes, out, commands):
+def counters(fetch, write, kernels, probe_bytes, out, commands):
+    """HBM bytes per launch of each kernel matching one of the regexes in
+    `kernels`, from a FETCH_SIZE run and a WRITE_SIZE run."""
     lines = ["# HBM traffic per launch from rocprofv3 counters", ""]
     for c in commands:
         lines.append(f"command: {c}")
@@ -82,21 +84,34 @@ def counters(fetch, write, kernel, probe_bytes, out, commands):
             raise SystemExit(f"{path}: no copy probe dispatch")
         pk = max(probe)  # KiB reported for the probe copy
         scale = probe_bytes / (pk * 1024.0)
-        ks = [k for k in vals if re.search(kernel, k)]
-        if not ks:
-            raise SystemExit(f"{path}: no dispatch of {kernel}")
-        k = ks[0]
-        kib = statistics.mean(vals[k])
-        result[label] = kib * 1024.0 * scale
-        lines.append(f"{ctr}: kernel {k}: {len(vals[k])} dispatches, mean {kib:.1f} KiB; "
-                     f"copy probe {probe_bytes} B reads as {pk:.1f} KiB -> scale {scale:.4f}; "
-                     f"scaled bytes per launch {result[label]:.4e}")
-    lines += ["", f"fetch_bytes_per_launch: {result['fetch']:.6e}",
-              f"write_bytes_per_launch: {result['write']:.6e}",
-              f"hbm_bytes_per_launch: {result['fetch'] + result['write']:.6e}",
-              f"kernel_source_sha256_16: {kernel_sources_hash()}"]
+        lines.append(f"{ctr}: copy probe {probe_bytes:.0f} B reads as {pk:.1f} KiB -> scale {scale:.4f}")
+        for kern in kernels:
+            ks = [k for k in vals if re.search(kern, k)]
+            if not ks:
+                raise SystemExit(f"{path}: no dispatch of {kern}")
+            k = ks[0]
+            kib = statistics.mean(vals[k])
+            result.setdefault(k, {})[label] = kib * 1024.0 * scale
+            lines.append(f"  {k}: {len(vals[k])} dispatches, mean {kib:.1f} KiB -> "
+                         f"{result[k][label]:.4e} B per launch")
+    lines.append("")
+    for k, r in result.items():
+        lines.append(f"bytes_per_launch[{k}]: fetch {r['fetch']:.6e} write {r['write']:.6e} "
+                     f"total {r['fetch'] + r['write']:.6e}")
+    lines.append(f"kernel_source_sha256_16: {kernel_sources_hash()}")
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def read_counters(path):
+    """{kernel: total HBM bytes per launch} and the source hash of a summary
+    written by `counters`."""
+    txt = open(path).read()
+    out = {}
+    for m in re.finditer(r"bytes_per_launch\[(.+?)\]: fetch \S+ write \S+ total (\S+)", txt):
+        out[m.group(1)] = float(m.group(2))
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    return out, (h.group(1) if h else None)
 
 
 def main():
@@ -109,7 +124,7 @@ def main():
     b = sub.add_parser("counters")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
-    b.add_argument("--kernel", default="k_fused")
+    b.add_argument("--kernel", action="append", default=[])
     b.add_argument("--probe-bytes", type=float, required=True)
     b.add_argument("out")
     b.add_argument("--command", action="append", default=[])
@@ -117,7 +132,8 @@ def main():
     if args.cmd == "stats":
         stats(args.csv, args.out, args.command)
     else:
-        counters(args.fetch, args.write, args.kernel, args.probe_bytes, args.out, args.command)
+        counters(args.fetch, args.write, args.kernel or ["k_fused"], args.probe_bytes, args.out,
+                 args.command)
 
 
 if __name__ == "__main__":
