@@ -180,6 +180,21 @@ int lbm_links(lbm_ctx* ctx, int32_t sim, uint32_t* out, int32_t* pid, int64_t ma
 /* Global FP64 mass of fluids a and b of simulation sim.  Synchronous. */
 int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * masses of fluids a and b of every simulation of the context, 2 doubles per
+ * simulation in order, as lbm_mass computes them one simulation at a time.  It
+ * allocates nothing: the accumulators live in a fixed device array of the
+ * library, 2 * LBM_NOALLOC_MAX_SIMS doubles per GPU, held until the process
+ * ends; a context of more simulations is rejected (LBM_ERANGE).  Every call on
+ * a GPU shares that GPU's array, so calls that overlap on one GPU (two
+ * streams, two threads) race; the array is cleared by a kernel at each call.
+ * out: host memory (the call then waits for the stream), or device memory on
+ * the context's device when dst_is_device (asynchronous on the stream, no
+ * memset: it may be captured into a graph). */
+#define LBM_NOALLOC_MAX_SIMS 1024
+int lbm_mass_all_noalloc(lbm_ctx* ctx, double* out, int32_t dst_is_device);
+
 /* Number of DEM sub-steps per lattice step of simulation sim (from the
  * collision-duration rule dt_DEM ~ t_c / 45). */
 int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out);

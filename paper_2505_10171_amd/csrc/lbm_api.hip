@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -32,7 +33,8 @@ hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, unsigned m
                           hipStream_t st);
 hipError_t launch_init_mask(const SimDev& s, hipStream_t st);
 hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st);
-hipError_t launch_mass(const SimDev& s, const float* rp, hipStream_t st);
+hipError_t launch_mass(const SimDev& s, const float* rp, double* acc, hipStream_t st);
+hipError_t launch_zero_f64(double* p, int n, hipStream_t st);
 hipError_t launch_mask_update(const Batch& b, int np_rows, int Bmax, bool with_release,
                               hipStream_t st);
 hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int mode,
@@ -45,7 +47,35 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st);
 
 using namespace lbm;
 
+// Device scratch of lbm_mass_all_noalloc: the FP64 mass accumulators of up to
+// LBM_NOALLOC_MAX_SIMS simulations.  Each GPU holds its own copy; host code
+// never uses this name as an address, only the pointer that
+// hipGetSymbolAddress returned for the device (noalloc_scratch).
+static __device__ __align__(256) double scratch[2 * LBM_NOALLOC_MAX_SIMS];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+bool g_scratch_done[MAX_DEVICES] = {};
+
+// Address of `scratch` on device dev (which must be current), resolved once per
+// device; the outcome (address or error) is kept for later calls.
+hipError_t noalloc_scratch(int dev, double** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? (double*)ptr : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  *out = g_scratch_ptr[dev];
+  return g_scratch_err[dev];
+}
 
 constexpr size_t ALIGN = 256;
 constexpr int MAX_PARTICLES = 4096;
@@ -234,6 +264,7 @@ struct Profiler {
 struct lbm_ctx {
   std::vector<SimHost> sims;
   hipStream_t stream;
+  int dev = 0;  // device current at creation
   char* ws;
   size_t ws_bytes;
   int err;
@@ -423,6 +454,13 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
   };
   if (!cfg || n_sims < 1 || !dev_workspace || history_steps < 0)
     return fail(LBM_EINVAL, "invalid arguments");
+  if (hipGetDevice(&ctx->dev) != hipSuccess) return fail(LBM_EHIP, "no current device");
+  {
+    // resolve the no-allocation scratch of this device once, while it is
+    // current; a failure is reported by lbm_mass_all_noalloc
+    double* unused = nullptr;
+    (void)noalloc_scratch(ctx->dev, &unused);
+  }
   size_t need = lbm_workspace_bytes(cfg, n_sims, parts, history_steps);
   if (need == 0) {
     char msg[256] = "invalid configuration";
@@ -1029,9 +1067,34 @@ int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]) {
   SimHost* sh = get_sim(ctx, sim);
   if (!sh) return set_err(ctx, LBM_ERANGE, "simulation index out of range");
   SimDev& d = sh->d;
-  HIPCHK(ctx, hipMemsetAsync(d.mass_acc, 0, 2 * sizeof(double), ctx->stream));
-  HIPCHK(ctx, launch_mass(d, d.rp[ctx->rd ^ 1], ctx->stream));
+  HIPCHK(ctx, launch_zero_f64(d.mass_acc, 2, ctx->stream));
+  HIPCHK(ctx, launch_mass(d, d.rp[ctx->rd ^ 1], d.mass_acc, ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(out, d.mass_acc, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  return lbm_sync(ctx);
+}
+
+int lbm_mass_all_noalloc(lbm_ctx* ctx, double* out, int32_t dst_is_device) {
+  if (!ctx || !out) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  const int n = (int)ctx->sims.size();
+  if (n > LBM_NOALLOC_MAX_SIMS)
+    return set_err(ctx, LBM_ERANGE,
+                   "lbm_mass_all_noalloc: %d simulations exceed its scratch of %d", n,
+                   LBM_NOALLOC_MAX_SIMS);
+  double* acc = nullptr;
+  const hipError_t e = noalloc_scratch(ctx->dev, &acc);
+  if (e != hipSuccess || !acc)
+    return set_err(ctx, LBM_EHIP, "lbm_mass_all_noalloc: no scratch address on device %d: %s",
+                   ctx->dev, hipGetErrorString(e));
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, launch_zero_f64(acc, 2 * n, st));
+  for (int si = 0; si < n; ++si) {
+    const SimDev& d = ctx->sims[si].d;
+    HIPCHK(ctx, launch_mass(d, d.rp[ctx->rd ^ 1], acc + 2 * si, st));
+  }
+  HIPCHK(ctx, hipMemcpyAsync(out, acc, 2 * sizeof(double) * (size_t)n,
+                             dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  if (dst_is_device) return LBM_OK;
   return lbm_sync(ctx);
 }
 

@@ -250,8 +250,10 @@ __global__ void k_init_pops(SimDev s, void* pops) {
 
 // --------------------------------------------------------- global mass (FP64)
 // masses of fluids a and b, sum of rho (1 +- phi) / 2 over fluid nodes, from
-// the moments rp (rho plane, phi plane) of the current state
-__global__ __launch_bounds__(256) void k_mass(SimDev s, const float* __restrict__ rp) {
+// the moments rp (rho plane, phi plane) of the current state, added into
+// acc[0], acc[1] (cleared by the caller)
+__global__ __launch_bounds__(256) void k_mass(SimDev s, const float* __restrict__ rp,
+                                              double* __restrict__ acc) {
   __shared__ double sh[2][256];
   double a = 0.0, b = 0.0;
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < s.N;
@@ -272,9 +274,15 @@ __global__ __launch_bounds__(256) void k_mass(SimDev s, const float* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(&s.mass_acc[0], sh[0][0]);
-    atomicAdd(&s.mass_acc[1], sh[1][0]);
+    atomicAdd(&acc[0], sh[0][0]);
+    atomicAdd(&acc[1], sh[1][0]);
   }
+}
+
+// n doubles set to zero (a kernel, not a memset: safe inside a captured graph)
+__global__ void k_zero_f64(double* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
 }
 
 enum { MODE_STEP = 0, MODE_FIELDS = 1 };
@@ -790,11 +798,18 @@ hipError_t launch_init_pops(const SimDev& s, void* pops, hipStream_t st) {
   return hipGetLastError();
 }
 
-// rp: moments (rho plane, phi plane) of the current state
-hipError_t launch_mass(const SimDev& s, const float* rp, hipStream_t st) {
+// rp: moments (rho plane, phi plane) of the current state; acc: 2 doubles,
+// cleared before
+hipError_t launch_mass(const SimDev& s, const float* rp, double* acc, hipStream_t st) {
   unsigned nb = nblocks(s.N, 256);
   if (nb > 4096) nb = 4096;
-  hipLaunchKernelGGL(k_mass, dim3(nb), dim3(256), 0, st, s, rp);
+  hipLaunchKernelGGL(k_mass, dim3(nb), dim3(256), 0, st, s, rp, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f64, dim3(nblocks(n, 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

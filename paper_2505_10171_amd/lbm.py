@@ -23,7 +23,7 @@ HIST_DOUBLES = 27
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_sync", "lbm_particles_sync",
            "lbm_fields", "lbm_fields2", "lbm_links", "lbm_mass", "lbm_dem_substeps", "lbm_destroy",
            "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_use_graph",
-           "lbm_autotune", "lbm_set_tile"]
+           "lbm_autotune", "lbm_set_tile", "lbm_mass_all_noalloc"]
 PROFILE_KINDS = ("fused", "particles", "moments", "interface")
 
 
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.lbm_fields2.argtypes = [vp, i32, C.c_uint32, vp, vp, vp, vp, vp, vp, i32]
     L.lbm_links.argtypes = [vp, i32, C.POINTER(C.c_uint32), C.POINTER(i32), i64, C.POINTER(i64)]
     L.lbm_mass.argtypes = [vp, i32, C.POINTER(C.c_double)]
+    L.lbm_mass_all_noalloc.argtypes = [vp, C.POINTER(C.c_double), i32]
     L.lbm_dem_substeps.argtypes = [vp, i32, C.POINTER(i32)]
     L.lbm_profile.argtypes = [vp, i32]
     L.lbm_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
@@ -310,6 +311,14 @@ class Context:
     def mass(self, sim: int = 0):
         out = np.zeros(2)
         self._check(load_library().lbm_mass(self.h, sim, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def mass_all_noalloc(self):
+        """FP64 masses (a, b) of every simulation, (n_sims, 2), through the
+        entry point that allocates nothing."""
+        out = np.zeros((self.n, 2))
+        self._check(load_library().lbm_mass_all_noalloc(
+            self.h, out.ctypes.data_as(C.POINTER(C.c_double)), 0))
         return out
 
     def profile(self, enable: bool = True, every: int = 1):
