@@ -1,20 +1,33 @@
 """Benchmark of the coupled LBM-DEM hot path on one MI355X.
 
-Workload: the drop-sweeping-particles configuration (256x128x96 lattice, drop of
-radius 30 pushed along x by a body force 5e-6 over a 110-degree wall, 20 spheres
-of radius 5), FP32 population storage.  A step is one whole coupled time step:
-collide-recolour-stream + bounce-back + momentum exchange, capillary force,
-DEM, mask update, refill and order parameter.
+The line's workload is the throughput-at-scale configuration: a 512x256x192
+lattice (25.2 M nodes) with a liquid slab filling 40 % of the height over a
+90-degree wall and 500 spheres of radius 4, FP32 population storage.  A step is
+one whole coupled time step: interface normal and curvature, collide-stream
+with bounce-back, momentum exchange on particle links, capillary force, DEM,
+mask update, refill and the order parameter of the new state.
 
-Prints one JSON line: throughput in MLUPS (all lattice nodes per step), the
-roofline of the dominant kernel (k_fused, HBM-bound) from HIP events recorded
-inside the timed steps, and the FP64 CPU oracle timed on a bounded sample of the
-same workload on this host.
+One JSON line:
+- value: MLUPS (all lattice nodes per step) of the FP32 run;
+- roofline: the fused-step group (k_interface, k_fused, k_links, k_moments:
+  the population and interface traffic of the step) against the method's
+  algorithmic bytes per node-step, 314 B in FP32 (every population of f and g
+  read and written once, phi written and read once, the mask read once), from
+  HIP events recorded on the library's stream inside the timed steps, with a
+  sub-entry per kernel against its own bytes;
+- fp16: the same run with FP16 population storage (162 B per node-step), and
+  its fields' distance to the FP32 run after the timed steps;
+- c2: the 256x128x96 drop-sweep workload (20 spheres), FP32;
+- c4: the batched ensemble of 256 uneven cubic boxes, runs per hour of
+  5,000-step runs, with graph replay;
+- cpu_baseline: the FP64 oracle timed on a bounded sample of the same workload
+  on this host's cores (all usable threads, and one thread), and, from the same
+  oracle runs, the GPU fields' error at the sampled step counts (the C3 sample
+  and one ensemble member of each box side).
 """
 import argparse
 import json
 import os
-import re
 import sys
 import time
 
@@ -23,179 +36,223 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (f+g+particles) & % HBM peak; ensemble runs/hour at ≤1e-3 error"
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "k_fused_drop_sweep_256x128x96_fp32_counters.txt")
+# algorithmic bytes per node-step of the method (both population sets read and
+# written once, phi written and read once, the uint16 mask read once)
+B_ALG = {"fp32": 314, "fp16": 162}
+GROUP = ("interface", "fused", "links", "moments")
+COUNTERS = {"fp32": os.path.join(ROOT, "profiles",
+                                 "fused_group_slab_512x256x192_fp32_counters.txt")}
+GROUP_KERNELS = ("k_interface", "k_fused<", "k_links<", "k_moments<")
 
 
-def traffic_from_profile():
-    """HBM bytes per k_fused launch from the committed rocprofv3 counter
-    summary, or None if it is missing or was taken on different kernel sources."""
-    from paper_2505_10171_amd.prof_summary import kernel_sources_hash
-    if not os.path.exists(COUNTERS):
+def kernel_bytes(storage, N, n_fluid):
+    """Algorithmic bytes per launch of each timed phase of the group, each
+    counting what that kernel must read and write once:
+    interface (k_interface): phi read, the normal (3 components + |G|) and
+        the CSF coefficient with the solid-link word written: 4 + 16 + 8 = 28 B
+        per node;
+    fused: per fluid node the 19 stored populations read and written (4 B
+        each, 2 B in FP16), the normal (12 B), the curvature word (8 B) and phi
+        (4 B); FP16 adds the two reference densities (8 B); per solid node the
+        curvature word (8 B);
+    moments: the 19 populations read, the colliding state's (rho, phi, normal)
+        read (20 B), the mask (2 B), the new (rho, phi) written (8 B).
+    k_links has O(particle links) work and no per-node bytes."""
+    p = 2 if storage == "fp16" else 4
+    ref = 8 if storage == "fp16" else 0
+    return {"interface": 28 * N,
+            "fused": n_fluid * (38 * p + 24 + ref) + (N - n_fluid) * 8,
+            "moments": N * (19 * p + 20 + 2 + 8),
+            "links": None}
+
+
+def traffic_from_profile(storage):
+    """Measured HBM bytes per step of the group kernels from the committed
+    rocprofv3 counter summary, or None if absent or taken on other sources."""
+    from paper_2505_10171_amd.prof_summary import kernel_sources_hash, read_counters
+    path = COUNTERS.get(storage)
+    if not path or not os.path.exists(path):
         return None
-    txt = open(COUNTERS).read()
-    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_sources_hash():
+    per, h = read_counters(path)
+    if h != kernel_sources_hash():
         return None
-    return float(b.group(1))
+    tot = 0.0
+    for k in GROUP_KERNELS:
+        hits = [v for name, v in per.items() if k in name]
+        if not hits:
+            return None
+        tot += hits[0]
+    return tot
 
 
-def cpu_baseline(work, steps):
-    from oracle import oracle as O
-    from oracle.oracle import OracleSim
+def run_lattice(work, steps, warmup):
+    """Time `steps` steps after `warmup`; phases from HIP events every 10th step."""
+    import torch
+    from paper_2505_10171_amd.lbm import Simulation
+    cfg = work["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    sim = Simulation(cfg, work["phi0"], work["particles"])
+    n_fluid = int((sim.phi_mask()[1] == 0).sum())
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True, every=10)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim = OracleSim(work["cfg"], work["phi0"], work["particles"])
-    t1 = time.perf_counter()
     sim.step(steps)
-    t2 = time.perf_counter()
-    N = work["cfg"]["nx"] * work["cfg"]["ny"] * work["cfg"]["nz"]
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile_read()
+    sim.profile(False)
+    fields = sim.fields()
     sim.close()
-    return dict(value=N * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=O.num_threads(),
-                kind="oracle",
-                sample=f"first {steps} steps of the same workload (FP64 oracle, OpenMP, "
-                       f"{t2 - t1:.1f} s; setup {t1 - t0:.1f} s excluded)")
+    del sim
+    torch.cuda.empty_cache()
+    ph = {k: v[0] / max(v[1], 1) for k, v in prof.items()}  # ms per step
+    storage = cfg["storage"]
+    kb = kernel_bytes(storage, N, n_fluid)
+    group_ms = sum(ph[k] for k in GROUP)
+    alg = B_ALG[storage] * N
+    kernels = {}
+    for k in GROUP:
+        e = {"avg_ms": round(ph[k], 5)}
+        if kb[k] is not None:
+            gbs = kb[k] / (ph[k] * 1e-3) / 1e9
+            e.update(alg_bytes=kb[k], achieved_gbs=round(gbs, 1),
+                     frac=round(gbs / HBM_PEAK_GBS, 4))
+        kernels[k] = e
+    achieved = alg / (group_ms * 1e-3) / 1e9
+    mlups = N * steps / (t1 - t0) / 1e6
+    traffic = traffic_from_profile(storage)
+    roof = {"bound": "hbm",
+            "kernel": "fused-step group: k_interface + k_fused + k_links + k_moments",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": alg, "alg_bytes_per_node": B_ALG[storage],
+            "avg_launch_ms": round(group_ms, 5), "kernels": kernels}
+    return dict(N=N, n_fluid=n_fluid, mlups=mlups, ms_per_step=(t1 - t0) * 1e3 / steps,
+                phases=ph, roofline=roof, fields=fields,
+                hbm_effective_frac=mlups * 1e6 * B_ALG[storage] / (HBM_PEAK_GBS * 1e9))
 
 
-def ensemble(args):
-    """Batched ensemble of C4 members (uneven cubic boxes, one sphere each) in
-    one context: every phase one launch over all members, pairs of steps
-    replayed from a HIP graph.  runs/hour = members x 3600 / wall time of one
-    full run (5,000 steps; timed whole by default, with --steps K the K-step
-    time is scaled by 5000/K).  The error gate re-runs the two smallest members
-    of the same storage type against the FP64 oracle for --gate-steps steps:
-    max relative L2 of u and phi <= 1e-3."""
+def rel(a, b):
     import numpy as np
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def field_errors(f, ref):
+    import numpy as np
+    fl = (ref[3] == 0) & (f[3] == 0)
+    return {"rho": rel(f[0][fl], ref[0][fl]), "u": rel(f[1][:, fl], ref[1][:, fl]),
+            "phi": rel(f[2][fl], ref[2][fl]), "masks_equal": bool(np.array_equal(f[3], ref[3]))}
+
+
+def gpu_fields_after(work, steps, sim=None):
+    """GPU fields of a fresh run of `steps` steps (one simulation or, with
+    sim, member `sim` of an ensemble context already stepped)."""
+    import torch
+    from paper_2505_10171_amd.lbm import Simulation
+    s = Simulation(work["cfg"], work["phi0"], work["particles"])
+    s.step(steps)
+    f = s.fields()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return f
+
+
+def ensemble(n_members, steps, warmup, storage="fp32"):
+    """The batched ensemble (uneven cubic boxes, one sphere each) in one
+    context, every phase one launch over all members, pairs of steps replayed
+    from a HIP graph.  runs/hour = members x 3600 / (time per step x 5,000).
+    Returns the rate and, per box side, the fields of the first member of that
+    side after warmup + steps steps (for the error gate)."""
     import torch
     from paper_2505_10171_amd import workloads as W
     from paper_2505_10171_amd.lbm import Context
-    members = [W.ensemble_member_c4(4, i, storage=args.storage) for i in range(args.members)]
-    run_steps = members[0]["steps"]  # one run of every member
-    steps = args.steps if args.steps_given else run_steps
+    members = [W.ensemble_member_c4(4, i, storage=storage) for i in range(n_members)]
+    run_steps = members[0]["steps"]
     nodes = sum(m["cfg"]["nx"] * m["cfg"]["ny"] * m["cfg"]["nz"] for m in members)
-    stream = torch.cuda.Stream()
-    ctx = Context(members, stream=stream)
+    ctx = Context(members, stream=torch.cuda.Stream())
     ctx.use_graph(True)
-    ctx.step(args.warmup + (args.warmup % 2))
+    warmup += warmup % 2
+    ctx.step(warmup)
     ctx.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.step(steps)
     ctx.sync()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wall = time.perf_counter() - t0
+    gate = {}
+    for i, m in enumerate(members):
+        L = m["cfg"]["nx"]
+        if L not in gate:
+            gate[L] = (i, ctx.fields(i))
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
-    wall = t1 - t0
-    # error gate on the two smallest members
+    return dict(members=n_members, nodes=nodes, steps=steps, run_steps=run_steps,
+                ms_per_step=wall * 1e3 / steps, mlups=nodes * steps / wall / 1e6,
+                runs_per_hour=n_members * 3600.0 / (wall / steps * run_steps),
+                gate_fields=gate, gate_steps=warmup + steps, storage=storage)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(c3_work, c3_steps, c3_gpu_fields, c4):
+    """The FP64 oracle, unchanged, on this host: the first c3_steps steps of the
+    C3 workload with all usable threads, then one more step on one thread;
+    from the same oracle runs, the GPU's error at those step counts: the C3
+    FP32 fields, and the ensemble's gate members (one per box side) after the
+    ensemble's warm-up and timed steps, within 1e-3 in u and phi."""
+    from oracle import oracle as O
     from oracle.oracle import OracleSim
-    order = sorted(range(len(members)), key=lambda i: members[i]["cfg"]["nx"])[:2]
-    gate = []
-    for i in order:
-        m = members[i]
-        g = Context([m])
-        g.step(args.gate_steps)
-        o = OracleSim(dict(m["cfg"], storage="fp32"), m["phi0"], m["particles"])
-        o.step(args.gate_steps)
-        rg, ug, pg, mg = g.fields()
-        ro, uo, po, mo = o.fields()
-        fl = mo == 0
-        eu = float(np.linalg.norm(ug[:, fl] - uo[:, fl]) / np.linalg.norm(uo[:, fl]))
-        ep = float(np.linalg.norm(pg[fl] - po[fl]) / np.linalg.norm(po[fl]))
-        gate.append(dict(member=i, L=m["cfg"]["nx"], u=eu, phi=ep))
-        g.close()
-        o.close()
-    ok = all(max(e["u"], e["phi"]) <= 1e-3 for e in gate)
-    out = {
-        "metric": "ensemble runs/hour at <=1e-3 error",
-        "value": round(args.members * 3600.0 / (wall / steps * run_steps), 1) if ok else 0.0,
-        "unit": "runs/hour", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"ensemble of {args.members} cubic boxes L in {{48,64,80,96}}, "
-                               f"one sphere each, {args.storage.upper()} storage",
-                   "members": args.members, "nodes": nodes, "storage": args.storage},
-        "mlups": round(nodes * steps / wall / 1e6, 1), "steps_per_run": run_steps,
-        "gate": {"steps": args.gate_steps, "members": gate, "passed": ok},
-    }
-    print(json.dumps(out), flush=True)
-
-
-def scale_c3(args):
-    """The 512x256x192 slab workload with 500 spheres, FP32 and FP16 storage on
-    the same run: MLUPS of each, the roofline of k_fused for each, and the
-    per-field error of FP16 against FP32 after the timed steps; both against
-    the FP64 oracle after --c3-oracle-steps steps."""
-    import numpy as np
-    import torch
     from paper_2505_10171_amd import workloads as W
-    from paper_2505_10171_amd.lbm import Simulation
-
-    def rel(a, b):
-        return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
-
-    res = {}
-    fields = {}
-    for storage in ("fp32", "fp16"):
-        w = W.slab_c3(storage=storage)
-        cfg = w["cfg"]
-        N = cfg["nx"] * cfg["ny"] * cfg["nz"]
-        sim = Simulation(cfg, w["phi0"], w["particles"])
-        n_fluid = int((sim.phi_mask()[1] == 0).sum())
-        sim.step(args.warmup)
-        sim.sync()
-        sim.profile(True, every=10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step(args.steps)
-        sim.sync()
-        t1 = time.perf_counter()
-        prof = sim.profile_read()
-        sim.profile(False)
-        pop_b, ref_b = (2, 8) if storage == "fp16" else (4, 0)
-        alg = n_fluid * (38 * pop_b + 24 + ref_b) + (N - n_fluid) * 8
-        t_f = prof["fused"][0] / max(prof["fused"][1], 1) * 1e-3
-        res[storage] = {"mlups": round(N * args.steps / (t1 - t0) / 1e6, 1),
-                        "ms_per_step": round((t1 - t0) * 1e3 / args.steps, 4),
-                        "k_fused_gbs": round(alg / t_f / 1e9, 1),
-                        "k_fused_frac": round(alg / t_f / (HBM_PEAK_GBS * 1e9), 4),
-                        "phase_ms_per_step": {k: round(v[0] / max(v[1], 1), 5)
-                                              for k, v in prof.items()}}
-        r, u, phi, mask = sim.fields()
-        fields[storage] = (r, u, phi, mask)
-        sim.close()
-        del sim
-        torch.cuda.empty_cache()
-    a, b = fields["fp16"], fields["fp32"]
-    fl = b[3] == 0
-    res["fp16_vs_fp32_after_timed_steps"] = {
-        "rho": rel(a[0][fl], b[0][fl]), "u": rel(a[1][:, fl], b[1][:, fl]),
-        "phi": rel(a[2][fl], b[2][fl]), "masks_equal": bool(np.array_equal(a[3], b[3]))}
-    if args.c3_oracle_steps > 0:
-        from oracle.oracle import OracleSim
-        w = W.slab_c3()
-        o = OracleSim(w["cfg"], w["phi0"], w["particles"])
-        o.step(args.c3_oracle_steps)
-        ro, uo, po, mo = o.fields()
+    threads = len(os.sched_getaffinity(0))
+    O.set_num_threads(threads)
+    N = c3_work["cfg"]["nx"] * c3_work["cfg"]["ny"] * c3_work["cfg"]["nz"]
+    t0 = time.perf_counter()
+    sim = OracleSim(c3_work["cfg"], c3_work["phi0"], c3_work["particles"])
+    t1 = time.perf_counter()
+    sim.step(c3_steps)
+    t2 = time.perf_counter()
+    err_c3 = field_errors(c3_gpu_fields, sim.fields())
+    O.set_num_threads(1)
+    t3 = time.perf_counter()
+    sim.step(1)
+    t4 = time.perf_counter()
+    O.set_num_threads(threads)
+    sim.close()
+    multi = N * c3_steps / (t2 - t1) / 1e6
+    single = N / (t4 - t3) / 1e6
+    gate = []
+    for L, (i, f) in sorted(c4["gate_fields"].items()):
+        m = W.ensemble_member_c4(4, i)
+        o = OracleSim(m["cfg"], m["phi0"], m["particles"])
+        o.step(c4["gate_steps"])
+        e = field_errors(f, o.fields())
         o.close()
-        fl = mo == 0
-        for storage in ("fp32", "fp16"):
-            w = W.slab_c3(storage=storage)
-            sim = Simulation(w["cfg"], w["phi0"], w["particles"])
-            sim.step(args.c3_oracle_steps)
-            r, u, phi, mask = sim.fields()
-            sim.close()
-            del sim
-            torch.cuda.empty_cache()
-            res[f"{storage}_vs_oracle_{args.c3_oracle_steps}_steps"] = {
-                "rho": rel(r[fl], ro[fl]), "u": rel(u[:, fl], uo[:, fl]),
-                "phi": rel(phi[fl], po[fl]), "masks_equal": bool(np.array_equal(mask, mo))}
-    out = {"metric": "MLUPS (f+g+particles), FP32 vs FP16 storage", "value": res["fp32"]["mlups"],
-           "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
-           "config": {"workload": "liquid slab 512x256x192, 500 spheres R=4"}, "c3": res}
-    print(json.dumps(out), flush=True)
+        gate.append(dict(member=i, L=L, u=e["u"], phi=e["phi"]))
+    return dict(
+        value=round(multi, 3), unit="MLUPS", cores=threads, kind="oracle",
+        sample=f"first {c3_steps} steps of the 512x256x192 slab with 500 spheres (FP64 oracle, "
+               f"OpenMP, {t2 - t1:.1f} s; setup {t1 - t0:.1f} s excluded); one more step on one "
+               f"thread {t4 - t3:.1f} s",
+        single_thread_mlups=round(single, 4), cpu_model=cpu_model(),
+        gpu_error_c3_fp32=err_c3,
+        ensemble_gate={"steps": c4["gate_steps"], "members": gate,
+                       "passed": all(max(g["u"], g["phi"]) <= 1e-3 for g in gate)})
 
 
 def surrogate(args):
@@ -205,25 +262,12 @@ def surrogate(args):
     ensemble rate (timed here on 256 members) divided by the fraction of runs
     the surrogate hands back to the plain method (confidence below 0.9), plus
     its own inference time."""
-    import torch
     from paper_2505_10171_amd import surrogate_eval as E
     train = E.load(E.TRAIN_FILES)
     held = E.load(E.HELDOUT_FILES)
     res = E.train_and_evaluate(train, held, epochs=args.srg_epochs)
-    # plain method rate on the same GPU: the batched ensemble
-    from paper_2505_10171_amd import workloads as W
-    from paper_2505_10171_amd.lbm import Context
-    members = [W.ensemble_member_c4(4, i) for i in range(256)]
-    ctx = Context(members, stream=torch.cuda.Stream())
-    ctx.use_graph(True)
-    ctx.step(4)
-    ctx.sync()
-    t0 = time.perf_counter()
-    ctx.step(200)
-    ctx.sync()
-    ms_step = (time.perf_counter() - t0) * 1e3 / 200
-    ctx.close()
-    plain_rph = 256 * 3600.0 / (ms_step * 1e-3 * 5000)
+    c4 = ensemble(256, 200, 4)
+    plain_rph = c4["runs_per_hour"]
     n = len(held["label"])
     f = res["fallback_fraction"]
     t_surr = res["infer_us"] * 1e-6 * max(1.0, n / res["infer_batch"])
@@ -247,44 +291,26 @@ def surrogate(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=500, help="timed steps of the C3 runs")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--only", choices=["c3", "c3-fp16", "c2", "c4", "table1"], default=None,
+                    help="run one part alone (for profiling): no line, a short summary")
+    ap.add_argument("--c2-steps", type=int, default=2000)
+    ap.add_argument("--c4-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter scaling)")
-    ap.add_argument("--ensemble", action="store_true",
-                    help="batched ensemble of uneven boxes (runs/hour) instead of the drop sweep")
-    ap.add_argument("--members", type=int, default=256)
-    ap.add_argument("--gate-steps", type=int, default=20)
     ap.add_argument("--surrogate", action="store_true",
                     help="train and evaluate the surrogate on the committed runs of the method")
     ap.add_argument("--srg-epochs", type=int, default=200)
-    ap.add_argument("--c3", action="store_true",
-                    help="512x256x192 slab with 500 spheres, FP32 vs FP16 storage")
-    ap.add_argument("--c3-oracle-steps", type=int, default=20)
     args = ap.parse_args()
-    args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
-
-    if args.ensemble:
-        return ensemble(args)
-    if args.surrogate:
-        return surrogate(args)
-    if args.c3:
-        return scale_c3(args)
     import torch
     from paper_2505_10171_amd import workloads as W
-    from paper_2505_10171_amd.lbm import Simulation
-
-    work = W.drop_sweep_c2()
-    work["cfg"]["storage"] = args.storage
-    cfg = work["cfg"]
-    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.copy_probe_mib > 0:
@@ -294,72 +320,75 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.surrogate:
+        return surrogate(args)
+    if args.only:
+        if args.only in ("c3", "c3-fp16"):
+            r = run_lattice(W.slab_c3(storage="fp16" if args.only == "c3-fp16" else "fp32"),
+                            args.steps, args.warmup)
+        elif args.only == "c2":
+            r = run_lattice(W.drop_sweep_c2(), args.steps, args.warmup)
+        elif args.only == "table1":
+            r = run_lattice(W.table1_n1(), args.steps, args.warmup)
+        else:
+            r = ensemble(256, args.c4_steps, 4)
+            r.pop("gate_fields")
+            print(json.dumps(r), flush=True)
+            return
+        r.pop("fields")
+        print(json.dumps({k: r[k] for k in ("mlups", "ms_per_step", "roofline", "phases")}),
+              flush=True)
+        return
 
-    sim = Simulation(cfg, work["phi0"], work["particles"])
-    rho, u, phi, mask = sim.fields()
-    n_fluid = int((mask == 0).sum())
-    sim.step(args.warmup)
-    sim.sync()
-
-    # HIP events around the phases of every 10th step of the timed region
-    # (events on every step would add about 4 % to the step time)
-    sim.profile(True, every=10)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = sim.profile_read()
-    sim.profile(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    mlups = N * args.steps / (t1 - t0) / 1e6
-
-    # algorithmic bytes of one k_fused launch.  Per fluid node: the 19 stored
-    # populations read and written once (4 B each, 2 B in FP16 storage; the
-    # colour is not stored), the interface normal (12 B), the curvature term +
-    # solid-link word (8 B) and phi (4 B) read; FP16 adds the reference
-    # densities: the node's previous one for decoding (4 B) and the current one
-    # of the nodes written to (4 B per node).  Per solid node the link word.
-    pop_b = 2 if args.storage == "fp16" else 4
-    ref_b = 8 if args.storage == "fp16" else 0
-    alg_bytes = n_fluid * (38 * pop_b + 12 + 8 + 4 + ref_b) + (N - n_fluid) * 8
-    fused_ms, fused_n = prof["fused"]
-    t_fused = fused_ms / max(fused_n, 1) * 1e-3
-    achieved = alg_bytes / t_fused / 1e9
-    traffic = traffic_from_profile() if args.storage == "fp32" else None
-    # whole-step effective fraction: B_alg per node-step (populations read and
-    # written by the collision and read by the moments pass, moments written,
-    # mask read) at the measured MLUPS
-    b_alg_node = 19 * pop_b * 3 + 8 + 2
+    c3w = W.slab_c3()
+    r32 = run_lattice(c3w, args.steps, args.warmup)
+    r16 = run_lattice(W.slab_c3(storage="fp16"), args.steps, args.warmup)
+    e16 = field_errors(r16["fields"], r32["fields"])
+    r2 = run_lattice(W.drop_sweep_c2(), args.c2_steps, 20)
+    c4 = ensemble(256, args.c4_steps, 4)
+    cfg = c3w["cfg"]
     out = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": round(r32["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(r32["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"drop sweeping particles 256x128x96, 20 spheres R=5, "
-                               f"{args.storage.upper()} population storage",
-                   "lattice": [cfg["nx"], cfg["ny"], cfg["nz"]], "particles": 20,
-                   "storage": args.storage, "global_batch": 1},
-        "roofline": {"bound": "hbm", "kernel": "k_fused",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(t_fused * 1e3, 5)},
-        "phase_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items()},
-        "hbm_effective_frac": round(mlups * 1e6 * b_alg_node / (HBM_PEAK_GBS * 1e9), 4),
+        "config": {"workload": "liquid slab 512x256x192 (40% of the height), 500 spheres R=4, "
+                               "90-degree wall, FP32 population storage",
+                   "lattice": [cfg["nx"], cfg["ny"], cfg["nz"]], "particles": 500,
+                   "storage": "fp32", "global_batch": 1},
+        "roofline": r32["roofline"],
+        "hbm_effective_frac": round(r32["hbm_effective_frac"], 4),
+        "phase_ms_per_step": {k: round(v, 5) for k, v in r32["phases"].items()},
+        "fp16": {"mlups": round(r16["mlups"], 1), "ms_per_step": round(r16["ms_per_step"], 5),
+                 "speedup_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
+                 "roofline": r16["roofline"],
+                 "hbm_effective_frac": round(r16["hbm_effective_frac"], 4),
+                 "phase_ms_per_step": {k: round(v, 5) for k, v in r16["phases"].items()},
+                 "error_vs_fp32_after_timed_steps": e16},
+        "c2": {"workload": "drop sweeping particles 256x128x96, 20 spheres R=5, FP32",
+               "steps": args.c2_steps, "mlups": round(r2["mlups"], 1),
+               "ms_per_step": round(r2["ms_per_step"], 5),
+               "roofline_frac": r2["roofline"]["frac"],
+               "hbm_effective_frac": round(r2["hbm_effective_frac"], 4)},
+        "c4": {"workload": "ensemble of 256 cubic boxes L in {48,64,80,96}, one sphere each, "
+                           "FP32, graph replay",
+               "runs_per_hour": round(c4["runs_per_hour"], 1), "run_steps": c4["run_steps"],
+               "timed_steps": c4["steps"], "ms_per_step": round(c4["ms_per_step"], 4),
+               "mlups": round(c4["mlups"], 1), "nodes": c4["nodes"]},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(work, args.cpu_steps)
+        c3_gpu = gpu_fields_after(c3w, args.cpu_steps)
+        cb = cpu_baseline(c3w, args.cpu_steps, c3_gpu, c4)
+        out["cpu_baseline"] = cb
+        out["c4"]["error_gate"] = cb["ensemble_gate"]
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

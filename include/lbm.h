@@ -202,9 +202,10 @@ int lbm_dem_substeps(lbm_ctx* ctx, int32_t sim, int32_t* out);
 /* Per-phase timing for benchmarks.  lbm_profile(ctx, k), k >= 1, starts (or
  * restarts) recording HIP events on the context's stream around the phases of
  * every k-th step (k = 1: every step):
- * kind 0 the fused collide-stream kernel, kind 1 the particle kernels
- * (capillary, DEM, mask update, refill), kind 2 the order-parameter kernel,
- * kind 3 the interface kernel (normal and curvature);
+ * kind 0 the fused collide-stream kernel, kind 1 the particle kernels other
+ * than the link kernel (capillary, DEM, mask update, refill), kind 2 the
+ * order-parameter kernel, kind 3 the interface kernels (normal and curvature),
+ * kind 4 the link kernel (moving-wall terms and momentum exchange);
  * lbm_profile(ctx, 0) stops.  lbm_profile_read waits for the recorded steps and
  * writes, for the first n_kinds kinds, the summed GPU time in milliseconds and
  * the number of timed launches (per simulation and step). */

@@ -1164,6 +1164,23 @@ int64_t orc_links(const orc_sim *s, uint32_t *out, int32_t *pid, int64_t max) {
   return cnt;
 }
 
+/* Sensitivity probe (not part of the method): round every colour population's
+ * departure from its rest value w_i rho0 / 2 to single precision, in place, as
+ * a store of the state in FP32 would; tests use it to measure how far the
+ * method's trajectory moves under storage rounding alone. */
+void orc_round_state_f32(orc_sim *s) {
+  const double h = 0.5 * s->c.rho0;
+#pragma omp parallel for schedule(static)
+  for (int64_t n = 0; n < s->N; ++n) {
+    if (s->mask[n] != 0) continue;
+    for (int i = 0; i < Q; ++i) {
+      const double r = WT[i] * h;
+      s->fa[n * Q + i] = r + (double)(float)(s->fa[n * Q + i] - r);
+      s->fb[n * Q + i] = r + (double)(float)(s->fb[n * Q + i] - r);
+    }
+  }
+}
+
 /* Global mass of each fluid, sums in node order. */
 void orc_mass(const orc_sim *s, double out[2]) {
   double a = 0.0, b = 0.0;

@@ -77,6 +77,7 @@ def lib():
         L.orc_omega.argtypes = [C.POINTER(OrcConfig), C.c_double]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_round_state_f32.argtypes = [C.c_void_p]
         L.orc_set_regularisation.argtypes = [C.c_double, C.c_double, C.c_int]
         L.orc_get_regularisation.argtypes = [dp, dp, C.POINTER(C.c_int)]
         _lib = L
@@ -226,6 +227,10 @@ class OracleSim:
         L.orc_links(self.h, out.ctypes.data_as(C.POINTER(C.c_uint32)),
                     pid.ctypes.data_as(C.POINTER(C.c_int32)), cnt)
         return out[:cnt], pid[:cnt]
+
+    def round_state_f32(self):
+        """Sensitivity probe: round the state's departures from rest to FP32."""
+        lib().orc_round_state_f32(self.h)
 
     def mass(self):
         out = np.zeros(2)

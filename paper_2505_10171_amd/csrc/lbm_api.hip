@@ -243,12 +243,15 @@ struct SimHost {
   double Rmax;
 };
 
-// Per-phase timing with HIP events on the context's stream: per step four
-// events bracket k_fused, the particle kernels and k_moments.  A small ring of
+// Per-phase timing with HIP events on the context's stream: per step six
+// events bracket the interface kernels, k_fused, k_links, the other particle
+// kernels and k_moments.  A small ring of
 // event sets is reused; a set is harvested (its elapsed times accumulated)
 // before it is recorded again.
 constexpr int PROF_RING = 32;
-constexpr int PROF_KINDS = 4;  // 0 k_fused, 1 particle kernels, 2 k_moments, 3 k_interface
+// 0 k_fused, 1 particle kernels but k_links, 2 k_moments, 3 interface (k_normal,
+// k_curv), 4 k_links
+constexpr int PROF_KINDS = 5;
 constexpr int PROF_EVENTS = PROF_KINDS + 1;
 struct Profiler {
   bool on = false;
@@ -306,14 +309,20 @@ static void set_tile(SimDev& d, int tx) {
   d.tiles_y = (d.ny + (256 / tx) - 1) / (256 / tx);
 }
 
-// tiling of the moments pass: the widest of 64, 32, 16 that the box fills
+// tiling of the moments and interface passes: x-y tiles, the widest of 64,
+// 32, 16 that the box fills, each block marching mkz planes up z: 12 on planes
+// of 64k nodes or more (the two extra planes a block loads at its ends are
+// then a sixth of its work, not a third), 6 on smaller ones, whose neighbour
+// planes stay in the caches anyway (measured: the moments pass of a 256x128
+// plane is slower with 12)
 static void set_mom_tiling(SimDev& d) {
   d.mtile_x = d.nx >= 64 ? 64 : (d.nx >= 32 ? 32 : 16);
   d.mtile_lx = d.mtile_x == 64 ? 6 : (d.mtile_x == 32 ? 5 : 4);
   const int ty = 256 / d.mtile_x;
+  d.mkz = (long long)d.nx * d.ny >= 65536 ? 12 : 6;
   d.mtiles_x = (d.nx + d.mtile_x - 1) / d.mtile_x;
   d.mtiles_y = (d.ny + ty - 1) / ty;
-  d.mtiles_z = (d.nz + MOM_KZ - 1) / MOM_KZ;
+  d.mtiles_z = (d.nz + d.mkz - 1) / d.mkz;
 }
 static unsigned mom_blocks(const SimDev& d) {
   return (unsigned)((long long)d.mtiles_x * d.mtiles_y * d.mtiles_z);
@@ -613,8 +622,8 @@ static int prof_harvest(lbm_ctx* ctx, int slot) {
   Profiler& P = ctx->prof;
   if (!P.pending[slot]) return LBM_OK;
   HIPCHK(ctx, hipEventSynchronize(P.ev[slot][PROF_EVENTS - 1]));
-  // events: 0 | interface | 1 | fused | 2 | particles | 3 | moments | 4
-  const int kind_of_gap[PROF_KINDS] = {3, 0, 1, 2};
+  // events: 0 | interface | 1 | fused | 2 | links | 3 | particles | 4 | moments | 5
+  const int kind_of_gap[PROF_KINDS] = {3, 0, 4, 1, 2};
   for (int k = 0; k < PROF_KINDS; ++k) {
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, P.ev[slot][k], P.ev[slot][k + 1]));
@@ -636,6 +645,7 @@ static int step_once(lbm_ctx* ctx, int slot) {
   HIPCHK(ctx, launch_fused(b, ctx->storage, ctx->nblk, 0, nullptr, nullptr, nullptr, nullptr, st));
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][2], st));
   HIPCHK(ctx, launch_links(b, ctx->storage, ctx->np_rows, ctx->Bmax, st));
+  if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], st));
   ctx->cur ^= 1;
   ctx->rd ^= 1;
   const Batch a = batch_all(ctx);
@@ -645,10 +655,10 @@ static int step_once(lbm_ctx* ctx, int slot) {
     HIPCHK(ctx, launch_mask_update(a, ctx->np_rows, ctx->Bmax, true, st));
     HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, REFILL_STEP, st));
   }
-  if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][3], st));
+  if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][4], st));
   HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, ctx->mnblk, MOM_STEP, st));
   if (slot >= 0) {
-    HIPCHK(ctx, hipEventRecord(P.ev[slot][4], st));
+    HIPCHK(ctx, hipEventRecord(P.ev[slot][5], st));
     P.pending[slot] = true;
   }
   return LBM_OK;

@@ -7,8 +7,6 @@
 
 namespace lbm {
 
-// planes one block of the moments pass marches through
-constexpr int MOM_KZ = 6;
 
 // ---------------------------------------------------------------- lattice
 // D3Q19: rest, +-x, +-y, +-z, (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1).
@@ -184,9 +182,9 @@ struct SimDev {
   int tile_x, tile_lx, tiles_x, tiles_y;
   // blocks of the moments pass: x-y tiles of mtile_x (16, 32 or 64) by
   // 256 / mtile_x nodes
-  // (mtile_x = 1 << mtile_lx), each over MOM_KZ planes; mtiles_x by mtiles_y
+  // (mtile_x = 1 << mtile_lx), each over mkz planes; mtiles_x by mtiles_y
   // by mtiles_z of them
-  int mtile_x, mtile_lx, mtiles_x, mtiles_y, mtiles_z;
+  int mtile_x, mtile_lx, mtiles_x, mtiles_y, mtiles_z, mkz;
 };
 
 // lattice node of thread threadIdx.x in block lb of simulation s; false if the

@@ -104,7 +104,7 @@ __device__ __forceinline__ int xcd_tile(int lin, int nblk) {
 // from phi alone.
 //
 // A block takes an x-y tile of the simulation's moments tiling and marches up
-// MOM_KZ planes.  The colour sources of three planes of the tile grown by one
+// s.mkz planes.  The colour sources of three planes of the tile grown by one
 // node sit in an LDS ring; the next plane's sources are loaded while the
 // current plane is summed.
 constexpr int MOM_HALO = 66 * 6;  // largest tile plane grown by one: (64 + 2)(4 + 2)
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   GLB uint16_t* __restrict__ MASK = gp(s.mask);
   const int tx = s.mtile_x, ty = 256 >> s.mtile_lx, HX = tx + 2, HY = ty + 2;
   const int bx = sb.y % s.mtiles_x, r = sb.y / s.mtiles_x;
-  const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * MOM_KZ;
-  const int kz = min(MOM_KZ, nz - z0);
+  const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * s.mkz;
+  const int kz = min(s.mkz, nz - z0);
   const int t = (int)threadIdx.x;
   const int lx = t & (tx - 1), ly = t >> s.mtile_lx;
   const int gx = bx * tx + lx, gy = by * ty + ly;
@@ -289,170 +289,210 @@ enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 
 // ------------------------------------------------------ interface kernels
 // Colour gradient G = 3 sum_i w_i c_i phi(x + c_i) (isotropic stencil, the value
-// at x for solid neighbours), the geometric wetting rotation next to solids, and
-// the normal n = G / max(|G|, EPS_G); written as the planes (n, |G|).
-__global__ __launch_bounds__(256) void k_normal(Batch bt) {
-  // blocks follow the moments tiling: an x-y tile marching MOM_KZ planes, phi
-  // of three planes of the tile grown by one node in an LDS ring
-  __shared__ float ring[3][MOM_HALO];
+// at x for solid neighbours), the geometric wetting rotation next to solids,
+// the normal n = G / max(|G|, EPS_G); then the curvature kappa = div n (same
+// stencil and closure), the CSF coefficient c = -sigma kappa max(|G|, EPS_G) / 2
+// (the surface-tension force is c n) and the set of directions whose neighbour
+// is solid (bit i, bit 31 = node solid).  Written: the normal planes (n_x, n_y,
+// n_z, |G|; NaN and -1 at a solid node) and the curvature word.
+//
+// One kernel: a block takes an x-y tile of the moments tiling and marches up
+// its s.mkz planes.  phi of the tile grown by two nodes sits in an LDS ring of
+// five planes, the normals of the tile grown by one node in a ring of three;
+// per plane z the block loads phi of plane z + 2, forms the normals of plane
+// z + 1 on the grown tile (a node's normal is formed once per block that needs
+// it: 1.55 times per node for 64 x 4 tiles) and the curvature of plane z.  The
+// normals never travel to HBM and back between the two stencils.
+constexpr int IF_PHI = 68 * 8;          // largest tile plane grown by two: (64 + 4)(4 + 4)
+constexpr int IF_NRM = MOM_HALO;  // grown by one: (64 + 2)(4 + 2)
+__global__ __launch_bounds__(256) void k_interface(Batch bt) {
+  __shared__ float fring[5][IF_PHI];
+  // normals of three planes, one array per component (the curvature reads
+  // only the components its stencil direction needs)
+  __shared__ float nrx[3][IF_NRM], nry[3][IF_NRM], nrz[3][IF_NRM], nrg[3][IF_NRM];
   const int2 sb = batch_block_in(bt, bt.mblk, blockIdx.x);
   const SimDev& s = bt.tab[sb.x];
-  GLB float* __restrict__ NX = gp(s.nrm);
   const int N = (int)s.N;
   const GLB float* __restrict__ PHI = gp((const float*)s.rp[bt.rd ^ 1]) + s.N;
+  GLB float* __restrict__ NX = gp(s.nrm);
+  GLB float* __restrict__ CUR = gp((float*)s.curv);
   const int nx = s.nx, ny = s.ny, nz = s.nz, P = nx * ny;
-  const int tx = s.mtile_x, ty = 256 >> s.mtile_lx, HX = tx + 2, HY = ty + 2;
+  const int tx = s.mtile_x, ty = 256 >> s.mtile_lx;
+  const int FX = tx + 4, FY = ty + 4, HX = tx + 2, HY = ty + 2;
   const int bx = sb.y % s.mtiles_x, r = sb.y / s.mtiles_x;
-  const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * MOM_KZ;
-  const int kz = min(MOM_KZ, nz - z0);
+  const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * s.mkz;
+  const int kz = min(s.mkz, nz - z0);
   const int t = (int)threadIdx.x;
   const int lx = t & (tx - 1), ly = t >> s.mtile_lx;
   const int gx = bx * tx + lx, gy = by * ty + ly;
   const bool in = gx < nx && gy < ny;
-  int hoff[2];
+  const int x0 = bx * tx, y0 = by * ty;
+  // this thread's phi region entries (t, t + 256, t + 512): plane offsets
+  int foff[3];
+  bool fon[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int k = t + 256 * j;
+    fon[j] = k < FX * FY;
+    const int fy = k / FX, fx = k - fy * FX;
+    foff[j] = fon[j] ? wrapi(x0 - 2 + fx, nx) + nx * wrapi(y0 - 2 + fy, ny) : 0;
+  }
+  // this thread's normal region entries (t, t + 256)
+  int hx_[2], hy_[2];
   bool hon[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int k = t + 256 * j;
     hon[j] = k < HX * HY;
-    const int hy = k / HX, hx = k - hy * HX;
-    int x = bx * tx - 1 + hx, y = by * ty - 1 + hy;
-    x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
-    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-    hoff[j] = hon[j] ? min(x, nx - 1) + nx * min(y, ny - 1) : 0;
+    hy_[j] = k / HX;
+    hx_[j] = k - hy_[j] * HX;
   }
-  auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+  auto zw = [&](int z) { return wrapi(z, nz); };
+  auto fslot = [&](int z) { return (z + 10) % 5; };  // z >= -2
+  auto nslot = [&](int z) { return (z + 3) % 3; };   // z >= -1
+  auto load_phi = [&](int z, float* v) {
+    const int zp = zw(z);
 #pragma unroll
-  for (int dz = 0; dz < 2; ++dz) {
-    const int zp = zwrap(z0 - 1 + dz);
+    for (int j = 0; j < 3; ++j) v[j] = fon[j] ? PHI[foff[j] + P * zp] : 0.f;
+  };
+  auto store_phi = [&](int z, const float* v) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (fon[j]) fring[fslot(z)][t + 256 * j] = v[j];
+  };
+  const float qnan = __int_as_float(0x7fc00000);
+  // normal of region entry (hx, hy) of plane z from the phi ring
+  auto normal = [&](int hx, int hy, int z) -> v4f {
+    const int c = (hx + 1) + FX * (hy + 1);
+    const float* fm = fring[fslot(z - 1)];
+    const float* f0 = fring[fslot(z)];
+    const float* fp = fring[fslot(z + 1)];
+    const float p0 = f0[c];
+    if (!(p0 < PHI_SOLID_TEST)) return v4f{qnan, qnan, qnan, -1.0f};
+    float Gx = 0.f, Gy = 0.f, Gz = 0.f;
+    bool solid = false;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int i = pair_dir(q);
+      const float* sp_ = cz(i) > 0 ? fp : (cz(i) < 0 ? fm : f0);
+      const float* sm_ = cz(i) > 0 ? fm : (cz(i) < 0 ? fp : f0);
+      float vp = sp_[c + cx(i) + FX * cy(i)];
+      float vm = sm_[c - cx(i) - FX * cy(i)];
+      const bool spd = vp > PHI_SOLID_TEST, smd = vm > PHI_SOLID_TEST;
+      solid |= spd | smd;
+      vp = spd ? p0 : vp;
+      vm = smd ? p0 : vm;
+      const float d = 3.0f * wq(i) * (vp - vm);
+      Gx += (float)cx(i) * d;
+      Gy += (float)cy(i) * d;
+      Gz += (float)cz(i) * d;
+    }
+    if (solid) {
+      // identify the solid: the lowest-index neighbouring particle, else the wall
+      const int ax = wrapi(x0 - 1 + hx, nx), ay = wrapi(y0 - 1 + hy, ny), az = zw(z);
+      const Nbr nb(ax, ay, az, nx, ny, nz);
+      int minp = 0x7fffffff;
+      bool wall = false;
+      for (int i = 1; i < Q; ++i) {
+        const uint16_t m = s.mask[nb(i)];
+        if (m >= 2) minp = min(minp, (int)m - 2);
+        else if (m == 1) wall = true;
+      }
+      wetting_rotate(s, ax, ay, az, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
+    }
+    const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
+    const float ig = 1.0f / fmaxf(g, EPS_G);
+    return v4f{Gx * ig, Gy * ig, Gz * ig, g};
+  };
+  auto normals = [&](int z) {
+    const int sl = nslot(z);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      if (hon[j]) ring[(z0 + 2 + dz) % 3][k_of(t, j)] = PHI[hoff[j] + P * zp];
-  }
-  float nxt[2];
-  auto fetch = [&](int z) {
-    const int zp = zwrap(z + 1);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) nxt[j] = hon[j] ? PHI[hoff[j] + P * zp] : 0.f;
+      if (hon[j]) {
+        const v4f v = normal(hx_[j], hy_[j], z);
+        const int k = t + 256 * j;
+        nrx[sl][k] = v.x;
+        nry[sl][k] = v.y;
+        nrz[sl][k] = v.z;
+        nrg[sl][k] = v.w;
+      }
   };
-  fetch(z0);
-  const float qnan = __int_as_float(0x7fc00000);
+  // prologue: phi of planes z0 - 2 .. z0 + 1, normals of planes z0 - 1, z0
+  {
+    float v[3];
+    for (int dz = -2; dz <= 1; ++dz) {
+      load_phi(z0 + dz, v);
+      store_phi(z0 + dz, v);
+    }
+  }
+  float nxt[3];
+  load_phi(z0 + 2, nxt);
+  __syncthreads();
+  normals(z0 - 1);
+  normals(z0);
   for (int zz = 0; zz < kz; ++zz) {
     const int z = z0 + zz;
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (hon[j]) ring[(z + 1) % 3][k_of(t, j)] = nxt[j];
+    store_phi(z + 2, nxt);
     __syncthreads();
-    if (zz + 1 < kz) fetch(z + 1);
+    if (zz + 1 < kz) load_phi(z + 3, nxt);
+    normals(z + 1);
+    __syncthreads();
     if (in) {
       const int c0 = (lx + 1) + HX * (ly + 1);
       const int n = gx + nx * (gy + ny * z);
-      // solid node: NaN normal (tells stencils the neighbour is solid), |G| = -1
-      v4f out = {qnan, qnan, qnan, -1.0f};
-      const float p0 = ring[z % 3][c0];
-      if (p0 < PHI_SOLID_TEST) {
-        float Gx = 0.f, Gy = 0.f, Gz = 0.f;
-        bool solid = false;
+      const int s0 = nslot(z);
+      const v4f own = v4f{nrx[s0][c0], nry[s0][c0], nrz[s0][c0], nrg[s0][c0]};
+      float c = 0.f;
+      uint32_t bits = 0x80000000u;
+      if (own.w >= 0.f) {
+        // the components c_i selects, of both neighbours of each pair (a NaN
+        // marks a solid neighbour: its value is replaced by the node's own)
+        float Pc[9][3], Mc[9][3];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
           const int i = pair_dir(q);
-          float vp = ring[(z + 3 + cz(i)) % 3][c0 + cx(i) + HX * cy(i)];
-          float vm = ring[(z + 3 - cz(i)) % 3][c0 - cx(i) - HX * cy(i)];
-          const bool sp = vp > PHI_SOLID_TEST, sm = vm > PHI_SOLID_TEST;
-          solid |= sp | sm;
-          vp = sp ? p0 : vp;
-          vm = sm ? p0 : vm;
-          const float d = 3.0f * wq(i) * (vp - vm);
-          Gx += (float)cx(i) * d;
-          Gy += (float)cy(i) * d;
-          Gz += (float)cz(i) * d;
+          const int sp_ = nslot(z + cz(i)), sm_ = nslot(z - cz(i));
+          const int cp = c0 + cx(i) + HX * cy(i), cm = c0 - cx(i) - HX * cy(i);
+          Pc[q][0] = cx(i) != 0 ? nrx[sp_][cp] : 0.f;
+          Mc[q][0] = cx(i) != 0 ? nrx[sm_][cm] : 0.f;
+          Pc[q][1] = cy(i) != 0 ? nry[sp_][cp] : 0.f;
+          Mc[q][1] = cy(i) != 0 ? nry[sm_][cm] : 0.f;
+          Pc[q][2] = cz(i) != 0 ? nrz[sp_][cp] : 0.f;
+          Mc[q][2] = cz(i) != 0 ? nrz[sm_][cm] : 0.f;
         }
-        if (solid) {
-          // identify the solid: the lowest-index neighbouring particle, else the wall
-          const Nbr nb(gx, gy, z, nx, ny, nz);
-          int minp = 0x7fffffff;
-          bool wall = false;
-          for (int i = 1; i < Q; ++i) {
-            const uint16_t m = s.mask[nb(i)];
-            if (m >= 2) minp = min(minp, (int)m - 2);
-            else if (m == 1) wall = true;
+        float kappa = 0.f;
+        bits = 0u;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const int i = pair_dir(q), o = opp(i);
+          float px = Pc[q][0], py = Pc[q][1], pz = Pc[q][2];
+          float mx = Mc[q][0], my = Mc[q][1], mz = Mc[q][2];
+          const bool sp = (px != px) | (py != py) | (pz != pz);
+          const bool sm = (mx != mx) | (my != my) | (mz != mz);
+          if (sp) {
+            px = own.x;
+            py = own.y;
+            pz = own.z;
           }
-          wetting_rotate(s, gx, gy, z, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
+          if (sm) {
+            mx = own.x;
+            my = own.y;
+            mz = own.z;
+          }
+          kappa += 3.0f * wq(i) *
+                   ((float)cx(i) * (px - mx) + (float)cy(i) * (py - my) + (float)cz(i) * (pz - mz));
+          bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
         }
-        const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
-        const float ig = 1.0f / fmaxf(g, EPS_G);
-        out = v4f{Gx * ig, Gy * ig, Gz * ig, g};
+        c = -0.5f * s.sigma * kappa * fmaxf(own.w, EPS_G);
       }
-      NX[n] = out.x;
-      NX[N + n] = out.y;
-      NX[2 * N + n] = out.z;
-      NX[3 * N + n] = out.w;
+      NX[n] = own.x;
+      NX[N + n] = own.y;
+      NX[2 * N + n] = own.z;
+      NX[3 * N + n] = own.w;
+      CUR[2 * n] = c;
+      CUR[2 * n + 1] = __uint_as_float(bits);
     }
-    __syncthreads();
   }
-}
-
-// Curvature kappa = div n (same stencil and closure) and the CSF coefficient
-// c = -sigma kappa max(|G|, EPS_G) / 2 (the surface-tension force is c n); plus
-// the set of directions whose neighbour is solid (bit i), bit 31 = node solid.
-__global__ __launch_bounds__(256) void k_curv(Batch bt) {
-  const int2 sb = batch_block(bt, xcd_tile(blockIdx.x, gridDim.x));
-  const SimDev& s = bt.tab[sb.x];
-  // normal planes: x, y, z components (NaN at solid nodes), then |G|
-  const GLB float* __restrict__ NX = gp((const float*)s.nrm);
-  const GLB float* __restrict__ NY = NX + s.N;
-  const GLB float* __restrict__ NZ = NY + s.N;
-  const GLB float* __restrict__ NG = NZ + s.N;
-  GLB float* __restrict__ cur = gp((float*)s.curv);
-  const int nx = s.nx, ny = s.ny, nz = s.nz;
-  int n, gx, gy, gz;
-  if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
-  float c = 0.f;
-  uint32_t bits = 0x80000000u;
-  const float g0 = NG[n];
-  const float ncx = NX[n], ncy = NY[n], ncz = NZ[n];
-  // only the components c_i selects are loaded (a NaN marks a solid
-  // neighbour), all before the node's own value is examined
-  const Nbr nb(gx, gy, gz, nx, ny, nz);
-  float P[9][3], M[9][3];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const int i = pair_dir(q), mp = nb(i), mm = nb(opp(i));
-    P[q][0] = cx(i) != 0 ? NX[mp] : 0.f;
-    M[q][0] = cx(i) != 0 ? NX[mm] : 0.f;
-    P[q][1] = cy(i) != 0 ? NY[mp] : 0.f;
-    M[q][1] = cy(i) != 0 ? NY[mm] : 0.f;
-    P[q][2] = cz(i) != 0 ? NZ[mp] : 0.f;
-    M[q][2] = cz(i) != 0 ? NZ[mm] : 0.f;
-  }
-  if (g0 >= 0.f) {
-    float kappa = 0.f;
-    bits = 0u;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const int i = pair_dir(q), o = opp(i);
-      float px = P[q][0], py = P[q][1], pz = P[q][2];
-      float mx = M[q][0], my = M[q][1], mz = M[q][2];
-      const bool sp = (px != px) | (py != py) | (pz != pz);
-      const bool sm = (mx != mx) | (my != my) | (mz != mz);
-      if (sp) {
-        px = ncx;
-        py = ncy;
-        pz = ncz;
-      }
-      if (sm) {
-        mx = ncx;
-        my = ncy;
-        mz = ncz;
-      }
-      kappa += 3.0f * wq(i) *
-               ((float)cx(i) * (px - mx) + (float)cy(i) * (py - my) + (float)cz(i) * (pz - mz));
-      bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
-    }
-    c = -0.5f * s.sigma * kappa * fmaxf(g0, EPS_G);
-  }
-  cur[2 * n] = c;
-  cur[2 * n + 1] = __uint_as_float(bits);
 }
 
 // ------------------------------------------------------------- fused kernel
@@ -735,8 +775,8 @@ static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 
 // mask-box side of the batch.
 // nblk: per-node blocks; mnblk: blocks of the moments tiling (k_normal)
 hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_normal, dim3(mnblk), dim3(256), 0, st, b);
-  hipLaunchKernelGGL(k_curv, dim3(nblk), dim3(256), 0, st, b);
+  (void)nblk;
+  hipLaunchKernelGGL(k_interface, dim3(mnblk), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_sync", "lbm_par
            "lbm_fields", "lbm_fields2", "lbm_links", "lbm_mass", "lbm_dem_substeps", "lbm_destroy",
            "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_use_graph",
            "lbm_autotune", "lbm_set_tile", "lbm_mass_all_noalloc"]
-PROFILE_KINDS = ("fused", "particles", "moments", "interface")
+PROFILE_KINDS = ("fused", "particles", "moments", "interface", "links")
 
 
 class LbmConfig(C.Structure):
@@ -326,8 +326,8 @@ class Context:
         self._check(load_library().lbm_profile(self.h, int(every) if enable else 0))
 
     def profile_read(self):
-        """{kind: (total_ms, launches)} for the fused, particle, moments and
-        interface phases."""
+        """{kind: (total_ms, launches)} for the fused, particle (other than
+        the links), moments, interface and link phases."""
         n = len(PROFILE_KINDS)
         ms = (C.c_double * n)()
         cnt = (C.c_int64 * n)()

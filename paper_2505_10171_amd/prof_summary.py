@@ -25,7 +25,8 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", "lbm_fluid.hip"),
-                  os.path.join(HERE, "csrc", "lbm_device.h")]
+                  os.path.join(HERE, "csrc", "lbm_device.h"),
+                  os.path.join(HERE, "csrc", "lbm_api.hip")]
 
 
 def kernel_sources_hash() -> str:

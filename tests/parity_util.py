@@ -106,26 +106,38 @@ def compare_history(hg, ho, names, R, label="", tol=1e-5):
     return out
 
 
-def oracle_final_fields(args):
-    """Worker for a process pool: (cfg, phi0, particles, steps, threads) -> the
-    oracle's (rho, u, phi, mask) after `steps` steps."""
-    cfg, phi0, parts, steps, threads = args
+def oracle_fields_at(args):
+    """Worker for a process pool: (cfg, phi0, particles, marks, threads,
+    round_f32) -> the oracle's (rho, u, phi, mask) after each step count in
+    marks.  With round_f32 the state's departures from rest are rounded to
+    single precision after every step (a sensitivity probe of the method to
+    FP32 storage, not the method)."""
+    cfg, phi0, parts, marks, threads, round_f32 = args
     from oracle import oracle as O
     from oracle.oracle import OracleSim
     O.set_num_threads(threads)
     o = OracleSim(cfg, phi0, parts)
-    o.step(steps)
-    out = o.fields()
+    out, t = [], 0
+    for mk in marks:
+        while t < mk:
+            if round_f32:
+                o.step(1)
+                o.round_state_f32()
+                t += 1
+            else:
+                o.step(mk - t)
+                t = mk
+        out.append(o.fields())
     o.close()
     return out
 
 
-def oracle_runs_parallel(jobs, steps):
-    """Oracle runs of several (cfg, phi0, particles) jobs in parallel processes,
-    the host's cores split between them."""
+def oracle_runs_parallel(jobs):
+    """Oracle runs of several (cfg, phi0, particles, marks, round_f32) jobs in
+    parallel processes, the host's cores split between them."""
     import multiprocessing as mp
     import os
     threads = max(1, (len(os.sched_getaffinity(0)) or 2) // len(jobs))
     ctx = mp.get_context("spawn")
     with ctx.Pool(len(jobs)) as pool:
-        return pool.map(oracle_final_fields, [(c, p, q, steps, threads) for c, p, q in jobs])
+        return pool.map(oracle_fields_at, [(c, p, q, m, threads, r) for c, p, q, m, r in jobs])
