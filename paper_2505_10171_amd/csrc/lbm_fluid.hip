@@ -298,18 +298,19 @@ enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 //
 // One kernel: a block takes an x-y tile of the moments tiling and marches up
 // its s.mkz planes.  phi of the tile grown by two nodes sits in an LDS ring of
-// five planes, the normals of the tile grown by one node in a ring of three;
+// four planes, the normals of the tile grown by one node in a ring of three;
 // per plane z the block loads phi of plane z + 2, forms the normals of plane
 // z + 1 on the grown tile (a node's normal is formed once per block that needs
 // it: 1.55 times per node for 64 x 4 tiles) and the curvature of plane z.  The
 // normals never travel to HBM and back between the two stencils.
 constexpr int IF_PHI = 68 * 8;          // largest tile plane grown by two: (64 + 4)(4 + 4)
 constexpr int IF_NRM = MOM_HALO;  // grown by one: (64 + 2)(4 + 2)
-__global__ __launch_bounds__(256) void k_interface(Batch bt) {
-  __shared__ float fring[5][IF_PHI];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_interface(Batch bt) {
+  __shared__ float fring[4][IF_PHI];
   // normals of three planes, one array per component (the curvature reads
-  // only the components its stencil direction needs)
-  __shared__ float nrx[3][IF_NRM], nry[3][IF_NRM], nrz[3][IF_NRM], nrg[3][IF_NRM];
+  // only the components its stencil direction needs); |G| only where the
+  // curvature needs it, at the tile's own nodes
+  __shared__ float nrx[3][IF_NRM], nry[3][IF_NRM], nrz[3][IF_NRM], nrg[3][256];
   const int2 sb = batch_block_in(bt, bt.mblk, blockIdx.x);
   const SimDev& s = bt.tab[sb.x];
   const int N = (int)s.N;
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) void k_interface(Batch bt) {
     hx_[j] = k - hy_[j] * HX;
   }
   auto zw = [&](int z) { return wrapi(z, nz); };
-  auto fslot = [&](int z) { return (z + 10) % 5; };  // z >= -2
+  auto fslot = [&](int z) { return (z + 8) & 3; };  // z >= -2
   auto nslot = [&](int z) { return (z + 3) % 3; };   // z >= -1
   auto load_phi = [&](int z, float* v) {
     const int zp = zw(z);
@@ -414,7 +415,9 @@ __global__ __launch_bounds__(256) void k_interface(Batch bt) {
         nrx[sl][k] = v.x;
         nry[sl][k] = v.y;
         nrz[sl][k] = v.z;
-        nrg[sl][k] = v.w;
+        // a tile node: its |G| kept for the curvature
+        const int tlx = hx_[j] - 1, tly = hy_[j] - 1;
+        if (tlx >= 0 && tlx < tx && tly >= 0 && tly < ty) nrg[sl][tlx + tx * tly] = v.w;
       }
   };
   // prologue: phi of planes z0 - 2 .. z0 + 1, normals of planes z0 - 1, z0
@@ -430,6 +433,7 @@ __global__ __launch_bounds__(256) void k_interface(Batch bt) {
   __syncthreads();
   normals(z0 - 1);
   normals(z0);
+  __syncthreads();  // the loop's first phi store reuses the slot of plane z0 - 2
   for (int zz = 0; zz < kz; ++zz) {
     const int z = z0 + zz;
     store_phi(z + 2, nxt);
@@ -441,32 +445,25 @@ __global__ __launch_bounds__(256) void k_interface(Batch bt) {
       const int c0 = (lx + 1) + HX * (ly + 1);
       const int n = gx + nx * (gy + ny * z);
       const int s0 = nslot(z);
-      const v4f own = v4f{nrx[s0][c0], nry[s0][c0], nrz[s0][c0], nrg[s0][c0]};
+      const v4f own = v4f{nrx[s0][c0], nry[s0][c0], nrz[s0][c0], nrg[s0][t]};
       float c = 0.f;
       uint32_t bits = 0x80000000u;
       if (own.w >= 0.f) {
-        // the components c_i selects, of both neighbours of each pair (a NaN
-        // marks a solid neighbour: its value is replaced by the node's own)
-        float Pc[9][3], Mc[9][3];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const int i = pair_dir(q);
-          const int sp_ = nslot(z + cz(i)), sm_ = nslot(z - cz(i));
-          const int cp = c0 + cx(i) + HX * cy(i), cm = c0 - cx(i) - HX * cy(i);
-          Pc[q][0] = cx(i) != 0 ? nrx[sp_][cp] : 0.f;
-          Mc[q][0] = cx(i) != 0 ? nrx[sm_][cm] : 0.f;
-          Pc[q][1] = cy(i) != 0 ? nry[sp_][cp] : 0.f;
-          Mc[q][1] = cy(i) != 0 ? nry[sm_][cm] : 0.f;
-          Pc[q][2] = cz(i) != 0 ? nrz[sp_][cp] : 0.f;
-          Mc[q][2] = cz(i) != 0 ? nrz[sm_][cm] : 0.f;
-        }
+        // pair by pair: the components c_i selects, of both neighbours (a
+        // NaN marks a solid neighbour: its value is replaced by the node's own)
         float kappa = 0.f;
         bits = 0u;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
           const int i = pair_dir(q), o = opp(i);
-          float px = Pc[q][0], py = Pc[q][1], pz = Pc[q][2];
-          float mx = Mc[q][0], my = Mc[q][1], mz = Mc[q][2];
+          const int sp_ = nslot(z + cz(i)), sm_ = nslot(z - cz(i));
+          const int cp = c0 + cx(i) + HX * cy(i), cm = c0 - cx(i) - HX * cy(i);
+          float px = cx(i) != 0 ? nrx[sp_][cp] : 0.f;
+          float mx = cx(i) != 0 ? nrx[sm_][cm] : 0.f;
+          float py = cy(i) != 0 ? nry[sp_][cp] : 0.f;
+          float my = cy(i) != 0 ? nry[sm_][cm] : 0.f;
+          float pz = cz(i) != 0 ? nrz[sp_][cp] : 0.f;
+          float mz = cz(i) != 0 ? nrz[sm_][cm] : 0.f;
           const bool sp = (px != px) | (py != py) | (pz != pz);
           const bool sm = (mx != mx) | (my != my) | (mz != mz);
           if (sp) {
