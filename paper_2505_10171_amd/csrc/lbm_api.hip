@@ -42,7 +42,7 @@ hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int 
 // kernel modes (lbm_fluid.hip, lbm_particles.hip): in a step, or between steps
 constexpr int MOM_STEP = 0, MOM_BOUNDARY = 1, REFILL_STEP = 0, REFILL_BOUNDARY = 1;
 hipError_t launch_capillary(const Batch& b, int np_rows, int cap_B, int npts, hipStream_t st);
-hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st);
+hipError_t launch_dem(const Batch& b, int np_max, int np_rows, int n_sub_max, hipStream_t st);
 }  // namespace lbm
 
 using namespace lbm;
@@ -87,7 +87,8 @@ struct SimLayout {
   int np, Bmask, Bcap, hist_cap;
   size_t pop_bytes, fresh_cap;
   size_t off_pops0, off_pops1, off_rp0, off_rp1, off_nrm, off_cur, off_mask, off_claim, off_fresh, off_fresh_own,
-      off_counters, off_P, off_ct, off_nb, off_hist, off_capbox, off_caporg, off_mass, off_step;
+      off_counters, off_P, off_ct, off_nb, off_view, off_hist, off_capbox, off_caporg, off_mass,
+      off_step;
   size_t total;
 };
 
@@ -173,6 +174,7 @@ SimLayout layout(const lbm_config& c, double Rmax, int hist_cap, size_t base) {
   L.off_P = take(sizeof(DevParticle) * L.np);
   L.off_ct = take(sizeof(Contact) * (size_t)L.np * MAXC);
   L.off_nb = take(sizeof(int) * (size_t)L.np * MAXNB);
+  L.off_view = take(sizeof(DemView) * 2 * (size_t)L.np);
   L.off_hist = take(sizeof(double) * (size_t)L.hist_cap * L.np * LBM_HIST_DOUBLES);
   L.off_capbox = take(sizeof(float4) * (size_t)L.np * L.Bcap * L.Bcap * L.Bcap);
   L.off_caporg = take(sizeof(int) * 3 * (size_t)L.np);
@@ -283,7 +285,7 @@ struct lbm_ctx {
   uint32_t* d_mblk = nullptr;
   int2* d_pmap = nullptr;
   unsigned nblk = 0;
-  int np_rows = 0, np_max = 0, Bmax = 0, cap_B = 0, npts = 0;
+  int np_rows = 0, np_max = 0, Bmax = 0, cap_B = 0, npts = 0, n_sub_max = 1;
   size_t fresh_cap_max = 0;
   unsigned mnblk = 0;  // blocks of the moments pass over the batch
   // graph replay of a pair of steps (captured with cur == graph_cur)
@@ -379,6 +381,7 @@ static int upload_tables(lbm_ctx* ctx, size_t off) {
   std::vector<uint32_t> blk(n_sims + 1, 0), mblk(n_sims + 1, 0);
   std::vector<int2> pmap;
   ctx->np_max = ctx->Bmax = ctx->cap_B = ctx->npts = 0;
+  ctx->n_sub_max = 1;
   ctx->fresh_cap_max = 0;
   for (int si = 0; si < n_sims; ++si) {
     const SimHost& sh = ctx->sims[si];
@@ -391,6 +394,7 @@ static int upload_tables(lbm_ctx* ctx, size_t off) {
     blk[si + 1] = (uint32_t)nb;
     for (int p = 0; p < sh.d.np; ++p) pmap.push_back(make_int2(si, p));
     ctx->np_max = std::max(ctx->np_max, sh.d.np);
+    if (sh.d.np > 0) ctx->n_sub_max = std::max(ctx->n_sub_max, sh.d.n_sub);
     if (sh.d.np > 0) {
       ctx->Bmax = std::max(ctx->Bmax, sh.L.Bmask);
       ctx->cap_B = std::max(ctx->cap_B, sh.d.cap_B);
@@ -534,6 +538,7 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.P = (DevParticle*)(b + sh.L.off_P);
     d.ct = (Contact*)(b + sh.L.off_ct);
     d.nb = (int*)(b + sh.L.off_nb);
+    d.view = (DemView*)(b + sh.L.off_view);
     d.hist = (double*)(b + sh.L.off_hist);
     d.hist_cap = sh.L.hist_cap;
     d.n_sub = n_sub;
@@ -651,7 +656,7 @@ static int step_once(lbm_ctx* ctx, int slot) {
   const Batch a = batch_all(ctx);
   if (ctx->np_rows > 0) {
     HIPCHK(ctx, launch_capillary(a, ctx->np_rows, ctx->cap_B, ctx->npts, st));
-    HIPCHK(ctx, launch_dem(a, ctx->np_max, st));
+    HIPCHK(ctx, launch_dem(a, ctx->np_max, ctx->np_rows, ctx->n_sub_max, st));
     HIPCHK(ctx, launch_mask_update(a, ctx->np_rows, ctx->Bmax, true, st));
     HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, REFILL_STEP, st));
   }

@@ -71,6 +71,12 @@ struct alignas(16) DevParticle {
 
 constexpr int LBM_HIST_DOUBLES_DEV = 27;
 
+// What a particle's contacts read of it: centre, contact radius, predicted
+// velocities and friction coefficients (96 bytes).
+struct DemView {
+  double x[3], Rc, vp[3], mu_s, wp[3], mu_r;
+};
+
 struct Contact {
   int partner;  // -1 wall surface, -2 wall underside, >= 0 particle, -100 free
   int pad;
@@ -164,6 +170,7 @@ struct SimDev {
   DevParticle* P;
   Contact* ct;         // np * MAXC
   int* nb;             // np * MAXNB candidate partners
+  DemView* view;       // 2 * np: the DEM's views of the particles, two sub-steps
   double* hist;        // hist_cap * np * 27
   int hist_cap;
   int n_sub;

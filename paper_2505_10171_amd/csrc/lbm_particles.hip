@@ -503,25 +503,6 @@ __device__ __forceinline__ void stage_in(double* dst, const double* src1, int n1
   }
 }
 
-// What a particle's contacts read of it: centre, contact radius, predicted
-// velocities and friction coefficients (96 bytes).
-struct DemView {
-  double x[3], Rc, vp[3], mu_s, wp[3], mu_r;
-};
-
-// Where the DEM keeps its data for one lattice step:
-// DEM_GLOBAL  particle records, contact tables and candidate lists in global
-//             memory;
-// DEM_SHARED  all three staged in LDS and written back at the end;
-// DEM_VIEW    records and contact tables in global memory, but the view of
-//             every particle (DemView) and the candidate lists (16-bit) in LDS,
-//             so that the all-pairs candidate search and the neighbour reads
-//             of the contact loop wait on LDS; the view is refreshed by its
-//             owner after each predictor update.
-enum DemMode { DEM_GLOBAL = 0, DEM_SHARED = 1, DEM_VIEW = 2 };
-constexpr uint16_t NB16_END = 0xFFFF;
-constexpr size_t DEM_VIEW_LDS = 160 * 1024;  // LDS a gfx950 workgroup can have
-
 // Contact forces and torques on one particle from the walls and from its
 // candidates.  T is the record type the particle data is read from (DevParticle
 // or DemView: the same field names); cand(q) is the q-th candidate or -1 past
@@ -581,9 +562,9 @@ __device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, cons
 // up to 32 MAXNB particles): thread (i, w) tests particle i against partners
 // 32 w .. 32 w + 31 (centre distance, minimum image, below Rc_i + Rc_j + skin)
 // and stores the hit mask as word w of row i of the candidate-list buffer
-// (MAXNB words per particle), which k_dem turns into the candidate list.
-// Positions and contact radii are those k_dem starts the step from (its
-// set-up changes neither).  Grid (ceil(np_max ceil(np_max / 32) / 256), nsim).
+// (MAXNB words per particle), which k_dem_setup turns into the candidate list.
+// Positions and contact radii are those the step starts from.  Grid
+// (ceil(np_max ceil(np_max / 32) / 256), nsim).
 __global__ __launch_bounds__(256) void k_dem_search(Batch bt) {
   const SimDev& s = bt.tab[blockIdx.y];
   const int np = s.np;
@@ -611,53 +592,34 @@ __global__ __launch_bounds__(256) void k_dem_search(Batch bt) {
   ((uint32_t*)s.nb)[(long long)i * MAXNB + w] = hit;
 }
 
-// One workgroup per simulation.  Fluid forces (momentum exchange + capillary)
-// are held over n_sub velocity-Verlet sub-steps; contacts are evaluated at the
-// new positions with the predicted velocities; gravity is the downward g_p.
-template <int MODE, bool PRE, int NT>
-__global__ __launch_bounds__(NT) void k_dem(Batch bt) {
-  // one workgroup per simulation
+// Boxes with few particles (their records, contact tables and candidate
+// lists fit 64 KB of LDS): one workgroup per simulation, everything staged in
+// LDS for the whole lattice step (the dependent FP64 chains then wait on LDS,
+// not on L2/HBM) and written back at the end.  Fluid forces (momentum exchange
+// + capillary) are held over n_sub velocity-Verlet sub-steps; contacts are
+// evaluated at the new positions with the predicted velocities; gravity is the
+// downward g_p.
+__global__ __launch_bounds__(256) void k_dem(Batch bt) {
   const SimDev& s = bt.tab[blockIdx.x];
   if (s.np == 0) return;
   extern __shared__ double dem_lds[];
-  DevParticle* PP = s.P;
-  Contact* CT = s.ct;
-  int* NB = s.nb;
-  DemView* V = nullptr;
-  uint16_t* NB16 = nullptr;
-  const size_t wP = (size_t)s.np * sizeof(DevParticle) / 8;
-  const size_t wC = (size_t)s.np * MAXC * sizeof(Contact) / 8;
-  if (MODE == DEM_SHARED) {
-    // particle records, contact tables and candidate lists in LDS for the
-    // whole lattice step (dependent FP64 chains then wait on LDS, not on
-    // L2/HBM), written back at the end
-    double* lp = dem_lds;
-    double* lc = lp + wP;
-    PP = (DevParticle*)lp;
-    CT = (Contact*)lc;
-    NB = (int*)(lc + wC);
-    // records and contact tables in one pass (lc follows lp)
-    stage_in(lp, (const double*)s.P, (int)wP, (const double*)s.ct, (int)wC);
-    __syncthreads();
-  }
-  if (MODE == DEM_VIEW) {
-    V = (DemView*)dem_lds;
-    NB16 = (uint16_t*)(V + s.np);
-  }
   const int np = s.np;
   const int nt = blockDim.x;
+  const size_t wP = (size_t)np * sizeof(DevParticle) / 8;
+  const size_t wC = (size_t)np * MAXC * sizeof(Contact) / 8;
+  double* lp = dem_lds;
+  double* lc = lp + wP;
+  DevParticle* PP = (DevParticle*)lp;
+  Contact* CT = (Contact*)lc;
+  int* NB = (int*)(lc + wC);
+  // records and contact tables in one pass (lc follows lp)
+  stage_in(lp, (const double*)s.P, (int)wP, (const double*)s.ct, (int)wC);
+  __syncthreads();
   const double dt = 1.0 / s.n_sub;
   const double skin = 1.5;
-  // what the pair search and the contacts read of particle j
-  auto rec = [&](int j) -> decltype(auto) {
-    if constexpr (MODE == DEM_VIEW)
-      return (const DemView&)V[j];
-    else
-      return (const DevParticle&)PP[j];
-  };
-  // per-step set-up
-  // fluid force and torque: mean of this and the previous lattice step (the
-  // averaging of the Verlet update over the previous and current step)
+  // per-step set-up: fluid force and torque, the mean of this and the previous
+  // lattice step (the averaging of the Verlet update over the previous and
+  // current step)
   for (int i = threadIdx.x; i < np; i += nt) {
     DevParticle& P = PP[i];
     for (int d = 0; d < 3; ++d) {
@@ -682,84 +644,43 @@ __global__ __launch_bounds__(NT) void k_dem(Batch bt) {
     P.Ff[2] -= P.g_p;
     P.Ro = P.R;
     P.havep = 1;
-    if (MODE == DEM_VIEW) {
-      DemView& v = V[i];
-      for (int d = 0; d < 3; ++d) v.x[d] = P.x[d];
-      v.Rc = P.Rc;
-      v.mu_s = P.mu_s;
-      v.mu_r = P.mu_r;
-    }
   }
   __syncthreads();
   // pair candidates within Rc_i + Rc_j + skin (ascending index)
   for (int i = threadIdx.x; i < np; i += nt) {
-    const auto& me = rec(i);
+    const DevParticle& me = PP[i];
     int* nb = NB + (long long)i * MAXNB;
-    uint16_t* nb16 = NB16 + (long long)i * MAXNB;
     int c = 0;
-    if (PRE) {
-      // the pair tests were made by k_dem_search: row i of the candidate-list
-      // buffer holds one hit mask per 32 partners; all words loaded at once
-      const uint32_t* hm = (const uint32_t*)NB + (long long)i * MAXNB;
-      const int nw = (np + 31) / 32;
-      uint32_t words[MAXNB];
-#pragma unroll
-      for (int w = 0; w < MAXNB; ++w) words[w] = w < nw ? hm[w] : 0u;
-#pragma unroll
-      for (int w = 0; w < MAXNB; ++w) {
-        uint32_t hit = words[w];
-        while (hit) {
-          const int j = 32 * w + __builtin_ctz(hit);
-          hit &= hit - 1;
-          if (c < MAXNB)
-            nb16[c++] = (uint16_t)j;
-          else
-            atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
-        }
-      }
-    } else {
-      // 32 partners per pass: the tests only set bits (no stores between the
-      // loads), then the hits are appended in ascending order
-      for (int j0 = 0; j0 < np; j0 += 32) {
-        const int jn = min(32, np - j0);
-        uint32_t hit = 0;
+    // 32 partners per pass: the tests only set bits (no stores between the
+    // loads), then the hits are appended in ascending order
+    for (int j0 = 0; j0 < np; j0 += 32) {
+      const int jn = min(32, np - j0);
+      uint32_t hit = 0;
 #pragma unroll 4
-        for (int u = 0; u < jn; ++u) {
-          const int j = j0 + u;
-          const auto& pj = rec(j);
-          double dx[3];
-          rel_vec(s, me.x, pj.x, dx);
-          const double lim = me.Rc + pj.Rc + skin;
-          if (j != i && dot3(dx, dx) < lim * lim) hit |= 1u << u;
-        }
-        while (hit) {
-          const int j = j0 + __builtin_ctz(hit);
-          hit &= hit - 1;
-          if (c < MAXNB) {
-            if (MODE == DEM_VIEW)
-              nb16[c++] = (uint16_t)j;
-            else
-              nb[c++] = j;
-          } else {
-            atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
-          }
-        }
+      for (int u = 0; u < jn; ++u) {
+        const int j = j0 + u;
+        double dx[3];
+        rel_vec(s, me.x, PP[j].x, dx);
+        const double lim = me.Rc + PP[j].Rc + skin;
+        if (j != i && dot3(dx, dx) < lim * lim) hit |= 1u << u;
+      }
+      while (hit) {
+        const int j = j0 + __builtin_ctz(hit);
+        hit &= hit - 1;
+        if (c < MAXNB)
+          nb[c++] = j;
+        else
+          atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
       }
     }
-    if (c < MAXNB) {
-      if (MODE == DEM_VIEW)
-        nb16[c] = NB16_END;
-      else
-        nb[c] = -1;
-    }
+    if (c < MAXNB) nb[c] = -1;
     // free pair springs whose partner is out of range
     Contact* tab = CT + (long long)i * MAXC;
     for (int k = 0; k < MAXC; ++k) {
       const int pt = tab[k].partner;
       if (pt < 0) continue;
       bool found = false;
-      for (int q = 0; q < c && q < MAXNB; ++q)
-        found |= (MODE == DEM_VIEW ? (int)nb16[q] : nb[q]) == pt;
+      for (int q = 0; q < c && q < MAXNB; ++q) found |= nb[q] == pt;
       if (!found) tab[k].partner = -100;
     }
   }
@@ -790,33 +711,16 @@ __global__ __launch_bounds__(NT) void k_dem(Batch bt) {
         else if (P.x[d] < 0.0)
           P.x[d] += L[d];
       }
-      if (MODE == DEM_VIEW) {
-        DemView& v = V[i];
-        for (int d = 0; d < 3; ++d) {
-          v.x[d] = P.x[d];
-          v.vp[d] = P.vp[d];
-          v.wp[d] = P.wp[d];
-        }
-      }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < np; i += nt) {
       DevParticle& P = PP[i];
       Contact* tab = CT + (long long)i * MAXC;
       double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0};
-      if constexpr (MODE == DEM_VIEW) {
-        const uint16_t* nb16 = NB16 + (long long)i * MAXNB;
-        dem_contacts(
-            s, tab, V[i],
-            [&](int q) {
-              const uint16_t u = nb16[q];
-              return u == NB16_END ? -1 : (int)u;
-            },
-            rec, dt, Fs, Ts);
-      } else {
-        const int* nb = NB + (long long)i * MAXNB;
-        dem_contacts(s, tab, P, [&](int q) { return nb[q]; }, rec, dt, Fs, Ts);
-      }
+      const int* nb = NB + (long long)i * MAXNB;
+      dem_contacts(
+          s, tab, P, [&](int q) { return nb[q]; },
+          [&](int j) -> const DevParticle& { return PP[j]; }, dt, Fs, Ts);
       for (int d = 0; d < 3; ++d) {
         P.Fcn[d] = Fs[d];
         P.Tcn[d] = Ts[d];
@@ -864,11 +768,354 @@ __global__ __launch_bounds__(NT) void k_dem(Batch bt) {
     }
   }
   __syncthreads();
-  if (MODE == DEM_SHARED) {
-    for (size_t k = threadIdx.x; k < wP; k += blockDim.x) ((double*)s.P)[k] = dem_lds[k];
-    for (size_t k = threadIdx.x; k < wC; k += blockDim.x) ((double*)s.ct)[k] = dem_lds[wP + k];
-  }
+  for (size_t k = threadIdx.x; k < wP; k += blockDim.x) ((double*)s.P)[k] = dem_lds[k];
+  for (size_t k = threadIdx.x; k < wC; k += blockDim.x) ((double*)s.ct)[k] = dem_lds[wP + k];
   if (threadIdx.x == 0) *s.step_counter = step + 1;
+}
+
+// ---------------------------------------------- DEM over the whole GPU
+// Boxes with more particles than the LDS variants hold well: each lattice step
+// runs k_dem_setup (one thread per particle: fluid force mean, candidate list,
+// predictor of the first sub-step), then per DEM sub-step one launch of
+// k_dem_sub with a wave per particle: lane q < MAXNB evaluates the contact
+// with candidate q, lanes MAXNB and MAXNB + 1 the wall and its underside; the
+// contact forces are summed over the wave, and lane 0 applies the corrector and
+// the predictor of the next sub-step.  The positions and predicted velocities
+// the contacts read are the view of the sub-step (two buffers, so that a
+// sub-step's predictor does not overwrite what its contacts still read), and
+// a particle's contact table is written only by its own wave.
+
+// Predictor of a sub-step (velocity Verlet, held fluid force, contact force of
+// the last sub-step): new centre, orientation and predicted velocities, into
+// the record and the view.
+__device__ void dem_predict(const SimDev& s, DevParticle& P, DemView& v, double dt) {
+  double th[3];
+  for (int d = 0; d < 3; ++d) {
+    if (P.kin) {
+      P.ao[d] = 0.0;
+      P.bo[d] = 0.0;
+    } else {
+      P.ao[d] = (P.Ff[d] + P.Fcp[d]) / P.mass;
+      P.bo[d] = (P.Tf[d] + P.Tcp[d]) / P.inertia;
+    }
+    P.x[d] += P.v[d] * dt + 0.5 * P.ao[d] * dt * dt;
+    th[d] = P.w[d] * dt + 0.5 * P.bo[d] * dt * dt;
+    P.vp[d] = P.v[d] + P.ao[d] * dt;
+    P.wp[d] = P.w[d] + P.bo[d] * dt;
+  }
+  quat_rotate(P.q, th);
+  const double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
+  for (int d = 0; d < 3; ++d) {
+    if (d == 2 && s.has_wall) continue;
+    if (P.x[d] >= L[d])
+      P.x[d] -= L[d];
+    else if (P.x[d] < 0.0)
+      P.x[d] += L[d];
+  }
+  for (int d = 0; d < 3; ++d) {
+    v.x[d] = P.x[d];
+    v.vp[d] = P.vp[d];
+    v.wp[d] = P.wp[d];
+  }
+}
+
+// Pair candidates of every particle within Rc_i + Rc_j + skin by a full loop
+// (boxes too large for the hit masks of k_dem_search), ascending, as lists
+// of the candidate-list buffer (-1 after the last).
+__global__ __launch_bounds__(64) void k_dem_lists(Batch bt, int np_rows) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= np_rows) return;
+  const int2 sp = batch_particle(bt, r);
+  const SimDev& s = bt.tab[sp.x];
+  const int i = sp.y, np = s.np;
+  const DevParticle* PP = s.P;
+  const double skin = 1.5;
+  const double xi[3] = {PP[i].x[0], PP[i].x[1], PP[i].x[2]};
+  const double Rci = PP[i].Rc;
+  int* nb = s.nb + (long long)i * MAXNB;
+  int c = 0;
+  for (int j = 0; j < np; ++j) {
+    if (j == i) continue;
+    const double xj[3] = {PP[j].x[0], PP[j].x[1], PP[j].x[2]};
+    double dx[3];
+    rel_vec(s, xi, xj, dx);
+    const double lim = Rci + PP[j].Rc + skin;
+    if (dot3(dx, dx) < lim * lim) {
+      if (c < MAXNB)
+        nb[c++] = j;
+      else
+        atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+    }
+  }
+  if (c < MAXNB) nb[c] = -1;
+}
+
+// Per-step set-up of one particle (thread): held fluid force and torque (mean
+// of this and the previous lattice step) and gravity, its candidate list (from
+// k_dem_search's hit masks when `masks`, else the lists of k_dem_lists), the
+// springs of partners that left it freed, the predictor of the first
+// sub-step into view 0, and the constant view fields in both views.
+__global__ __launch_bounds__(64) void k_dem_setup(Batch bt, int np_rows, int masks) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= np_rows) return;
+  const int2 sp = batch_particle(bt, r);
+  const SimDev& s = bt.tab[sp.x];
+  const int i = sp.y, np = s.np;
+  DevParticle& P = s.P[i];
+  for (int d = 0; d < 3; ++d) {
+    P.Fcap[d] = P.Fca[d];
+    P.Tcap[d] = P.Tca[d];
+    P.Fca[d] = 0.0;
+    P.Tca[d] = 0.0;
+    const double fc = P.Fh[d] + P.Fcap[d], tc = P.Th[d] + P.Tcap[d];
+    const double fp = P.havep ? P.Ffp[d] : fc, tp = P.havep ? P.Tfp[d] : tc;
+    P.Ff[d] = 0.5 * (fc + fp);
+    P.Tf[d] = 0.5 * (tc + tp);
+    P.Ffp[d] = fc;
+    P.Tfp[d] = tc;
+    P.Fh_last[d] = P.Fh[d];
+    P.Th_last[d] = P.Th[d];
+    P.Fh[d] = 0.0;
+    P.Th[d] = 0.0;
+    P.xo[d] = P.x[d];
+    P.Facc[d] = 0.0;
+    P.Tacc[d] = 0.0;
+  }
+  P.Ff[2] -= P.g_p;
+  P.Ro = P.R;
+  P.havep = 1;
+  // the step counter advances here (the sub-steps' history record takes the
+  // value before it)
+  if (i == 0) *s.step_counter += 1;
+  int* nb = s.nb + (long long)i * MAXNB;
+  int c = 0;
+  if (masks) {
+    // row i holds one hit mask per 32 partners: all words read before the
+    // list overwrites them
+    const int nw = (np + 31) / 32;
+    uint32_t words[MAXNB];
+#pragma unroll
+    for (int w = 0; w < MAXNB; ++w) words[w] = w < nw ? ((const uint32_t*)nb)[w] : 0u;
+#pragma unroll
+    for (int w = 0; w < MAXNB; ++w) {
+      uint32_t hit = words[w];
+      while (hit) {
+        const int j = 32 * w + __builtin_ctz(hit);
+        hit &= hit - 1;
+        if (c < MAXNB)
+          nb[c++] = j;
+        else
+          atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+      }
+    }
+    if (c < MAXNB) nb[c] = -1;
+  } else {
+    while (c < MAXNB && nb[c] >= 0) ++c;
+  }
+  // free pair springs whose partner is out of range
+  Contact* tab = s.ct + (long long)i * MAXC;
+  for (int k = 0; k < MAXC; ++k) {
+    const int pt = tab[k].partner;
+    if (pt < 0) continue;
+    bool found = false;
+    for (int q = 0; q < c; ++q) found |= nb[q] == pt;
+    if (!found) tab[k].partner = -100;
+  }
+  DemView* V0 = s.view;
+  DemView* V1 = s.view + np;
+  V0[i].Rc = V1[i].Rc = P.Rc;
+  V0[i].mu_s = V1[i].mu_s = P.mu_s;
+  V0[i].mu_r = V1[i].mu_r = P.mu_r;
+  dem_predict(s, P, V0[i], 1.0 / s.n_sub);
+}
+
+// The contact force of one active contact whose spring slot sl is known
+// (normal spring-dashpot, sliding and rolling friction after Luding's model as
+// the paper describes it); the same arithmetic as contact().
+__device__ __forceinline__ void contact_force(const SimDev& s, Contact* sl, double delta,
+                                              const double* nh, const double* vi,
+                                              const double* wi, const double* vj,
+                                              const double* wj, double Rci, double Rcj,
+                                              const double* armj, double mu, double mur,
+                                              double dt, double* Fo, double* To) {
+  double vrel[3];
+  for (int d = 0; d < 3; ++d) vrel[d] = vi[d] - vj[d];
+  const double ddot = -dot3(vrel, nh);
+  const double Fn = s.kn * delta + s.gn * ddot;
+  double ri[3], rj[3], t1[3], t2[3], vc[3];
+  for (int d = 0; d < 3; ++d) ri[d] = -(Rci - 0.5 * delta) * nh[d];
+  for (int d = 0; d < 3; ++d) rj[d] = ri[d] + armj[d];
+  cross3(wi, ri, t1);
+  cross3(wj, rj, t2);
+  for (int d = 0; d < 3; ++d) vc[d] = vrel[d] + t1[d] - t2[d];
+  const double vn = dot3(vc, nh);
+  double vt[3];
+  for (int d = 0; d < 3; ++d) vt[d] = vc[d] - vn * nh[d];
+  double xt[3], xr[3];
+  for (int d = 0; d < 3; ++d) {
+    xt[d] = sl->xt[d];
+    xr[d] = sl->xr[d];
+  }
+  double xn = dot3(xt, nh);
+  for (int d = 0; d < 3; ++d) xt[d] -= xn * nh[d];
+  xn = dot3(xr, nh);
+  for (int d = 0; d < 3; ++d) xr[d] -= xn * nh[d];
+  const double Fcap = mu * (Fn > 0.0 ? Fn : 0.0);
+  double Ft[3];
+  capped_spring(s.kt, s.gt, Fcap, xt, vt, dt, Ft);
+  const double ap = (Rcj > 0.0) ? Rci * Rcj / (Rci + Rcj) : Rci;
+  double nwi[3], nwj[3], vr[3], Fr[3];
+  cross3(nh, wi, nwi);
+  cross3(nh, wj, nwj);
+  for (int d = 0; d < 3; ++d) vr[d] = -ap * (nwi[d] - nwj[d]);
+  const double Rcap = mur * (Fn > 0.0 ? Fn : 0.0);
+  capped_spring(s.kr, s.gr, Rcap, xr, vr, dt, Fr);
+  for (int d = 0; d < 3; ++d) {
+    sl->xt[d] = xt[d];
+    sl->xr[d] = xr[d];
+  }
+  double Tt[3], Tr[3];
+  cross3(ri, Ft, Tt);
+  cross3(nh, Fr, Tr);
+  for (int d = 0; d < 3; ++d) {
+    Fo[d] = Fn * nh[d] + Ft[d];
+    To[d] = Tt[d] + ap * Tr[d];
+  }
+}
+
+// One DEM sub-step of every particle: a wave per particle (four per block).
+__global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub) {
+  const int r = blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+  const int lane = (int)threadIdx.x & 63;
+  if (r >= np_rows) return;  // the whole wave
+  const int2 sp = batch_particle(bt, r);
+  const SimDev& s = bt.tab[sp.x];
+  if (sub >= s.n_sub) return;
+  const int i = sp.y, np = s.np;
+  const double dt = 1.0 / s.n_sub;
+  const DemView* V = s.view + (sub & 1) * np;
+  const DemView& me = V[i];
+  Contact* tab = s.ct + (long long)i * MAXC;
+  int ids[MAXC];
+#pragma unroll
+  for (int k = 0; k < MAXC; ++k) ids[k] = tab[k].partner;
+  // this lane's partner: candidate `lane`, or the wall (-1) or its underside (-2)
+  int partner = -100;
+  if (lane < MAXNB) {
+    const int j = s.nb[(long long)i * MAXNB + lane];
+    partner = j >= 0 ? j : -100;
+    // lanes past the list's end stay idle (a list shorter than MAXNB ends at -1)
+    if (j >= 0)
+      for (int q = 0; q < lane; ++q)
+        if (s.nb[(long long)i * MAXNB + q] < 0) partner = -100;
+  } else if (lane == MAXNB && s.has_wall) {
+    partner = -1;
+  } else if (lane == MAXNB + 1 && s.has_wall) {
+    partner = -2;
+  }
+  const double zero[3] = {0.0, 0.0, 0.0};
+  double delta = 0.0, nh[3] = {0.0, 0.0, 0.0}, arm[3] = {0.0, 0.0, 0.0};
+  const double* vj = zero;
+  const double* wj = zero;
+  double Rcj = 0.0, mu = me.mu_s, mur = me.mu_r;
+  if (partner >= 0) {
+    const DemView& pj = V[partner];
+    rel_vec(s, me.x, pj.x, arm);  // X_i - X_j, min image
+    const double dist = sqrt(dot3(arm, arm));
+    Rcj = pj.Rc;
+    delta = me.Rc + Rcj - dist;
+    if (dist > 0.0)
+      for (int d = 0; d < 3; ++d) nh[d] = arm[d] / dist;
+    vj = pj.vp;
+    wj = pj.wp;
+    mu = 0.5 * (me.mu_s + pj.mu_s);
+    mur = 0.5 * (me.mu_r + pj.mu_r);
+  } else if (partner == -1) {
+    delta = me.Rc - (me.x[2] - 0.5);
+    nh[2] = 1.0;
+  } else if (partner == -2) {
+    delta = me.Rc - (((double)s.nz - 0.5) - me.x[2]);
+    nh[2] = -1.0;
+  }
+  const bool has = partner != -100;
+  const bool active = has && delta > 0.0;
+  int found = -1, nfree = 0;
+#pragma unroll
+  for (int k = MAXC - 1; k >= 0; --k)
+    if (has && ids[k] == partner) found = k;
+  // new contacts take the free slots in lane order (free before this pass)
+  const unsigned long long need = __ballot(active && found < 0);
+  const int rank = __popcll(need & ((1ull << lane) - 1ull));
+  int slot = found;
+  if (active && found < 0) {
+    slot = -1;
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k)
+      if (ids[k] == -100) {
+        if (nfree == rank) slot = k;
+        ++nfree;
+      }
+    if (slot < 0) {
+      atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+    } else {
+      tab[slot].partner = partner;
+      for (int d = 0; d < 3; ++d) tab[slot].xt[d] = tab[slot].xr[d] = 0.0;
+    }
+  }
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  if (active && slot >= 0) {
+    double Fo[3], To[3];
+    contact_force(s, &tab[slot], delta, nh, me.vp, me.wp, vj, wj, me.Rc, Rcj, arm, mu, mur, dt,
+                  Fo, To);
+    for (int d = 0; d < 3; ++d) {
+      acc[d] = Fo[d];
+      acc[3 + d] = To[d];
+    }
+  } else if (has && !active && found >= 0) {
+    tab[found].partner = -100;  // the contact ended: its springs are released
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+  if (lane != 0) return;
+  DevParticle& P = s.P[i];
+  for (int d = 0; d < 3; ++d) {
+    if (!P.kin) {
+      const double an = (P.Ff[d] + acc[d]) / P.mass;
+      const double bn = (P.Tf[d] + acc[3 + d]) / P.inertia;
+      P.v[d] += 0.5 * (P.ao[d] + an) * dt;
+      P.w[d] += 0.5 * (P.bo[d] + bn) * dt;
+    }
+    P.Fcp[d] = acc[d];
+    P.Tcp[d] = acc[3 + d];
+    P.Facc[d] += acc[d];
+    P.Tacc[d] += acc[3 + d];
+  }
+  if (sub + 1 < s.n_sub) {
+    dem_predict(s, P, s.view[((sub + 1) & 1) * np + i], dt);
+    return;
+  }
+  // the last sub-step: contact means and the history record
+  for (int d = 0; d < 3; ++d) {
+    P.Fcon[d] = P.Facc[d] / s.n_sub;
+    P.Tcon[d] = P.Tacc[d] / s.n_sub;
+  }
+  if (s.hist_cap > 0) {
+    const unsigned long long step = *s.step_counter - 1;  // advanced by k_dem_setup
+    double* h = s.hist + ((long long)(step % (unsigned long long)s.hist_cap) * np + i) *
+                             LBM_HIST_DOUBLES_DEV;
+    for (int d = 0; d < 3; ++d) {
+      h[d] = P.Fh_last[d];
+      h[3 + d] = P.Th_last[d];
+      h[6 + d] = P.Fcap[d];
+      h[9 + d] = P.Tcap[d];
+      h[12 + d] = P.Fcon[d];
+      h[15 + d] = P.Tcon[d];
+      h[18 + d] = P.x[d];
+      h[21 + d] = P.v[d];
+      h[24 + d] = P.w[d];
+    }
+  }
 }
 
 // ------------------------------------------------------------ host launchers
@@ -923,8 +1170,9 @@ hipError_t launch_capillary(const Batch& b, int np_rows, int cap_B, int npts, hi
   return hipGetLastError();
 }
 
-// np_max: the most particles of one simulation in the batch
-hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
+// np_max: the most particles of one simulation in the batch; np_rows: particle
+// rows of the batch; n_sub_max: the most DEM sub-steps of one simulation
+hipError_t launch_dem(const Batch& b, int np_max, int np_rows, int n_sub_max, hipStream_t st) {
   if (np_max == 0) return hipSuccess;
   static int max_lds = -1;
   if (max_lds < 0) {
@@ -936,41 +1184,26 @@ hipError_t launch_dem(const Batch& b, int np_max, hipStream_t st) {
   }
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
-  const size_t need_view = (size_t)np_max * (sizeof(DemView) + MAXNB * sizeof(uint16_t));
-  // one thread per particle where possible; the launch bound follows the
-  // block size, so that boxes of up to 512 particles keep their contact-phase
-  // values in registers (1,024 threads leave 128 VGPRs a lane)
-  const unsigned nt = np_max > 512 ? 1024u : (np_max > 256 ? 512u : 256u);
   if (need <= (size_t)max_lds && need <= 64 * 1024) {
-    hipLaunchKernelGGL((k_dem<DEM_SHARED, false, 256>), dim3(b.nsim), dim3(nt), need, st, b);
-  } else if (need_view <= DEM_VIEW_LDS && np_max < NB16_END) {
-    static bool lds_set = false;  // above 64 KB of LDS needs the attribute once
-    if (!lds_set) {
-      for (const void* f : {(const void*)k_dem<DEM_VIEW, false, 1024>,
-                            (const void*)k_dem<DEM_VIEW, true, 512>,
-                            (const void*)k_dem<DEM_VIEW, true, 1024>}) {
-        const hipError_t e =
-            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DEM_VIEW_LDS);
-        if (e != hipSuccess) return e;
-      }
-      lds_set = true;
-    }
-    if (np_max <= 32 * MAXNB) {
-      // the pair tests on many CUs first; the hit masks fit the list buffer
-      const long long nw = (np_max + 31) / 32;
-      const unsigned gx = (unsigned)(((long long)np_max * nw + 255) / 256);
-      hipLaunchKernelGGL(k_dem_search, dim3(gx, b.nsim), dim3(256), 0, st, b);
-      if (nt <= 512)
-        hipLaunchKernelGGL((k_dem<DEM_VIEW, true, 512>), dim3(b.nsim), dim3(nt), need_view, st, b);
-      else
-        hipLaunchKernelGGL((k_dem<DEM_VIEW, true, 1024>), dim3(b.nsim), dim3(nt), need_view, st,
-                           b);
-    } else {
-      hipLaunchKernelGGL((k_dem<DEM_VIEW, false, 1024>), dim3(b.nsim), dim3(nt), need_view, st, b);
-    }
-  } else {
-    hipLaunchKernelGGL((k_dem<DEM_GLOBAL, false, 1024>), dim3(b.nsim), dim3(nt), 0, st, b);
+    // few particles: one workgroup per simulation, everything in LDS
+    hipLaunchKernelGGL(k_dem, dim3(b.nsim), dim3(256), need, st, b);
+    return hipGetLastError();
   }
+  // many particles: set-up, then a launch per sub-step with a wave per particle
+  const unsigned g64 = (unsigned)((np_rows + 63) / 64);
+  if (np_max <= 32 * MAXNB) {
+    // the pair tests on many CUs; the hit masks fit the list buffer
+    const long long nw = (np_max + 31) / 32;
+    const unsigned gx = (unsigned)(((long long)np_max * nw + 255) / 256);
+    hipLaunchKernelGGL(k_dem_search, dim3(gx, b.nsim), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_dem_setup, dim3(g64), dim3(64), 0, st, b, np_rows, 1);
+  } else {
+    hipLaunchKernelGGL(k_dem_lists, dim3(g64), dim3(64), 0, st, b, np_rows);
+    hipLaunchKernelGGL(k_dem_setup, dim3(g64), dim3(64), 0, st, b, np_rows, 0);
+  }
+  const unsigned g4 = (unsigned)((np_rows + 3) / 4);
+  for (int sub = 0; sub < n_sub_max; ++sub)
+    hipLaunchKernelGGL(k_dem_sub, dim3(g4), dim3(256), 0, st, b, np_rows, sub);
   return hipGetLastError();
 }
 
