@@ -35,6 +35,13 @@
  *   S14 DEM: contacts, sliding and rolling friction, Verlet integration
  *   S15 new solid mask, refilling of fresh fluid nodes
  *
+ * Geometry: the static solid is the node plane z = 0 (has_wall 1), a tube
+ * along x (has_wall 2: nodes with (y - yc)^2 + (z - zc)^2 >= R_t^2 are solid,
+ * yc = (ny - 1)/2, zc = (nz - 1)/2, section "Benchmarking hydrodynamic force"),
+ * or nothing (has_wall 0).  With open_x the x direction is not periodic: the
+ * planes x = -1/2 and x = nx - 1/2 are pressure boundaries held by the
+ * anti-bounce-back rule of that section (pressure inlet/outlet eq.).
+ *
  * Readings of passages that are silent, ambiguous or garbled are listed where
  * they are used; each is marked "reading:".
  */
@@ -72,6 +79,9 @@ typedef struct {
   double kn, kt, kr, gn, gt, gr, delta_R;
   double cap_k, cap_dang_deg;
   int32_t n_particles, pad0;
+  int32_t open_x, pad1;    /* 1: pressure boundaries at both ends of x      */
+  double rho_in, rho_out;  /* their densities (pressure rho / 3)            */
+  double tube_R;           /* radius of the tube (has_wall 2)               */
 } orc_config;
 
 typedef struct {
@@ -192,6 +202,10 @@ static inline void ncoord(const orc_sim *s, int64_t n, int *x, int *y, int *z) {
   *y = (int)(r % s->c.ny);
   *z = (int)(r / s->c.ny);
 }
+/* direction i leaves the domain through an open end of x */
+static inline int outside(const orc_sim *s, int x, int i) {
+  return s->c.open_x && (x + CV[i][0] < 0 || x + CV[i][0] >= s->c.nx);
+}
 static inline int64_t neighbour(const orc_sim *s, int x, int y, int z, int i) {
   return nidx(s, wrapi(x + CV[i][0], s->c.nx), wrapi(y + CV[i][1], s->c.ny),
               wrapi(z + CV[i][2], s->c.nz));
@@ -279,15 +293,25 @@ static double local_omega(const orc_config *c, double phi) {
 /* ------------------------------------------------------------------ masks */
 /* reading: node x is inside particle p iff ((dx*dx)+(dy*dy))+(dz*dz) < R*R in
  * FP64 without fused multiply-add, with d = x - X wrapped once into (-L/2,L/2];
- * equality counts as fluid.  The node plane z = 0 is the wall.  A node inside
+ * equality counts as fluid.  The static wall is as above (a tube node is solid
+ * iff its squared distance from the axis is at least R_t^2).  A node inside
  * several particles belongs to the lowest index. */
+static int static_wall(const orc_config *c, int y, int z) {
+  if (c->has_wall == 1) return z == 0;
+  if (c->has_wall == 2) {
+    double dy = y - 0.5 * (c->ny - 1), dz = z - 0.5 * (c->nz - 1);
+    return (dy * dy) + (dz * dz) >= c->tube_R * c->tube_R;
+  }
+  return 0;
+}
+
 static void build_mask(const orc_sim *s, uint16_t *m) {
   const orc_config *c = &s->c;
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < s->N; ++n) {
     int x, y, z;
     ncoord(s, n, &x, &y, &z);
-    m[n] = (c->has_wall && z == 0) ? 1 : 0;
+    m[n] = static_wall(c, y, z) ? 1 : 0;
   }
   for (int p = 0; p < c->n_particles; ++p) {
     const orc_particle *P = &s->P[p];
@@ -363,6 +387,7 @@ static int wet_blend = 1;
 static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, double G[3]) {
   int solid_p = -1, has_wall = 0;
   for (int i = 1; i < Q; ++i) {
+    if (outside(s, x, i)) continue; /* an open end is no solid */
     uint16_t mv = s->mask[neighbour(s, x, y, z, i)];
     if (mv >= 2) {
       int p = mv - 2;
@@ -381,11 +406,20 @@ static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, doubl
     double dn = norm3(d);
     for (int k = 0; k < 3; ++k) ns[k] = d[k] / dn;
     theta = s->P[solid_p].theta_deg * M_PI / 180.0;
-  } else {
+  } else if (s->c.has_wall == 1) {
     /* the wall plane z = 0 is below node z = 1 and, through the periodic
      * z direction, above node z = nz - 1 */
     ns[0] = ns[1] = 0.0;
     ns[2] = (z == 1) ? 1.0 : -1.0;
+    theta = s->c.theta_wall_deg * M_PI / 180.0;
+  } else {
+    /* tube: the wall's outward normal points from the node to the axis */
+    double dy = y - 0.5 * (s->c.ny - 1), dz = z - 0.5 * (s->c.nz - 1);
+    double r = sqrt(dy * dy + dz * dz);
+    if (!(r > 0.0)) return;
+    ns[0] = 0.0;
+    ns[1] = -dy / r;
+    ns[2] = -dz / r;
     theta = s->c.theta_wall_deg * M_PI / 180.0;
   }
   double a = dot3(G, ns);
@@ -415,7 +449,8 @@ static void prepare(orc_sim *s) {
   }
   /* S2 - S4
    * reading: isotropic gradient G = 3 sum_i w_i c_i phi(x + c_i); a solid
-   * neighbour contributes the value at x (zero-gradient closure). */
+   * neighbour, or one beyond an open end, contributes the value at x
+   * (zero-gradient closure). */
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < N; ++n) {
     double *G = s->G + 3 * n, *nr = s->nrm + 3 * n;
@@ -427,7 +462,7 @@ static void prepare(orc_sim *s) {
     double p0 = s->phi[n];
     for (int i = 1; i < Q; ++i) {
       int64_t m = neighbour(s, x, y, z, i);
-      double pv = (s->mask[m] == 0) ? s->phi[m] : p0;
+      double pv = (!outside(s, x, i) && s->mask[m] == 0) ? s->phi[m] : p0;
       for (int k = 0; k < 3; ++k) G[k] += 3.0 * WT[i] * CV[i][k] * pv;
     }
     wetting_node(s, n, x, y, z, G);
@@ -452,7 +487,7 @@ static void prepare(orc_sim *s) {
     double kappa = 0.0;
     for (int i = 1; i < Q; ++i) {
       int64_t m = neighbour(s, x, y, z, i);
-      const double *nv = (s->mask[m] == 0) ? s->nrm + 3 * m : n0;
+      const double *nv = (!outside(s, x, i) && s->mask[m] == 0) ? s->nrm + 3 * m : n0;
       kappa += 3.0 * WT[i] * (CV[i][0] * nv[0] + CV[i][1] * nv[1] + CV[i][2] * nv[2]);
     }
     double phi = s->phi[n];
@@ -586,6 +621,23 @@ static void stream_bounce(orc_sim *s) {
     s->fa_new[n * Q] = a[0];
     s->fb_new[n * Q] = b[0];
     for (int i = 1; i < Q; ++i) {
+      if (outside(s, x, i)) {
+        /* Anti-bounce-back at the pressure boundary (pressure inlet/outlet
+         * eq.): f_opp(x) = -f*_i(x) + 2 w_i rho_w [1 + (c_i.u_w)^2/(2 cs^4)
+         * - u_w^2/(2 cs^2)] with p_w = cs^2 rho_w.  reading: u_w is the
+         * velocity of the boundary node itself; the rule is applied to each
+         * fluid with its share rho_w (1 +- phi)/2 of rho_w, phi that of the
+         * boundary node (the colour leaving and entering is the node's). */
+        int o = OPPD[i];
+        double rw = (x + CV[i][0] < 0) ? s->c.rho_in : s->c.rho_out;
+        const double *uw = s->u + 3 * n;
+        double cu = CV[i][0] * uw[0] + CV[i][1] * uw[1] + CV[i][2] * uw[2];
+        double e = 2.0 * WT[i] * rw * (1.0 + 4.5 * cu * cu - 1.5 * dot3(uw, uw));
+        double ph = s->phi[n];
+        s->fa_new[n * Q + o] = -a[i] + 0.5 * (1.0 + ph) * e;
+        s->fb_new[n * Q + o] = -b[i] + 0.5 * (1.0 - ph) * e;
+        continue;
+      }
       int64_t m = neighbour(s, x, y, z, i);
       uint16_t mv = s->mask[m];
       if (mv == 0) {
@@ -612,6 +664,7 @@ static void stream_bounce(orc_sim *s) {
     int x, y, z;
     ncoord(s, n, &x, &y, &z);
     for (int i = 1; i < Q; ++i) {
+      if (outside(s, x, i)) continue;
       uint16_t mv = s->mask[neighbour(s, x, y, z, i)];
       if (mv < 2) continue;
       int p = mv - 2, o = OPPD[i];
@@ -768,7 +821,21 @@ static void contacts_all(orc_sim *s, const double *vp, const double *wp, double 
     orc_particle *P = &s->P[i];
     double Rci = P->R + c->delta_R;
     double Fsum[3] = {0, 0, 0}, Tsum[3] = {0, 0, 0}, Fo[3], To[3];
-    if (c->has_wall) {
+    if (c->has_wall == 2) {
+      /* reading: the tube's surface is the cylinder r = R_t (a node is solid
+       * from r >= R_t on); the contact normal points from the wall to the
+       * centre, towards the axis */
+      double dy = P->x[1] - 0.5 * (c->ny - 1), dz = P->x[2] - 0.5 * (c->nz - 1);
+      double r = sqrt(dy * dy + dz * dz);
+      double nw[3] = {0.0, r > 0.0 ? -dy / r : 0.0, r > 0.0 ? -dz / r : 0.0};
+      double dw = Rci - (c->tube_R - r);
+      if (contact(s, i, -1, dw, nw, vp + 3 * i, wp + 3 * i, zero, zero, Rci, 0.0, zero, P->mu_s,
+                  P->mu_r, dt, Fo, To))
+        for (int d = 0; d < 3; ++d) {
+          Fsum[d] += Fo[d];
+          Tsum[d] += To[d];
+        }
+    } else if (c->has_wall) {
       double nb[3] = {0, 0, 1}, nt[3] = {0, 0, -1};
       double db = Rci - (P->x[2] - 0.5);
       if (contact(s, i, -1, db, nb, vp + 3 * i, wp + 3 * i, zero, zero, Rci, 0.0, zero, P->mu_s,
@@ -880,6 +947,7 @@ static void dem(orc_sim *s, const double *Fext) {
       double L[3] = {(double)c->nx, (double)c->ny, (double)c->nz};
       for (int d = 0; d < 3; ++d) {
         if (d == 2 && c->has_wall) continue;
+        if (d == 0 && c->open_x) continue;
         if (P->x[d] >= L[d])
           P->x[d] -= L[d];
         else if (P->x[d] < 0.0)
@@ -908,6 +976,14 @@ static void dem(orc_sim *s, const double *Fext) {
     for (int d = 0; d < 3; ++d) {
       s->P[i].F_con[d] = Facc[3 * i + d] / s->n_sub;
       s->P[i].T_con[d] = Tacc[3 * i + d] / s->n_sub;
+    }
+  /* a particle must keep R + 4 nodes from an open end: the lattice work
+   * around it (mask box, links, capillary points, refill) never reaches the
+   * boundary planes then */
+  if (c->open_x)
+    for (int i = 0; i < np; ++i) {
+      const orc_particle *P = &s->P[i];
+      if (P->x[0] < P->R + 4.0 || P->x[0] > (double)(c->nx - 1) - P->R - 4.0) s->status = -5;
     }
   free(vp); free(wp); free(Fc); free(Tc); free(Ff); free(Tf); free(ao); free(bo);
   free(Facc); free(Tacc);
@@ -945,6 +1021,7 @@ static void update_mask_and_refill(orc_sim *s) {
     double sa = 0.0, sb = 0.0;
     int cnt = 0;
     for (int i = 1; i < Q; ++i) {
+      if (outside(s, x, i)) continue;
       int64_t m = neighbour(s, x, y, z, i);
       if (s->mask_new[m] != 0) continue;
       if (s->mask[m] >= 2) continue; /* also fresh */
@@ -984,6 +1061,9 @@ void orc_destroy(orc_sim *s);
 orc_sim *orc_create(const orc_config *cfg, const float *phi0, const orc_particle *parts) {
   build_tables();
   if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 3) return NULL;
+  if (cfg->has_wall < 0 || cfg->has_wall > 2) return NULL;
+  if (cfg->has_wall == 2 && !(cfg->tube_R > 0.0)) return NULL;
+  if (cfg->open_x && (!(cfg->rho_in > 0.0) || !(cfg->rho_out > 0.0) || cfg->nx < 2)) return NULL;
   orc_sim *s = calloc(1, sizeof(orc_sim));
   s->c = *cfg;
   s->N = (int64_t)cfg->nx * cfg->ny * cfg->nz;
@@ -1059,7 +1139,7 @@ static int unstable(const orc_sim *s) {
 }
 
 /* One step per iteration; returns 0, or -4 if the flow became unstable, -5 if
- * a contact table overflowed. */
+ * a contact table overflowed or a particle came within R + 4 of an open end. */
 int orc_step(orc_sim *s, int nsteps) {
   for (int t = 0; t < nsteps; ++t) {
     prepare(s);            /* S1 - S7 */

@@ -27,7 +27,9 @@ class OrcConfig(C.Structure):
                 ("kn", C.c_double), ("kt", C.c_double), ("kr", C.c_double),
                 ("gn", C.c_double), ("gt", C.c_double), ("gr", C.c_double),
                 ("delta_R", C.c_double), ("cap_k", C.c_double), ("cap_dang_deg", C.c_double),
-                ("n_particles", C.c_int32), ("pad0", C.c_int32)]
+                ("n_particles", C.c_int32), ("pad0", C.c_int32),
+                ("open_x", C.c_int32), ("pad1", C.c_int32),
+                ("rho_in", C.c_double), ("rho_out", C.c_double), ("tube_R", C.c_double)]
 
 
 class OrcParticle(C.Structure):
@@ -98,6 +100,10 @@ def make_config(cfg: dict, n_particles: int) -> OrcConfig:
     for k in range(3):
         c.body_force[k] = float(cfg["body_force"][k])
     c.n_particles = n_particles
+    c.open_x = int(cfg.get("open_x", 0))
+    c.rho_in = float(cfg.get("rho_in", cfg["rho0"]))
+    c.rho_out = float(cfg.get("rho_out", cfg["rho0"]))
+    c.tube_R = float(cfg.get("tube_R", 0.0))
     return c
 
 
