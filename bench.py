@@ -20,6 +20,11 @@ One JSON line:
 - c2: the 256x128x96 drop-sweep workload (20 spheres), FP32;
 - c4: the batched ensemble of 256 uneven cubic boxes, runs per hour of
   5,000-step runs, with graph replay;
+- table1: the paper's own drop-particle run (Table 1: 400x181x71, R_p = 10,
+  drop radius 5 R_p, viscosity ratio 10), FP32;
+- tube: the hydrodynamic-force benchmark's set-up (a sphere of radius 12.2 in
+  pressure-driven flow through a tube of radius 40 between anti-bounce-back
+  pressure ends, 320x83x83), FP32;
 - cpu_baseline: the FP64 oracle timed on a bounded sample of the same workload
   on this host's cores (all usable threads, and one thread), and, from the same
   oracle runs, the GPU fields' error at the sampled step counts (the C3 sample
@@ -293,10 +298,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed steps of the C3 runs")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--only", choices=["c3", "c3-fp16", "c2", "c4", "table1"], default=None,
+    ap.add_argument("--only", choices=["c3", "c3-fp16", "c2", "c4", "table1", "tube"], default=None,
                     help="run one part alone (for profiling): no line, a short summary")
     ap.add_argument("--c2-steps", type=int, default=2000)
     ap.add_argument("--c4-steps", type=int, default=200)
+    ap.add_argument("--table1-steps", type=int, default=2000)
+    ap.add_argument("--tube-steps", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -330,6 +337,8 @@ def main():
             r = run_lattice(W.drop_sweep_c2(), args.steps, args.warmup)
         elif args.only == "table1":
             r = run_lattice(W.table1_n1(), args.steps, args.warmup)
+        elif args.only == "tube":
+            r = run_lattice(W.tube_segre(), args.steps, args.warmup)
         else:
             r = ensemble(256, args.c4_steps, 4)
             r.pop("gate_fields")
@@ -346,6 +355,8 @@ def main():
     e16 = field_errors(r16["fields"], r32["fields"])
     r2 = run_lattice(W.drop_sweep_c2(), args.c2_steps, 20)
     c4 = ensemble(256, args.c4_steps, 4)
+    rt1 = run_lattice(W.table1_n1(), args.table1_steps, 20)
+    rtb = run_lattice(W.tube_segre(), args.tube_steps, 20)
     cfg = c3w["cfg"]
     out = {
         "metric": METRIC,
@@ -383,6 +394,17 @@ def main():
                "runs_per_hour": round(c4["runs_per_hour"], 1), "run_steps": c4["run_steps"],
                "timed_steps": c4["steps"], "ms_per_step": round(c4["ms_per_step"], 4),
                "mlups": round(c4["mlups"], 1), "nodes": c4["nodes"]},
+        "table1": {"workload": "the paper's drop-particle run: 400x181x71, R_p=10, drop R_d=50, "
+                               "viscosity ratio 10 (drop tau 2.138, air 0.664), wall 100 deg, "
+                               "particle 92 deg, Bo=1.25, FP32",
+                   "steps": args.table1_steps, "mlups": round(rt1["mlups"], 1),
+                   "ms_per_step": round(rt1["ms_per_step"], 5),
+                   "roofline_frac": rt1["roofline"]["frac"]},
+        "tube": {"workload": "sphere R_p=12.2 in pressure-driven flow through a tube R_t=40, "
+                             "320x83x83, open ends (anti-bounce-back), tau 1.871, FP32",
+                 "steps": args.tube_steps, "mlups": round(rtb["mlups"], 1),
+                 "ms_per_step": round(rtb["ms_per_step"], 5),
+                 "roofline_frac": rtb["roofline"]["frac"]},
     }
     if not args.no_cpu:
         c3_gpu = gpu_fields_after(c3w, args.cpu_steps)

@@ -23,7 +23,7 @@
  *    planes of N values (u_x, then u_y, then u_z).
  *  - D3Q19 order: 0 rest; 1..6 +x,-x,+y,-y,+z,-z; 7..10 (+-1,+-1,0),
  *    11..14 (+-1,0,+-1), 15..18 (0,+-1,+-1), each group in ++,+-,-+,-- order.
- *  - Mask codes: 0 fluid, 1 wall, 2+p inside particle p.  A node is inside
+ *  - Mask codes: 0 fluid, 1 static wall (lbm_wall), 2+p inside particle p.  A node is inside
  *    particle p iff ((dx*dx)+(dy*dy))+(dz*dz) < R*R in FP64 without fused
  *    multiply-add, d = x - X wrapped once into (-L/2, L/2]; ties are fluid;
  *    the lowest particle index wins.
@@ -65,6 +65,17 @@ enum lbm_storage {
                          the node they left, and are rebuilt from them      */
 };
 
+/* Static solid of a simulation (lbm_config.has_wall). */
+enum lbm_wall {
+  LBM_WALL_NONE = 0,  /* fully periodic box                                   */
+  LBM_WALL_PLANE = 1, /* the node plane z = 0 (the substrate of the drop runs)  */
+  LBM_WALL_TUBE = 2   /* a tube along x: node (x, y, z) is solid iff
+                         (y - (ny-1)/2)^2 + (z - (nz-1)/2)^2 >= tube_R^2 (the
+                         hydrodynamic benchmark of the section "Benchmarking
+                         hydrodynamic force"); wetting and DEM contact use the
+                         cylinder's normal, from the wall towards the axis     */
+};
+
 enum lbm_field_bits {
   LBM_F_RHO = 1u,  /* total density rho                              (float) */
   LBM_F_U = 2u,    /* velocity with half the force (velocity eq.)   (float) */
@@ -84,7 +95,7 @@ enum lbm_field_bits {
  * parameter table. */
 typedef struct {
   int32_t nx, ny, nz;   /* lattice size; nz >= 3, 19 (nx ny nz + 63) < 2^32 */
-  int32_t has_wall;     /* 1: node plane z = 0 is a solid wall [1]           */
+  int32_t has_wall;     /* lbm_wall [LBM_WALL_PLANE]                         */
   double rho0;          /* reference density [0.05]                          */
   double tau_a, tau_b;  /* relaxation times of fluids a and b (> 1/2) [1, 1] */
   double sigma;         /* surface tension [0.01]                            */
@@ -98,6 +109,17 @@ typedef struct {
   double cap_dang_deg;  /* Lagrangian grid spacing in degrees [2]            */
   int32_t storage;      /* lbm_storage                                       */
   int32_t n_particles;  /* spheres in this simulation (<= 4096)              */
+  /* Open x ends (section "Benchmarking hydrodynamic force", pressure
+   * inlet/outlet eq.): with open_x = 1 the x direction is not periodic; the
+   * planes x = -1/2 and x = nx - 1/2 are pressure boundaries of density rho_in
+   * and rho_out (p = rho / 3), held by anti-bounce-back with the boundary
+   * node's own velocity; each fluid takes the node's colour share of rho_w.
+   * Stencils take the node's own value beyond an open end.  Particles must keep
+   * R + 4 nodes from both ends (LBM_ERANGE otherwise).  [0] */
+  int32_t open_x;
+  int32_t pad0;
+  double rho_in, rho_out;
+  double tube_R;        /* tube radius (LBM_WALL_TUBE)                       */
 } lbm_config;
 
 /* FP64 particle record, in and out. */
@@ -228,6 +250,15 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* chosen);
 /* Set the block shape of one simulation by hand (tile width 0, 16, 32, 64,
  * 128 or 256; LBM_EINVAL otherwise). */
 int lbm_set_tile(lbm_ctx* ctx, int32_t sim, int32_t tile_x);
+
+/* Marching depth of the interface and moments passes of one simulation: each
+ * block takes an x-y tile of 64 x 4 nodes (32 x 8 or 16 x 16 on narrow boxes)
+ * and marches up `planes` planes (1..256; 0 restores the default: 12 on planes
+ * of at least 65,536 nodes unless that gives between 1,536 and 6,144 blocks,
+ * else 6).  Results are identical with any depth;
+ * deeper blocks re-read fewer halo planes, shallower ones give more blocks
+ * to fill the GPU. */
+int lbm_set_march(lbm_ctx* ctx, int32_t sim, int32_t planes);
 
 /* Graph replay of steps.  With enable = 1, lbm_step captures two consecutive
  * steps of every simulation into a HIP graph on the context's stream the first

@@ -112,6 +112,11 @@ bool valid_config(const lbm_config& c, char* msg, size_t len) {
   if (!(c.theta_wall_deg > 0.0 && c.theta_wall_deg < 180.0))
     return fail("wall contact angle must be in (0, 180) degrees");
   if (c.storage != LBM_STORE_FP32 && c.storage != LBM_STORE_FP16) return fail("unknown storage");
+  if (c.has_wall < LBM_WALL_NONE || c.has_wall > LBM_WALL_TUBE) return fail("unknown wall kind");
+  if (c.has_wall == LBM_WALL_TUBE && !(c.tube_R > 0.0)) return fail("tube radius must be positive");
+  if (c.open_x != 0 && c.open_x != 1) return fail("open_x must be 0 or 1");
+  if (c.open_x && (!(c.rho_in > 0.0) || !(c.rho_out > 0.0)))
+    return fail("boundary densities must be positive");
   if (c.n_particles < 0 || c.n_particles > MAX_PARTICLES) return fail("n_particles out of range");
   if (c.n_particles > 0) {
     if (!(c.kn > 0.0) || c.kt < 0.0 || c.kr < 0.0 || c.gn < 0.0 || c.gt < 0.0 || c.gr < 0.0 ||
@@ -137,6 +142,10 @@ bool valid_particle(const lbm_config& c, const lbm_particle& p, char* msg, size_
   }
   if (p.mu_s < 0.0 || p.mu_r < 0.0) {
     snprintf(msg, len, "friction coefficients must be >= 0");
+    return false;
+  }
+  if (c.open_x && (p.x[0] < p.R + 4.0 || p.x[0] > (double)(c.nx - 1) - p.R - 4.0)) {
+    snprintf(msg, len, "particle within R + 4 nodes of an open x end");
     return false;
   }
   return true;
@@ -317,11 +326,25 @@ static void set_tile(SimDev& d, int tx) {
 // then a sixth of its work, not a third), 6 on smaller ones, whose neighbour
 // planes stay in the caches anyway (measured: the moments pass of a 256x128
 // plane is slower with 12)
-static void set_mom_tiling(SimDev& d) {
+// planes: marching depth of a block (0: the default).  The default marches
+// 12 planes on planes of at least 65,536 nodes, 6 on smaller ones; and 6 also
+// where 12-plane blocks would fill the 1,536 resident slots of the interface
+// pass (six blocks per CU) between one and four times over, so that the last
+// partial round of long blocks leaves most CUs idle (the 400 x 181 x 71 run:
+// interface + moments 268 us at 12 planes, 245 us at 6; the 512 x 256 x 192
+// slab and boxes of under one round are within 1 % either way).
+static void set_mom_tiling(SimDev& d, int planes = 0) {
   d.mtile_x = d.nx >= 64 ? 64 : (d.nx >= 32 ? 32 : 16);
   d.mtile_lx = d.mtile_x == 64 ? 6 : (d.mtile_x == 32 ? 5 : 4);
   const int ty = 256 / d.mtile_x;
-  d.mkz = (long long)d.nx * d.ny >= 65536 ? 12 : 6;
+  if (planes > 0) {
+    d.mkz = planes;
+  } else {
+    d.mkz = (long long)d.nx * d.ny >= 65536 ? 12 : 6;
+    const long long tiles = (long long)((d.nx + d.mtile_x - 1) / d.mtile_x) * ((d.ny + ty - 1) / ty);
+    const long long b12 = tiles * ((d.nz + 11) / 12);
+    if (d.mkz == 12 && b12 > 1536 && b12 < 4 * 1536) d.mkz = 6;
+  }
   d.mtiles_x = (d.nx + d.mtile_x - 1) / d.mtile_x;
   d.mtiles_y = (d.ny + ty - 1) / ty;
   d.mtiles_z = (d.nz + d.mkz - 1) / d.mkz;
@@ -330,11 +353,18 @@ static unsigned mom_blocks(const SimDev& d) {
   return (unsigned)((long long)d.mtiles_x * d.mtiles_y * d.mtiles_z);
 }
 
+// open x ends or a tube: the interface kernel's general instance
+static int general_geometry(const lbm_config& c) {
+  return c.open_x || c.has_wall == LBM_WALL_TUBE;
+}
 static Batch batch_all(const lbm_ctx* c) {
-  return Batch{c->d_tab, c->d_blk, c->d_mblk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd};
+  int open = 0;
+  for (const SimHost& sh : c->sims) open |= general_geometry(sh.cfg);
+  return Batch{c->d_tab, c->d_blk, c->d_mblk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd, open};
 }
 static Batch batch_one(const lbm_ctx* c, int si) {
-  return Batch{c->d_tab + si, nullptr, nullptr, nullptr, 1, c->cur, c->rd};
+  return Batch{c->d_tab + si, nullptr, nullptr, nullptr, 1, c->cur, c->rd,
+               general_geometry(c->sims[si].cfg)};
 }
 
 // workspace tail holding the batch tables
@@ -508,7 +538,13 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.nx = c.nx;
     d.ny = c.ny;
     d.nz = c.nz;
-    d.has_wall = c.has_wall ? 1 : 0;
+    d.has_wall = c.has_wall;
+    d.open_x = c.open_x;
+    d.drho_in = (float)(c.rho_in - c.rho0);
+    d.drho_out = (float)(c.rho_out - c.rho0);
+    d.tube_R2 = c.tube_R * c.tube_R;
+    d.tube_yc = 0.5 * (c.ny - 1);
+    d.tube_zc = 0.5 * (c.nz - 1);
     d.N = sh.L.N;
     set_mom_tiling(d);
     d.storage = c.storage;
@@ -845,6 +881,21 @@ int lbm_set_tile(lbm_ctx* ctx, int32_t sim, int32_t tile_x) {
   return upload_tables(ctx, 0);
 }
 
+int lbm_set_march(lbm_ctx* ctx, int32_t sim, int32_t planes) {
+  if (!ctx) return LBM_EINVAL;
+  if (ctx->err) return LBM_ESTATE;
+  if (sim < 0 || sim >= (int)ctx->sims.size())
+    return set_err(ctx, LBM_ERANGE, "simulation index out of range");
+  if (planes < 0 || planes > 256) return set_err(ctx, LBM_EINVAL, "planes must be in [0, 256]");
+  if (ctx->graph_exec) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+  }
+  set_mom_tiling(ctx->sims[sim].d, planes);
+  return upload_tables(ctx, 0);
+}
+
 int lbm_profile(lbm_ctx* ctx, int32_t enable) {
   if (!ctx) return LBM_EINVAL;
   if (ctx->err) return LBM_ESTATE;
@@ -905,6 +956,8 @@ static int check_status(lbm_ctx* ctx, int only = -1) {
     if (cnt[1] & ST_CONTACT_FULL)
       return set_err(ctx, LBM_ERANGE, "contact table or pair candidate list overflow");
     if (cnt[1] & ST_FRESH_FULL) return set_err(ctx, LBM_ERANGE, "fresh-node list overflow");
+    if (cnt[1] & ST_OPEN_END)
+      return set_err(ctx, LBM_ERANGE, "a particle came within R + 4 nodes of an open x end");
   }
   return LBM_OK;
 }

@@ -145,7 +145,13 @@ struct Codec<1> {
 };
 
 struct SimDev {
-  int nx, ny, nz, has_wall;
+  int nx, ny, nz, has_wall;  // has_wall: 0 none, 1 the plane z = 0, 2 a tube along x
+  // open x ends (pressure boundaries at x = -1/2 and nx - 1/2) and their
+  // densities as departures from rho0 (formed in FP64: a small pressure drop
+  // keeps its digits); tube radius squared and axis (has_wall 2)
+  int open_x;
+  float drho_in, drho_out;
+  double tube_R2, tube_yc, tube_zc;
   long long N;
   int storage, np;
   float rho0, sigma, beta, inv2nua, inv2nub;
@@ -220,7 +226,31 @@ __device__ __forceinline__ bool tile_node(const SimDev& s, int lb, int& n, int& 
   return true;
 }
 
-enum StatusBits : uint32_t { ST_UNSTABLE = 1u, ST_CONTACT_FULL = 2u, ST_FRESH_FULL = 4u };
+enum StatusBits : uint32_t {
+  ST_UNSTABLE = 1u,
+  ST_CONTACT_FULL = 2u,
+  ST_FRESH_FULL = 4u,
+  ST_OPEN_END = 8u  // a particle came within R + 4 nodes of an open x end
+};
+
+// Static solid of the simulation at node row (y, z) (walls do not vary along
+// x): the plane z = 0, or the outside of a tube of radius R_t about the axis
+// through ((ny - 1)/2, (nz - 1)/2): solid iff dy^2 + dz^2 >= R_t^2 (dy, dz are
+// multiples of 1/2, so the sum is exact in FP64).
+__host__ __device__ inline bool static_wall(const SimDev& s, int y, int z) {
+  if (s.has_wall == 1) return z == 0;
+  if (s.has_wall == 2) {
+    const double dy = (double)y - s.tube_yc, dz = (double)z - s.tube_zc;
+    return dy * dy + dz * dz >= s.tube_R2;
+  }
+  return false;
+}
+
+// A particle keeps R + 4 nodes from an open x end: its mask box, links,
+// capillary points and refill stay clear of the boundary planes.
+__host__ __device__ inline bool near_open_end(const SimDev& s, double x, double R) {
+  return s.open_x && (x < R + 4.0 || x > (double)(s.nx - 1) - R - 4.0);
+}
 
 // One launch covers a batch of simulations (an ensemble, or a single one).
 // Per-node kernels run 256-node blocks; blk[s] is the first global block of
@@ -236,6 +266,7 @@ struct Batch {
   const int2* pmap;
   int nsim;
   int cur, rd;
+  int open;  // some simulation of the batch has open x ends or a tube wall
 };
 
 // (simulation, block within it) of global block g, given the block prefix blk
@@ -336,12 +367,16 @@ __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const v4f c = cs_src(i);
+      // an all-NaN source: the population entered through an open end (the
+      // anti-bounce-back, applied to each fluid with the node's colour shares,
+      // gives phi(x) f_i + r(x) w_i (c_i . n(x)))
+      const bool open = c.x != c.x;
       const bool solid = c.y != c.y;
       const float fi = d[i] + wq(i) * rho0;
       const float ts = (float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w;
       const float to = (float)cx(i) * own.y + (float)cy(i) * own.z + (float)cz(i) * own.w;
       const float ph = solid ? own.x : c.x;
-      const float t = solid ? -to : ts;
+      const float t = open ? to : (solid ? -to : ts);
       sg += ph * fi + wq(i) * t;
     }
   }

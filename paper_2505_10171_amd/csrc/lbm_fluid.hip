@@ -28,6 +28,8 @@ namespace lbm {
 // Between those thresholds and twice their value the rotated vector is blended
 // in with weight w = min(1, |t|/EPS_GT - 1) min(1, |G|/EPS_G - 1), so that G is
 // continuous in phi (no last-bit difference can switch the rotation on or off).
+// GENERAL: the tube's wall normal is compiled in.
+template <bool GENERAL = true>
 __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, int gz, int minp,
                                                bool wall_nb, float& Gx, float& Gy, float& Gz) {
   float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
@@ -44,10 +46,20 @@ __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, 
     nsz = (float)(dz / dn);
     nc = P.neg_cos_t;
     ns = P.sin_t;
-  } else if (wall_nb) {
+  } else if (wall_nb && (!GENERAL || s.has_wall == 1)) {
     nsx = 0.f;
     nsy = 0.f;
     nsz = (gz == 1) ? 1.f : -1.f;
+    nc = s.wall_neg_cos;
+    ns = s.wall_sin;
+  } else if (wall_nb) {
+    // tube: the wall's outward normal points from the node to the axis
+    const double dy = (double)gy - s.tube_yc, dz = (double)gz - s.tube_zc;
+    const double r = sqrt(dy * dy + dz * dz);
+    if (!(r > 0.0)) return;
+    nsx = 0.f;
+    nsy = (float)(-dy / r);
+    nsz = (float)(-dz / r);
     nc = s.wall_neg_cos;
     ns = s.wall_sin;
   } else {
@@ -134,6 +146,8 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   const bool in = gx < nx && gy < ny;
   // this thread's halo records of a plane: t and t + 256 (a plane has at
   // most 396); past a partial tile's end they are only kept in bounds
+  // (-1: beyond an open x end; its record is all NaN, the mark of a
+  // population that entered through the pressure boundary)
   int hoff[2];
   bool hon[2];
 #pragma unroll
@@ -142,10 +156,13 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
     hon[j] = k < HX * HY;
     const int hy = k / HX, hx = k - hy * HX;
     int x = bx * tx - 1 + hx, y = by * ty - 1 + hy;
+    const bool out = s.open_x && (x < 0 || x >= nx);
     x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
     y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-    hoff[j] = hon[j] ? min(x, nx - 1) + nx * min(y, ny - 1) : 0;
+    hoff[j] = !hon[j] ? 0 : out ? -1 : min(x, nx - 1) + nx * min(y, ny - 1);
   }
+  const float qnan = __int_as_float(0x7fc00000);
+  const v4f open_rec = v4f{qnan, qnan, qnan, qnan};
   auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
   // planes z0 - 1 and z0 into the ring
 #pragma unroll
@@ -153,7 +170,9 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
     const int zp = zwrap(z0 - 1 + dz);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      if (hon[j]) ring[(z0 + 2 + dz) % 3][k_of(t, j)] = colour_source(RO, NX, N, hoff[j] + P * zp, hb);
+      if (hon[j])
+        ring[(z0 + 2 + dz) % 3][k_of(t, j)] =
+            hoff[j] < 0 ? open_rec : colour_source(RO, NX, N, hoff[j] + P * zp, hb);
   }
   // sources of plane z + 1 are loaded one plane ahead; the node's populations
   // at the top of its plane, in flight across the barrier
@@ -162,7 +181,9 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
     const int zp = zwrap(z + 1);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      nxt[j] = hon[j] ? colour_source(RO, NX, N, hoff[j] + P * zp, hb) : v4f{0.f, 0.f, 0.f, 0.f};
+      nxt[j] = !hon[j]      ? v4f{0.f, 0.f, 0.f, 0.f}
+               : hoff[j] < 0 ? open_rec
+                             : colour_source(RO, NX, N, hoff[j] + P * zp, hb);
   };
   fetch_sources(z0);
   for (int zz = 0; zz < kz; ++zz) {
@@ -223,7 +244,8 @@ __global__ void k_init_mask(SimDev s) {
   long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= s.N) return;
   int z = (int)(n / ((long long)s.nx * s.ny));
-  s.mask[n] = (s.has_wall && z == 0) ? 1 : 0;
+  const int y = (int)((n / s.nx) % s.ny);
+  s.mask[n] = static_wall(s, y, z) ? 1 : 0;
   s.claim[n] = 0xFFFFFFFFu;
 }
 
@@ -305,6 +327,10 @@ enum { MODE_STEP = 0, MODE_FIELDS = 1 };
 // normals never travel to HBM and back between the two stencils.
 constexpr int IF_PHI = 68 * 8;          // largest tile plane grown by two: (64 + 4)(4 + 4)
 constexpr int IF_NRM = MOM_HALO;  // grown by one: (64 + 2)(4 + 2)
+// OPEN: the batch has simulations with open x ends or a tube wall (a
+// separate instance, so that the periodic box on a plane carries none of their
+// bookkeeping).
+template <bool OPEN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_interface(Batch bt) {
   __shared__ float fring[4][IF_PHI];
   // normals of three planes, one array per component (the curvature reads
@@ -329,6 +355,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   const bool in = gx < nx && gy < ny;
   const int x0 = bx * tx, y0 = by * ty;
   // this thread's phi region entries (t, t + 256, t + 512): plane offsets
+  // (-1: beyond an open x end, where phi reads as a solid's: the gradient and
+  // curvature take the node's own value there and the direction is flagged)
   int foff[3];
   bool fon[3];
 #pragma unroll
@@ -336,7 +364,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     const int k = t + 256 * j;
     fon[j] = k < FX * FY;
     const int fy = k / FX, fx = k - fy * FX;
-    foff[j] = fon[j] ? wrapi(x0 - 2 + fx, nx) + nx * wrapi(y0 - 2 + fy, ny) : 0;
+    const int ax = x0 - 2 + fx;
+    foff[j] = !fon[j] ? 0
+              : (OPEN && s.open_x && (ax < 0 || ax >= nx)) ? -1
+                                                   : wrapi(ax, nx) + nx * wrapi(y0 - 2 + fy, ny);
   }
   // this thread's normal region entries (t, t + 256)
   int hx_[2], hy_[2];
@@ -354,7 +385,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   auto load_phi = [&](int z, float* v) {
     const int zp = zw(z);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) v[j] = fon[j] ? PHI[foff[j] + P * zp] : 0.f;
+    for (int j = 0; j < 3; ++j)
+      v[j] = !fon[j] ? 0.f : (OPEN && foff[j] < 0) ? PHI_SOLID : PHI[foff[j] + P * zp];
   };
   auto store_phi = [&](int z, const float* v) {
 #pragma unroll
@@ -399,7 +431,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         if (m >= 2) minp = min(minp, (int)m - 2);
         else if (m == 1) wall = true;
       }
-      wetting_rotate(s, ax, ay, az, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
+      wetting_rotate<OPEN>(s, ax, ay, az, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
     }
     const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
     const float ig = 1.0f / fmaxf(g, EPS_G);
@@ -604,12 +636,24 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
     const float R = STORE ? RM[node] : 0.f;
     IO::st(dp_ + pidx(i, N, node), wq(i) * rho0, inv_rho0 * (1.0f / wq(i)), wq(i) * R, dv);
   };
-  // push to the neighbour in direction i, or bounce back into direction opp(i)
+  // push to the neighbour in direction i, or bounce back into direction opp(i);
+  // through an open x end the anti-bounce-back of the pressure boundary
+  // (pressure inlet/outlet eq.): f_opp = -f*_i + 2 w_i rho_w (1 + 9/2 (c_i.u)^2
+  // - 3/2 u^2), u the node's velocity, p_w = rho_w / 3
   auto emit = [&](int i, float dv) {
-    if (bits & (1u << i))
-      st_pop(opp(i), n, dv);
-    else
+    if (bits & (1u << i)) {
+      if (s.open_x && ((cx(i) < 0 && gx == 0) || (cx(i) > 0 && gx == nx - 1))) {
+        const float drw = cx(i) < 0 ? s.drho_in : s.drho_out;
+        const float cu = (float)cx(i) * ux + (float)cy(i) * uy + (float)cz(i) * uz;
+        const float w = wq(i);
+        // as deviations from w rho0: -d*_i + 2 w (drho_w + rho_w (9/2 cu^2 - 3/2 u^2))
+        st_pop(opp(i), n, -dv + 2.0f * w * (drw + (rho0 + drw) * (4.5f * cu * cu - 1.5f * uu)));
+      } else {
+        st_pop(opp(i), n, dv);
+      }
+    } else {
       st_pop(i, nb(i), dv);
+    }
   };
 
   {
@@ -773,7 +817,10 @@ static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 
 // nblk: per-node blocks; mnblk: blocks of the moments tiling (k_normal)
 hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipStream_t st) {
   (void)nblk;
-  hipLaunchKernelGGL(k_interface, dim3(mnblk), dim3(256), 0, st, b);
+  if (b.open)
+    hipLaunchKernelGGL(k_interface<true>, dim3(mnblk), dim3(256), 0, st, b);
+  else
+    hipLaunchKernelGGL(k_interface<false>, dim3(mnblk), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ __global__ void k_claim(Batch bt) {
     const int ix = k % b.w[0], iy = (k / b.w[0]) % b.w[1], iz = k / (b.w[0] * b.w[1]);
     const int x = wrapi(b.lo[0] + ix, s.nx), y = wrapi(b.lo[1] + iy, s.ny),
               z = wrapi(b.lo[2] + iz, s.nz);
-    if (s.has_wall && z == 0) continue;
+    if (static_wall(s, y, z)) continue;
     if (inside_sphere(x, y, z, P.x, P.R, s.nx, s.ny, s.nz)) {
       const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
       atomicMin(&s.claim[n], (uint32_t)p);
@@ -503,6 +503,38 @@ __device__ __forceinline__ void stage_in(double* dst, const double* src1, int n1
   }
 }
 
+// Contact geometry of a particle at x with the static wall: partner -1 is the
+// plane's top face (normal +z, surface z = 1/2) or the tube (the cylinder
+// r = R_t, normal from the wall to the centre, towards the axis), -2 the
+// plane's underside seen through the periodic z direction (normal -z, surface
+// z = nz - 1/2).  delta is the overlap with the mechanical radius Rc; false if
+// the simulation has no such wall face.
+__device__ __forceinline__ bool wall_geom(const SimDev& s, const double* x, double Rc, int partner,
+                                          double& delta, double* nh) {
+  nh[0] = nh[1] = nh[2] = 0.0;
+  if (s.has_wall == 1) {
+    if (partner == -1) {
+      delta = Rc - (x[2] - 0.5);
+      nh[2] = 1.0;
+    } else {
+      delta = Rc - (((double)s.nz - 0.5) - x[2]);
+      nh[2] = -1.0;
+    }
+    return true;
+  }
+  if (s.has_wall == 2 && partner == -1) {
+    const double dy = x[1] - s.tube_yc, dz = x[2] - s.tube_zc;
+    const double r = sqrt(dy * dy + dz * dz);
+    if (r > 0.0) {
+      nh[1] = -dy / r;
+      nh[2] = -dz / r;
+    }
+    delta = Rc - (sqrt(s.tube_R2) - r);
+    return true;
+  }
+  return false;
+}
+
 // Contact forces and torques on one particle from the walls and from its
 // candidates.  T is the record type the particle data is read from (DevParticle
 // or DemView: the same field names); cand(q) is the q-th candidate or -1 past
@@ -520,18 +552,11 @@ __device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, cons
   int ids[MAXC];
 #pragma unroll
   for (int k = 0; k < MAXC; ++k) ids[k] = tab[k].partner;
-  if (s.has_wall) {
-    const double nb_[3] = {0, 0, 1}, nt_[3] = {0, 0, -1};
-    const double db = Rci - (me.x[2] - 0.5);
-    if (contact(s, tab, ids, -1, db, nb_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
-                dt, Fo, To))
-      for (int d = 0; d < 3; ++d) {
-        Fs[d] += Fo[d];
-        Ts[d] += To[d];
-      }
-    const double dtp = Rci - (((double)s.nz - 0.5) - me.x[2]);
-    if (contact(s, tab, ids, -2, dtp, nt_, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s, me.mu_r,
-                dt, Fo, To))
+  for (int w = -1; w >= -2; --w) {
+    double dw, nw[3];
+    if (!wall_geom(s, me.x, Rci, w, dw, nw)) continue;
+    if (contact(s, tab, ids, w, dw, nw, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s,
+                me.mu_r, dt, Fo, To))
       for (int d = 0; d < 3; ++d) {
         Fs[d] += Fo[d];
         Ts[d] += To[d];
@@ -705,7 +730,7 @@ __global__ __launch_bounds__(256) void k_dem(Batch bt) {
       quat_rotate(P.q, th);
       const double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
       for (int d = 0; d < 3; ++d) {
-        if (d == 2 && s.has_wall) continue;
+        if ((d == 2 && s.has_wall) || (d == 0 && s.open_x)) continue;
         if (P.x[d] >= L[d])
           P.x[d] -= L[d];
         else if (P.x[d] < 0.0)
@@ -751,6 +776,7 @@ __global__ __launch_bounds__(256) void k_dem(Batch bt) {
       P.Fcon[d] = P.Facc[d] / s.n_sub;
       P.Tcon[d] = P.Tacc[d] / s.n_sub;
     }
+    if (near_open_end(s, P.x[0], P.R)) atomicOr(&s.counters[1], (uint32_t)ST_OPEN_END);
     if (s.hist_cap > 0) {
       double* h = s.hist + ((long long)(step % (unsigned long long)s.hist_cap) * np + i) *
                                LBM_HIST_DOUBLES_DEV;
@@ -806,7 +832,7 @@ __device__ void dem_predict(const SimDev& s, DevParticle& P, DemView& v, double 
   quat_rotate(P.q, th);
   const double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
   for (int d = 0; d < 3; ++d) {
-    if (d == 2 && s.has_wall) continue;
+    if ((d == 2 && s.has_wall) || (d == 0 && s.open_x)) continue;
     if (P.x[d] >= L[d])
       P.x[d] -= L[d];
     else if (P.x[d] < 0.0)
@@ -1030,12 +1056,8 @@ __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub)
     wj = pj.wp;
     mu = 0.5 * (me.mu_s + pj.mu_s);
     mur = 0.5 * (me.mu_r + pj.mu_r);
-  } else if (partner == -1) {
-    delta = me.Rc - (me.x[2] - 0.5);
-    nh[2] = 1.0;
-  } else if (partner == -2) {
-    delta = me.Rc - (((double)s.nz - 0.5) - me.x[2]);
-    nh[2] = -1.0;
+  } else if (partner != -100) {
+    if (!wall_geom(s, me.x, me.Rc, partner, delta, nh)) partner = -100;
   }
   const bool has = partner != -100;
   const bool active = has && delta > 0.0;
@@ -1100,6 +1122,7 @@ __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub)
     P.Fcon[d] = P.Facc[d] / s.n_sub;
     P.Tcon[d] = P.Tacc[d] / s.n_sub;
   }
+  if (near_open_end(s, P.x[0], P.R)) atomicOr(&s.counters[1], (uint32_t)ST_OPEN_END);
   if (s.hist_cap > 0) {
     const unsigned long long step = *s.step_counter - 1;  // advanced by k_dem_setup
     double* h = s.hist + ((long long)(step % (unsigned long long)s.hist_cap) * np + i) *
@@ -1185,8 +1208,10 @@ hipError_t launch_dem(const Batch& b, int np_max, int np_rows, int n_sub_max, hi
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
   if (need <= (size_t)max_lds && need <= 64 * 1024) {
-    // few particles: one workgroup per simulation, everything in LDS
-    hipLaunchKernelGGL(k_dem, dim3(b.nsim), dim3(256), need, st, b);
+    // few particles: one workgroup per simulation, everything in LDS; a
+    // single wave up to 64 particles (its barriers cost next to nothing)
+    const unsigned nt = np_max <= 64 ? 64u : 256u;
+    hipLaunchKernelGGL(k_dem, dim3(b.nsim), dim3(nt), need, st, b);
     return hipGetLastError();
   }
   // many particles: set-up, then a launch per sub-step with a wave per particle

@@ -23,7 +23,7 @@ HIST_DOUBLES = 27
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_step", "lbm_sync", "lbm_particles_sync",
            "lbm_fields", "lbm_fields2", "lbm_links", "lbm_mass", "lbm_dem_substeps", "lbm_destroy",
            "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_use_graph",
-           "lbm_autotune", "lbm_set_tile", "lbm_mass_all_noalloc"]
+           "lbm_autotune", "lbm_set_tile", "lbm_set_march", "lbm_mass_all_noalloc"]
 PROFILE_KINDS = ("fused", "particles", "moments", "interface", "links")
 
 
@@ -35,7 +35,9 @@ class LbmConfig(C.Structure):
                 ("kn", C.c_double), ("kt", C.c_double), ("kr", C.c_double),
                 ("gn", C.c_double), ("gt", C.c_double), ("gr", C.c_double),
                 ("delta_R", C.c_double), ("cap_k", C.c_double), ("cap_dang_deg", C.c_double),
-                ("storage", C.c_int32), ("n_particles", C.c_int32)]
+                ("storage", C.c_int32), ("n_particles", C.c_int32),
+                ("open_x", C.c_int32), ("pad0", C.c_int32),
+                ("rho_in", C.c_double), ("rho_out", C.c_double), ("tube_R", C.c_double)]
 
 
 class LbmParticle(C.Structure):
@@ -86,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.lbm_use_graph.argtypes = [vp, i32]
     L.lbm_autotune.argtypes = [vp, i32, C.POINTER(i32)]
     L.lbm_set_tile.argtypes = [vp, i32, i32]
+    L.lbm_set_march.argtypes = [vp, i32, i32]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = [vp]
@@ -112,6 +115,10 @@ def make_config(cfg: dict, n_particles: int) -> LbmConfig:
     st = cfg.get("storage", "fp32")
     c.storage = LBM_STORE_FP16 if st in ("fp16", LBM_STORE_FP16) else LBM_STORE_FP32
     c.n_particles = int(n_particles)
+    c.open_x = int(cfg.get("open_x", 0))
+    c.rho_in = float(cfg.get("rho_in", cfg["rho0"]))
+    c.rho_out = float(cfg.get("rho_out", cfg["rho0"]))
+    c.tube_R = float(cfg.get("tube_R", 0.0))
     return c
 
 
@@ -343,6 +350,9 @@ class Context:
 
     def set_tile(self, sim: int, tile_x: int):
         self._check(load_library().lbm_set_tile(self.h, int(sim), int(tile_x)))
+
+    def set_march(self, sim: int, planes: int):
+        self._check(load_library().lbm_set_march(self.h, int(sim), int(planes)))
 
     def use_graph(self, enable: bool = True):
         """Replay pairs of steps from a captured HIP graph (needs a non-null stream)."""

@@ -232,3 +232,43 @@ def drop_meets_sphere(seed: int = 7, storage: str = "fp32"):
     parts = [particle(x, R, theta_deg=60.0, mu_s=0.4, mu_r=0.04, g_p=10.0 * cfg["sigma"] * R,
                       sigma=cfg["sigma"])]
     return dict(name="drop meets sphere 96x64x40", cfg=cfg, phi0=phi0, particles=parts, steps=200)
+
+
+def tube_segre(seed: int = 8, R_t: float = 40.0, R_p: float = 12.2, length: float = 8.0,
+               l_frac: float = 0.21, rho_f: float = 1.05, nu: float = 0.457,
+               v_in: float = 0.0113, storage: str = "fp32"):
+    """The hydrodynamic-force benchmark (section "Benchmarking hydrodynamic
+    force"): a neutrally buoyant sphere of radius R_p = 12.2 in pressure-driven
+    Poiseuille flow through a tube of radius R_t = 40, fluid density 1.05,
+    kinematic viscosity 0.457 (tau = 1.871), mean velocity 0.0113 set by the
+    Hagen-Poiseuille pressure drop 8 rho nu v_in L / R_t^2 between the open
+    ends; the sphere starts 0.21 R_t off the axis, two tube radii behind the
+    inlet plane's clearance.  The tube length, which the paper does not give,
+    is `length` radii.  The off-axis direction is drawn from the seed."""
+    g = rng(seed, 0)
+    ny = nz = int(2 * R_t) + 3
+    nx = int(length * R_t)
+    tau = 0.5 + 3.0 * nu
+    dp = 8.0 * rho_f * nu * v_in * nx / (R_t * R_t)
+    drho = 3.0 * dp
+    cfg = config(nx, ny, nz, has_wall=2, tube_R=R_t, open_x=1, rho0=rho_f,
+                 rho_in=rho_f + 0.5 * drho, rho_out=rho_f - 0.5 * drho, tau_a=tau, tau_b=tau,
+                 sigma=0.0, storage=storage)
+    a = g.uniform(0.0, 2.0 * np.pi)
+    l = l_frac * R_t
+    x = (2.0 * R_t, 0.5 * (ny - 1) + l * np.cos(a), 0.5 * (nz - 1) + l * np.sin(a))
+    parts = [particle(x, R_p, rho_p=rho_f, g_p=0.0, mu_s=0.0, mu_r=0.0)]
+    return dict(name=f"sphere in tube flow {nx}x{ny}x{nz}, R_t={R_t:g}, R_p={R_p:g}",
+                cfg=cfg, phi0=None, particles=parts, steps=20000,
+                params=dict(drho=drho, v_in=v_in, l0=l))
+
+
+def tube_reduced(seed: int = 9, storage: str = "fp32"):
+    """tube_segre scaled to R_t = 8, R_p = 3 on a 48-node tube (the same
+    viscosity, mean velocity 0.005 so that the pressure drop stays a few per
+    cent of the density): a parity case the oracle finishes in seconds."""
+    w = tube_segre(seed=seed, R_t=8.0, R_p=3.0, length=6.0, v_in=0.005, storage=storage)
+    p = w["particles"][0]
+    p["x"] = (16.0, p["x"][1], p["x"][2])
+    w["steps"] = 200
+    return w

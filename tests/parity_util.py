@@ -31,9 +31,10 @@ def boundary_nodes(mask):
     return (~solid) & nb
 
 
-def compare_fields(g, o, tol=1e-5, node_tol=1e-4, label="", fields=None):
+def compare_fields(g, o, tol=1e-5, node_tol=1e-4, label="", fields=None, open_x=False):
     """GPU context g against oracle o (or precomputed oracle fields).  Returns
-    the relative L2 errors and the boundary-node errors."""
+    the relative L2 errors and the boundary-node errors.  open_x: the planes
+    x = 0 and x = nx - 1 (pressure-boundary nodes) count as boundary nodes."""
     rg, ug, pg, mg = g.fields()
     ro, uo, po, mo = fields if fields is not None else o.fields()
     assert np.array_equal(mg, mo), f"{label}: masks differ at {np.argwhere(mg != mo)[:5]}"
@@ -41,6 +42,9 @@ def compare_fields(g, o, tol=1e-5, node_tol=1e-4, label="", fields=None):
     e = dict(rho=rel_l2(rg[fl], ro[fl]), u=rel_l2(ug[:, fl], uo[:, fl]),
              phi=rel_l2(pg[fl], po[fl]))
     bn = boundary_nodes(mo)
+    if open_x:
+        bn[:, :, 0] |= fl[:, :, 0]
+        bn[:, :, -1] |= fl[:, :, -1]
     en = {}
     if bn.any():
         for k, a, b in (("rho", rg, ro), ("u", ug, uo), ("phi", pg, po)):

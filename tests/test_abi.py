@@ -98,6 +98,15 @@ def test_workspace_sizing_and_validation():
     bad = dict(cfg, theta_wall_deg=180.0)
     c = (lbm.LbmConfig * 1)(lbm.make_config(bad, 0))
     assert L.lbm_workspace_bytes(c, 1, None, 0) == 0
+    # open x ends and the tube wall: kinds and boundary densities are checked
+    for bad in (dict(cfg, has_wall=3), dict(cfg, has_wall=2, tube_R=0.0),
+                dict(cfg, open_x=1, rho_in=0.0), dict(cfg, open_x=1, rho_out=-1.0),
+                dict(cfg, open_x=2)):
+        c = (lbm.LbmConfig * 1)(lbm.make_config(bad, 0))
+        assert L.lbm_workspace_bytes(c, 1, None, 0) == 0, bad
+    ok = dict(cfg, has_wall=2, tube_R=7.5, open_x=1, rho_in=0.051, rho_out=0.049)
+    c = (lbm.LbmConfig * 1)(lbm.make_config(ok, 0))
+    assert L.lbm_workspace_bytes(c, 1, None, 0) == nb
     # FP16 storage halves the population bytes
     c16 = (lbm.LbmConfig * 1)(lbm.make_config(dict(cfg, storage="fp16"), 0))
     assert L.lbm_workspace_bytes(c16, 1, None, 0) < 0.5 * (nb - 46 * N) + 48 * N + 4096
