@@ -1261,6 +1261,39 @@ void orc_round_state_f32(orc_sim *s) {
   }
 }
 
+/* Round x to the nearest binary16 value (round half to even), subnormals
+ * included; |x| stays far below the binary16 range here. */
+static double round_binary16(double x) {
+  if (x == 0.0 || !isfinite(x)) return x;
+  const double sub = ldexp(1.0, -24); /* spacing of the subnormals */
+  if (fabs(x) < ldexp(1.0, -14)) return nearbyint(x / sub) * sub;
+  int e;
+  const double m = frexp(x, &e); /* x = m 2^e, 0.5 <= |m| < 1 */
+  return ldexp(nearbyint(ldexp(m, 11)), e - 11);
+}
+
+/* Sensitivity probe, not the method: the total population of every fluid node
+ * rounded as a 16-bit store relative to the node's density would round it,
+ * h = (f - w_i rho)/(w_i rho0) to binary16, the colour difference fa - fb
+ * kept. */
+void orc_round_state_f16(orc_sim *s) {
+  const double r0 = s->c.rho0;
+#pragma omp parallel for schedule(static)
+  for (int64_t n = 0; n < s->N; ++n) {
+    if (s->mask[n] != 0) continue;
+    double *a = s->fa + n * Q, *b = s->fb + n * Q;
+    double rho = 0.0;
+    for (int i = 0; i < Q; ++i) rho += a[i] + b[i];
+    for (int i = 0; i < Q; ++i) {
+      const double f = a[i] + b[i], g = a[i] - b[i];
+      const double h = round_binary16((f - WT[i] * rho) / (WT[i] * r0));
+      const double fr = WT[i] * rho + WT[i] * r0 * h;
+      a[i] = 0.5 * (fr + g);
+      b[i] = 0.5 * (fr - g);
+    }
+  }
+}
+
 /* Global mass of each fluid, sums in node order. */
 void orc_mass(const orc_sim *s, double out[2]) {
   double a = 0.0, b = 0.0;

@@ -80,6 +80,7 @@ def lib():
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_round_state_f32.argtypes = [C.c_void_p]
+        L.orc_round_state_f16.argtypes = [C.c_void_p]
         L.orc_set_regularisation.argtypes = [C.c_double, C.c_double, C.c_int]
         L.orc_get_regularisation.argtypes = [dp, dp, C.POINTER(C.c_int)]
         _lib = L
@@ -237,6 +238,11 @@ class OracleSim:
     def round_state_f32(self):
         """Sensitivity probe: round the state's departures from rest to FP32."""
         lib().orc_round_state_f32(self.h)
+
+    def round_state_f16(self):
+        """Sensitivity probe: round each total population as a 16-bit store
+        relative to the node's density would (the colour difference kept)."""
+        lib().orc_round_state_f16(self.h)
 
     def mass(self):
         out = np.zeros(2)

@@ -395,13 +395,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   };
   const float qnan = __int_as_float(0x7fc00000);
   // normal of region entry (hx, hy) of plane z from the phi ring
-  auto normal = [&](int hx, int hy, int z) -> v4f {
+  // SOL: a solid (or open-end) node may lie in the three phi planes read;
+  // without, the per-neighbour tests are left out (a block-uniform choice)
+  auto normal = [&](int hx, int hy, int z, auto SOL) -> v4f {
     const int c = (hx + 1) + FX * (hy + 1);
     const float* fm = fring[fslot(z - 1)];
     const float* f0 = fring[fslot(z)];
     const float* fp = fring[fslot(z + 1)];
     const float p0 = f0[c];
-    if (!(p0 < PHI_SOLID_TEST)) return v4f{qnan, qnan, qnan, -1.0f};
+    if (decltype(SOL)::value && !(p0 < PHI_SOLID_TEST)) return v4f{qnan, qnan, qnan, -1.0f};
     float Gx = 0.f, Gy = 0.f, Gz = 0.f;
     bool solid = false;
 #pragma unroll
@@ -411,16 +413,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
       const float* sm_ = cz(i) > 0 ? fm : (cz(i) < 0 ? fp : f0);
       float vp = sp_[c + cx(i) + FX * cy(i)];
       float vm = sm_[c - cx(i) - FX * cy(i)];
-      const bool spd = vp > PHI_SOLID_TEST, smd = vm > PHI_SOLID_TEST;
-      solid |= spd | smd;
-      vp = spd ? p0 : vp;
-      vm = smd ? p0 : vm;
+      if constexpr (decltype(SOL)::value) {
+        const bool spd = vp > PHI_SOLID_TEST, smd = vm > PHI_SOLID_TEST;
+        solid |= spd | smd;
+        vp = spd ? p0 : vp;
+        vm = smd ? p0 : vm;
+      }
       const float d = 3.0f * wq(i) * (vp - vm);
       Gx += (float)cx(i) * d;
       Gy += (float)cy(i) * d;
       Gz += (float)cz(i) * d;
     }
-    if (solid) {
+    if (decltype(SOL)::value && solid) {
       // identify the solid: the lowest-index neighbouring particle, else the wall
       const int ax = wrapi(x0 - 1 + hx, nx), ay = wrapi(y0 - 1 + hy, ny), az = zw(z);
       const Nbr nb(ax, ay, az, nx, ny, nz);
@@ -437,12 +441,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     const float ig = 1.0f / fmaxf(g, EPS_G);
     return v4f{Gx * ig, Gy * ig, Gz * ig, g};
   };
-  auto normals = [&](int z) {
+  auto normals = [&](int z, auto SOL) {
     const int sl = nslot(z);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
       if (hon[j]) {
-        const v4f v = normal(hx_[j], hy_[j], z);
+        const v4f v = normal(hx_[j], hy_[j], z, SOL);
         const int k = t + 256 * j;
         nrx[sl][k] = v.x;
         nry[sl][k] = v.y;
@@ -452,28 +456,74 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         if (tlx >= 0 && tlx < tx && tly >= 0 && tly < ty) nrg[sl][tlx + tx * tly] = v.w;
       }
   };
+  const std::integral_constant<bool, true> with_solids;
+  const std::integral_constant<bool, false> no_solids;
+  auto has_solid = [&](const float* v) {
+    bool r = false;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r |= fon[j] && v[j] > PHI_SOLID_TEST;
+    return (int)r;
+  };
   // prologue: phi of planes z0 - 2 .. z0 + 1, normals of planes z0 - 1, z0
+  int psol = 0;
   {
     float v[3];
     for (int dz = -2; dz <= 1; ++dz) {
       load_phi(z0 + dz, v);
       store_phi(z0 + dz, v);
+      psol |= has_solid(v);
     }
   }
   float nxt[3];
   load_phi(z0 + 2, nxt);
-  __syncthreads();
-  normals(z0 - 1);
-  normals(z0);
+  // bit k: a solid in phi plane (z + 2 - k) of the current plane z, once the
+  // loop has shifted in plane z + 2 (the prologue's planes all take the
+  // block's flag over the four)
+  uint32_t hist = __syncthreads_or(psol) ? 0xFu : 0u;
+  if (hist) {
+    normals(z0 - 1, with_solids);
+    normals(z0, with_solids);
+  } else {
+    normals(z0 - 1, no_solids);
+    normals(z0, no_solids);
+  }
   __syncthreads();  // the loop's first phi store reuses the slot of plane z0 - 2
   for (int zz = 0; zz < kz; ++zz) {
     const int z = z0 + zz;
     store_phi(z + 2, nxt);
-    __syncthreads();
+    hist = (hist << 1) | (__syncthreads_or(has_solid(nxt)) ? 1u : 0u);
     if (zz + 1 < kz) load_phi(z + 3, nxt);
-    normals(z + 1);
+    if (hist & 7u)  // planes z .. z + 2
+      normals(z + 1, with_solids);
+    else
+      normals(z + 1, no_solids);
     __syncthreads();
-    if (in) {
+    // the curvature reads the normals of planes z - 1 .. z + 1
+    const bool csol = (hist & 0xEu) != 0u;
+    if (in && !csol) {
+      const int c0 = (lx + 1) + HX * (ly + 1);
+      const int n = gx + nx * (gy + ny * z);
+      const int s0 = nslot(z);
+      const v4f own = v4f{nrx[s0][c0], nry[s0][c0], nrz[s0][c0], nrg[s0][t]};
+      float kappa = 0.f;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const int i = pair_dir(q);
+        const int sp_ = nslot(z + cz(i)), sm_ = nslot(z - cz(i));
+        const int cp = c0 + cx(i) + HX * cy(i), cm = c0 - cx(i) - HX * cy(i);
+        float dn = 0.f;
+        if (cx(i) != 0) dn += (float)cx(i) * (nrx[sp_][cp] - nrx[sm_][cm]);
+        if (cy(i) != 0) dn += (float)cy(i) * (nry[sp_][cp] - nry[sm_][cm]);
+        if (cz(i) != 0) dn += (float)cz(i) * (nrz[sp_][cp] - nrz[sm_][cm]);
+        kappa += 3.0f * wq(i) * dn;
+      }
+      NX[n] = own.x;
+      NX[N + n] = own.y;
+      NX[2 * N + n] = own.z;
+      NX[3 * N + n] = own.w;
+      CUR[2 * n] = -0.5f * s.sigma * kappa * fmaxf(own.w, EPS_G);
+      CUR[2 * n + 1] = __uint_as_float(0u);
+    } else if (in) {
       const int c0 = (lx + 1) + HX * (ly + 1);
       const int n = gx + nx * (gy + ny * z);
       const int s0 = nslot(z);

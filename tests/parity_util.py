@@ -112,11 +112,13 @@ def compare_history(hg, ho, names, R, label="", tol=1e-5):
 
 def oracle_fields_at(args):
     """Worker for a process pool: (cfg, phi0, particles, marks, threads,
-    round_f32) -> the oracle's (rho, u, phi, mask) after each step count in
-    marks.  With round_f32 the state's departures from rest are rounded to
-    single precision after every step (a sensitivity probe of the method to
-    FP32 storage, not the method)."""
-    cfg, phi0, parts, marks, threads, round_f32 = args
+    probe) -> the oracle's (rho, u, phi, mask) after each step count in marks.
+    probe "f32" (or True): the state's departures from rest are rounded to
+    single precision after every step; "f16": every total population is
+    rounded as a 16-bit store relative to its node's density would round it
+    (sensitivity probes of the method to the storage, not the method)."""
+    cfg, phi0, parts, marks, threads, probe = args
+    round_f32 = probe in (True, "f32", "f16")
     from oracle import oracle as O
     from oracle.oracle import OracleSim
     O.set_num_threads(threads)
@@ -126,7 +128,10 @@ def oracle_fields_at(args):
         while t < mk:
             if round_f32:
                 o.step(1)
-                o.round_state_f32()
+                if probe == "f16":
+                    o.round_state_f16()
+                else:
+                    o.round_state_f32()
                 t += 1
             else:
                 o.step(mk - t)
@@ -137,7 +142,7 @@ def oracle_fields_at(args):
 
 
 def oracle_runs_parallel(jobs):
-    """Oracle runs of several (cfg, phi0, particles, marks, round_f32) jobs in
+    """Oracle runs of several (cfg, phi0, particles, marks, probe) jobs in
     parallel processes, the host's cores split between them."""
     import multiprocessing as mp
     import os
