@@ -154,8 +154,10 @@ size_t lbm_workspace_bytes(const lbm_config* cfg, int32_t n_sims,
  * workspace, uploads phi0 (per simulation a host float array of nx*ny*nz
  * values, or NULL for phi = +1 everywhere) and the particles (per simulation
  * cfg[s].n_particles host records, state at rest is allowed), sets the fluid at
- * rest with f_a = w rho0 (1+phi0)/2, f_b = w rho0 (1-phi0)/2, builds the solid
- * mask and the first moments (rho0, phi0).  The workspace must be 256-byte aligned
+ * rest with f_a = w rho0 (1+phi0)/2, f_b = w rho0 (1-phi0)/2 (the equilibrium
+ * of the paper's lattice Boltzmann section at zero velocity, split by the
+ * order-parameter eq.), builds the solid mask (coupling section: nodes inside
+ * a sphere are solid) and the first moments (rho0, phi0).  The workspace must be 256-byte aligned
  * and at least lbm_workspace_bytes long (LBM_EINVAL / LBM_ENOMEM otherwise).
  * hip_stream is a hipStream_t (NULL: the null stream).  On success *out owns the
  * context. */
@@ -175,9 +177,12 @@ int lbm_sync(lbm_ctx* ctx);
 /* dir 0 (PULL): copy simulation sim's n particle records to parts, and, if
  * history is not NULL, up to max_steps most recent history records (oldest
  * first, LBM_HIST_DOUBLES * n doubles per step) to history; *n_hist (may be
- * NULL) receives the number of steps written.  dir 1 (PUSH): replace the
- * particle state (x, v, w, q and properties) from parts; contact springs are
- * kept; the mask is rebuilt and fresh fluid nodes are refilled.  Synchronous. */
+ * NULL) receives the number of steps written.  The records carry the forces of
+ * the paper's hydrodynamic force and torque eqs. (momentum exchange), the
+ * capillary-force eq. and the DEM's net contact force.  dir 1 (PUSH): replace
+ * the particle state (x, v, w, q and properties) from parts (a prescribed
+ * path, as the detachment benchmark's); contact springs are kept; the mask is
+ * rebuilt and fresh fluid nodes are refilled (refilling eqs.).  Synchronous. */
 int lbm_particles_sync(lbm_ctx* ctx, int32_t sim, int32_t dir, lbm_particle* parts, int32_t n,
                        double* history, int32_t max_steps, int32_t* n_hist);
 
@@ -199,7 +204,9 @@ int lbm_fields2(lbm_ctx* ctx, int32_t sim, uint32_t what, float* rho, float* u, 
 int lbm_links(lbm_ctx* ctx, int32_t sim, uint32_t* out, int32_t* pid, int64_t max,
               int64_t* count);
 
-/* Global FP64 mass of fluids a and b of simulation sim.  Synchronous. */
+/* Global FP64 mass of fluids a and b of simulation sim: the sums over fluid
+ * nodes of rho^a = rho (1 + phi)/2 and rho^b = rho (1 - phi)/2 (order-parameter
+ * eq.).  Synchronous. */
 int lbm_mass(lbm_ctx* ctx, int32_t sim, double out[2]);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -112,7 +112,8 @@ def compare_history(hg, ho, names, R, label="", tol=1e-5):
 
 def oracle_fields_at(args):
     """Worker for a process pool: (cfg, phi0, particles, marks, threads,
-    probe) -> the oracle's (rho, u, phi, mask) after each step count in marks.
+    probe) -> the oracle's (rho, u, phi, mask, particle centres) after each
+    step count in marks.
     probe "f32" (or True): the state's departures from rest are rounded to
     single precision after every step; "f16": every total population is
     rounded as a 16-bit store relative to its node's density would round it
@@ -136,7 +137,7 @@ def oracle_fields_at(args):
             else:
                 o.step(mk - t)
                 t = mk
-        out.append(o.fields())
+        out.append(tuple(o.fields()) + (np.array([q["x"] for q in o.particles()]),))
     o.close()
     return out
 
