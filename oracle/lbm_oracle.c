@@ -38,7 +38,11 @@
  * Geometry: the static solid is the node plane z = 0 (has_wall 1), a tube
  * along x (has_wall 2: nodes with (y - yc)^2 + (z - zc)^2 >= R_t^2 are solid,
  * yc = (ny - 1)/2, zc = (nz - 1)/2, section "Benchmarking hydrodynamic force"),
- * or nothing (has_wall 0).  With open_x the x direction is not periodic: the
+ * the plane with up to 8 boxes of solid nodes standing on it or above it
+ * (has_wall 3: a textured wall, the paper's stated future work; box b holds
+ * the nodes lo_b <= x <= hi_b in every axis, its solid surface is the box
+ * grown by half a node, [lo_b - 1/2, hi_b + 1/2], as half-way bounce-back
+ * places it), or nothing (has_wall 0).  With open_x the x direction is not periodic: the
  * planes x = -1/2 and x = nx - 1/2 are pressure boundaries held by the
  * anti-bounce-back rule of that section (pressure inlet/outlet eq.).
  *
@@ -82,6 +86,8 @@ typedef struct {
   int32_t open_x, pad1;    /* 1: pressure boundaries at both ends of x      */
   double rho_in, rho_out;  /* their densities (pressure rho / 3)            */
   double tube_R;           /* radius of the tube (has_wall 2)               */
+  int32_t n_boxes, pad2;   /* boxes of the textured wall (has_wall 3)       */
+  int32_t boxes[8][6];     /* per box: lo x, y, z, hi x, y, z (node indices) */
 } orc_config;
 
 typedef struct {
@@ -296,13 +302,30 @@ static double local_omega(const orc_config *c, double phi) {
  * equality counts as fluid.  The static wall is as above (a tube node is solid
  * iff its squared distance from the axis is at least R_t^2).  A node inside
  * several particles belongs to the lowest index. */
-static int static_wall(const orc_config *c, int y, int z) {
+static int static_wall(const orc_config *c, int x, int y, int z) {
   if (c->has_wall == 1) return z == 0;
+  if (c->has_wall == 3) {
+    if (z == 0) return 1;
+    for (int b = 0; b < c->n_boxes; ++b) {
+      const int32_t *B = c->boxes[b];
+      if (x >= B[0] && x <= B[3] && y >= B[1] && y <= B[4] && z >= B[2] && z <= B[5]) return 1;
+    }
+    return 0;
+  }
   if (c->has_wall == 2) {
     double dy = y - 0.5 * (c->ny - 1), dz = z - 0.5 * (c->nz - 1);
     return (dy * dy) + (dz * dz) >= c->tube_R * c->tube_R;
   }
   return 0;
+}
+
+/* d = p - (the point of box b's solid surface nearest to p): zero inside */
+static void box_offset(const int32_t *B, const double p[3], double d[3]) {
+  for (int k = 0; k < 3; ++k) {
+    double lo = B[k] - 0.5, hi = B[3 + k] + 0.5;
+    double q = p[k] < lo ? lo : (p[k] > hi ? hi : p[k]);
+    d[k] = p[k] - q;
+  }
 }
 
 static void build_mask(const orc_sim *s, uint16_t *m) {
@@ -311,7 +334,7 @@ static void build_mask(const orc_sim *s, uint16_t *m) {
   for (int64_t n = 0; n < s->N; ++n) {
     int x, y, z;
     ncoord(s, n, &x, &y, &z);
-    m[n] = static_wall(c, y, z) ? 1 : 0;
+    m[n] = static_wall(c, x, y, z) ? 1 : 0;
   }
   for (int p = 0; p < c->n_particles; ++p) {
     const orc_particle *P = &s->P[p];
@@ -411,6 +434,26 @@ static void wetting_node(const orc_sim *s, int64_t n, int x, int y, int z, doubl
      * z direction, above node z = nz - 1 */
     ns[0] = ns[1] = 0.0;
     ns[2] = (z == 1) ? 1.0 : -1.0;
+    theta = s->c.theta_wall_deg * M_PI / 180.0;
+  } else if (s->c.has_wall == 3) {
+    /* reading: the normal of the nearest point of the solid surface (the
+     * plane's top face z = 1/2 or, through the periodic z direction, its
+     * underside z = nz - 1/2; the boxes grown by half a node), from it to the
+     * node; on ties the plane, then the lowest box index */
+    double dt = z - 0.5, du = ((double)s->c.nz - 0.5) - z;
+    double best = dt <= du ? dt : du;
+    ns[0] = ns[1] = 0.0;
+    ns[2] = dt <= du ? 1.0 : -1.0;
+    const double xp[3] = {(double)x, (double)y, (double)z};
+    for (int b = 0; b < s->c.n_boxes; ++b) {
+      double d[3];
+      box_offset(s->c.boxes[b], xp, d);
+      double dn = norm3(d);
+      if (dn > 0.0 && dn < best) {
+        best = dn;
+        for (int k = 0; k < 3; ++k) ns[k] = d[k] / dn;
+      }
+    }
     theta = s->c.theta_wall_deg * M_PI / 180.0;
   } else {
     /* tube: the wall's outward normal points from the node to the axis */
@@ -851,6 +894,23 @@ static void contacts_all(orc_sim *s, const double *vp, const double *wp, double 
           Fsum[d] += Fo[d];
           Tsum[d] += To[d];
         }
+      /* reading: each box of a textured wall is a contact partner of its own
+       * (id -3 - b) at the nearest point of its grown surface, the normal from
+       * there to the centre; no contact while the centre is inside it */
+      for (int b = 0; c->has_wall == 3 && b < c->n_boxes; ++b) {
+        double d[3], nbx[3] = {0, 0, 0};
+        box_offset(c->boxes[b], P->x, d);
+        double dn = norm3(d);
+        if (dn > 0.0)
+          for (int k = 0; k < 3; ++k) nbx[k] = d[k] / dn;
+        double db2 = dn > 0.0 ? Rci - dn : -1.0;
+        if (contact(s, i, -3 - b, db2, nbx, vp + 3 * i, wp + 3 * i, zero, zero, Rci, 0.0, zero,
+                    P->mu_s, P->mu_r, dt, Fo, To))
+          for (int k = 0; k < 3; ++k) {
+            Fsum[k] += Fo[k];
+            Tsum[k] += To[k];
+          }
+      }
     }
     for (int j = 0; j < np; ++j) {
       if (j == i) continue;
@@ -1061,7 +1121,16 @@ void orc_destroy(orc_sim *s);
 orc_sim *orc_create(const orc_config *cfg, const float *phi0, const orc_particle *parts) {
   build_tables();
   if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 3) return NULL;
-  if (cfg->has_wall < 0 || cfg->has_wall > 2) return NULL;
+  if (cfg->has_wall < 0 || cfg->has_wall > 3) return NULL;
+  if (cfg->has_wall == 3) {
+    if (cfg->n_boxes < 0 || cfg->n_boxes > 8 || cfg->open_x) return NULL;
+    const int L[3] = {cfg->nx, cfg->ny, cfg->nz};
+    for (int b = 0; b < cfg->n_boxes; ++b)
+      for (int k = 0; k < 3; ++k)
+        if (cfg->boxes[b][k] < 0 || cfg->boxes[b][k] > cfg->boxes[b][3 + k] ||
+            cfg->boxes[b][3 + k] >= L[k])
+          return NULL;
+  }
   if (cfg->has_wall == 2 && !(cfg->tube_R > 0.0)) return NULL;
   if (cfg->open_x && (!(cfg->rho_in > 0.0) || !(cfg->rho_out > 0.0) || cfg->nx < 2)) return NULL;
   orc_sim *s = calloc(1, sizeof(orc_sim));
