@@ -25,6 +25,8 @@ One JSON line:
 - tube: the hydrodynamic-force benchmark's set-up (a sphere of radius 12.2 in
   pressure-driven flow through a tube of radius 40 between anti-bounce-back
   pressure ends, 320x83x83), FP32;
+- textured: a drop on a textured wall (eight pillars) with six spheres,
+  256x128x64, FP32;
 - cpu_baseline: the FP64 oracle timed on a bounded sample of the same workload
   on this host's cores (all usable threads, and one thread), and, from the same
   oracle runs, the GPU fields' error at the sampled step counts (the C3 sample
@@ -298,12 +300,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed steps of the C3 runs")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--only", choices=["c3", "c3-fp16", "c2", "c4", "table1", "tube"], default=None,
+    ap.add_argument("--only", choices=["c3", "c3-fp16", "c2", "c4", "table1", "tube", "textured"],
+                    default=None,
                     help="run one part alone (for profiling): no line, a short summary")
     ap.add_argument("--c2-steps", type=int, default=2000)
     ap.add_argument("--c4-steps", type=int, default=200)
     ap.add_argument("--table1-steps", type=int, default=2000)
     ap.add_argument("--tube-steps", type=int, default=2000)
+    ap.add_argument("--textured-steps", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -339,6 +343,8 @@ def main():
             r = run_lattice(W.table1_n1(), args.steps, args.warmup)
         elif args.only == "tube":
             r = run_lattice(W.tube_segre(), args.steps, args.warmup)
+        elif args.only == "textured":
+            r = run_lattice(W.textured_wall(), args.steps, args.warmup)
         else:
             r = ensemble(256, args.c4_steps, 4)
             r.pop("gate_fields")
@@ -357,6 +363,7 @@ def main():
     c4 = ensemble(256, args.c4_steps, 4)
     rt1 = run_lattice(W.table1_n1(), args.table1_steps, 20)
     rtb = run_lattice(W.tube_segre(), args.tube_steps, 20)
+    rtx = run_lattice(W.textured_wall(), args.textured_steps, 20)
     cfg = c3w["cfg"]
     out = {
         "metric": METRIC,
@@ -405,6 +412,11 @@ def main():
                  "steps": args.tube_steps, "mlups": round(rtb["mlups"], 1),
                  "ms_per_step": round(rtb["ms_per_step"], 5),
                  "roofline_frac": rtb["roofline"]["frac"]},
+        "textured": {"workload": "drop R=24 on a textured wall (8 pillars 12x12x8) with 6 spheres R=4, "
+                                 "256x128x64, wall 110 deg, FP32",
+                     "steps": args.textured_steps, "mlups": round(rtx["mlups"], 1),
+                     "ms_per_step": round(rtx["ms_per_step"], 5),
+                     "roofline_frac": rtx["roofline"]["frac"]},
     }
     if not args.no_cpu:
         c3_gpu = gpu_fields_after(c3w, args.cpu_steps)

@@ -69,12 +69,22 @@ enum lbm_storage {
 enum lbm_wall {
   LBM_WALL_NONE = 0,  /* fully periodic box                                   */
   LBM_WALL_PLANE = 1, /* the node plane z = 0 (the substrate of the drop runs)  */
-  LBM_WALL_TUBE = 2   /* a tube along x: node (x, y, z) is solid iff
+  LBM_WALL_TUBE = 2,  /* a tube along x: node (x, y, z) is solid iff
                          (y - (ny-1)/2)^2 + (z - (nz-1)/2)^2 >= tube_R^2 (the
                          hydrodynamic benchmark of the section "Benchmarking
                          hydrodynamic force"); wetting and DEM contact use the
                          cylinder's normal, from the wall towards the axis     */
+  LBM_WALL_BOXES = 3  /* a textured wall (the future work of the paper's
+                         conclusions): the plane z = 0 and n_boxes boxes of
+                         solid nodes; box b holds the nodes with
+                         boxes[b][k] <= x_k <= boxes[b][3+k]; its solid surface
+                         is the box grown by half a node.  Wetting takes the
+                         normal of the nearest surface point (ties: the plane,
+                         then the lowest box); each box is a DEM contact
+                         partner of its own at its nearest surface point.
+                         Needs open_x = 0                                    */
 };
+#define LBM_MAX_BOXES 8
 
 enum lbm_field_bits {
   LBM_F_RHO = 1u,  /* total density rho                              (float) */
@@ -120,6 +130,9 @@ typedef struct {
   int32_t pad0;
   double rho_in, rho_out;
   double tube_R;        /* tube radius (LBM_WALL_TUBE)                       */
+  int32_t n_boxes;      /* boxes of a textured wall (LBM_WALL_BOXES), <= 8   */
+  int32_t pad1;
+  int32_t boxes[LBM_MAX_BOXES][6]; /* lo x, y, z, hi x, y, z node indices  */
 } lbm_config;
 
 /* FP64 particle record, in and out. */

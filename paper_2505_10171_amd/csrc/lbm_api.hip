@@ -112,7 +112,16 @@ bool valid_config(const lbm_config& c, char* msg, size_t len) {
   if (!(c.theta_wall_deg > 0.0 && c.theta_wall_deg < 180.0))
     return fail("wall contact angle must be in (0, 180) degrees");
   if (c.storage != LBM_STORE_FP32 && c.storage != LBM_STORE_FP16) return fail("unknown storage");
-  if (c.has_wall < LBM_WALL_NONE || c.has_wall > LBM_WALL_TUBE) return fail("unknown wall kind");
+  if (c.has_wall < LBM_WALL_NONE || c.has_wall > LBM_WALL_BOXES) return fail("unknown wall kind");
+  if (c.has_wall == LBM_WALL_BOXES) {
+    if (c.n_boxes < 0 || c.n_boxes > LBM_MAX_BOXES) return fail("n_boxes out of range");
+    if (c.open_x) return fail("a textured wall needs a periodic x direction");
+    const int L[3] = {c.nx, c.ny, c.nz};
+    for (int b = 0; b < c.n_boxes; ++b)
+      for (int k = 0; k < 3; ++k)
+        if (c.boxes[b][k] < 0 || c.boxes[b][k] > c.boxes[b][3 + k] || c.boxes[b][3 + k] >= L[k])
+          return fail("a box of the textured wall lies outside the lattice");
+  }
   if (c.has_wall == LBM_WALL_TUBE && !(c.tube_R > 0.0)) return fail("tube radius must be positive");
   if (c.open_x != 0 && c.open_x != 1) return fail("open_x must be 0 or 1");
   if (c.open_x && (!(c.rho_in > 0.0) || !(c.rho_out > 0.0)))
@@ -295,6 +304,7 @@ struct lbm_ctx {
   int2* d_pmap = nullptr;
   unsigned nblk = 0;
   int np_rows = 0, np_max = 0, Bmax = 0, cap_B = 0, npts = 0, n_sub_max = 1;
+  bool cap_needed = false;  // some simulation with particles has a capillary force
   size_t fresh_cap_max = 0;
   unsigned mnblk = 0;  // blocks of the moments pass over the batch
   // graph replay of a pair of steps (captured with cur == graph_cur)
@@ -355,7 +365,7 @@ static unsigned mom_blocks(const SimDev& d) {
 
 // open x ends or a tube: the interface kernel's general instance
 static int general_geometry(const lbm_config& c) {
-  return c.open_x || c.has_wall == LBM_WALL_TUBE;
+  return c.open_x || c.has_wall == LBM_WALL_TUBE || c.has_wall == LBM_WALL_BOXES;
 }
 static Batch batch_all(const lbm_ctx* c) {
   int open = 0;
@@ -411,6 +421,7 @@ static int upload_tables(lbm_ctx* ctx, size_t off) {
   std::vector<uint32_t> blk(n_sims + 1, 0), mblk(n_sims + 1, 0);
   std::vector<int2> pmap;
   ctx->np_max = ctx->Bmax = ctx->cap_B = ctx->npts = 0;
+  ctx->cap_needed = false;
   ctx->n_sub_max = 1;
   ctx->fresh_cap_max = 0;
   for (int si = 0; si < n_sims; ++si) {
@@ -429,6 +440,7 @@ static int upload_tables(lbm_ctx* ctx, size_t off) {
       ctx->Bmax = std::max(ctx->Bmax, sh.L.Bmask);
       ctx->cap_B = std::max(ctx->cap_B, sh.d.cap_B);
       ctx->npts = std::max(ctx->npts, sh.d.cap_na * sh.d.cap_nphi);
+      ctx->cap_needed |= sh.d.cap_pref != 0.0;
       ctx->fresh_cap_max = std::max(ctx->fresh_cap_max, (size_t)sh.d.fresh_cap);
     }
   }
@@ -545,6 +557,9 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
     d.tube_R2 = c.tube_R * c.tube_R;
     d.tube_yc = 0.5 * (c.ny - 1);
     d.tube_zc = 0.5 * (c.nz - 1);
+    d.n_boxes = c.has_wall == LBM_WALL_BOXES ? c.n_boxes : 0;
+    for (int b = 0; b < d.n_boxes; ++b)
+      for (int k = 0; k < 6; ++k) d.boxes[b][k] = c.boxes[b][k];
     d.N = sh.L.N;
     set_mom_tiling(d);
     d.storage = c.storage;
@@ -691,7 +706,9 @@ static int step_once(lbm_ctx* ctx, int slot) {
   ctx->rd ^= 1;
   const Batch a = batch_all(ctx);
   if (ctx->np_rows > 0) {
-    HIPCHK(ctx, launch_capillary(a, ctx->np_rows, ctx->cap_B, ctx->npts, st));
+    // without surface tension (sigma = 0) the capillary force is zero: the DEM
+    // reads the accumulators it cleared itself
+    if (ctx->cap_needed) HIPCHK(ctx, launch_capillary(a, ctx->np_rows, ctx->cap_B, ctx->npts, st));
     HIPCHK(ctx, launch_dem(a, ctx->np_max, ctx->np_rows, ctx->n_sub_max, st));
     HIPCHK(ctx, launch_mask_update(a, ctx->np_rows, ctx->Bmax, true, st));
     HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, REFILL_STEP, st));

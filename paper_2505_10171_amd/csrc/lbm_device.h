@@ -42,8 +42,13 @@ constexpr float EPS_T = 1e-3f;   // capillary direction length below which a poi
 constexpr int MAXC = 16;        // contact slots per particle
 constexpr int MAXNB = 24;       // DEM pair candidates per particle
 constexpr uint16_t FRESH_BIT = 0x8000;
-constexpr float PHI_SOLID = 4.0f;       // phi stored at solid nodes (never a fluid value)
+// phi stored at solid nodes (never a fluid value): PHI_SOLID + the node's mask
+// code, 5 on the static wall, 6 + p inside particle p (exact in FP32), so that
+// the stencils tell solids, and which solid, from phi alone; PHI_SOLID itself
+// stands for the nodes beyond an open end
+constexpr float PHI_SOLID = 4.0f;
 constexpr float PHI_SOLID_TEST = 2.0f;  // phi above this marks a solid node
+__host__ __device__ inline float solid_phi(uint32_t mask_code) { return PHI_SOLID + (float)mask_code; }
 
 // -------------------------------------------------------------- particles
 struct alignas(16) DevParticle {
@@ -152,6 +157,11 @@ struct SimDev {
   int open_x;
   float drho_in, drho_out;
   double tube_R2, tube_yc, tube_zc;
+  // boxes of solid nodes on the plane (has_wall 3, a textured wall): per box
+  // lo x, y, z, hi x, y, z (node indices, inclusive); the solid surface is the
+  // box grown by half a node
+  int n_boxes;
+  int boxes[8][6];
   long long N;
   int storage, np;
   float rho0, sigma, beta, inv2nua, inv2nub;
@@ -233,12 +243,20 @@ enum StatusBits : uint32_t {
   ST_OPEN_END = 8u  // a particle came within R + 4 nodes of an open x end
 };
 
-// Static solid of the simulation at node row (y, z) (walls do not vary along
-// x): the plane z = 0, or the outside of a tube of radius R_t about the axis
-// through ((ny - 1)/2, (nz - 1)/2): solid iff dy^2 + dz^2 >= R_t^2 (dy, dz are
-// multiples of 1/2, so the sum is exact in FP64).
-__host__ __device__ inline bool static_wall(const SimDev& s, int y, int z) {
+// Static solid of the simulation at node (x, y, z): the plane z = 0; the
+// outside of a tube of radius R_t about the axis through ((ny - 1)/2,
+// (nz - 1)/2), solid iff dy^2 + dz^2 >= R_t^2 (dy, dz are multiples of 1/2, so
+// the sum is exact in FP64); or the plane with its boxes.
+__host__ __device__ inline bool static_wall(const SimDev& s, int x, int y, int z) {
   if (s.has_wall == 1) return z == 0;
+  if (s.has_wall == 3) {
+    if (z == 0) return true;
+    for (int b = 0; b < s.n_boxes; ++b) {
+      const int* B = s.boxes[b];
+      if (x >= B[0] && x <= B[3] && y >= B[1] && y <= B[4] && z >= B[2] && z <= B[5]) return true;
+    }
+    return false;
+  }
   if (s.has_wall == 2) {
     const double dy = (double)y - s.tube_yc, dz = (double)z - s.tube_zc;
     return dy * dy + dz * dz >= s.tube_R2;

@@ -36,20 +36,51 @@ __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, 
   if (!(g > EPS_G)) return;
   float nsx, nsy, nsz, nc, ns;
   if (minp >= 0) {
+    // in FP64, rounded once to FP32 (the wetting direction next to a particle
+    // moves the velocity there at the 1e-5 level)
     const DevParticle& P = s.P[minp];
-    double dx = wrapd((double)gx - P.x[0], (double)s.nx);
-    double dy = wrapd((double)gy - P.x[1], (double)s.ny);
-    double dz = wrapd((double)gz - P.x[2], (double)s.nz);
-    double dn = sqrt(dx * dx + dy * dy + dz * dz);
-    nsx = (float)(dx / dn);
-    nsy = (float)(dy / dn);
-    nsz = (float)(dz / dn);
+    const double dx = wrapd((double)gx - P.x[0], (double)s.nx);
+    const double dy = wrapd((double)gy - P.x[1], (double)s.ny);
+    const double dz = wrapd((double)gz - P.x[2], (double)s.nz);
+    const double idn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    nsx = (float)(dx * idn);
+    nsy = (float)(dy * idn);
+    nsz = (float)(dz * idn);
     nc = P.neg_cos_t;
     ns = P.sin_t;
   } else if (wall_nb && (!GENERAL || s.has_wall == 1)) {
     nsx = 0.f;
     nsy = 0.f;
     nsz = (gz == 1) ? 1.f : -1.f;
+    nc = s.wall_neg_cos;
+    ns = s.wall_sin;
+  } else if (wall_nb && s.has_wall == 3) {
+    // textured wall: the normal of the nearest point of the solid surface (the
+    // plane's top face z = 1/2, or its underside z = nz - 1/2 through the
+    // periodic z direction; the boxes grown by half a node), from it to the
+    // node; on ties the plane, then the lowest box index
+    const double dt = (double)gz - 0.5, du = ((double)s.nz - 0.5) - (double)gz;
+    double best = dt <= du ? dt : du;
+    double bx = 0.0, by = 0.0, bz = dt <= du ? 1.0 : -1.0;
+    for (int b = 0; b < s.n_boxes; ++b) {
+      const int* B = s.boxes[b];
+      const double p[3] = {(double)gx, (double)gy, (double)gz};
+      double d[3];
+      for (int k = 0; k < 3; ++k) {
+        const double lo = B[k] - 0.5, hi = B[3 + k] + 0.5;
+        d[k] = p[k] - (p[k] < lo ? lo : (p[k] > hi ? hi : p[k]));
+      }
+      const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (dn > 0.0 && dn < best) {
+        best = dn;
+        bx = d[0] / dn;
+        by = d[1] / dn;
+        bz = d[2] / dn;
+      }
+    }
+    nsx = (float)bx;
+    nsy = (float)by;
+    nsz = (float)bz;
     nc = s.wall_neg_cos;
     ns = s.wall_sin;
   } else if (wall_nb) {
@@ -112,7 +143,7 @@ __device__ __forceinline__ int xcd_tile(int lin, int nblk) {
 // rebuilt from the state that collided (the colour source (phi, r n) of each
 // node, formed from its moments and normal).  Runs after the
 // refill, which has written the moments of the fresh nodes; clears their FRESH
-// mark.  Solid nodes get (rho0, PHI_SOLID), so that stencils can tell solids
+// mark.  Solid nodes get (rho0, solid_phi(mask)), so that stencils can tell solids
 // from phi alone.
 //
 // A block takes an x-y tile of the simulation's moments tiling and marches up
@@ -210,7 +241,7 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
         MASK[n] = (uint16_t)(m & ~FRESH_BIT);
       } else if (m != 0) {
         RN[n] = s.rho0;
-        RN[N + n] = PHI_SOLID;
+        RN[N + n] = solid_phi(m);
       } else {
         RN[n] = rabs;
         RN[N + n] = sg / rabs;
@@ -221,7 +252,7 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
 }
 
 // Between steps, after the mask changed with the populations in place (and
-// the refill of fresh nodes): solid nodes get (rho0, PHI_SOLID), fresh nodes
+// the refill of fresh nodes): solid nodes get (rho0, solid_phi(mask)), fresh nodes
 // lose their mark, fluid nodes keep their moments.
 __global__ __launch_bounds__(256) void k_moments_boundary(Batch bt) {
   const int2 sb = batch_block(bt, blockIdx.x);
@@ -235,7 +266,7 @@ __global__ __launch_bounds__(256) void k_moments_boundary(Batch bt) {
   } else if (m != 0) {
     float* RN = s.rp[bt.rd ^ 1];
     RN[n] = s.rho0;
-    RN[s.N + n] = PHI_SOLID;
+    RN[s.N + n] = solid_phi(m);
   }
 }
 
@@ -244,13 +275,13 @@ __global__ void k_init_mask(SimDev s) {
   long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= s.N) return;
   int z = (int)(n / ((long long)s.nx * s.ny));
-  const int y = (int)((n / s.nx) % s.ny);
-  s.mask[n] = static_wall(s, y, z) ? 1 : 0;
+  const int x = (int)(n % s.nx), y = (int)((n / s.nx) % s.ny);
+  s.mask[n] = static_wall(s, x, y, z) ? 1 : 0;
   s.claim[n] = 0xFFFFFFFFu;
 }
 
 // fluid at rest: f = w rho0 (d = 0), moments (rho0, phi0) in both moment
-// buffers (phi0 staged in the phi plane of rp[0]; (rho0, PHI_SOLID) at solids)
+// buffers (phi0 staged in the phi plane of rp[0]; (rho0, solid_phi(mask)) at solids)
 template <int STORE>
 __global__ void k_init_pops(SimDev s, void* pops) {
   using IO = Codec<STORE>;
@@ -263,7 +294,8 @@ __global__ void k_init_pops(SimDev s, void* pops) {
     const float wr0 = wq(i) * s.rho0;
     IO::st(b + pidx(i, (int)s.N, (int)n), wr0, 1.0f / wr0, wr0, 0.f);
   }
-  const float p0 = (s.mask[n] == 0) ? s.rp[0][s.N + n] : PHI_SOLID;
+  const uint16_t m0 = s.mask[n];
+  const float p0 = (m0 == 0) ? s.rp[0][s.N + n] : solid_phi(m0);
   for (int k = 0; k < 2; ++k) {
     s.rp[k][n] = s.rho0;
     s.rp[k][s.N + n] = p0;
@@ -424,18 +456,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
       Gy += (float)cy(i) * d;
       Gz += (float)cz(i) * d;
     }
-    if (decltype(SOL)::value && solid) {
-      // identify the solid: the lowest-index neighbouring particle, else the wall
-      const int ax = wrapi(x0 - 1 + hx, nx), ay = wrapi(y0 - 1 + hy, ny), az = zw(z);
-      const Nbr nb(ax, ay, az, nx, ny, nz);
-      int minp = 0x7fffffff;
+    // the wetting rotation applies only inside the interface (|G| > EPS_G, its
+    // own first test); only there the solid is identified, from the phi
+    // codes of the neighbours in the ring: the lowest-index particle, else
+    // the wall (an open end is neither)
+    if (decltype(SOL)::value && solid && sqrtf(Gx * Gx + Gy * Gy + Gz * Gz) > EPS_G) {
+      float pmin = 3.0e38f;
       bool wall = false;
-      for (int i = 1; i < Q; ++i) {
-        const uint16_t m = s.mask[nb(i)];
-        if (m >= 2) minp = min(minp, (int)m - 2);
-        else if (m == 1) wall = true;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const int i = pair_dir(q);
+        const float* sp_ = cz(i) > 0 ? fp : (cz(i) < 0 ? fm : f0);
+        const float* sm_ = cz(i) > 0 ? fm : (cz(i) < 0 ? fp : f0);
+        const float vp = sp_[c + cx(i) + FX * cy(i)];
+        const float vm = sm_[c - cx(i) - FX * cy(i)];
+        wall |= vp == solid_phi(1) || vm == solid_phi(1);
+        if (vp >= solid_phi(2)) pmin = fminf(pmin, vp);
+        if (vm >= solid_phi(2)) pmin = fminf(pmin, vm);
       }
-      wetting_rotate<OPEN>(s, ax, ay, az, minp == 0x7fffffff ? -1 : minp, wall, Gx, Gy, Gz);
+      if (wall || pmin < 3.0e38f) {
+        const int ax = wrapi(x0 - 1 + hx, nx), ay = wrapi(y0 - 1 + hy, ny), az = zw(z);
+        const int minp = pmin < 3.0e38f ? (int)(pmin - solid_phi(2)) : -1;
+        wetting_rotate<OPEN>(s, ax, ay, az, minp, wall, Gx, Gy, Gz);
+      }
     }
     const float g = sqrtf(Gx * Gx + Gy * Gy + Gz * Gz);
     const float ig = 1.0f / fmaxf(g, EPS_G);
@@ -584,7 +627,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // next moments pass rebuilds it from phi, rho and n of this state.  At
 // particle links the moving-wall term and the momentum exchange are added by
 // k_links.
-template <int STORE, int MODE>
+// OPEN: the batch has simulations with open x ends (their anti-bounce-back is
+// compiled into this instance only).
+template <int STORE, int MODE, bool OPEN>
 __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out_rho,
                                               float* __restrict__ out_u,
                                               float* __restrict__ out_phi,
@@ -692,7 +737,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   // - 3/2 u^2), u the node's velocity, p_w = rho_w / 3
   auto emit = [&](int i, float dv) {
     if (bits & (1u << i)) {
-      if (s.open_x && ((cx(i) < 0 && gx == 0) || (cx(i) > 0 && gx == nx - 1))) {
+      if (OPEN && s.open_x && ((cx(i) < 0 && gx == 0) || (cx(i) > 0 && gx == nx - 1))) {
         const float drw = cx(i) < 0 ? s.drho_in : s.drho_out;
         const float cu = (float)cx(i) * ux + (float)cy(i) * uy + (float)cz(i) * uz;
         const float w = wq(i);
@@ -877,18 +922,24 @@ hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipSt
 hipError_t launch_fused(const Batch& b, int storage, unsigned nblk, int mode, float* orho,
                         float* ou, float* ophi, float* oF, hipStream_t st) {
   const dim3 grid(nblk);
-  if (storage == 0) {
-    if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_fused<0, MODE_STEP>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
+  // the fields pass writes no populations: it needs no open-end instance
+  if (mode != MODE_STEP) {
+    if (storage == 0)
+      hipLaunchKernelGGL((k_fused<0, MODE_FIELDS, false>), grid, dim3(256), 0, st, b, orho, ou,
+                         ophi, oF);
     else
-      hipLaunchKernelGGL((k_fused<0, MODE_FIELDS>), grid, dim3(256), 0, st, b, orho, ou, ophi,
-                         oF);
+      hipLaunchKernelGGL((k_fused<1, MODE_FIELDS, false>), grid, dim3(256), 0, st, b, orho, ou,
+                         ophi, oF);
+  } else if (storage == 0) {
+    if (b.open)
+      hipLaunchKernelGGL((k_fused<0, MODE_STEP, true>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
+    else
+      hipLaunchKernelGGL((k_fused<0, MODE_STEP, false>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
   } else {
-    if (mode == MODE_STEP)
-      hipLaunchKernelGGL((k_fused<1, MODE_STEP>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
+    if (b.open)
+      hipLaunchKernelGGL((k_fused<1, MODE_STEP, true>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
     else
-      hipLaunchKernelGGL((k_fused<1, MODE_FIELDS>), grid, dim3(256), 0, st, b, orho, ou, ophi,
-                         oF);
+      hipLaunchKernelGGL((k_fused<1, MODE_STEP, false>), grid, dim3(256), 0, st, b, orho, ou, ophi, oF);
   }
   return hipGetLastError();
 }

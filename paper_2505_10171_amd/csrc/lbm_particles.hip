@@ -54,7 +54,7 @@ __global__ void k_claim(Batch bt) {
     const int ix = k % b.w[0], iy = (k / b.w[0]) % b.w[1], iz = k / (b.w[0] * b.w[1]);
     const int x = wrapi(b.lo[0] + ix, s.nx), y = wrapi(b.lo[1] + iy, s.ny),
               z = wrapi(b.lo[2] + iz, s.nz);
-    if (static_wall(s, y, z)) continue;
+    if (static_wall(s, x, y, z)) continue;
     if (inside_sphere(x, y, z, P.x, P.R, s.nx, s.ny, s.nz)) {
       const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
       atomicMin(&s.claim[n], (uint32_t)p);
@@ -222,6 +222,7 @@ __global__ void k_capbox(Batch bt) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) org[k] = (int)floor(P.x[k] - P.R);
   if (blockIdx.x == 0 && threadIdx.x < 3) s.capbox_org[3 * p + threadIdx.x] = org[threadIdx.x];
+  if (s.cap_pref == 0.0) return;  // no surface tension: no capillary force
   float4* box = s.capbox + (long long)p * B * B * B;
   // phi of the state that collided this step (the buffers have swapped)
   const float* PHI = s.rp[bt.rd] + s.N;
@@ -250,6 +251,7 @@ __global__ __launch_bounds__(256) void k_capillary(Batch bt) {
   const SimDev& s = bt.tab[sp.x];
   const int p = sp.y;
   DevParticle& P = s.P[p];
+  if (s.cap_pref == 0.0) return;  // no surface tension: no capillary force
   const int B = s.cap_B;
   const float4* box = s.capbox + (long long)p * B * B * B;
   const int org0 = (int)floor(P.x[0] - P.R), org1 = (int)floor(P.x[1] - P.R),
@@ -512,7 +514,27 @@ __device__ __forceinline__ void stage_in(double* dst, const double* src1, int n1
 __device__ __forceinline__ bool wall_geom(const SimDev& s, const double* x, double Rc, int partner,
                                           double& delta, double* nh) {
   nh[0] = nh[1] = nh[2] = 0.0;
-  if (s.has_wall == 1) {
+  if (s.has_wall == 3 && partner <= -3) {
+    // box -3 - b of a textured wall: its nearest surface point; no contact
+    // while the centre is inside the box
+    const int b = -3 - partner;
+    if (b >= s.n_boxes) return false;
+    const int* B = s.boxes[b];
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+      const double lo = B[k] - 0.5, hi = B[3 + k] + 0.5;
+      d[k] = x[k] - (x[k] < lo ? lo : (x[k] > hi ? hi : x[k]));
+    }
+    const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(dn > 0.0)) {
+      delta = -1.0;
+      return true;
+    }
+    for (int k = 0; k < 3; ++k) nh[k] = d[k] / dn;
+    delta = Rc - dn;
+    return true;
+  }
+  if (s.has_wall == 1 || s.has_wall == 3) {
     if (partner == -1) {
       delta = Rc - (x[2] - 0.5);
       nh[2] = 1.0;
@@ -552,7 +574,7 @@ __device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, cons
   int ids[MAXC];
 #pragma unroll
   for (int k = 0; k < MAXC; ++k) ids[k] = tab[k].partner;
-  for (int w = -1; w >= -2; --w) {
+  for (int w = -1; w >= -2 - (s.has_wall == 3 ? s.n_boxes : 0); --w) {
     double dw, nw[3];
     if (!wall_geom(s, me.x, Rci, w, dw, nw)) continue;
     if (contact(s, tab, ids, w, dw, nw, me.vp, me.wp, zero, zero, Rci, 0.0, zero, me.mu_s,
@@ -1038,6 +1060,8 @@ __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub)
     partner = -1;
   } else if (lane == MAXNB + 1 && s.has_wall) {
     partner = -2;
+  } else if (lane >= MAXNB + 2 && s.has_wall == 3 && lane - (MAXNB + 2) < s.n_boxes) {
+    partner = -3 - (lane - (MAXNB + 2));  // a box of the textured wall
   }
   const double zero[3] = {0.0, 0.0, 0.0};
   double delta = 0.0, nh[3] = {0.0, 0.0, 0.0}, arm[3] = {0.0, 0.0, 0.0};
@@ -1208,10 +1232,9 @@ hipError_t launch_dem(const Batch& b, int np_max, int np_rows, int n_sub_max, hi
   const size_t need = (size_t)np_max * (sizeof(DevParticle) + MAXC * sizeof(Contact)) +
                       (size_t)np_max * MAXNB * sizeof(int);
   if (need <= (size_t)max_lds && need <= 64 * 1024) {
-    // few particles: one workgroup per simulation, everything in LDS; a
-    // single wave up to 64 particles (its barriers cost next to nothing)
-    const unsigned nt = np_max <= 64 ? 64u : 256u;
-    hipLaunchKernelGGL(k_dem, dim3(b.nsim), dim3(nt), need, st, b);
+    // few particles: one workgroup per simulation, everything in LDS (256
+    // threads: a single wave was slower, C2 DEM 44 against 35 us)
+    hipLaunchKernelGGL(k_dem, dim3(b.nsim), dim3(256), need, st, b);
     return hipGetLastError();
   }
   // many particles: set-up, then a launch per sub-step with a wave per particle

@@ -37,7 +37,8 @@ class LbmConfig(C.Structure):
                 ("delta_R", C.c_double), ("cap_k", C.c_double), ("cap_dang_deg", C.c_double),
                 ("storage", C.c_int32), ("n_particles", C.c_int32),
                 ("open_x", C.c_int32), ("pad0", C.c_int32),
-                ("rho_in", C.c_double), ("rho_out", C.c_double), ("tube_R", C.c_double)]
+                ("rho_in", C.c_double), ("rho_out", C.c_double), ("tube_R", C.c_double),
+                ("n_boxes", C.c_int32), ("pad1", C.c_int32), ("boxes", C.c_int32 * 48)]
 
 
 class LbmParticle(C.Structure):
@@ -119,6 +120,11 @@ def make_config(cfg: dict, n_particles: int) -> LbmConfig:
     c.rho_in = float(cfg.get("rho_in", cfg["rho0"]))
     c.rho_out = float(cfg.get("rho_out", cfg["rho0"]))
     c.tube_R = float(cfg.get("tube_R", 0.0))
+    boxes = list(cfg.get("boxes", ()))
+    c.n_boxes = len(boxes)
+    for b, box in enumerate(boxes[:8]):
+        for k in range(6):
+            c.boxes[6 * b + k] = int(box[k])
     return c
 
 

@@ -272,3 +272,32 @@ def tube_reduced(seed: int = 9, storage: str = "fp32"):
     p["x"] = (16.0, p["x"][1], p["x"][2])
     w["steps"] = 200
     return w
+
+
+def textured_wall(seed: int = 10, storage: str = "fp32"):
+    """A textured wall (the future work of the paper's conclusions): a
+    256x128x64 box whose floor carries eight square pillars (12 x 12 nodes, 8
+    high, in a 4 x 2 array), a drop of radius 24 resting on the pillar tops and
+    pushed along x by 4e-6 (wall 110 degrees), and six spheres of radius 4 on
+    the floor between the pillars at seeded positions (contact angle 60-120
+    degrees)."""
+    g = rng(seed, 0)
+    nx, ny, nz = 256, 128, 64
+    boxes = [(cx - 6, cy - 6, 1, cx + 5, cy + 5, 8) for cx in (48, 96, 144, 192) for cy in (40, 88)]
+    cfg = config(nx, ny, nz, has_wall=3, boxes=boxes, theta_wall_deg=110.0,
+                 body_force=(4e-6, 0.0, 0.0), storage=storage)
+    phi0 = drop_phi0(nx, ny, nz, (72.0, 64.0, 8.5), 24.0)
+    R = 4.0
+    Rc = R + cfg["delta_R"]
+    parts = []
+    tries = 0
+    while len(parts) < 6 and tries < 100000:
+        tries += 1
+        x = (g.uniform(110.0, 250.0), g.uniform(Rc, ny - Rc), 0.5 + Rc)
+        clear = all(max(b[0] - 0.5 - x[0], x[0] - b[3] - 0.5, b[1] - 0.5 - x[1], x[1] - b[4] - 0.5)
+                    > Rc + 1.0 for b in boxes)
+        apart = all(np.hypot(x[0] - q["x"][0], x[1] - q["x"][1]) > 2 * Rc + 1.0 for q in parts)
+        if clear and apart:
+            parts.append(particle(x, R, theta_deg=g.uniform(60.0, 120.0), sigma=cfg["sigma"]))
+    return dict(name=f"textured wall {nx}x{ny}x{nz}, 8 pillars, drop R=24, 6 spheres",
+                cfg=cfg, phi0=phi0, particles=parts, steps=5000)

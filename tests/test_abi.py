@@ -99,12 +99,18 @@ def test_workspace_sizing_and_validation():
     c = (lbm.LbmConfig * 1)(lbm.make_config(bad, 0))
     assert L.lbm_workspace_bytes(c, 1, None, 0) == 0
     # open x ends and the tube wall: kinds and boundary densities are checked
-    for bad in (dict(cfg, has_wall=3), dict(cfg, has_wall=2, tube_R=0.0),
+    for bad in (dict(cfg, has_wall=4), dict(cfg, has_wall=2, tube_R=0.0),
                 dict(cfg, open_x=1, rho_in=0.0), dict(cfg, open_x=1, rho_out=-1.0),
-                dict(cfg, open_x=2)):
+                dict(cfg, open_x=2), dict(cfg, has_wall=3, boxes=[(0, 0, 1, 64, 3, 3)]),
+                dict(cfg, has_wall=3, boxes=[(5, 0, 1, 4, 3, 3)]),
+                dict(cfg, has_wall=3, boxes=[(0, 0, 1, 3, 3, 3)] * 9),
+                dict(cfg, has_wall=3, open_x=1, boxes=[(0, 0, 1, 3, 3, 3)])):
         c = (lbm.LbmConfig * 1)(lbm.make_config(bad, 0))
         assert L.lbm_workspace_bytes(c, 1, None, 0) == 0, bad
     ok = dict(cfg, has_wall=2, tube_R=7.5, open_x=1, rho_in=0.051, rho_out=0.049)
+    c = (lbm.LbmConfig * 1)(lbm.make_config(ok, 0))
+    assert L.lbm_workspace_bytes(c, 1, None, 0) == nb
+    ok = dict(cfg, has_wall=3, boxes=[(0, 0, 1, 63, 31, 3), (10, 10, 4, 12, 12, 9)])
     c = (lbm.LbmConfig * 1)(lbm.make_config(ok, 0))
     assert L.lbm_workspace_bytes(c, 1, None, 0) == nb
     # FP16 storage halves the population bytes
