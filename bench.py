@@ -318,7 +318,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+              "decomposition is described, not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2505_10171_amd import workloads as W

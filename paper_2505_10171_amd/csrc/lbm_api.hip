@@ -363,18 +363,23 @@ static unsigned mom_blocks(const SimDev& d) {
   return (unsigned)((long long)d.mtiles_x * d.mtiles_y * d.mtiles_z);
 }
 
-// open x ends or a tube: the interface kernel's general instance
+// open x ends, a tube or a textured wall: the interface kernel's general
+// instance; open x ends: the fused kernel's
 static int general_geometry(const lbm_config& c) {
   return c.open_x || c.has_wall == LBM_WALL_TUBE || c.has_wall == LBM_WALL_BOXES;
 }
 static Batch batch_all(const lbm_ctx* c) {
-  int open = 0;
-  for (const SimHost& sh : c->sims) open |= general_geometry(sh.cfg);
-  return Batch{c->d_tab, c->d_blk, c->d_mblk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd, open};
+  int general = 0, open = 0;
+  for (const SimHost& sh : c->sims) {
+    general |= general_geometry(sh.cfg);
+    open |= sh.cfg.open_x;
+  }
+  return Batch{c->d_tab, c->d_blk, c->d_mblk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd,
+               general, open};
 }
 static Batch batch_one(const lbm_ctx* c, int si) {
   return Batch{c->d_tab + si, nullptr, nullptr, nullptr, 1, c->cur, c->rd,
-               general_geometry(c->sims[si].cfg)};
+               general_geometry(c->sims[si].cfg), c->sims[si].cfg.open_x};
 }
 
 // workspace tail holding the batch tables

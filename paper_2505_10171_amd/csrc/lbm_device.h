@@ -284,7 +284,8 @@ struct Batch {
   const int2* pmap;
   int nsim;
   int cur, rd;
-  int open;  // some simulation of the batch has open x ends or a tube wall
+  int general;  // some simulation has open x ends, a tube or a textured wall
+  int open;     // some simulation has open x ends
 };
 
 // (simulation, block within it) of global block g, given the block prefix blk

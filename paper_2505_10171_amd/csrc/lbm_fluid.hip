@@ -59,9 +59,14 @@ __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, 
     // plane's top face z = 1/2, or its underside z = nz - 1/2 through the
     // periodic z direction; the boxes grown by half a node), from it to the
     // node; on ties the plane, then the lowest box index
+    // (distances compared squared: node and surface coordinates are
+    // multiples of 1/2, so the squares are exact; one square root, for the
+    // winner)
     const double dt = (double)gz - 0.5, du = ((double)s.nz - 0.5) - (double)gz;
-    double best = dt <= du ? dt : du;
+    const double dp = dt <= du ? dt : du;
+    double best2 = dp * dp;
     double bx = 0.0, by = 0.0, bz = dt <= du ? 1.0 : -1.0;
+    bool boxed = false;
     for (int b = 0; b < s.n_boxes; ++b) {
       const int* B = s.boxes[b];
       const double p[3] = {(double)gx, (double)gy, (double)gz};
@@ -70,13 +75,20 @@ __device__ __forceinline__ void wetting_rotate(const SimDev& s, int gx, int gy, 
         const double lo = B[k] - 0.5, hi = B[3 + k] + 0.5;
         d[k] = p[k] - (p[k] < lo ? lo : (p[k] > hi ? hi : p[k]));
       }
-      const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      if (dn > 0.0 && dn < best) {
-        best = dn;
-        bx = d[0] / dn;
-        by = d[1] / dn;
-        bz = d[2] / dn;
+      const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (d2 > 0.0 && d2 < best2) {
+        best2 = d2;
+        bx = d[0];
+        by = d[1];
+        bz = d[2];
+        boxed = true;
       }
+    }
+    if (boxed) {
+      const double idn = 1.0 / sqrt(best2);
+      bx *= idn;
+      by *= idn;
+      bz *= idn;
     }
     nsx = (float)bx;
     nsy = (float)by;
@@ -832,6 +844,8 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
     if (d2 < rhi * rhi && (rlo <= 0.0 || d2 >= rlo * rlo)) {
       // the node's and its neighbours' masks, its density and the 18
       // populations that bounce-back may have written, all in one round trip
+      // (reading the populations only after the masks, in the link directions,
+      // moves less data but adds a round trip: C2 16 -> 20 us)
       const Nbr nb(gx, gy, gz, nx, ny, nz);
       const uint16_t me = (uint16_t)(2 + p);
       const uint16_t m0 = MASK[n];
@@ -912,7 +926,7 @@ static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 
 // nblk: per-node blocks; mnblk: blocks of the moments tiling (k_normal)
 hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipStream_t st) {
   (void)nblk;
-  if (b.open)
+  if (b.general)
     hipLaunchKernelGGL(k_interface<true>, dim3(mnblk), dim3(256), 0, st, b);
   else
     hipLaunchKernelGGL(k_interface<false>, dim3(mnblk), dim3(256), 0, st, b);
