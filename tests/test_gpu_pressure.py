@@ -169,3 +169,23 @@ def test_march_depth_gives_identical_results():
     for f in out[1:]:
         for a, b in zip(out[0], f):
             assert np.array_equal(a, b)
+
+
+def test_held_sphere_against_the_tube():
+    """A sphere held (prescribed velocity zero) at overlap 0.2 with the tube's
+    wall, off-axis along a diagonal of the section: its contact force against
+    the oracle's (the cylinder as a DEM contact surface)."""
+    Rt, R, d0 = 8.0, 3.0, 0.2
+    cfg = W.config(20, 19, 19, has_wall=2, tube_R=Rt)
+    Rc = R + cfg["delta_R"]
+    c = 9.0
+    e = np.array([0.0, 1.0, -1.0]) / np.sqrt(2.0)   # from the axis towards the wall
+    x0 = np.array([10.0, c, c]) + e * (Rt - Rc + d0)
+    parts = [W.particle(tuple(x0), R, g_p=0.0, kinematic=1)]
+    o = OracleSim(cfg, None, parts)
+    g = _gpu(cfg, None, parts)
+    o.step(2)
+    g.step(2)
+    fo, fg = np.array(o.particles()[0]["F_con"]), np.array(g.particles()[0]["F_con"])
+    assert np.abs(fo + cfg["kn"] * d0 * e).max() <= 1e-12
+    assert np.abs(fg - fo).max() <= 1e-9 * np.abs(fo).max()
