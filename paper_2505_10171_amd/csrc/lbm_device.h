@@ -342,6 +342,22 @@ __host__ __device__ __forceinline__ unsigned pidx(int i, int N, int n) {
          ((unsigned)n % POP_BLOCK);
 }
 
+// population 0 of node n; population i sits at i * POP_BLOCK past it (64-bit
+// arithmetic, so that the 19 loads share one address and immediate offsets)
+template <class T>
+__device__ __forceinline__ T* pop_base(T* pops, int n) {
+  return pops + ((size_t)((unsigned)n / POP_BLOCK) * (size_t)(Q * POP_BLOCK) +
+                 (size_t)((unsigned)n % POP_BLOCK));
+}
+
+// element idx of a plane through a 32-bit byte offset from the plane's base
+// (a plane holds fewer than 2^30 elements): with the base uniform the load takes
+// the scalar-base form and one 32-bit register instead of a 64-bit address
+template <class T>
+__device__ __forceinline__ T at(const T* base, unsigned idx) {
+  return *(const T*)((const char*)base + (unsigned)(idx * (unsigned)sizeof(T)));
+}
+
 // Moments of the post-stream state at fluid node n (order-parameter eq.), with
 // the colour populations rebuilt from the state that collided.  The
 // recolouring (recolouring eqs.) gave the population leaving x' in direction i
@@ -360,8 +376,10 @@ __host__ __device__ __forceinline__ unsigned pidx(int i, int N, int n) {
 template <int STORE, class PT>
 __device__ __forceinline__ void load_pops(PT pops, int N, int n, float rho0, float Rd, float* d) {
   using IO = Codec<STORE>;
+  (void)N;
+  const auto pb = pop_base(pops, n);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = IO::ld(pops + pidx(i, N, n), wq(i) * rho0, wq(i) * Rd);
+  for (int i = 0; i < Q; ++i) d[i] = IO::ld(pb + i * POP_BLOCK, wq(i) * rho0, wq(i) * Rd);
 }
 
 // The sums from the populations d; CSRC(i): colour source of x - c_i
@@ -369,7 +387,9 @@ __device__ __forceinline__ void load_pops(PT pops, int N, int n, float rho0, flo
 template <class CSRC>
 __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v4f own, float rho0,
                                             float& rabs, float& sg) {
-  rabs = d[0] + wq(0) * rho0;
+  // f_i = d_i + w_i rho0 with one rounding (an explicit fused multiply-add:
+  // left to the compiler, its contraction depends on where w_i rho0 is formed)
+  rabs = __fmaf_rn(wq(0), rho0, d[0]);
   const float sg0 = own.x * rabs;
   // every source fluid: no selects.  A solid source carries NaN in r n, which
   // turns the sum to NaN; only then the sum is redone with the bounce rule.
@@ -377,7 +397,7 @@ __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const v4f c = cs_src(i);
-    const float fi = d[i] + wq(i) * rho0;
+    const float fi = __fmaf_rn(wq(i), rho0, d[i]);
     rabs += fi;
     sg += c.x * fi + wq(i) * ((float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w);
   }
@@ -391,7 +411,7 @@ __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v
       // gives phi(x) f_i + r(x) w_i (c_i . n(x)))
       const bool open = c.x != c.x;
       const bool solid = c.y != c.y;
-      const float fi = d[i] + wq(i) * rho0;
+      const float fi = __fmaf_rn(wq(i), rho0, d[i]);
       const float ts = (float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w;
       const float to = (float)cx(i) * own.y + (float)cy(i) * own.z + (float)cz(i) * own.w;
       const float ph = solid ? own.x : c.x;
@@ -404,11 +424,14 @@ __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v
 // Colour source (phi, r n_x, r n_y, r n_z) of node m of the state that
 // collided, r = beta rho (1 - phi^2) / 2, from its moments RO (rho plane, phi
 // plane) and normal planes NX; NaN in r n at a solid node (its normal is NaN).
+__device__ __forceinline__ v4f colour_record(float rho, float phi, float nx, float ny, float nz,
+                                             float hb) {
+  const float r = hb * rho * (1.0f - phi) * (1.0f + phi);
+  return v4f{phi, r * nx, r * ny, r * nz};
+}
 __device__ __forceinline__ v4f colour_source(const GLB float* RO, const GLB float* NX, int N,
                                              int m, float hb) {
-  const float rho = RO[m], phi = RO[N + m];
-  const float r = hb * rho * (1.0f - phi) * (1.0f + phi);
-  return v4f{phi, r * NX[m], r * NX[N + m], r * NX[2 * N + m]};
+  return colour_record(RO[m], RO[N + m], NX[m], NX[N + m], NX[2 * N + m], hb);
 }
 
 // both, for one node, with the colour sources read from the global planes

@@ -160,8 +160,7 @@ __device__ __forceinline__ int xcd_tile(int lin, int nblk) {
 //
 // A block takes an x-y tile of the simulation's moments tiling and marches up
 // s.mkz planes.  The colour sources of three planes of the tile grown by one
-// node sit in an LDS ring; the next plane's sources are loaded while the
-// current plane is summed.
+// node sit in an LDS ring; each plane adds the sources of the plane above.
 constexpr int MOM_HALO = 66 * 6;  // largest tile plane grown by one: (64 + 2)(4 + 2)
 template <int STORE>
 __global__ __launch_bounds__(256) void k_moments(Batch bt) {
@@ -217,50 +216,68 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
         ring[(z0 + 2 + dz) % 3][k_of(t, j)] =
             hoff[j] < 0 ? open_rec : colour_source(RO, NX, N, hoff[j] + P * zp, hb);
   }
-  // sources of plane z + 1 are loaded one plane ahead; the node's populations
-  // at the top of its plane, in flight across the barrier
-  v4f nxt[2];
-  auto fetch_sources = [&](int z) {
+  // Each plane takes one round of global loads: the node's populations and
+  // the raw moments and normal of the next plane's halo records, all issued
+  // before the first wait (indices clamped in bounds instead of branches, which
+  // would wait inside them); the records are formed once the loads are in.
+  float sr[2][5];
+  auto fetch_raw = [&](int z) {
     const int zp = zwrap(z + 1);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      nxt[j] = !hon[j]      ? v4f{0.f, 0.f, 0.f, 0.f}
-               : hoff[j] < 0 ? open_rec
-                             : colour_source(RO, NX, N, hoff[j] + P * zp, hb);
+    for (int j = 0; j < 2; ++j) {
+      const int m = max(hoff[j], 0) + P * zp;
+      sr[j][0] = RO[m];
+      sr[j][1] = RO[N + m];
+      sr[j][2] = NX[m];
+      sr[j][3] = NX[N + m];
+      sr[j][4] = NX[2 * N + m];
+    }
   };
-  fetch_sources(z0);
+  const int gxc = min(gx, nx - 1), gyc = min(gy, ny - 1);
+  const float rho0 = s.rho0;  // kept in a register: the stores below may alias s
+  // a plane's results are stored once the next plane's loads are in, so that
+  // they are in flight during the sums instead of ahead of the next loads
+  int pn = -1;
+  uint16_t pm = 0;
+  float prabs = 0.f, psg = 0.f;
+  auto store_pending = [&]() {
+    if (pn < 0) return;
+    if (pm & FRESH_BIT) {  // refilled node: moments written by the refill
+      MASK[pn] = (uint16_t)(pm & ~FRESH_BIT);
+    } else if (pm != 0) {
+      RN[pn] = rho0;
+      RN[N + pn] = solid_phi(pm);
+    } else {
+      RN[pn] = prabs;
+      RN[N + pn] = psg / prabs;
+    }
+  };
   for (int zz = 0; zz < kz; ++zz) {
     const int z = z0 + zz;
-    const int n = gx + nx * (gy + ny * z);
+    const int n = gxc + nx * (gyc + ny * z);
     float d[Q];
-    uint16_t m = 0;
-    if (in) {
-      m = MASK[n];
-      load_pops<STORE>(pops, N, n, s.rho0, STORE ? RO[n] : 0.f, d);
-    }
+    const uint16_t m = MASK[n];
+    load_pops<STORE>(pops, N, n, rho0, STORE ? RO[n] : 0.f, d);
+    fetch_raw(z);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      if (hon[j]) ring[(z + 1) % 3][k_of(t, j)] = nxt[j];
+      if (hon[j])
+        ring[(z + 1) % 3][k_of(t, j)] =
+            hoff[j] < 0 ? open_rec
+                        : colour_record(sr[j][0], sr[j][1], sr[j][2], sr[j][3], sr[j][4], hb);
+    store_pending();
     __syncthreads();
-    if (zz + 1 < kz) fetch_sources(z + 1);
     if (in) {
       const int c0 = (lx + 1) + HX * (ly + 1);
-      float rabs, sg;
       colour_sums(
           d, [&](int i) { return ring[(z + 3 - cz(i)) % 3][c0 - cx(i) - HX * cy(i)]; },
-          ring[z % 3][c0], s.rho0, rabs, sg);
-      if (m & FRESH_BIT) {  // refilled node: moments written by the refill
-        MASK[n] = (uint16_t)(m & ~FRESH_BIT);
-      } else if (m != 0) {
-        RN[n] = s.rho0;
-        RN[N + n] = solid_phi(m);
-      } else {
-        RN[n] = rabs;
-        RN[N + n] = sg / rabs;
-      }
+          ring[z % 3][c0], rho0, prabs, psg);
+      pn = n;
+      pm = m;
     }
     __syncthreads();
   }
+  store_pending();
 }
 
 // Between steps, after the mask changed with the populations in place (and
@@ -543,6 +560,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     normals(z0, no_solids);
   }
   __syncthreads();  // the loop's first phi store reuses the slot of plane z0 - 2
+  // kept in a register: read from s after the stores below, it would be a
+  // load behind them (they may alias s) and its wait would wait for them too
+  const float csf = -0.5f * s.sigma;
   for (int zz = 0; zz < kz; ++zz) {
     const int z = z0 + zz;
     store_phi(z + 2, nxt);
@@ -576,7 +596,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
       NX[N + n] = own.y;
       NX[2 * N + n] = own.z;
       NX[3 * N + n] = own.w;
-      CUR[2 * n] = -0.5f * s.sigma * kappa * fmaxf(own.w, EPS_G);
+      CUR[2 * n] = csf * kappa * fmaxf(own.w, EPS_G);
       CUR[2 * n + 1] = __uint_as_float(0u);
     } else if (in) {
       const int c0 = (lx + 1) + HX * (ly + 1);
@@ -617,7 +637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                    ((float)cx(i) * (px - mx) + (float)cy(i) * (py - my) + (float)cz(i) * (pz - mz));
           bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
         }
-        c = -0.5f * s.sigma * kappa * fmaxf(own.w, EPS_G);
+        c = csf * kappa * fmaxf(own.w, EPS_G);
       }
       NX[n] = own.x;
       NX[N + n] = own.y;
@@ -664,7 +684,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   if (!tile_node(s, sb.y, n, gx, gy, gz)) return;
   const float rho0 = s.rho0;
   const float inv_rho0 = 1.0f / rho0;
-  const float2 cb = make_float2(cur[2 * n], cur[2 * n + 1]);
+  const float2 cb = make_float2(at(cur, 2u * (unsigned)n), at(cur, 2u * (unsigned)n + 1u));
   const uint32_t bits = __float_as_uint(cb.y);
 
   if (bits & 0x80000000u) {
@@ -693,11 +713,20 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
   }
   const Nbr nb(gx, gy, gz, nx, ny, nz);
   float d[Q];
-  const float Rn = STORE ? RP[n] : 0.f;
+  const float Rn = STORE ? at(RP, (unsigned)n) : 0.f;
+  const auto pb = pop_base(sp_, n);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = IO::ld(sp_ + pidx(i, N, n), wq(i) * rho0, wq(i) * Rn);
-  const float3 nc = make_float3(NX[n], NX[N + n], NX[2 * N + n]);
-  const float phi = RM[N + n];
+  for (int i = 0; i < Q; ++i) d[i] = IO::ld(pb + i * POP_BLOCK, wq(i) * rho0, wq(i) * Rn);
+  // FP16: the densities of this state at the node and at its 18 neighbours,
+  // the references the pushed populations are encoded with.  Loaded here with
+  // the populations (neighbour indices wrap, so every load is in bounds): a
+  // load at the push, behind the stores before it, would wait for those too.
+  float Rd[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) Rd[i] = STORE ? at(RM, (unsigned)(i == 0 ? n : nb(i))) : 0.f;
+  const float3 nc =
+      make_float3(at(NX, (unsigned)n), at(NX + N, (unsigned)n), at(NX + 2 * N, (unsigned)n));
+  const float phi = at(RM + N, (unsigned)n);
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -739,8 +768,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
 
   // FP16: each population is encoded with the density of the node that
   // stores it
-  auto st_pop = [&](int i, int node, float dv) {
-    const float R = STORE ? RM[node] : 0.f;
+  auto st_pop = [&](int i, int node, float R, float dv) {
     IO::st(dp_ + pidx(i, N, node), wq(i) * rho0, inv_rho0 * (1.0f / wq(i)), wq(i) * R, dv);
   };
   // push to the neighbour in direction i, or bounce back into direction opp(i);
@@ -754,12 +782,12 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
         const float cu = (float)cx(i) * ux + (float)cy(i) * uy + (float)cz(i) * uz;
         const float w = wq(i);
         // as deviations from w rho0: -d*_i + 2 w (drho_w + rho_w (9/2 cu^2 - 3/2 u^2))
-        st_pop(opp(i), n, -dv + 2.0f * w * (drw + (rho0 + drw) * (4.5f * cu * cu - 1.5f * uu)));
+        st_pop(opp(i), n, Rd[0], -dv + 2.0f * w * (drw + (rho0 + drw) * (4.5f * cu * cu - 1.5f * uu)));
       } else {
-        st_pop(opp(i), n, dv);
+        st_pop(opp(i), n, Rd[0], dv);
       }
     } else {
-      st_pop(i, nb(i), dv);
+      st_pop(i, nb(i), Rd[i], dv);
     }
   };
 
@@ -767,7 +795,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
     const float w0 = wq(0);
     const float deq = w0 * (drho - 1.5f * rho * uu);
     const float fb = w0 * (-3.0f * uF);
-    st_pop(0, n, d[0] - om * (d[0] - deq) + cfs * fb);
+    st_pop(0, n, Rd[0], d[0] - om * (d[0] - deq) + cfs * fb);
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
