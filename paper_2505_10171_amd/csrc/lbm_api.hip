@@ -370,16 +370,19 @@ static int general_geometry(const lbm_config& c) {
 }
 static Batch batch_all(const lbm_ctx* c) {
   int general = 0, open = 0;
+  int mlx = c->sims.empty() ? 0 : c->sims[0].d.mtile_lx;
   for (const SimHost& sh : c->sims) {
     general |= general_geometry(sh.cfg);
     open |= sh.cfg.open_x;
+    if (sh.d.mtile_lx != mlx) mlx = 0;
   }
   return Batch{c->d_tab, c->d_blk, c->d_mblk, c->d_pmap, (int)c->sims.size(), c->cur, c->rd,
-               general, open};
+               general, open, mlx};
 }
 static Batch batch_one(const lbm_ctx* c, int si) {
   return Batch{c->d_tab + si, nullptr, nullptr, nullptr, 1, c->cur, c->rd,
-               general_geometry(c->sims[si].cfg), c->sims[si].cfg.open_x};
+               general_geometry(c->sims[si].cfg), c->sims[si].cfg.open_x,
+               c->sims[si].d.mtile_lx};
 }
 
 // workspace tail holding the batch tables

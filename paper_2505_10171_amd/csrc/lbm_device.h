@@ -286,6 +286,7 @@ struct Batch {
   int cur, rd;
   int general;  // some simulation has open x ends, a tube or a textured wall
   int open;     // some simulation has open x ends
+  int mlx;      // log2 of the moments tiles' x width if every simulation has the same, else 0
 };
 
 // (simulation, block within it) of global block g, given the block prefix blk
@@ -372,6 +373,17 @@ __device__ __forceinline__ T at(const T* base, unsigned idx) {
 // with f_i = d_i + w_i rho0 rounded as the collision formed it, and sg = sum of
 // the colour differences: in the bulk of either fluid (phi' = +-1, r' = 0)
 // sg = +-rabs exactly.
+// c_i . a over the components where c_i is not zero, in the order x, y, z: equal
+// to the full sum for finite a (the compiler keeps a zero term as 0 * a, since
+// IEEE arithmetic does not fold it); -0 + v is v for every v
+__device__ __forceinline__ float cdot(int i, float ax, float ay, float az) {
+  float r = -0.0f;
+  if (cx(i) != 0) r += (float)cx(i) * ax;
+  if (cy(i) != 0) r += (float)cy(i) * ay;
+  if (cz(i) != 0) r += (float)cz(i) * az;
+  return r;
+}
+
 // The node's populations f_i - w_i rho0 (decoded with the reference density Rd).
 template <int STORE, class PT>
 __device__ __forceinline__ void load_pops(PT pops, int N, int n, float rho0, float Rd, float* d) {
@@ -399,7 +411,7 @@ __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v
     const v4f c = cs_src(i);
     const float fi = __fmaf_rn(wq(i), rho0, d[i]);
     rabs += fi;
-    sg += c.x * fi + wq(i) * ((float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w);
+    sg += c.x * fi + wq(i) * cdot(i, c.y, c.z, c.w);
   }
   if (sg != sg) {
     sg = sg0;
@@ -412,8 +424,8 @@ __device__ __forceinline__ void colour_sums(const float* d, CSRC cs_src, const v
       const bool open = c.x != c.x;
       const bool solid = c.y != c.y;
       const float fi = __fmaf_rn(wq(i), rho0, d[i]);
-      const float ts = (float)cx(i) * c.y + (float)cy(i) * c.z + (float)cz(i) * c.w;
-      const float to = (float)cx(i) * own.y + (float)cy(i) * own.z + (float)cz(i) * own.w;
+      const float ts = cdot(i, c.y, c.z, c.w);
+      const float to = cdot(i, own.y, own.z, own.w);
       const float ph = solid ? own.x : c.x;
       const float t = open ? to : (solid ? -to : ts);
       sg += ph * fi + wq(i) * t;

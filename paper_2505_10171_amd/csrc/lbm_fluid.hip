@@ -162,7 +162,9 @@ __device__ __forceinline__ int xcd_tile(int lin, int nblk) {
 // s.mkz planes.  The colour sources of three planes of the tile grown by one
 // node sit in an LDS ring; each plane adds the sources of the plane above.
 constexpr int MOM_HALO = 66 * 6;  // largest tile plane grown by one: (64 + 2)(4 + 2)
-template <int STORE>
+// LX: log2 of the tiles' x width when the launch fixes it (the tile's LDS
+// offsets are then immediates), 0 to read it from the simulation
+template <int STORE, int LX>
 __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   using IO = Codec<STORE>;
   using T = typename IO::T;
@@ -178,12 +180,13 @@ __global__ __launch_bounds__(256) void k_moments(Batch bt) {
   const GLB float* __restrict__ RO = gp((const float*)s.rp[bt.rd]);
   GLB float* __restrict__ RN = gp(s.rp[bt.rd ^ 1]);
   GLB uint16_t* __restrict__ MASK = gp(s.mask);
-  const int tx = s.mtile_x, ty = 256 >> s.mtile_lx, HX = tx + 2, HY = ty + 2;
+  const int tlx = LX > 0 ? LX : s.mtile_lx;
+  const int tx = 1 << tlx, ty = 256 >> tlx, HX = tx + 2, HY = ty + 2;
   const int bx = sb.y % s.mtiles_x, r = sb.y / s.mtiles_x;
   const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * s.mkz;
   const int kz = min(s.mkz, nz - z0);
   const int t = (int)threadIdx.x;
-  const int lx = t & (tx - 1), ly = t >> s.mtile_lx;
+  const int lx = t & (tx - 1), ly = t >> tlx;
   const int gx = bx * tx + lx, gy = by * ty + ly;
   const bool in = gx < nx && gy < ny;
   // this thread's halo records of a plane: t and t + 256 (a plane has at
@@ -391,7 +394,8 @@ constexpr int IF_NRM = MOM_HALO;  // grown by one: (64 + 2)(4 + 2)
 // OPEN: the batch has simulations with open x ends or a tube wall (a
 // separate instance, so that the periodic box on a plane carries none of their
 // bookkeeping).
-template <bool OPEN>
+// LX: as for the moments pass
+template <bool OPEN, int LX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_interface(Batch bt) {
   __shared__ float fring[4][IF_PHI];
   // normals of three planes, one array per component (the curvature reads
@@ -405,13 +409,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   GLB float* __restrict__ NX = gp(s.nrm);
   GLB float* __restrict__ CUR = gp((float*)s.curv);
   const int nx = s.nx, ny = s.ny, nz = s.nz, P = nx * ny;
-  const int tx = s.mtile_x, ty = 256 >> s.mtile_lx;
+  const int tlx = LX > 0 ? LX : s.mtile_lx;
+  const int tx = 1 << tlx, ty = 256 >> tlx;
   const int FX = tx + 4, FY = ty + 4, HX = tx + 2, HY = ty + 2;
   const int bx = sb.y % s.mtiles_x, r = sb.y / s.mtiles_x;
   const int by = r % s.mtiles_y, z0 = (r / s.mtiles_y) * s.mkz;
   const int kz = min(s.mkz, nz - z0);
   const int t = (int)threadIdx.x;
-  const int lx = t & (tx - 1), ly = t >> s.mtile_lx;
+  const int lx = t & (tx - 1), ly = t >> tlx;
   const int gx = bx * tx + lx, gy = by * ty + ly;
   const bool in = gx < nx && gy < ny;
   const int x0 = bx * tx, y0 = by * ty;
@@ -480,10 +485,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         vp = spd ? p0 : vp;
         vm = smd ? p0 : vm;
       }
-      const float d = 3.0f * wq(i) * (vp - vm);
-      Gx += (float)cx(i) * d;
-      Gy += (float)cy(i) * d;
-      Gz += (float)cz(i) * d;
+      // G += 3 w_i c_i (phi(x + c_i) - phi(x - c_i)), each term one fused
+      // multiply-add; terms with a zero lattice coefficient add nothing and are
+      // left out (the compiler keeps 0 * d, which IEEE arithmetic does not fold)
+      const float k = 3.0f * wq(i), df = vp - vm;
+      if (cx(i) != 0) Gx = __fmaf_rn((float)cx(i) * k, df, Gx);
+      if (cy(i) != 0) Gy = __fmaf_rn((float)cy(i) * k, df, Gy);
+      if (cz(i) != 0) Gz = __fmaf_rn((float)cz(i) * k, df, Gz);
     }
     // the wetting rotation applies only inside the interface (|G| > EPS_G, its
     // own first test); only there the solid is identified, from the phi
@@ -633,8 +641,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             my = own.y;
             mz = own.z;
           }
-          kappa += 3.0f * wq(i) *
-                   ((float)cx(i) * (px - mx) + (float)cy(i) * (py - my) + (float)cz(i) * (pz - mz));
+          kappa += 3.0f * wq(i) * cdot(i, px - mx, py - my, pz - mz);
           bits |= (sp ? (1u << i) : 0u) | (sm ? (1u << o) : 0u);
         }
         c = csf * kappa * fmaxf(own.w, EPS_G);
@@ -731,9 +738,9 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     drho += d[i];
-    jx += (float)cx(i) * d[i];
-    jy += (float)cy(i) * d[i];
-    jz += (float)cz(i) * d[i];
+    if (cx(i) != 0) jx += (float)cx(i) * d[i];
+    if (cy(i) != 0) jy += (float)cy(i) * d[i];
+    if (cz(i) != 0) jz += (float)cz(i) * d[i];
   }
   const float rho = rho0 + drho;
   // force: CSF surface tension c n + body force on fluid a (weight (1+phi)/2)
@@ -779,7 +786,7 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
     if (bits & (1u << i)) {
       if (OPEN && s.open_x && ((cx(i) < 0 && gx == 0) || (cx(i) > 0 && gx == nx - 1))) {
         const float drw = cx(i) < 0 ? s.drho_in : s.drho_out;
-        const float cu = (float)cx(i) * ux + (float)cy(i) * uy + (float)cz(i) * uz;
+        const float cu = cdot(i, ux, uy, uz);
         const float w = wq(i);
         // as deviations from w rho0: -d*_i + 2 w (drho_w + rho_w (9/2 cu^2 - 3/2 u^2))
         st_pop(opp(i), n, Rd[0], -dv + 2.0f * w * (drw + (rho0 + drw) * (4.5f * cu * cu - 1.5f * uu)));
@@ -802,8 +809,8 @@ __global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out
     const int i = pair_dir(q);
     const int o = opp(i);
     const float w = wq(i);
-    const float cu = (float)cx(i) * ux + (float)cy(i) * uy + (float)cz(i) * uz;
-    const float cF = (float)cx(i) * Fx + (float)cy(i) * Fy + (float)cz(i) * Fz;
+    const float cu = cdot(i, ux, uy, uz);
+    const float cF = cdot(i, Fx, Fy, Fz);
     const float eqs = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
     const float eqa = w * rho * 3.0f * cu;
     const float fs = w * (9.0f * cu * cF - 3.0f * uF);
@@ -876,17 +883,18 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
       // moves less data but adds a round trip: C2 16 -> 20 us)
       const Nbr nb(gx, gy, gz, nx, ny, nz);
       const uint16_t me = (uint16_t)(2 + p);
-      const uint16_t m0 = MASK[n];
+      const uint16_t m0 = at(MASK, (unsigned)n);
       uint32_t lm = 0;  // bit i: the neighbour in direction i is a solid node of p
 #pragma unroll
-      for (int i = 1; i < Q; ++i) lm |= (MASK[nb(i)] == me) ? (1u << i) : 0u;
-      const float rho = RM[n];
+      for (int i = 1; i < Q; ++i) lm |= (at(MASK, (unsigned)nb(i)) == me) ? (1u << i) : 0u;
+      const float rho = at(RM, (unsigned)n);
       const float Re = STORE ? rho : 0.f;
+      const auto pb = pop_base(dp_, n);
       float ds[Q];
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const int o = opp(i);
-        ds[i] = IO::ld(dp_ + pidx(o, N, n), wq(o) * rho0, wq(o) * Re);
+        ds[i] = IO::ld(pb + o * POP_BLOCK, wq(o) * rho0, wq(o) * Re);
       }
       if (m0 != 0) lm = 0;
       if (lm) {
@@ -905,7 +913,7 @@ __global__ __launch_bounds__(256) void k_links(Batch bt) {
           const float cu = (float)(-(cx(i) * uwx + cy(i) * uwy + cz(i) * uwz));  // c_opp . u_w
           const float corr = 6.0f * wq(i) * rho * cu;
           const float dso = ds[i] + corr;
-          IO::st(dp_ + pidx(o, N, n), wr0, 1.0f / wr0, wq(o) * Re, dso);
+          IO::st(pb + o * POP_BLOCK, wr0, 1.0f / wr0, wq(o) * Re, dso);
           const double wr = wqd(i) * (double)rho0;
           const double fin = (double)ds[i] + wr;
           const double fout = (double)dso + wr;
@@ -954,10 +962,18 @@ static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 
 // nblk: per-node blocks; mnblk: blocks of the moments tiling (k_normal)
 hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipStream_t st) {
   (void)nblk;
-  if (b.general)
-    hipLaunchKernelGGL(k_interface<true>, dim3(mnblk), dim3(256), 0, st, b);
-  else
-    hipLaunchKernelGGL(k_interface<false>, dim3(mnblk), dim3(256), 0, st, b);
+  const bool w64 = b.mlx == 6;  // 64-wide tiles: the instance with them fixed
+  if (b.general) {
+    if (w64)
+      hipLaunchKernelGGL((k_interface<true, 6>), dim3(mnblk), dim3(256), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_interface<true, 0>), dim3(mnblk), dim3(256), 0, st, b);
+  } else {
+    if (w64)
+      hipLaunchKernelGGL((k_interface<false, 6>), dim3(mnblk), dim3(256), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_interface<false, 0>), dim3(mnblk), dim3(256), 0, st, b);
+  }
   return hipGetLastError();
 }
 
@@ -1005,10 +1021,16 @@ hipError_t launch_moments(const Batch& b, int storage, unsigned nblk, unsigned m
                           hipStream_t st) {
   if (mode == MOM_BOUNDARY)
     hipLaunchKernelGGL(k_moments_boundary, dim3(nblk), dim3(256), 0, st, b);
-  else if (storage == 0)
-    hipLaunchKernelGGL(k_moments<0>, dim3(mnblk), dim3(256), 0, st, b);
-  else
-    hipLaunchKernelGGL(k_moments<1>, dim3(mnblk), dim3(256), 0, st, b);
+  else if (b.mlx == 6) {
+    if (storage == 0)
+      hipLaunchKernelGGL((k_moments<0, 6>), dim3(mnblk), dim3(256), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_moments<1, 6>), dim3(mnblk), dim3(256), 0, st, b);
+  } else if (storage == 0) {
+    hipLaunchKernelGGL((k_moments<0, 0>), dim3(mnblk), dim3(256), 0, st, b);
+  } else {
+    hipLaunchKernelGGL((k_moments<1, 0>), dim3(mnblk), dim3(256), 0, st, b);
+  }
   return hipGetLastError();
 }
 
