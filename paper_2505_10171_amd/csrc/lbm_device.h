@@ -317,16 +317,17 @@ __device__ __forceinline__ int2 batch_particle(const Batch& b, int r) {
 struct Nbr {
   int X[3], Y[3], Z[3];
   __device__ __forceinline__ Nbr(int gx, int gy, int gz, int nx, int ny, int nz) {
-    const int nxny = nx * ny;
+    // two multiplies; the wrapped rows and planes are a uniform offset away
+    const int nxny = nx * ny, ylast = nxny - nx, zlast = nxny * (nz - 1);
     X[0] = gx == 0 ? nx - 1 : gx - 1;
     X[1] = gx;
     X[2] = gx == nx - 1 ? 0 : gx + 1;
-    Y[0] = (gy == 0 ? ny - 1 : gy - 1) * nx;
     Y[1] = gy * nx;
-    Y[2] = (gy == ny - 1 ? 0 : gy + 1) * nx;
-    Z[0] = (gz == 0 ? nz - 1 : gz - 1) * nxny;
+    Y[0] = gy == 0 ? Y[1] + ylast : Y[1] - nx;
+    Y[2] = gy == ny - 1 ? Y[1] - ylast : Y[1] + nx;
     Z[1] = gz * nxny;
-    Z[2] = (gz == nz - 1 ? 0 : gz + 1) * nxny;
+    Z[0] = gz == 0 ? Z[1] + zlast : Z[1] - nxny;
+    Z[2] = gz == nz - 1 ? Z[1] - zlast : Z[1] + nxny;
   }
   __device__ __forceinline__ int operator()(int i) const {
     return X[1 + cx(i)] + Y[1 + cy(i)] + Z[1 + cz(i)];
@@ -337,9 +338,10 @@ struct Nbr {
 // holding its 19 populations as 19 runs of 64 values (a wave's 19 loads stay
 // within 4.75 KB (FP32) instead of 19 planes apart); 19 N < 2^32
 constexpr int POP_BLOCK = 64;
-__host__ __device__ __forceinline__ unsigned pidx(int i, int N, int n) {
+__device__ __forceinline__ unsigned pidx(int i, int N, int n) {
   (void)N;
-  return ((unsigned)n / POP_BLOCK) * (unsigned)(Q * POP_BLOCK) + (unsigned)i * POP_BLOCK +
+  // n / 64 < 2^22 (19 N < 2^32): the full-rate 24-bit multiply suffices
+  return __umul24((unsigned)n / POP_BLOCK, (unsigned)(Q * POP_BLOCK)) + (unsigned)i * POP_BLOCK +
          ((unsigned)n % POP_BLOCK);
 }
 
