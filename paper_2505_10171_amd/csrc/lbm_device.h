@@ -71,7 +71,10 @@ struct alignas(16) DevParticle {
   double Fcn[3], Tcn[3];    // contact force/torque of the current sub-step
   double Ffp[3], Tfp[3];    // fluid force/torque of the previous lattice step
   double Fca[3], Tca[3];    // capillary accumulators (FP64 atomics)
-  int havep, pad2;          // 1 once Ffp/Tfp hold a previous step
+  int havep;                // 1 once Ffp/Tfp hold a previous step
+  // 1: the capillary box of this step holds a fluid node with |G| near EPS_G
+  // or above (set by the box kernel, cleared by the DEM with the accumulators)
+  int cap_on;
 };
 
 constexpr int LBM_HIST_DOUBLES_DEV = 27;

@@ -216,7 +216,7 @@ __global__ void k_capbox(Batch bt) {
   const int2 sp = batch_particle(bt, blockIdx.y);
   const SimDev& s = bt.tab[sp.x];
   const int p = sp.y;
-  const DevParticle& P = s.P[p];
+  DevParticle& P = s.P[p];
   const int B = s.cap_B;
   int org[3];
 #pragma unroll
@@ -226,6 +226,11 @@ __global__ void k_capbox(Batch bt) {
   float4* box = s.capbox + (long long)p * B * B * B;
   // phi of the state that collided this step (the buffers have swapped)
   const float* PHI = s.rp[bt.rd] + s.N;
+  // a particle whose box holds no fluid node with |G| near EPS_G or above gets
+  // no force: every point's G is a convex combination of corner values, so it
+  // would fail the |G| > EPS_G test of the force kernel (the 0.99 margin covers
+  // rounding); the box's nodes say so here, once, for that kernel
+  bool iface = false;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < B * B * B; k += gridDim.x * blockDim.x) {
     const int ix = k % B, iy = (k / B) % B, iz = k / (B * B);
     const int x = wrapi(org[0] + ix, s.nx), y = wrapi(org[1] + iy, s.ny), z = wrapi(org[2] + iz, s.nz);
@@ -238,7 +243,9 @@ __global__ void k_capbox(Batch bt) {
       v = make_float4(PHI[n], s.nrm[n] * gm, s.nrm[s.N + n] * gm, s.nrm[2 * s.N + n] * gm);
     }
     box[k] = v;
+    iface |= v.x <= 1.5f && v.y * v.y + v.z * v.z + v.w * v.w > (0.99f * EPS_G) * (0.99f * EPS_G);
   }
+  if (__syncthreads_or(iface) && threadIdx.x == 0) P.cap_on = 1;
 }
 
 // Capillary force (capillary-force eq.): sum over the polar/azimuthal grid of
@@ -261,15 +268,8 @@ __global__ __launch_bounds__(256) void k_capillary(Batch bt) {
   const int na = s.cap_na, nph = s.cap_nphi;
   // the polar and azimuthal grids are fixed: their sines and cosines once per
   // workgroup (same arguments, same values as per point)
-  // a particle whose box holds no node with |G| near EPS_G or above gets no
-  // force: every point's G is a convex combination of corner values, so it
-  // would fail the |G| > EPS_G test below (the 0.99 margin covers rounding)
-  bool iface = false;
-  for (int k = threadIdx.x; k < B * B * B; k += blockDim.x) {
-    const float4 v = box[k];
-    iface |= v.x <= 1.5f && v.y * v.y + v.z * v.z + v.w * v.w > (0.99f * EPS_G) * (0.99f * EPS_G);
-  }
-  if (!__syncthreads_or(iface)) return;
+  // no fluid node of the box near the interface (the box kernel's flag): no force
+  if (!P.cap_on) return;
   constexpr int TAB = 512;
   __shared__ double t_sa[TAB], t_ca[TAB], t_sp[TAB], t_cp[TAB];
   const bool tab = na <= TAB && nph <= TAB;
@@ -691,6 +691,7 @@ __global__ __launch_bounds__(256) void k_dem(Batch bt) {
     P.Ff[2] -= P.g_p;
     P.Ro = P.R;
     P.havep = 1;
+    P.cap_on = 0;
   }
   __syncthreads();
   // pair candidates within Rc_i + Rc_j + skin (ascending index)
@@ -932,6 +933,7 @@ __global__ __launch_bounds__(64) void k_dem_setup(Batch bt, int np_rows, int mas
   P.Ff[2] -= P.g_p;
   P.Ro = P.R;
   P.havep = 1;
+  P.cap_on = 0;
   // the step counter advances here (the sub-steps' history record takes the
   // value before it)
   if (i == 0) *s.step_counter += 1;
