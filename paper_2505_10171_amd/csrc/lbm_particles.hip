@@ -939,11 +939,15 @@ __global__ __launch_bounds__(64) void k_dem_setup(Batch bt, int np_rows, int mas
   if (i == 0) *s.step_counter += 1;
   int* nb = s.nb + (long long)i * MAXNB;
   int c = 0;
+  // membership of a partner in this step's candidate list, from registers (a
+  // re-read of the list just written would wait for its stores, per slot)
+  uint32_t words[MAXNB];
+  int lst[MAXNB];
+  int jlast = -1;  // masks: the last partner the list took (it is capped at MAXNB)
   if (masks) {
     // row i holds one hit mask per 32 partners: all words read before the
     // list overwrites them
     const int nw = (np + 31) / 32;
-    uint32_t words[MAXNB];
 #pragma unroll
     for (int w = 0; w < MAXNB; ++w) words[w] = w < nw ? ((const uint32_t*)nb)[w] : 0u;
 #pragma unroll
@@ -952,24 +956,43 @@ __global__ __launch_bounds__(64) void k_dem_setup(Batch bt, int np_rows, int mas
       while (hit) {
         const int j = 32 * w + __builtin_ctz(hit);
         hit &= hit - 1;
-        if (c < MAXNB)
+        if (c < MAXNB) {
           nb[c++] = j;
-        else
+          jlast = j;
+        } else {
           atomicOr(&s.counters[1], (uint32_t)ST_CONTACT_FULL);
+        }
       }
     }
     if (c < MAXNB) nb[c] = -1;
   } else {
-    while (c < MAXNB && nb[c] >= 0) ++c;
+    // the list as k_dem_lists wrote it: entries up to the first negative one
+    bool end = false;
+#pragma unroll
+    for (int w = 0; w < MAXNB; ++w) {
+      lst[w] = nb[w];
+      end |= lst[w] < 0;
+      c += end ? 0 : 1;
+    }
   }
+  auto listed = [&](int pt) {
+    bool r = false;
+    if (masks) {
+      // the list holds the set bits in increasing order up to jlast
+#pragma unroll
+      for (int w = 0; w < MAXNB; ++w) r |= (w == (pt >> 5)) && ((words[w] >> (pt & 31)) & 1u);
+      return r && pt <= jlast;
+    }
+#pragma unroll
+    for (int w = 0; w < MAXNB; ++w) r |= w < c && lst[w] == pt;
+    return r;
+  };
   // free pair springs whose partner is out of range
   Contact* tab = s.ct + (long long)i * MAXC;
   for (int k = 0; k < MAXC; ++k) {
     const int pt = tab[k].partner;
     if (pt < 0) continue;
-    bool found = false;
-    for (int q = 0; q < c; ++q) found |= nb[q] == pt;
-    if (!found) tab[k].partner = -100;
+    if (!listed(pt)) tab[k].partner = -100;
   }
   DemView* V0 = s.view;
   DemView* V1 = s.view + np;
@@ -1051,13 +1074,12 @@ __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub)
   for (int k = 0; k < MAXC; ++k) ids[k] = tab[k].partner;
   // this lane's partner: candidate `lane`, or the wall (-1) or its underside (-2)
   int partner = -100;
+  // lanes past the list's end stay idle (a list shorter than MAXNB ends at -1):
+  // a lane is past it when a lower lane holds a negative entry (one ballot)
+  const int j = lane < MAXNB ? s.nb[(long long)i * MAXNB + lane] : 0;
+  const unsigned long long neg = __ballot(j < 0);
   if (lane < MAXNB) {
-    const int j = s.nb[(long long)i * MAXNB + lane];
-    partner = j >= 0 ? j : -100;
-    // lanes past the list's end stay idle (a list shorter than MAXNB ends at -1)
-    if (j >= 0)
-      for (int q = 0; q < lane; ++q)
-        if (s.nb[(long long)i * MAXNB + q] < 0) partner = -100;
+    partner = (j >= 0 && (neg & ((1ull << lane) - 1ull)) == 0ull) ? j : -100;
   } else if (lane == MAXNB && s.has_wall) {
     partner = -1;
   } else if (lane == MAXNB + 1 && s.has_wall) {
@@ -1065,10 +1087,10 @@ __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub)
   } else if (lane >= MAXNB + 2 && s.has_wall == 3 && lane - (MAXNB + 2) < s.n_boxes) {
     partner = -3 - (lane - (MAXNB + 2));  // a box of the textured wall
   }
-  const double zero[3] = {0.0, 0.0, 0.0};
+  // the partner's velocities by value (a pointer that may also point at a
+  // local array of zeros puts that array in scratch and makes the loads generic)
   double delta = 0.0, nh[3] = {0.0, 0.0, 0.0}, arm[3] = {0.0, 0.0, 0.0};
-  const double* vj = zero;
-  const double* wj = zero;
+  double vj[3] = {0.0, 0.0, 0.0}, wj[3] = {0.0, 0.0, 0.0};
   double Rcj = 0.0, mu = me.mu_s, mur = me.mu_r;
   if (partner >= 0) {
     const DemView& pj = V[partner];
@@ -1078,8 +1100,10 @@ __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub)
     delta = me.Rc + Rcj - dist;
     if (dist > 0.0)
       for (int d = 0; d < 3; ++d) nh[d] = arm[d] / dist;
-    vj = pj.vp;
-    wj = pj.wp;
+    for (int d = 0; d < 3; ++d) {
+      vj[d] = pj.vp[d];
+      wj[d] = pj.wp[d];
+    }
     mu = 0.5 * (me.mu_s + pj.mu_s);
     mur = 0.5 * (me.mu_r + pj.mu_r);
   } else if (partner != -100) {
