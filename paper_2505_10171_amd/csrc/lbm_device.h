@@ -448,7 +448,8 @@ __device__ __forceinline__ v4f colour_record(float rho, float phi, float nx, flo
 }
 __device__ __forceinline__ v4f colour_source(const GLB float* RO, const GLB float* NX, int N,
                                              int m, float hb) {
-  return colour_record(RO[m], RO[N + m], NX[m], NX[N + m], NX[2 * N + m], hb);
+  const unsigned u = (unsigned)m;
+  return colour_record(at(RO, u), at(RO + N, u), at(NX, u), at(NX + N, u), at(NX + 2 * N, u), hb);
 }
 
 // both, for one node, with the colour sources read from the global planes

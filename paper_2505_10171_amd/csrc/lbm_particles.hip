@@ -606,37 +606,38 @@ __device__ __forceinline__ void dem_contacts(const SimDev& s, Contact* tab, cons
 }
 
 // The pair tests of the DEM's candidate search spread over the GPU (boxes with
-// up to 32 MAXNB particles): thread (i, w) tests particle i against partners
+// up to 32 MAXNB particles): the tests of particle i against partners
 // 32 w .. 32 w + 31 (centre distance, minimum image, below Rc_i + Rc_j + skin)
-// and stores the hit mask as word w of row i of the candidate-list buffer
+// form the hit mask stored as word w of row i of the candidate-list buffer
 // (MAXNB words per particle), which k_dem_setup turns into the candidate list.
 // Positions and contact radii are those the step starts from.  Grid
-// (ceil(np_max ceil(np_max / 32) / 256), nsim).
+// (ceil(32 np_max ceil(np_max / 32) / 256), nsim).
 __global__ __launch_bounds__(256) void k_dem_search(Batch bt) {
+  // one thread per (particle i, partner j): half a wave takes the 32 partners
+  // of one hit word and a ballot forms the word (one round of loads)
   const SimDev& s = bt.tab[blockIdx.y];
   const int np = s.np;
   const int nw = (np + 31) / 32;
   const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long long)np * nw) return;
-  // consecutive lanes take consecutive particles of one partner word, so the
-  // partner reads are the same address across the wave
-  const int i = (int)(t % np), w = (int)(t / np);
-  const DevParticle* PP = s.P;
-  const double skin = 1.5;
-  const double xi[3] = {PP[i].x[0], PP[i].x[1], PP[i].x[2]};
-  const double Rci = PP[i].Rc;
-  const int j0 = 32 * w, jn = min(32, np - j0);
-  uint32_t hit = 0;
-#pragma unroll 4
-  for (int u = 0; u < jn; ++u) {
-    const int j = j0 + u;
+  const long long r = t / 32;  // word index (i, w)
+  const int u = (int)(t & 31);
+  const bool inr = r < (long long)np * nw;
+  const int i = inr ? (int)(r / nw) : 0, w = inr ? (int)(r % nw) : 0;
+  const int j = 32 * w + u;
+  bool hit = false;
+  if (inr && j < np && j != i) {
+    const DevParticle* PP = s.P;
+    const double skin = 1.5;
+    const double xi[3] = {PP[i].x[0], PP[i].x[1], PP[i].x[2]};
     const double xj[3] = {PP[j].x[0], PP[j].x[1], PP[j].x[2]};
     double dx[3];
     rel_vec(s, xi, xj, dx);
-    const double lim = Rci + PP[j].Rc + skin;
-    if (j != i && dot3(dx, dx) < lim * lim) hit |= 1u << u;
+    const double lim = PP[i].Rc + PP[j].Rc + skin;
+    hit = dot3(dx, dx) < lim * lim;
   }
-  ((uint32_t*)s.nb)[(long long)i * MAXNB + w] = hit;
+  const unsigned long long b = __ballot(hit);
+  const uint32_t word = (uint32_t)(b >> (threadIdx.x & 32));
+  if (inr && u == 0) ((uint32_t*)s.nb)[(long long)i * MAXNB + w] = word;
 }
 
 // Boxes with few particles (their records, contact tables and candidate
@@ -1268,7 +1269,7 @@ hipError_t launch_dem(const Batch& b, int np_max, int np_rows, int n_sub_max, hi
   if (np_max <= 32 * MAXNB) {
     // the pair tests on many CUs; the hit masks fit the list buffer
     const long long nw = (np_max + 31) / 32;
-    const unsigned gx = (unsigned)(((long long)np_max * nw + 255) / 256);
+    const unsigned gx = (unsigned)(((long long)np_max * nw * 32 + 255) / 256);
     hipLaunchKernelGGL(k_dem_search, dim3(gx, b.nsim), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_dem_setup, dim3(g64), dim3(64), 0, st, b, np_rows, 1);
   } else {
