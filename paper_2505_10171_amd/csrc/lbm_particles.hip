@@ -72,24 +72,29 @@ __global__ void k_release(Batch bt) {
   double Xo[3] = {P.xo[0], P.xo[1], P.xo[2]};
   const Box b = particle_box(s, Xo, P.Ro);
   const int vol = b.w[0] * b.w[1] * b.w[2];
+  // the record's fields held in registers (the stores below may alias it)
+  const int nx = s.nx, ny = s.ny, nz = s.nz;
+  GLB uint16_t* __restrict__ MASK = gp(s.mask);
+  const GLB uint32_t* __restrict__ CLAIM = gp((const uint32_t*)s.claim);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < vol; k += gridDim.x * blockDim.x) {
     const int ix = k % b.w[0], iy = (k / b.w[0]) % b.w[1], iz = k / (b.w[0] * b.w[1]);
-    const int x = wrapi(b.lo[0] + ix, s.nx), y = wrapi(b.lo[1] + iy, s.ny),
-              z = wrapi(b.lo[2] + iz, s.nz);
-    const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
-    if (s.mask[n] != (uint16_t)(2 + p)) continue;
-    const uint32_t c = s.claim[n];
+    const int x = wrapi(b.lo[0] + ix, nx), y = wrapi(b.lo[1] + iy, ny), z = wrapi(b.lo[2] + iz, nz);
+    const unsigned n = (unsigned)(x + nx * (y + ny * z));
+    // mask and claim in one round trip
+    const uint16_t m = at((const GLB uint16_t*)MASK, n);
+    const uint32_t c = at(CLAIM, n);
+    if (m != (uint16_t)(2 + p)) continue;
     if (c == 0xFFFFFFFFu) {
-      s.mask[n] = FRESH_BIT;
+      MASK[n] = FRESH_BIT;
       const uint32_t slot = atomicAdd(&s.counters[0], 1u);
       if (slot < s.fresh_cap) {
-        s.fresh[slot] = (uint32_t)n;
+        s.fresh[slot] = n;
         s.fresh_own[slot] = (uint32_t)p;
       } else {
         atomicOr(&s.counters[1], (uint32_t)ST_FRESH_FULL);
       }
     } else if (c != (uint32_t)p) {
-      s.mask[n] = (uint16_t)(2 + c);
+      MASK[n] = (uint16_t)(2 + c);
     }
   }
 }
@@ -102,14 +107,17 @@ __global__ void k_cover(Batch bt) {
   const DevParticle& P = s.P[p];
   const Box b = particle_box(s, P.x, P.R);
   const int vol = b.w[0] * b.w[1] * b.w[2];
+  // the record's fields held in registers (the stores below may alias it)
+  const int nx = s.nx, ny = s.ny, nz = s.nz;
+  GLB uint16_t* __restrict__ MASK = gp(s.mask);
+  GLB uint32_t* __restrict__ CLAIM = gp(s.claim);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < vol; k += gridDim.x * blockDim.x) {
     const int ix = k % b.w[0], iy = (k / b.w[0]) % b.w[1], iz = k / (b.w[0] * b.w[1]);
-    const int x = wrapi(b.lo[0] + ix, s.nx), y = wrapi(b.lo[1] + iy, s.ny),
-              z = wrapi(b.lo[2] + iz, s.nz);
-    const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
-    if (s.claim[n] == (uint32_t)p) {
-      s.mask[n] = (uint16_t)(2 + p);
-      s.claim[n] = 0xFFFFFFFFu;
+    const int x = wrapi(b.lo[0] + ix, nx), y = wrapi(b.lo[1] + iy, ny), z = wrapi(b.lo[2] + iz, nz);
+    const unsigned n = (unsigned)(x + nx * (y + ny * z));
+    if (at((const GLB uint32_t*)CLAIM, n) == (uint32_t)p) {
+      MASK[n] = (uint16_t)(2 + p);
+      CLAIM[n] = 0xFFFFFFFFu;
     }
   }
 }
@@ -224,8 +232,11 @@ __global__ void k_capbox(Batch bt) {
   if (blockIdx.x == 0 && threadIdx.x < 3) s.capbox_org[3 * p + threadIdx.x] = org[threadIdx.x];
   if (s.cap_pref == 0.0) return;  // no surface tension: no capillary force
   float4* box = s.capbox + (long long)p * B * B * B;
-  // phi of the state that collided this step (the buffers have swapped)
-  const float* PHI = s.rp[bt.rd] + s.N;
+  // phi of the state that collided this step (the buffers have swapped); the
+  // record's fields held in registers (the box stores may alias the record)
+  const int nx = s.nx, ny = s.ny, nz = s.nz, N = (int)s.N;
+  const GLB float* __restrict__ PHI = gp((const float*)s.rp[bt.rd]) + N;
+  const GLB float* __restrict__ NRM = gp((const float*)s.nrm);
   // a particle whose box holds no fluid node with |G| near EPS_G or above gets
   // no force: every point's G is a convex combination of corner values, so it
   // would fail the |G| > EPS_G test of the force kernel (the 0.99 margin covers
@@ -233,15 +244,18 @@ __global__ void k_capbox(Batch bt) {
   bool iface = false;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < B * B * B; k += gridDim.x * blockDim.x) {
     const int ix = k % B, iy = (k / B) % B, iz = k / (B * B);
-    const int x = wrapi(org[0] + ix, s.nx), y = wrapi(org[1] + iy, s.ny), z = wrapi(org[2] + iz, s.nz);
-    const long long n = (long long)x + (long long)s.nx * ((long long)y + (long long)s.ny * z);
-    float4 v = make_float4(2.f, 0.f, 0.f, 0.f);  // phi = 2 marks a solid node
-    const float gw = s.nrm[3 * s.N + n];
-    if (gw >= 0.f) {
-      // G = n max(|G|, EPS_G): the colour gradient after the wetting rotation
-      const float gm = fmaxf(gw, EPS_G);
-      v = make_float4(PHI[n], s.nrm[n] * gm, s.nrm[s.N + n] * gm, s.nrm[2 * s.N + n] * gm);
-    }
+    const int x = wrapi(org[0] + ix, nx), y = wrapi(org[1] + iy, ny), z = wrapi(org[2] + iz, nz);
+    const unsigned n = (unsigned)(x + nx * (y + ny * z));
+    // every plane read at once and the solid case taken by selects (a load
+    // used only inside a branch is made there, a second round trip)
+    const float gw = at(NRM + 3 * N, n), ph = at(PHI, n);
+    const float n0 = at(NRM, n), n1 = at(NRM + N, n), n2 = at(NRM + 2 * N, n);
+    // G = n max(|G|, EPS_G): the colour gradient after the wetting rotation;
+    // phi = 2 marks a solid node
+    const bool fl = gw >= 0.f;
+    const float gm = fmaxf(gw, EPS_G);
+    const float4 v = make_float4(fl ? ph : 2.f, fl ? n0 * gm : 0.f, fl ? n1 * gm : 0.f,
+                                 fl ? n2 * gm : 0.f);
     box[k] = v;
     iface |= v.x <= 1.5f && v.y * v.y + v.z * v.z + v.w * v.w > (0.99f * EPS_G) * (0.99f * EPS_G);
   }
