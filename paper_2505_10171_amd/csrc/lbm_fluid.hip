@@ -669,7 +669,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // OPEN: the batch has simulations with open x ends (their anti-bounce-back is
 // compiled into this instance only).
 template <int STORE, int MODE, bool OPEN>
-__global__ __launch_bounds__(256) void k_fused(Batch bt, float* __restrict__ out_rho,
+// six waves per SIMD: the FP16 instance fits 80 VGPRs without spills (it took
+// 85 and five waves; eight waves spill and nearly double its time); the FP32
+// instances need fewer anyway
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fused(Batch bt, float* __restrict__ out_rho,
                                               float* __restrict__ out_u,
                                               float* __restrict__ out_phi,
                                               float* __restrict__ out_F) {
