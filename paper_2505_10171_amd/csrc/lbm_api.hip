@@ -350,10 +350,14 @@ static void set_mom_tiling(SimDev& d, int planes = 0) {
   if (planes > 0) {
     d.mkz = planes;
   } else {
+    // 1,536 = the interface pass's resident blocks (six per CU): a depth whose
+    // blocks overflow one round by a fraction leaves most CUs idle at the end
     d.mkz = (long long)d.nx * d.ny >= 65536 ? 12 : 6;
     const long long tiles = (long long)((d.nx + d.mtile_x - 1) / d.mtile_x) * ((d.ny + ty - 1) / ty);
     const long long b12 = tiles * ((d.nz + 11) / 12);
     if (d.mkz == 12 && b12 > 1536 && b12 < 4 * 1536) d.mkz = 6;
+    const long long b6 = tiles * ((d.nz + 5) / 6), b8 = tiles * ((d.nz + 7) / 8);
+    if (d.mkz == 6 && b6 > 1536 && b8 <= 1536) d.mkz = 8;
   }
   d.mtiles_x = (d.nx + d.mtile_x - 1) / d.mtile_x;
   d.mtiles_y = (d.ny + ty - 1) / ty;
