@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_capillary(Batch bt) {
   DevParticle& P = s.P[p];
   if (s.cap_pref == 0.0) return;  // no surface tension: no capillary force
   const int B = s.cap_B;
-  const float4* box = s.capbox + (long long)p * B * B * B;
+  const GLB v4f* box = gp((const v4f*)s.capbox) + (long long)p * B * B * B;
   const int org0 = (int)floor(P.x[0] - P.R), org1 = (int)floor(P.x[1] - P.R),
             org2 = (int)floor(P.x[2] - P.R);
   const double R = P.R, da = s.cap_dang;
@@ -314,28 +314,38 @@ __global__ __launch_bounds__(256) void k_capillary(Batch bt) {
     // per-point arithmetic in FP64: the torque is a small residual of large,
     // cancelling per-point moments
     double W = 0.0, phi = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
+    // the eight corners loaded at once; a solid corner (phi = 2) takes weight
+    // 0, which adds exact zeros (the box holds finite values): the same sums as
+    // leaving it out, without a load round trip per corner
+    v4f cv[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-      const float4 v = box[(i0 + ox) + B * ((i1 + oy) + B * (i2 + oz))];
-      if (v.x > 1.5f) continue;
-      const double w = (ox ? fr0 : 1.0 - fr0) * (oy ? fr1 : 1.0 - fr1) * (oz ? fr2 : 1.0 - fr2);
-      W += w;
-      phi += w * (double)v.x;
-      Gx += w * (double)v.y;
-      Gy += w * (double)v.z;
-      Gz += w * (double)v.w;
+      cv[c] = box[(i0 + ox) + B * ((i1 + oy) + B * (i2 + oz))];
     }
-    if (!(W > 0.0)) continue;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+      const v4f v = cv[c];
+      const double w = (ox ? fr0 : 1.0 - fr0) * (oy ? fr1 : 1.0 - fr1) * (oz ? fr2 : 1.0 - fr2);
+      const double wf = v.x > 1.5f ? 0.0 : w;
+      W += wf;
+      phi += wf * (double)v.x;
+      Gx += wf * (double)v.y;
+      Gy += wf * (double)v.z;
+      Gz += wf * (double)v.w;
+    }
+    // the three tests at once, after the values they need (W = 0 gives NaN,
+    // which fails them): a test on W and phi alone before G is formed would let
+    // the compiler load the corners' G only after it, a second round trip
     const double iW = 1.0 / W;
     phi *= iW;
     Gx *= iW;
     Gy *= iW;
     Gz *= iW;
     const double wgt = 1.0 - phi * phi;
-    if (!(wgt > 0.0)) continue;
     const double g = sqrt(Gx * Gx + Gy * Gy + Gz * Gz);
-    if (!(g > (double)EPS_G)) continue;
+    if (!(W > 0.0) || !(wgt > 0.0) || !(g > (double)EPS_G)) continue;
     const double ig = 1.0 / g;
     const double nx_ = Gx * ig, ny_ = Gy * ig, nz_ = Gz * ig;
     const double a = nx_ * sh[0] + ny_ * sh[1] + nz_ * sh[2];
