@@ -863,34 +863,58 @@ __global__ __launch_bounds__(256) void k_dem(Batch bt) {
 // the last sub-step): new centre, orientation and predicted velocities, into
 // the record and the view.
 __device__ void dem_predict(const SimDev& s, DevParticle& P, DemView& v, double dt) {
-  double th[3];
+  // every field read before the first store (a load behind a store to the
+  // record would wait for it)
+  const int kin = P.kin;
+  const double mass = P.mass, inertia = P.inertia;
+  const int nx = s.nx, ny = s.ny, nz = s.nz, has_wall = s.has_wall, open_x = s.open_x;
+  double Ff[3], Fcp[3], Tf[3], Tcp[3], X[3], V[3], W[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (P.kin) {
-      P.ao[d] = 0.0;
-      P.bo[d] = 0.0;
+    Ff[d] = P.Ff[d];
+    Fcp[d] = P.Fcp[d];
+    Tf[d] = P.Tf[d];
+    Tcp[d] = P.Tcp[d];
+    X[d] = P.x[d];
+    V[d] = P.v[d];
+    W[d] = P.w[d];
+  }
+  double th[3], ao[3], bo[3], vp[3], wp[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (kin) {
+      ao[d] = 0.0;
+      bo[d] = 0.0;
     } else {
-      P.ao[d] = (P.Ff[d] + P.Fcp[d]) / P.mass;
-      P.bo[d] = (P.Tf[d] + P.Tcp[d]) / P.inertia;
+      ao[d] = (Ff[d] + Fcp[d]) / mass;
+      bo[d] = (Tf[d] + Tcp[d]) / inertia;
     }
-    P.x[d] += P.v[d] * dt + 0.5 * P.ao[d] * dt * dt;
-    th[d] = P.w[d] * dt + 0.5 * P.bo[d] * dt * dt;
-    P.vp[d] = P.v[d] + P.ao[d] * dt;
-    P.wp[d] = P.w[d] + P.bo[d] * dt;
+    X[d] += V[d] * dt + 0.5 * ao[d] * dt * dt;
+    th[d] = W[d] * dt + 0.5 * bo[d] * dt * dt;
+    vp[d] = V[d] + ao[d] * dt;
+    wp[d] = W[d] + bo[d] * dt;
+  }
+  const double L[3] = {(double)nx, (double)ny, (double)nz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if ((d == 2 && has_wall) || (d == 0 && open_x)) continue;
+    if (X[d] >= L[d])
+      X[d] -= L[d];
+    else if (X[d] < 0.0)
+      X[d] += L[d];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    P.ao[d] = ao[d];
+    P.bo[d] = bo[d];
+    P.x[d] = X[d];
+    P.vp[d] = vp[d];
+    P.wp[d] = wp[d];
+    v.x[d] = X[d];
+    v.vp[d] = vp[d];
+    v.wp[d] = wp[d];
   }
   quat_rotate(P.q, th);
-  const double L[3] = {(double)s.nx, (double)s.ny, (double)s.nz};
-  for (int d = 0; d < 3; ++d) {
-    if ((d == 2 && s.has_wall) || (d == 0 && s.open_x)) continue;
-    if (P.x[d] >= L[d])
-      P.x[d] -= L[d];
-    else if (P.x[d] < 0.0)
-      P.x[d] += L[d];
-  }
-  for (int d = 0; d < 3; ++d) {
-    v.x[d] = P.x[d];
-    v.vp[d] = P.vp[d];
-    v.wp[d] = P.wp[d];
-  }
 }
 
 // Pair candidates of every particle within Rc_i + Rc_j + skin by a full loop
@@ -936,27 +960,42 @@ __global__ __launch_bounds__(64) void k_dem_setup(Batch bt, int np_rows, int mas
   const SimDev& s = bt.tab[sp.x];
   const int i = sp.y, np = s.np;
   DevParticle& P = s.P[i];
+  // every field read before the first store (a load behind a store to the
+  // record waits for it: one round trip per component otherwise)
+  double Fca[3], Tca[3], Fh[3], Th[3], Ffp[3], Tfp[3], X[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    P.Fcap[d] = P.Fca[d];
-    P.Tcap[d] = P.Tca[d];
+    Fca[d] = P.Fca[d];
+    Tca[d] = P.Tca[d];
+    Fh[d] = P.Fh[d];
+    Th[d] = P.Th[d];
+    Ffp[d] = P.Ffp[d];
+    Tfp[d] = P.Tfp[d];
+    X[d] = P.x[d];
+  }
+  const int havep = P.havep;
+  const double g_p = P.g_p, R = P.R;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    P.Fcap[d] = Fca[d];
+    P.Tcap[d] = Tca[d];
     P.Fca[d] = 0.0;
     P.Tca[d] = 0.0;
-    const double fc = P.Fh[d] + P.Fcap[d], tc = P.Th[d] + P.Tcap[d];
-    const double fp = P.havep ? P.Ffp[d] : fc, tp = P.havep ? P.Tfp[d] : tc;
-    P.Ff[d] = 0.5 * (fc + fp);
+    const double fc = Fh[d] + Fca[d], tc = Th[d] + Tca[d];
+    const double fp = havep ? Ffp[d] : fc, tp = havep ? Tfp[d] : tc;
+    P.Ff[d] = 0.5 * (fc + fp) - (d == 2 ? g_p : 0.0);
     P.Tf[d] = 0.5 * (tc + tp);
     P.Ffp[d] = fc;
     P.Tfp[d] = tc;
-    P.Fh_last[d] = P.Fh[d];
-    P.Th_last[d] = P.Th[d];
+    P.Fh_last[d] = Fh[d];
+    P.Th_last[d] = Th[d];
     P.Fh[d] = 0.0;
     P.Th[d] = 0.0;
-    P.xo[d] = P.x[d];
+    P.xo[d] = X[d];
     P.Facc[d] = 0.0;
     P.Tacc[d] = 0.0;
   }
-  P.Ff[2] -= P.g_p;
-  P.Ro = P.R;
+  P.Ro = R;
   P.havep = 1;
   P.cap_on = 0;
   // the step counter advances here (the sub-steps' history record takes the
@@ -1178,17 +1217,34 @@ __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub)
     for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
   if (lane != 0) return;
   DevParticle& P = s.P[i];
+  // every field read before the first store (a load behind a store to the
+  // record would wait for it)
+  const int kin = P.kin;
+  const double mass = P.mass, inertia = P.inertia;
+  double Ff[3], Tf[3], ao[3], bo[3], Vv[3], Ww[3], Fa[3], Ta[3];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if (!P.kin) {
-      const double an = (P.Ff[d] + acc[d]) / P.mass;
-      const double bn = (P.Tf[d] + acc[3 + d]) / P.inertia;
-      P.v[d] += 0.5 * (P.ao[d] + an) * dt;
-      P.w[d] += 0.5 * (P.bo[d] + bn) * dt;
+    Ff[d] = P.Ff[d];
+    Tf[d] = P.Tf[d];
+    ao[d] = P.ao[d];
+    bo[d] = P.bo[d];
+    Vv[d] = P.v[d];
+    Ww[d] = P.w[d];
+    Fa[d] = P.Facc[d];
+    Ta[d] = P.Tacc[d];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!kin) {
+      const double an = (Ff[d] + acc[d]) / mass;
+      const double bn = (Tf[d] + acc[3 + d]) / inertia;
+      P.v[d] = Vv[d] + 0.5 * (ao[d] + an) * dt;
+      P.w[d] = Ww[d] + 0.5 * (bo[d] + bn) * dt;
     }
     P.Fcp[d] = acc[d];
     P.Tcp[d] = acc[3 + d];
-    P.Facc[d] += acc[d];
-    P.Tacc[d] += acc[3 + d];
+    P.Facc[d] = Fa[d] + acc[d];
+    P.Tacc[d] = Ta[d] + acc[3 + d];
   }
   if (sub + 1 < s.n_sub) {
     dem_predict(s, P, s.view[((sub + 1) & 1) * np + i], dt);
