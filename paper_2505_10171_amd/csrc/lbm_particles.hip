@@ -1122,8 +1122,8 @@ __device__ __forceinline__ void contact_force(const SimDev& s, Contact* sl, doub
 
 // One DEM sub-step of every particle: a wave per particle (four per block).
 __global__ __launch_bounds__(256) void k_dem_sub(Batch bt, int np_rows, int sub) {
-  // the wave's particle row, uniform over the wave: said so, the simulation
-  // record, the particle's view and its contact table are read by scalar loads
+  // the particle row is the same for the whole wave; declared uniform, it lets
+  // the simulation record and the particle's own data be read by scalar loads
   const int r = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + ((int)threadIdx.x >> 6));
   const int lane = (int)threadIdx.x & 63;
   if (r >= np_rows) return;  // the whole wave
