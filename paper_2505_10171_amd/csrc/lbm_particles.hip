@@ -83,10 +83,20 @@ __global__ void k_release(Batch bt) {
     // mask and claim in one round trip
     const uint16_t m = at((const GLB uint16_t*)MASK, n);
     const uint32_t c = at(CLAIM, n);
-    if (m != (uint16_t)(2 + p)) continue;
-    if (c == 0xFFFFFFFFu) {
+    const bool mine = m == (uint16_t)(2 + p);
+    const bool fresh = mine && c == 0xFFFFFFFFu;
+    // the wave's fresh nodes take consecutive slots of the fresh list: one
+    // atomic per wave (the list's order does not matter to the refill)
+    const unsigned long long want = __ballot(fresh);
+    uint32_t base0 = 0;
+    const int lane = (int)(threadIdx.x & 63);
+    const int first = want ? __ffsll((long long)want) - 1 : 0;
+    if (want && lane == first) base0 = atomicAdd(&s.counters[0], (uint32_t)__popcll(want));
+    base0 = (uint32_t)__shfl((int)base0, first, 64);
+    if (!mine) continue;
+    if (fresh) {
       MASK[n] = FRESH_BIT;
-      const uint32_t slot = atomicAdd(&s.counters[0], 1u);
+      const uint32_t slot = base0 + (uint32_t)__popcll(want & ((1ull << lane) - 1ull));
       if (slot < s.fresh_cap) {
         s.fresh[slot] = n;
         s.fresh_own[slot] = (uint32_t)p;
@@ -158,16 +168,20 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
         const int mx = wrapi(x + cx(dir), s.nx), my = wrapi(y + cy(dir), s.ny),
                   mz = wrapi(z + cz(dir), s.nz);
         const int m = mx + s.nx * (my + s.ny * mz);
-        if (s.mask[m] == 0) {
-          float rho, sg;
-          if (MODE == REFILL_STEP) {
-            const Nbr nbm(mx, my, mz, s.nx, s.ny, s.nz);
-            rebuild_moments<STORE>(gp((const T*)b), RO, gp((const float*)s.nrm), N, m, nbm,
-                                   s.rho0, 0.5f * s.beta, STORE ? RO[m] : 0.f, rho, sg);
-          } else {
-            rho = RN[m];
-            sg = rho * RN[N + m];
-          }
+        // the neighbour's moments formed whether or not it is fluid, so that
+        // their loads go out with its mask's (a solid or fresh neighbour's
+        // values are discarded)
+        const bool fl = s.mask[m] == 0;
+        float rho, sg;
+        if (MODE == REFILL_STEP) {
+          const Nbr nbm(mx, my, mz, s.nx, s.ny, s.nz);
+          rebuild_moments<STORE>(gp((const T*)b), RO, gp((const float*)s.nrm), N, m, nbm,
+                                 s.rho0, 0.5f * s.beta, STORE ? RO[m] : 0.f, rho, sg);
+        } else {
+          rho = RN[m];
+          sg = rho * RN[N + m];
+        }
+        if (fl) {
           ra = 0.5f * (rho + sg);
           rb = 0.5f * (rho - sg);
           c = 1;
