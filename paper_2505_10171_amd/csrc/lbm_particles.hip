@@ -168,20 +168,16 @@ __global__ __launch_bounds__(256) void k_refill(Batch bt) {
         const int mx = wrapi(x + cx(dir), s.nx), my = wrapi(y + cy(dir), s.ny),
                   mz = wrapi(z + cz(dir), s.nz);
         const int m = mx + s.nx * (my + s.ny * mz);
-        // the neighbour's moments formed whether or not it is fluid, so that
-        // their loads go out with its mask's (a solid or fresh neighbour's
-        // values are discarded)
-        const bool fl = s.mask[m] == 0;
-        float rho, sg;
-        if (MODE == REFILL_STEP) {
-          const Nbr nbm(mx, my, mz, s.nx, s.ny, s.nz);
-          rebuild_moments<STORE>(gp((const T*)b), RO, gp((const float*)s.nrm), N, m, nbm,
-                                 s.rho0, 0.5f * s.beta, STORE ? RO[m] : 0.f, rho, sg);
-        } else {
-          rho = RN[m];
-          sg = rho * RN[N + m];
-        }
-        if (fl) {
+        if (s.mask[m] == 0) {
+          float rho, sg;
+          if (MODE == REFILL_STEP) {
+            const Nbr nbm(mx, my, mz, s.nx, s.ny, s.nz);
+            rebuild_moments<STORE>(gp((const T*)b), RO, gp((const float*)s.nrm), N, m, nbm,
+                                   s.rho0, 0.5f * s.beta, STORE ? RO[m] : 0.f, rho, sg);
+          } else {
+            rho = RN[m];
+            sg = rho * RN[N + m];
+          }
           ra = 0.5f * (rho + sg);
           rb = 0.5f * (rho - sg);
           c = 1;
