@@ -37,7 +37,7 @@ hipError_t launch_mass(const SimDev& s, const float* rp, double* acc, hipStream_
 hipError_t launch_zero_f64(double* p, int n, hipStream_t st);
 hipError_t launch_mask_update(const Batch& b, int np_rows, int Bmax, bool with_release,
                               hipStream_t st);
-hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int mode,
+hipError_t launch_refill(const Batch& b, int storage, size_t fresh_cap_max, int np_max, int mode,
                          hipStream_t st);
 // kernel modes (lbm_fluid.hip, lbm_particles.hip): in a step, or between steps
 constexpr int MOM_STEP = 0, MOM_BOUNDARY = 1, REFILL_STEP = 0, REFILL_BOUNDARY = 1;
@@ -477,7 +477,7 @@ static int post_dem_pipeline(lbm_ctx* ctx, int si, bool with_release) {
   const Batch b = batch_one(ctx, si);
   if (s.np > 0) {
     HIPCHK(ctx, launch_mask_update(b, s.np, sh.L.Bmask, with_release, ctx->stream));
-    HIPCHK(ctx, launch_refill(b, ctx->storage, s.fresh_cap, REFILL_BOUNDARY, ctx->stream));
+    HIPCHK(ctx, launch_refill(b, ctx->storage, s.fresh_cap, s.np, REFILL_BOUNDARY, ctx->stream));
   }
   HIPCHK(ctx, launch_moments(b, ctx->storage, sim_blocks(s), 0, MOM_BOUNDARY, ctx->stream));
   return LBM_OK;
@@ -723,7 +723,7 @@ static int step_once(lbm_ctx* ctx, int slot) {
     if (ctx->cap_needed) HIPCHK(ctx, launch_capillary(a, ctx->np_rows, ctx->cap_B, ctx->npts, st));
     HIPCHK(ctx, launch_dem(a, ctx->np_max, ctx->np_rows, ctx->n_sub_max, st));
     HIPCHK(ctx, launch_mask_update(a, ctx->np_rows, ctx->Bmax, true, st));
-    HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, REFILL_STEP, st));
+    HIPCHK(ctx, launch_refill(a, ctx->storage, ctx->fresh_cap_max, ctx->np_max, REFILL_STEP, st));
   }
   if (slot >= 0) HIPCHK(ctx, hipEventRecord(P.ev[slot][4], st));
   HIPCHK(ctx, launch_moments(a, ctx->storage, ctx->nblk, ctx->mnblk, MOM_STEP, st));
