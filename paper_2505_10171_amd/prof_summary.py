@@ -7,6 +7,11 @@
 ``stats`` condenses a ``--kernel-trace --stats`` kernel_stats CSV into a short
 table (calls, average and total duration, share of GPU time per kernel).
 
+``sq`` condenses one ``--pmc`` run of SQ counters into per-thread instruction
+counts of each kernel (a thread is one lane of a wave: INSTS / WAVES) and the
+time the vector-ALU instructions alone take to issue (4 cycles per wave64
+instruction on each of the 1,024 SIMDs at 2.4 GHz).
+
 ``counters`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs into HBM
 bytes per launch of each kernel named (``--kernel`` regex, repeatable).  Both runs must contain one plain device copy of
 known size (the largest ``__amd_rocclr_copyBuffer`` dispatch): each counter is
@@ -104,6 +109,37 @@ def counters(fetch, write, kernels, probe_bytes, out, commands):
     print("\n".join(lines))
 
 
+SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
+
+
+def sq(path, out, commands):
+    """Per-kernel means of every SQ counter in one --pmc run, with per-thread
+    instruction counts and the vector-ALU issue time."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        name = short_name(r["Kernel_Name"])
+        per.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = ["# SQ counters per launch (rocprofv3 --pmc)", ""]
+    for c in commands:
+        lines.append(f"command: {c}")
+    lines.append("")
+    for name, ctr in per.items():
+        m = {k: statistics.mean(v) for k, v in ctr.items()}
+        lines.append(f"{name}: {len(next(iter(ctr.values())))} dispatches")
+        for k in sorted(m):
+            lines.append(f"  {k:24s} {m[k]:.4e}")
+        waves = m.get("SQ_WAVES", 0.0)
+        if waves:
+            for k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS"):
+                if k in m:
+                    lines.append(f"  {k.lower()}_per_thread  {m[k] / waves:.1f}")
+        if "SQ_INSTS_VALU" in m:
+            t = m["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * CLOCK_HZ)
+            lines.append(f"  valu_issue_us            {t * 1e6:.1f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def read_counters(path):
     """{kernel: total HBM bytes per launch} and the source hash of a summary
     written by `counters`."""
@@ -129,8 +165,14 @@ def main():
     b.add_argument("--probe-bytes", type=float, required=True)
     b.add_argument("out")
     b.add_argument("--command", action="append", default=[])
+    c = sub.add_parser("sq")
+    c.add_argument("csv")
+    c.add_argument("out")
+    c.add_argument("--command", action="append", default=[])
     args = ap.parse_args()
-    if args.cmd == "stats":
+    if args.cmd == "sq":
+        sq(args.csv, args.out, args.command)
+    elif args.cmd == "stats":
         stats(args.csv, args.out, args.command)
     else:
         counters(args.fetch, args.write, args.kernel or ["k_fused"], args.probe_bytes, args.out,
