@@ -269,8 +269,8 @@ struct SimHost {
 // event sets is reused; a set is harvested (its elapsed times accumulated)
 // before it is recorded again.
 constexpr int PROF_RING = 32;
-// 0 k_fused, 1 particle kernels but k_links, 2 k_moments, 3 interface (k_normal,
-// k_curv), 4 k_links
+// 0 k_fused, 1 particle kernels but k_links, 2 k_moments, 3 k_interface,
+// 4 k_links
 constexpr int PROF_KINDS = 5;
 constexpr int PROF_EVENTS = PROF_KINDS + 1;
 struct Profiler {

@@ -9,8 +9,8 @@
 // h_i = (f_i - w_i R) / (w_i rho0) with R the node's density of the previous
 // state.  All arithmetic is FP32; momentum exchange sums are FP64.
 //
-// A step of the fluid runs k_normal and k_curv (interface normal, curvature
-// and CSF coefficient from phi), k_fused (collision, force, streaming and
+// A step of the fluid runs k_interface (interface normal, curvature and CSF
+// coefficient from phi, in one z-march), k_fused (collision, force, streaming and
 // bounce-back of f, one thread per node, reading and writing every population
 // exactly once), k_links (moving-wall terms and momentum exchange at particle
 // links) and k_moments (density and order parameter of the post-stream state).
@@ -962,7 +962,7 @@ static inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 
 // Batched launchers: one launch over every simulation of the batch.
 // nblk: total 256-node blocks; np_rows: total particle rows; Bmax: the largest
 // mask-box side of the batch.
-// nblk: per-node blocks; mnblk: blocks of the moments tiling (k_normal)
+// nblk: per-node blocks; mnblk: blocks of the moments tiling (k_interface)
 hipError_t launch_interface(const Batch& b, unsigned nblk, unsigned mnblk, hipStream_t st) {
   (void)nblk;
   const bool w64 = b.mlx == 6;  // 64-wide tiles: the instance with them fixed
