@@ -435,15 +435,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
               : (OPEN && s.open_x && (ax < 0 || ax >= nx)) ? -1
                                                    : wrapi(ax, nx) + nx * wrapi(y0 - 2 + fy, ny);
   }
-  // this thread's normal region entries (t, t + 256)
+  // this thread's normal region entries: first its own column and row of the
+  // region's first tx x ty entries, then the region's two top rows and its
+  // two right columns (2 tx + 2 ty + 4 <= 256 entries for the tiles used), so
+  // that a wave's entries lie in whole rows: its phi reads are consecutive
+  // LDS words (taken in region order, a wave's 64 entries crossed a row end,
+  // and two of them met in one LDS bank)
   int hx_[2], hy_[2];
   bool hon[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int k = t + 256 * j;
-    hon[j] = k < HX * HY;
-    hy_[j] = k / HX;
-    hx_[j] = k - hy_[j] * HX;
+  hx_[0] = lx;
+  hy_[0] = ly;
+  hon[0] = true;
+  {
+    const int u = t - 2 * tx;
+    hon[1] = u < 2 * HY;
+    hx_[1] = u < 0 ? lx : tx + (u & 1);
+    hy_[1] = u < 0 ? ty + (t >> tlx) : (u >> 1);
   }
   auto zw = [&](int z) { return wrapi(z, nz); };
   auto fslot = [&](int z) { return (z + 8) & 3; };  // z >= -2
@@ -527,7 +534,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     for (int j = 0; j < 2; ++j)
       if (hon[j]) {
         const v4f v = normal(hx_[j], hy_[j], z, SOL);
-        const int k = t + 256 * j;
+        const int k = hx_[j] + HX * hy_[j];
         nrx[sl][k] = v.x;
         nry[sl][k] = v.y;
         nrz[sl][k] = v.z;
