@@ -331,7 +331,9 @@ static void set_tile(SimDev& d, int tx) {
 }
 
 // tiling of the moments and interface passes: x-y tiles, the widest of 64,
-// 32, 16 that the box fills, each block marching mkz planes up z: 12 on planes
+// 32, 16 whose whole tiles cover the box's width with at most 15 % to spare
+// (else 16: an 80-wide box takes five 16-wide tiles, not two 64-wide ones of
+// which the second is three-quarters idle), each block marching mkz planes up z: 12 on planes
 // of 64k nodes or more (the two extra planes a block loads at its ends are
 // then a sixth of its work, not a third), 6 on smaller ones, whose neighbour
 // planes stay in the caches anyway (measured: the moments pass of a 256x128
@@ -344,7 +346,13 @@ static void set_tile(SimDev& d, int tx) {
 // interface + moments 268 us at 12 planes, 245 us at 6; the 512 x 256 x 192
 // slab and boxes of under one round are within 1 % either way).
 static void set_mom_tiling(SimDev& d, int planes = 0) {
-  d.mtile_x = d.nx >= 64 ? 64 : (d.nx >= 32 ? 32 : 16);
+  d.mtile_x = 16;
+  for (int w : {64, 32}) {
+    if (100LL * ((d.nx + w - 1) / w) * w <= 115LL * d.nx) {
+      d.mtile_x = w;
+      break;
+    }
+  }
   d.mtile_lx = d.mtile_x == 64 ? 6 : (d.mtile_x == 32 ? 5 : 4);
   const int ty = 256 / d.mtile_x;
   if (planes > 0) {
