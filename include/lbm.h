@@ -273,7 +273,7 @@ int lbm_set_tile(lbm_ctx* ctx, int32_t sim, int32_t tile_x);
 
 /* Marching depth of the interface and moments passes of one simulation: each
  * block takes an x-y tile of 64 x 4, 32 x 8 or 16 x 16 nodes (the widest
- * whose whole tiles cover the box's width with at most 15 % to spare, else
+ * whose whole tiles cover the box's width with at most 20 % to spare, else
  * 16 x 16) and marches up `planes` planes (1..256; 0 restores the default: 12 on planes
  * of at least 65,536 nodes unless that gives between 1,536 and 6,144 blocks,
  * else 6, or 8 where 6 gives more than 1,536 blocks and 8 at most 1,536).

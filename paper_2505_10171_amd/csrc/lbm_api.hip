@@ -331,9 +331,10 @@ static void set_tile(SimDev& d, int tx) {
 }
 
 // tiling of the moments and interface passes: x-y tiles, the widest of 64,
-// 32, 16 whose whole tiles cover the box's width with at most 15 % to spare
-// (else 16: an 80-wide box takes five 16-wide tiles, not two 64-wide ones of
-// which the second is three-quarters idle), each block marching mkz planes up z: 12 on planes
+// 32, 16 whose whole tiles cover the box's width with at most 20 % to spare
+// (else 16: an 80-wide box takes three 32-wide tiles, not two 64-wide ones of
+// which the second is three-quarters idle; measured on the ensemble of 48- to
+// 96-wide boxes: 20 % beat 15 % and 34 %), each block marching mkz planes up z: 12 on planes
 // of 64k nodes or more (the two extra planes a block loads at its ends are
 // then a sixth of its work, not a third), 6 on smaller ones, whose neighbour
 // planes stay in the caches anyway (measured: the moments pass of a 256x128
@@ -348,7 +349,7 @@ static void set_tile(SimDev& d, int tx) {
 static void set_mom_tiling(SimDev& d, int planes = 0) {
   d.mtile_x = 16;
   for (int w : {64, 32}) {
-    if (100LL * ((d.nx + w - 1) / w) * w <= 115LL * d.nx) {
+    if (100LL * ((d.nx + w - 1) / w) * w <= 120LL * d.nx) {
       d.mtile_x = w;
       break;
     }
