@@ -276,8 +276,9 @@ int lbm_set_tile(lbm_ctx* ctx, int32_t sim, int32_t tile_x);
  * whose whole tiles cover the box's width with at most 20 % to spare, else
  * 16 x 16) and marches up `planes` planes (1..256; 0 restores the default: 12 on planes
  * of at least 65,536 nodes unless that gives between 1,536 and 6,144 blocks,
- * else 6, or 8 where 6 gives more than 1,536 blocks and 8 at most 1,536).
- * Results are identical with any depth;
+ * else 6, or 8 where 6 gives more than 1,536 blocks and 8 at most 1,536; a
+ * context of several simulations whose blocks at depth 24 number at least
+ * 6,144 starts every simulation at 24).  Results are identical with any depth;
  * deeper blocks re-read fewer halo planes, shallower ones give more blocks
  * to fill the GPU. */
 int lbm_set_march(lbm_ctx* ctx, int32_t sim, int32_t planes);

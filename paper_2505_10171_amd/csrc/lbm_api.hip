@@ -673,6 +673,17 @@ int lbm_create(const lbm_config* cfg, int32_t n_sims, const float* const* phi0,
       if (hipStreamSynchronize(st) != hipSuccess) return fail(LBM_EHIP, "synchronise failed");
     }
   }
+  // a batch whose blocks fill the GPU several times over even at a depth of
+  // 24 planes marches 24 (each block re-reads its two halo planes once per 24
+  // planes, not per 6 or 12; measured on the ensemble of 256 boxes 48 to 96
+  // wide: 8.75 ms per step at the single-box depths, 8.54 at 12, 8.36 at 24)
+  if (ctx->sims.size() > 1) {
+    long long deep = 0;
+    for (const SimHost& sh : ctx->sims)
+      deep += (long long)sh.d.mtiles_x * sh.d.mtiles_y * ((sh.d.nz + 23) / 24);
+    if (deep >= 4 * 1536)
+      for (SimHost& sh : ctx->sims) set_mom_tiling(sh.d, 24);
+  }
   // batch tables: simulation records, block prefix, particle rows
   ctx->storage = cfg[0].storage;
   if (int rc = upload_tables(ctx, off)) return fail(rc, ctx->msg);
